@@ -1,0 +1,155 @@
+"""Pins of the oracle's discretization and direct solvers (CPU only).
+
+Each test checks the oracle against something other than itself: exact
+algebraic structure, closed-form spectra, an independently built separable
+operator, the free-space Hankel field, or brute-force dense algebra.
+"""
+import numpy as np
+import pytest
+
+from oracle import assemble, direct, fastdiag, hankel, pml
+import workloads as W
+
+
+def _stencil(n, omega, npml, c=None, C=pml.DEFAULT_C):
+    c = W.constant_medium(n) if c is None else c
+    return assemble.stencil(c, omega, npml, C)
+
+
+def test_sigma_profile_shape():
+    # eq. sigma: zero inside [eta, 1-eta], quadratic growth to C/eta at the walls, mirror symmetric.
+    eta, C = 0.25, 7.0
+    t = np.linspace(0, 1, 101)
+    s = pml.sigma(t, eta, C)
+    assert np.all(s[(t >= eta) & (t <= 1 - eta)] == 0)
+    assert s[0] == pytest.approx(C / eta)
+    assert s[-1] == pytest.approx(C / eta)
+    np.testing.assert_allclose(s, s[::-1], rtol=0, atol=1e-12)
+    # quadratic: sigma(eta/2) = (C/eta) / 4
+    assert pml.sigma(np.array([eta / 2]), eta, C)[0] == pytest.approx(C / eta / 4)
+    # outgoing damping: Im(1/s) = sigma/omega > 0
+    z = 1.0 / pml.stretch(t, 3.0, eta, C)
+    np.testing.assert_allclose(z.imag, s / 3.0, rtol=1e-14)
+
+
+def test_operator_symmetric_bitwise_and_layer_structure():
+    n = 31
+    st = _stencil(n, 2 * np.pi * 3, 5, W.random_field_medium(n, 7))
+    A = assemble.matrix(st)
+    assert abs(A - A.T).max() == 0.0
+    Ad = A.toarray()
+    for m in range(2, n + 1):
+        blk = Ad[(m - 1) * n:m * n, (m - 2) * n:(m - 1) * n]     # A_{m,m-1}
+        assert np.count_nonzero(blk - np.diag(np.diag(blk))) == 0
+        np.testing.assert_array_equal(blk, Ad[(m - 2) * n:(m - 1) * n, (m - 1) * n:m * n].T)
+        Amm = Ad[(m - 1) * n:m * n, (m - 1) * n:m * n]
+        np.testing.assert_array_equal(Amm, assemble.layer_tridiag(st, m))
+    # no coupling beyond adjacent layers
+    assert np.count_nonzero(Ad[2 * n:3 * n, 0:n]) == 0
+
+
+def test_row_sums_of_interior_rows():
+    n = 15
+    c = W.random_field_medium(n, 3)
+    st = _stencil(n, 2 * np.pi * 2, 4, c)
+    A = assemble.matrix(st).toarray()
+    rs = A.sum(axis=1).reshape(n, n)
+    expect = st.omega ** 2 / (st.s1s2 * c ** 2)
+    np.testing.assert_allclose(rs[1:-1, 1:-1], expect[1:-1, 1:-1], rtol=1e-13)
+
+
+def test_without_pml_spectrum_is_closed_form():
+    # pml = 0, constant c: A = Dirichlet 5-point Laplacian + omega^2/c^2, whose
+    # eigenvalues are omega^2/c^2 - (4/h^2)(sin^2(k1 pi h/2) + sin^2(k2 pi h/2)).
+    n, c0, omega = 9, 1.3, 5.0
+    st = _stencil(n, omega, 0, W.constant_medium(n, c0))
+    ev = np.sort(np.linalg.eigvals(assemble.matrix(st).toarray()).real)
+    h = 1.0 / (n + 1)
+    k = np.arange(1, n + 1)
+    mu = (4 / h ** 2) * np.sin(k * np.pi * h / 2) ** 2
+    expect = np.sort((omega ** 2 / c0 ** 2 - (mu[:, None] + mu[None, :])).ravel())
+    np.testing.assert_allclose(ev, expect, rtol=1e-12, atol=1e-9)
+
+
+def test_apply_matches_matrix():
+    n = 20
+    st = _stencil(n, 2 * np.pi * 2, 4, W.random_field_medium(n, 2))
+    rng = np.random.default_rng(0)
+    u = rng.standard_normal((3, n * n)) + 1j * rng.standard_normal((3, n * n))
+    A = assemble.matrix(st)
+    np.testing.assert_allclose(assemble.apply(st, u), (A @ u.T).T, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("n", [3, 7, 15])
+def test_direct_solvers_agree_on_tiny_grids(n):
+    c = W.random_field_medium(n, 11) if n > 3 else np.array([[1.0, 1.1, 0.9], [1.2, 1.0, 0.8], [1.0, 0.95, 1.05]])
+    st = _stencil(n, 2 * np.pi * 1.5, max(1, n // 5), c)
+    rng = np.random.default_rng(n)
+    f = rng.standard_normal(n * n) + 1j * rng.standard_normal(n * n)
+    u_dense = direct.solve_dense(st, f)
+    for u in (direct.solve_sparse(st, f), direct.solve_banded(st, f)):
+        assert np.linalg.norm(u - u_dense) / np.linalg.norm(u_dense) < 1e-12
+    assert direct.relative_residual(st, u_dense, f) < 1e-12
+
+
+@pytest.mark.parametrize("n,npml,freq", [(63, 12, 8), (255, 16, 32)])
+def test_sparse_lu_matches_fast_diagonalization(n, npml, freq):
+    omega = 2 * np.pi * freq
+    st = _stencil(n, omega, npml)
+    f = W.gaussian_source(n, (0.5, 0.5)).ravel()
+    u_lu = direct.solve_sparse(st, f)
+    u_fd = fastdiag.solve_constant(n, omega, npml, 1.0, f)
+    assert np.linalg.norm(u_lu - u_fd) / np.linalg.norm(u_fd) < 1e-10
+
+
+def test_hankel_field_second_order_convergence():
+    # c = 1, omega = 2 pi 4, absorbing layer 0.2 wide, centre source; compare on
+    # the annulus 0.1 <= r <= 0.3 (outside source and layer).
+    omega = 2 * np.pi * 4
+    errs = []
+    for n in (63, 127, 255):
+        h = 1.0 / (n + 1)
+        npml = int(round(0.2 / h))
+        st = _stencil(n, omega, npml)
+        f = W.gaussian_source(n, (0.5, 0.5)).ravel()
+        u = direct.solve_sparse(st, f).reshape(n, n)
+        ur, r = hankel.gaussian_field(n, omega, (0.5, 0.5))
+        mask = (r >= 0.1) & (r <= 0.3)
+        errs.append(np.linalg.norm(u[mask] - ur[mask]) / np.linalg.norm(ur[mask]))
+    assert errs[-1] < 2e-2
+    for a, b in zip(errs[:-1], errs[1:]):
+        assert 3.5 < a / b < 4.5, errs
+
+
+def test_incoming_convention_fails_hankel_pin():
+    # Planted mistake: flipping the sign of the stretching makes waves grow in
+    # the layer; the field no longer matches the outgoing Hankel function.
+    n, omega = 127, 2 * np.pi * 4
+    h = 1.0 / (n + 1)
+    npml = int(round(0.2 / h))
+    st = _stencil(n, omega, npml)
+    # rebuild with sigma -> -sigma, i.e. s -> conj(s)
+    st_bad = assemble.stencil(W.constant_medium(n), omega, npml, C=-pml.DEFAULT_C)
+    f = W.gaussian_source(n, (0.5, 0.5)).ravel()
+    ur, r = hankel.gaussian_field(n, omega, (0.5, 0.5))
+    mask = (r >= 0.1) & (r <= 0.3)
+    good = direct.solve_sparse(st, f).reshape(n, n)
+    bad = direct.solve_sparse(st_bad, f).reshape(n, n)
+    e_good = np.linalg.norm(good[mask] - ur[mask]) / np.linalg.norm(ur[mask])
+    e_bad = np.linalg.norm(bad[mask] - ur[mask]) / np.linalg.norm(ur[mask])
+    assert e_good < 1e-2 and e_bad > 0.2
+
+
+def test_dropped_edge_term_fails_fast_diagonalization_pin():
+    # Planted mistake: a centre coefficient that forgets the north edge.
+    n, npml, omega = 31, 6, 2 * np.pi * 4
+    st = _stencil(n, omega, npml)
+    D_bad = st.D + st.N
+    st_bad = assemble.Stencil(n=st.n, omega=st.omega, h=st.h, W=st.W, E=st.E, S=st.S, N=st.N,
+                              D=D_bad, s1s2=st.s1s2, c=st.c)
+    f = W.gaussian_source(n, (0.5, 0.5)).ravel()
+    u_fd = fastdiag.solve_constant(n, omega, npml, 1.0, f)
+    ok = direct.solve_sparse(st, f)
+    bad = direct.solve_sparse(st_bad, f)
+    assert np.linalg.norm(ok - u_fd) / np.linalg.norm(u_fd) < 1e-10
+    assert np.linalg.norm(bad - u_fd) / np.linalg.norm(u_fd) > 1e-3
