@@ -1,0 +1,173 @@
+"""Benchmark: 2D Helmholtz solves/s at relative residual 1e-6, complex64 sweep
+(FP64 residual and Arnoldi) beside the complex128 sweep, on one MI355X.
+
+Workload (n=255): omega = 2 pi 32 (8 points per wavelength), velocity
+c = 1 + 0.3 * smooth Gaussian random field (correlation 0.1, seed 1), PML 16
+points, centre Gaussian source, H-matrix Schur complements with leaf 16 and
+rank <= 8 at relative tolerance 1e-6.
+
+One step is the whole hot path for one right-hand side with the inputs
+already in device memory: stencil coefficients, the layer-by-layer
+factorization with H-matrix Schur complements, and flexible GMRES with the
+sweep as preconditioner until ||f - A u|| <= 1e-6 ||f||.
+
+Prints one JSON line.  `roofline` covers the sweep kernel (one launch = one
+application of the preconditioner, 2n-1 layer steps), timed with HIP events
+inside the library on the stream it runs on.  `cpu_baseline` times the CPU
+oracle (sparse LU, the plain definition u = A^{-1} f) on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "2D Helmholtz solves/s at rel. residual 1e-6: complex64 vs FP64 sweep"
+
+
+def sweep_bytes(plan, n, elem, nrhs=1):
+    """Algorithmic bytes of one sweep launch: every layer's factor data is
+    read once per layer step (2n-1 steps), plus the couplings, the input and
+    output fields (complex128) and the forward work vector (written, then read)."""
+    np_, b, L, r = plan["n_p"], plan["b"], plan["levels"], plan["r"]
+    e_layer = np_ * b + L * r * np_ + ((1 << L) - 1) * 4 * r * r
+    fac = (2 * n - 1) * e_layer * elem
+    coup = 2 * (n - 1) * np_ * elem
+    vec = nrhs * (2 * n * n * 16 + 2 * n * np_ * elem)
+    return fac + coup * nrhs + vec
+
+
+def run_gpu(wl, precision, steps, warmup, tol):
+    import torch
+    from paper_1007_4290_amd.solver import Solver
+
+    c = wl.velocity()
+    f = torch.as_tensor(wl.sources(), device="cuda:0")
+    s = Solver(c, wl.omega, wl.pml, leaf=wl.leaf, rank=wl.rank, rank_tol=wl.rank_tol, precision=precision)
+    for _ in range(warmup):
+        s.factor()
+        s.solve(f, tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sweep_ms, applies, factor_ms, iters, res = 0.0, 0, 0.0, [], []
+    for _ in range(steps):
+        s.factor()
+        factor_ms += s.timings()["factor_ms"]
+        u, it, rr = s.solve(f, tol=tol)
+        tm = s.timings()
+        sweep_ms += tm["sweep_ms"]
+        applies += tm["applies"]
+        iters.append(it[0])
+        res.append(rr[0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # solve phase alone (factorization reused)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        s.solve(f, tol=tol)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    info = s.plan_info()
+    info.update({"b": wl.leaf, "r": wl.rank})
+    return {
+        "ms_per_step": 1e3 * (t1 - t0) / steps,
+        "solve_ms": 1e3 * (t3 - t2) / steps,
+        "factor_ms": factor_ms / steps,
+        "sweep_ms_avg": sweep_ms / max(applies, 1),
+        "iters": iters,
+        "relres": max(res),
+        "plan": info,
+        "u": u.cpu().numpy(),
+    }
+
+
+def cpu_baseline(wl, budget_s=10.0):
+    """The oracle's direct solve (SuperLU factor + solve), timed on the host."""
+    from oracle import assemble, direct
+    c = wl.velocity()
+    f = wl.sources()[0]
+    t0 = time.perf_counter()
+    count = 0
+    u = None
+    while True:
+        st = assemble.stencil(c, wl.omega, wl.pml)
+        u = direct.solve_sparse(st, f)
+        count += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{count} complete oracle solves (assembly + SuperLU factor + solve) of the "
+                      f"n={wl.n} workload in {dt:.1f} s on one host core"}, u
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import workloads as W
+
+    tol = 1e-6
+    wl = W.get("helm255_grf", precision="c64")
+    r64 = run_gpu(wl, "c64", args.steps, args.warmup, tol)
+    print(f"[bench] c64: {r64['ms_per_step']:.2f} ms/step, iters {r64['iters'][0]}", file=sys.stderr, flush=True)
+    r128 = run_gpu(wl, "c128", args.steps, args.warmup, tol)
+    print(f"[bench] c128: {r128['ms_per_step']:.2f} ms/step, iters {r128['iters'][0]}", file=sys.stderr, flush=True)
+
+    plan = r64["plan"]
+    nbytes = sweep_bytes(plan, wl.n, 8)
+    achieved = nbytes / (r64["sweep_ms_avg"] * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": 1e3 / r64["ms_per_step"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "helm255_grf", "n": wl.n, "omega": "2pi*32", "pml": wl.pml,
+                   "medium": "1+0.3*GRF(l=0.1,seed=1)", "source": "centre Gaussian", "leaf": wl.leaf,
+                   "rank": wl.rank, "rank_tol": wl.rank_tol, "gmres_tol": tol, "n_p": plan["n_p"],
+                   "levels": plan["levels"]},
+        "c64": {"solves_per_s": 1e3 / r64["ms_per_step"], "factor_ms": r64["factor_ms"],
+                "solve_ms": r64["solve_ms"], "solve_phase_solves_per_s": 1e3 / r64["solve_ms"],
+                "gmres_iters": r64["iters"][0], "relres": r64["relres"]},
+        "c128": {"solves_per_s": 1e3 / r128["ms_per_step"], "factor_ms": r128["factor_ms"],
+                 "solve_ms": r128["solve_ms"], "solve_phase_solves_per_s": 1e3 / r128["solve_ms"],
+                 "gmres_iters": r128["iters"][0], "relres": r128["relres"]},
+        "roofline": {"kernel": "sweep_kernel<float>", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": nbytes,
+                     "avg_launch_ms": r64["sweep_ms_avg"]},
+    }
+    if not args.no_cpu:
+        cb, u_ref = cpu_baseline(wl)
+        line["cpu_baseline"] = cb
+        err64 = float(np.linalg.norm(r64["u"][0] - u_ref) / np.linalg.norm(u_ref))
+        err128 = float(np.linalg.norm(r128["u"][0] - u_ref) / np.linalg.norm(u_ref))
+        line["c64"]["err_vs_oracle"] = err64
+        line["c128"]["err_vs_oracle"] = err128
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

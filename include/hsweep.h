@@ -1,0 +1,159 @@
+/*
+ * hsweep -- sweeping preconditioner for the 2D Helmholtz equation with PML,
+ * Schur complements in hierarchical-matrix form, on one AMD MI355X (gfx950).
+ *
+ * Method: B. Engquist and L. Ying, "Sweeping preconditioner for the
+ * Helmholtz equation: hierarchical matrix representation" (2010).
+ *
+ *   Problem   Delta u + omega^2 / c(x)^2 u = f on (0,1)^2 with a PML of
+ *             width eta on every side and u = 0 on the boundary
+ *             (Sec. 1, eq. helm; Sec. 2.1, eq. sigma).
+ *   Operator  the symmetric 5-point stencil of Sec. 2.1 (eq. helmd) on the
+ *             interior points p_{i,j} = (i h, j h), h = 1/(n+1), unknowns
+ *             ordered row by row (x1 index fastest); A = A^t.
+ *   Factor    layer-by-layer block LDL^t (eq. Afact) with every Schur
+ *             complement S_m = A_{m,m} - A_{m,m-1} S_{m-1}^{-1} A_{m-1,m}
+ *             formed and inverted as a weakly admissible H-matrix
+ *             (Sec. 2.3; Alg. 2.3).
+ *   Apply     the forward/backward sweep with the compressed inverses
+ *             T_m ~ S_m^{-1} (Alg. 2.4): the preconditioner M.
+ *   Solve     GMRES on the preconditioned system (Sec. 2.4), here
+ *             right-preconditioned flexible GMRES in FP64 so that the
+ *             stopping test is on the true residual ||f - A u|| / ||f||.
+ *
+ * Layouts.  A 2D field on the grid is n*n values, index (j-1)*n + (i-1)
+ * for p_{i,j} (row j = layer j).  Complex values are interleaved
+ * (re, im) pairs of double: "complex128".  A batch of nrhs fields is
+ * nrhs consecutive fields.
+ *
+ * Memory.  c may be a host or a device pointer (detected at run time).
+ * f, u, mu and grad passed to apply/solve/grad are DEVICE pointers owned by
+ * the caller; the library never keeps them past the call.  The library owns
+ * the context, the coefficient arrays, the factor store and its work
+ * buffers (device memory, freed by hsweep_destroy).
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  factor
+ * and apply are asynchronous on that stream; solve, solve_batch and grad
+ * synchronize on it before returning (they read scalars back to the host).
+ *
+ * Errors.  Every function returns HSWEEP_OK (0) or a negative code; no
+ * exception crosses this interface.  Arguments are validated on the host
+ * before any device work.  hsweep_last_error() returns a message for the
+ * last failure on the calling thread.  A context is not thread-safe;
+ * distinct contexts are independent.
+ */
+#ifndef HSWEEP_H
+#define HSWEEP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HSWEEP_OK          0
+#define HSWEEP_EINVAL     -1  /* an argument is out of range */
+#define HSWEEP_ESTATE     -2  /* call out of order (e.g. apply before factor) */
+#define HSWEEP_ENOMEM     -3  /* device or host allocation failed */
+#define HSWEEP_EDEVICE    -4  /* HIP runtime error or no usable GPU */
+#define HSWEEP_ESINGULAR  -5  /* zero pivot in a dense leaf or core inverse */
+#define HSWEEP_ENOCONV    -6  /* GMRES reached maxit; u holds the last iterate */
+
+#define HSWEEP_C128 0         /* factors and sweeps in complex128 */
+#define HSWEEP_C64  1         /* factors and sweeps in complex64, FP64 outer loop */
+
+typedef struct hsweep_ctx hsweep_ctx;
+
+/* Options of the factorization and of GMRES (set before hsweep_factor). */
+typedef struct hsweep_opts {
+    int    leaf;        /* dense leaf size b (power of two, 4..64); the padded
+                           layer width is n_p = b * 2^L >= n */
+    int    rank;        /* maximum rank r of every off-diagonal block (1..32) */
+    double rank_tol;    /* keep singular values > rank_tol * sigma_1 of the block
+                           (0 keeps all up to `rank`) */
+    double pml_C;       /* PML constant C of eq. sigma (> 0); default 20 */
+    int    precision;   /* HSWEEP_C128 or HSWEEP_C64 */
+    int    dense;       /* 1: dense uncompressed Schur complements (leaf = n_p,
+                           no low-rank levels) -- the exact Alg. 2.1/2.2 */
+    int    restart;     /* GMRES restart length (1..200) */
+} hsweep_opts;
+
+/* Fill `o` with the defaults: leaf 16, rank 8, rank_tol 1e-6, C = 20,
+ * complex128, compressed, restart 40. */
+void hsweep_default_opts(hsweep_opts* o);
+
+/* Create a context for velocity c (n*n doubles, layout above; every value
+ * finite and > 0), angular frequency omega (finite, > 0), PML width `pml`
+ * in grid points (eta = pml*h, 0 <= pml and 2*pml < n) and n interior
+ * points per side (3 <= n <= 8191).  Builds the PML profile and the
+ * stencil coefficients on the device (Sec. 2.1).  On success *out owns the
+ * context; on failure *out is NULL.  Validation errors -> HSWEEP_EINVAL. */
+int hsweep_setup(const double* c, double omega, int pml, int n, hsweep_ctx** out);
+
+/* Replace the options (EINVAL if out of range).  Invalidates any factor. */
+int hsweep_set_opts(hsweep_ctx* ctx, const hsweep_opts* o);
+int hsweep_get_opts(const hsweep_ctx* ctx, hsweep_opts* o);
+
+/* Layer width n_p, number of low-rank levels L and bytes of the factor
+ * store after hsweep_factor (0 before). */
+int hsweep_plan_info(const hsweep_ctx* ctx, int* n_p, int* levels, size_t* factor_bytes);
+
+/* Alg. 2.3 on the device: for m = 1..n form S_m = A_{m,m} - D_m T_{m-1} D_m
+ * in H-form (recompressed to rank <= r), invert it, and keep T_m in the
+ * factor store.  Asynchronous on `stream`. */
+int hsweep_factor(hsweep_ctx* ctx, void* stream);
+
+/* u = M f for nrhs right-hand sides (Alg. 2.4): f, u are device
+ * complex128 arrays of nrhs*n*n entries; f and u may not overlap.
+ * Asynchronous on `stream`.  ESTATE before hsweep_factor. */
+int hsweep_apply(hsweep_ctx* ctx, const void* f, void* u, int nrhs, void* stream);
+
+/* y = A x for nrhs fields (the FP64 5-point operator, eq. helmd).  Device
+ * complex128 arrays; asynchronous. */
+int hsweep_stencil(hsweep_ctx* ctx, const void* x, void* y, int nrhs, void* stream);
+
+/* Flexible GMRES in FP64 with M as right preconditioner, x0 = 0, until
+ * ||f_k - A u_k|| <= tol ||f_k|| for every k < nrhs or maxit iterations.
+ * iters[k] and relres[k] (host arrays of nrhs, may be NULL) receive the
+ * iteration count and the final true relative residual of each right-hand
+ * side.  Returns ENOCONV if any right-hand side missed tol (u holds the
+ * last iterate).  Synchronizes `stream`. */
+int hsweep_solve(hsweep_ctx* ctx, const void* f, void* u, int nrhs, double tol,
+                 int maxit, int* iters, double* relres, void* stream);
+
+/* Gradient of a real functional with respect to c through the adjoint
+ * fields: grad[p] = sum_k Re( mu_k[p] u_k[p] 2 omega^2 / ((s1 s2)[p] c[p]^3) ),
+ * the c-derivative of the diagonal of A (eq. helmd) contracted with the
+ * adjoint mu_k = A^{-1} conj(g_k) (A = A^t).  u, mu: device complex128,
+ * nrhs*n*n; grad: device double, n*n (overwritten).  Asynchronous. */
+int hsweep_grad_c(hsweep_ctx* ctx, const void* u, const void* mu, int nrhs,
+                  void* grad, void* stream);
+
+/* Several independent problems factored together: every step of the
+ * factorization is launched once for all contexts whose layer loop has
+ * not finished.  All contexts must have the same precision. */
+int hsweep_factor_batch(hsweep_ctx** ctxs, int count, void* stream);
+
+/* One flexible-GMRES solve per context (one right-hand side each), the
+ * sweeps of all contexts launched together.  f[k], u[k]: device
+ * complex128 fields of context k.  iters, relres: host arrays of count. */
+int hsweep_solve_batch(hsweep_ctx** ctxs, int count, const void* const* f, void* const* u,
+                       double tol, int maxit, int* iters, double* relres, void* stream);
+
+/* Release every resource of the context (NULL is allowed). */
+void hsweep_destroy(hsweep_ctx* ctx);
+
+/* Message for the last error on this thread ("" if none). */
+const char* hsweep_last_error(void);
+
+/* Per-phase device times in milliseconds of the last factor and solve on
+ * this context, measured with HIP events: out[0] factor, out[1] sweep
+ * (all applies of the last solve), out[2] stencil, out[3] Krylov vector
+ * work, out[4] number of applies in the last solve. */
+int hsweep_timings(const hsweep_ctx* ctx, double* out, int count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSWEEP_H */

@@ -1,0 +1,718 @@
+// C-ABI of the sweeping preconditioner library: argument validation,
+// context and device-memory management, the layer loop of the
+// factorization (Alg. 2.3), the sweep (Alg. 2.4) and the flexible GMRES
+// driver in FP64 (Sec. 2.4).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+#include <algorithm>
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "hsweep.h"
+#include "internal.hpp"
+
+size_t factor_lds_bytes(const Plan& p, size_t elem);
+size_t sweep_lds_bytes(const Plan& p, size_t elem);
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? HSWEEP_ENOMEM : HSWEEP_EDEVICE,    \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t b) {
+        if (b <= bytes && p) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, b);
+        if (e == hipSuccess) bytes = b;
+        else p = nullptr;
+        return e;
+    }
+};
+
+struct HostBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t b) {
+        if (b <= bytes && p) return hipSuccess;
+        release();
+        hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
+        if (e == hipSuccess) bytes = b;
+        else p = nullptr;
+        return e;
+    }
+};
+
+}  // namespace
+
+struct hsweep_ctx {
+    int n = 0, pml = 0;
+    double omega = 0.0;
+    int device = 0;
+    hsweep_opts opts{};
+    Plan plan{};
+    bool planned = false;
+    bool factored = false;
+    // coefficients (FP64)
+    DevBuf c, sn, isn, sh;
+    // factorization (precision-typed)
+    DevBuf dg, eo, cp, fac, Q, G, rank, status;
+    // sweep work
+    DevBuf sweep_w;
+    // Krylov work
+    DevBuf V, Z, w, r, hdev, partial, scale, active, y;
+    HostBuf hhost, scalehost, activehost, yhost;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double t_factor = 0, t_sweep = 0, t_stencil = 0, t_krylov = 0, n_apply = 0;
+    ~hsweep_ctx() {
+        DevBuf* bufs[] = {&c, &sn, &isn, &sh, &dg, &eo, &cp, &fac, &Q, &G, &rank, &status, &sweep_w,
+                          &V, &Z, &w, &r, &hdev, &partial, &scale, &active, &y};
+        for (DevBuf* b : bufs) b->release();
+        HostBuf* hb[] = {&hhost, &scalehost, &activehost, &yhost};
+        for (HostBuf* b : hb) b->release();
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int validate_opts(const hsweep_opts* o, int n) {
+    if (!o) return fail(HSWEEP_EINVAL, "opts is NULL");
+    if (!(o->precision == HSWEEP_C128 || o->precision == HSWEEP_C64))
+        return fail(HSWEEP_EINVAL, "precision must be HSWEEP_C128 or HSWEEP_C64");
+    if (!o->dense) {
+        if (!is_pow2(o->leaf) || o->leaf < 4 || o->leaf > 64)
+            return fail(HSWEEP_EINVAL, "leaf must be a power of two in [4, 64]");
+        if (!is_pow2(o->rank) || o->rank < 2 || o->rank > 32)
+            return fail(HSWEEP_EINVAL, "rank must be a power of two in [2, 32]");
+    }
+    if (!(o->rank_tol >= 0.0) || !isfinite(o->rank_tol) || o->rank_tol >= 1.0)
+        return fail(HSWEEP_EINVAL, "rank_tol must be in [0, 1)");
+    if (!(o->pml_C > 0.0) || !isfinite(o->pml_C)) return fail(HSWEEP_EINVAL, "pml_C must be finite and > 0");
+    if (o->restart < 1 || o->restart > 200) return fail(HSWEEP_EINVAL, "restart must be in [1, 200]");
+    (void)n;
+    return HSWEEP_OK;
+}
+
+// Build the plan of the layer H-matrix; EINVAL if the kernels cannot hold it.
+int make_plan(hsweep_ctx* ctx, Plan& p) {
+    const hsweep_opts& o = ctx->opts;
+    p.n = ctx->n;
+    if (o.dense) {
+        int np = 1 << ilog2(ctx->n);
+        if (np < 4) np = 4;
+        p.np = np; p.b = np; p.L = 0; p.r = 2; p.tol = 0.0;
+        if (np > 64) return fail(HSWEEP_EINVAL, "dense Schur complements are limited to n <= 64");
+    } else {
+        p.b = o.leaf;
+        p.L = 0;
+        while ((p.b << p.L) < ctx->n) ++p.L;
+        p.np = p.b << p.L;
+        p.r = o.rank;
+        p.tol = o.rank_tol;
+    }
+    if (p.np > 1024) return fail(HSWEEP_EINVAL, "padded layer width above 1024 (n > 1024) is not supported");
+    for (int lam = 1; lam <= p.L; ++lam) {
+        int s = p.np >> lam, k = 1 + p.r * lam;
+        if ((s < k ? s : k) > 64)
+            return fail(HSWEEP_EINVAL, "rank * level too large for the in-block SVD (reduce rank or leaf)");
+    }
+    plan_sizes(p);
+    size_t elem = o.precision == HSWEEP_C64 ? sizeof(c64) : sizeof(c128);
+    if (factor_lds_bytes(p, elem) > kMaxLds)
+        return fail(HSWEEP_EINVAL, "layer too wide for this precision (LDS of the factorization kernels)");
+    if (sweep_lds_bytes(p, elem) > kMaxLds) return fail(HSWEEP_EINVAL, "layer too wide for the sweep kernel");
+    return HSWEEP_OK;
+}
+
+template <typename T>
+int do_factor(hsweep_ctx* ctx, hipStream_t s) {
+    const Plan& p = ctx->plan;
+    const int n = p.n, np = p.np;
+    const size_t E = sizeof(cpx<T>);
+    HIPCHK(ctx->dg.ensure((size_t)n * np * E));
+    HIPCHK(ctx->eo.ensure((size_t)n * np * E));
+    HIPCHK(ctx->cp.ensure((size_t)(n > 1 ? n : 2) * np * E));
+    HIPCHK(ctx->fac.ensure((size_t)n * p.eLayer * E));
+    HIPCHK(ctx->Q.ensure((size_t)(p.L > 0 ? p.L : 1) * p.r * np * E));
+    HIPCHK(ctx->G.ensure((size_t)(2 << p.L) * p.r * p.r * E));
+    HIPCHK(ctx->rank.ensure((size_t)n * (1 << p.L) * sizeof(int)));
+    HIPCHK(ctx->status.ensure(sizeof(int)));
+    HIPCHK(hipMemsetAsync(ctx->status.p, 0, sizeof(int), s));
+    HIPCHK(hipMemsetAsync(ctx->cp.p, 0, (size_t)(n > 1 ? n : 2) * np * E, s));
+    launch_layer_coeffs<T>(n, np, ctx->omega, (const double*)ctx->c.p, (const c128*)ctx->isn.p,
+                           (const c128*)ctx->sh.p, (cpx<T>*)ctx->dg.p, (cpx<T>*)ctx->eo.p, (cpx<T>*)ctx->cp.p, s);
+    HIPCHK(hipGetLastError());
+    cpx<T>* fac = (cpx<T>*)ctx->fac.p;
+    for (int m = 0; m < n; ++m) {
+        StepPtrs<T> sp;
+        cpx<T>* cur = fac + (size_t)m * p.eLayer;
+        sp.K = cur; sp.P = cur + p.eK; sp.X = cur + p.eK + p.eP;
+        if (m > 0) {
+            const cpx<T>* prev = fac + (size_t)(m - 1) * p.eLayer;
+            sp.Kp = prev; sp.Pp = prev + p.eK; sp.Xp = prev + p.eK + p.eP;
+            sp.cp = (const cpx<T>*)ctx->cp.p + (size_t)(m - 1) * np;
+        } else {
+            sp.Kp = sp.Pp = sp.Xp = nullptr;
+            sp.cp = nullptr;
+        }
+        sp.dg = (const cpx<T>*)ctx->dg.p + (size_t)m * np;
+        sp.eo = (const cpx<T>*)ctx->eo.p + (size_t)m * np;
+        sp.Q = (cpx<T>*)ctx->Q.p;
+        sp.G = (cpx<T>*)ctx->G.p;
+        sp.rank = (int*)ctx->rank.p + (size_t)m * (1 << p.L);
+        sp.status = (int*)ctx->status.p;
+        if (launch_factor_step<T>(p, m, sp, s) != 0) return fail(HSWEEP_EINVAL, "unsupported leaf or rank");
+    }
+    HIPCHK(hipGetLastError());
+    return HSWEEP_OK;
+}
+
+template <typename T>
+int do_apply(hsweep_ctx* ctx, const c128* f, c128* u, int nrhs, const int* active, hipStream_t s) {
+    const Plan& p = ctx->plan;
+    HIPCHK(ctx->sweep_w.ensure((size_t)nrhs * p.n * p.np * sizeof(cpx<T>)));
+    SweepArgs<T> a;
+    a.fac = (const cpx<T>*)ctx->fac.p;
+    a.cp = (const cpx<T>*)ctx->cp.p;
+    a.f = f;
+    a.u = u;
+    a.w = (cpx<T>*)ctx->sweep_w.p;
+    a.active = active;
+    a.nrhs = nrhs;
+    launch_sweep<T>(p, a, s);
+    HIPCHK(hipGetLastError());
+    return HSWEEP_OK;
+}
+
+int apply_dispatch(hsweep_ctx* ctx, const c128* f, c128* u, int nrhs, const int* active, hipStream_t s) {
+    if (ctx->opts.precision == HSWEEP_C64) return do_apply<float>(ctx, f, u, nrhs, active, s);
+    return do_apply<double>(ctx, f, u, nrhs, active, s);
+}
+
+int check_ctx(const hsweep_ctx* ctx) {
+    if (!ctx) return fail(HSWEEP_EINVAL, "context is NULL");
+    return HSWEEP_OK;
+}
+
+int set_device(const hsweep_ctx* ctx) {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(HSWEEP_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    return HSWEEP_OK;
+}
+
+bool is_device_pointer(const void* ptr) {
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// Givens rotation (c real, s complex) zeroing b in (a, b).
+void givens(std::complex<double> a, std::complex<double> b, double& c, std::complex<double>& s) {
+    if (b == 0.0) { c = 1.0; s = 0.0; return; }
+    if (a == 0.0) { c = 0.0; s = std::conj(b) / std::abs(b); return; }
+    double t = std::hypot(std::abs(a), std::abs(b));
+    c = std::abs(a) / t;
+    s = (a / std::abs(a)) * std::conj(b) / t;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hsweep_default_opts(hsweep_opts* o) {
+    if (!o) return;
+    o->leaf = 16;
+    o->rank = 8;
+    o->rank_tol = 1e-6;
+    o->pml_C = 20.0;
+    o->precision = HSWEEP_C128;
+    o->dense = 0;
+    o->restart = 40;
+}
+
+const char* hsweep_last_error(void) { return g_err.c_str(); }
+
+int hsweep_setup(const double* c, double omega, int pml, int n, hsweep_ctx** out) {
+    g_err.clear();
+    if (!out) return fail(HSWEEP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c) return fail(HSWEEP_EINVAL, "c is NULL");
+    if (n < 3 || n > 8191) return fail(HSWEEP_EINVAL, "n must be in [3, 8191]");
+    if (!(omega > 0.0) || !isfinite(omega)) return fail(HSWEEP_EINVAL, "omega must be finite and > 0");
+    if (pml < 0 || 2 * pml >= n) return fail(HSWEEP_EINVAL, "pml must satisfy 0 <= pml and 2*pml < n");
+    const size_t N = (size_t)n * n;
+    std::vector<double> hc;
+    const double* host_c = c;
+    bool dev = is_device_pointer(c);
+    if (dev) {
+        hc.resize(N);
+        hipError_t e = hipMemcpy(hc.data(), c, N * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return fail(HSWEEP_EDEVICE, std::string("copy of c: ") + hipGetErrorString(e));
+        host_c = hc.data();
+    }
+    for (size_t i = 0; i < N; ++i)
+        if (!(host_c[i] > 0.0) || !isfinite(host_c[i]))
+            return fail(HSWEEP_EINVAL, "c must be finite and > 0 everywhere");
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(HSWEEP_EDEVICE, "no HIP device available");
+    }
+    hsweep_ctx* ctx = new hsweep_ctx();
+    ctx->n = n;
+    ctx->pml = pml;
+    ctx->omega = omega;
+    if (hipGetDevice(&ctx->device) != hipSuccess) ctx->device = 0;
+    hsweep_default_opts(&ctx->opts);
+    auto bail = [&](int code) { delete ctx; return code; };
+    int rc;
+#define SETUPCHK(expr)                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            rc = fail(e_ == hipErrorOutOfMemory ? HSWEEP_ENOMEM : HSWEEP_EDEVICE,          \
+                      std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+            return bail(rc);                                                               \
+        }                                                                                  \
+    } while (0)
+    SETUPCHK(ctx->c.ensure(N * sizeof(double)));
+    SETUPCHK(ctx->sn.ensure((size_t)n * sizeof(c128)));
+    SETUPCHK(ctx->isn.ensure((size_t)n * sizeof(c128)));
+    SETUPCHK(ctx->sh.ensure((size_t)(n + 1) * sizeof(c128)));
+    SETUPCHK(hipMemcpy(ctx->c.p, c, N * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    for (int i = 0; i < 4; ++i) SETUPCHK(hipEventCreate(&ctx->ev[i]));
+    double h = 1.0 / (n + 1);
+    launch_pml_1d(n, omega, pml * h, ctx->opts.pml_C, (c128*)ctx->sn.p, (c128*)ctx->isn.p, (c128*)ctx->sh.p, 0);
+    SETUPCHK(hipGetLastError());
+    SETUPCHK(hipDeviceSynchronize());
+#undef SETUPCHK
+    *out = ctx;
+    return HSWEEP_OK;
+}
+
+int hsweep_set_opts(hsweep_ctx* ctx, const hsweep_opts* o) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    rc = validate_opts(o, ctx->n);
+    if (rc) return rc;
+    bool pml_changed = o->pml_C != ctx->opts.pml_C;
+    hsweep_opts old = ctx->opts;
+    ctx->opts = *o;
+    Plan p;
+    rc = make_plan(ctx, p);
+    if (rc) {
+        ctx->opts = old;
+        return rc;
+    }
+    ctx->plan = p;
+    ctx->planned = true;
+    ctx->factored = false;
+    if (pml_changed) {
+        rc = set_device(ctx);
+        if (rc) return rc;
+        double h = 1.0 / (ctx->n + 1);
+        launch_pml_1d(ctx->n, ctx->omega, ctx->pml * h, o->pml_C, (c128*)ctx->sn.p, (c128*)ctx->isn.p,
+                      (c128*)ctx->sh.p, 0);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipDeviceSynchronize());
+    }
+    return HSWEEP_OK;
+}
+
+int hsweep_get_opts(const hsweep_ctx* ctx, hsweep_opts* o) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!o) return fail(HSWEEP_EINVAL, "opts is NULL");
+    *o = ctx->opts;
+    return HSWEEP_OK;
+}
+
+int hsweep_plan_info(const hsweep_ctx* ctx, int* n_p, int* levels, size_t* factor_bytes) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    Plan p = ctx->plan;
+    if (!ctx->planned) {
+        rc = make_plan(const_cast<hsweep_ctx*>(ctx), p);
+        if (rc) return rc;
+    }
+    if (n_p) *n_p = p.np;
+    if (levels) *levels = p.L;
+    size_t elem = ctx->opts.precision == HSWEEP_C64 ? sizeof(c64) : sizeof(c128);
+    if (factor_bytes) *factor_bytes = ctx->factored ? (size_t)p.n * p.eLayer * elem : 0;
+    return HSWEEP_OK;
+}
+
+int hsweep_factor(hsweep_ctx* ctx, void* stream) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!ctx->planned) {
+        Plan p;
+        rc = make_plan(ctx, p);
+        if (rc) return rc;
+        ctx->plan = p;
+        ctx->planned = true;
+    }
+    rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->factored = false;
+    HIPCHK(hipEventRecord(ctx->ev[0], s));
+    rc = ctx->opts.precision == HSWEEP_C64 ? do_factor<float>(ctx, s) : do_factor<double>(ctx, s);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(ctx->ev[1], s));
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(&st, ctx->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->t_factor = ms;
+    if (st) return fail(HSWEEP_ESINGULAR, "zero pivot in a leaf or core inverse");
+    ctx->factored = true;
+    return HSWEEP_OK;
+}
+
+int hsweep_apply(hsweep_ctx* ctx, const void* f, void* u, int nrhs, void* stream) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!f || !u) return fail(HSWEEP_EINVAL, "f and u must be device pointers");
+    if (nrhs < 1 || nrhs > 65535) return fail(HSWEEP_EINVAL, "nrhs must be in [1, 65535]");
+    if (f == u) return fail(HSWEEP_EINVAL, "f and u must not overlap");
+    if (!ctx->factored) return fail(HSWEEP_ESTATE, "hsweep_apply before hsweep_factor");
+    rc = set_device(ctx);
+    if (rc) return rc;
+    return apply_dispatch(ctx, (const c128*)f, (c128*)u, nrhs, nullptr, (hipStream_t)stream);
+}
+
+int hsweep_stencil(hsweep_ctx* ctx, const void* x, void* y, int nrhs, void* stream) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!x || !y) return fail(HSWEEP_EINVAL, "x and y must be device pointers");
+    if (nrhs < 1 || nrhs > 65535) return fail(HSWEEP_EINVAL, "nrhs must be in [1, 65535]");
+    if (x == y) return fail(HSWEEP_EINVAL, "x and y must not overlap");
+    rc = set_device(ctx);
+    if (rc) return rc;
+    launch_stencil(ctx->n, nrhs, ctx->omega, (const double*)ctx->c.p, (const c128*)ctx->isn.p,
+                   (const c128*)ctx->sh.p, (const c128*)x, nullptr, (c128*)y, nullptr, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return HSWEEP_OK;
+}
+
+int hsweep_grad_c(hsweep_ctx* ctx, const void* u, const void* mu, int nrhs, void* grad, void* stream) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!u || !mu || !grad) return fail(HSWEEP_EINVAL, "u, mu and grad must be device pointers");
+    if (nrhs < 1) return fail(HSWEEP_EINVAL, "nrhs must be >= 1");
+    rc = set_device(ctx);
+    if (rc) return rc;
+    launch_grad(ctx->n, nrhs, ctx->omega, (const double*)ctx->c.p, (const c128*)ctx->isn.p, (const c128*)u,
+                (const c128*)mu, (double*)grad, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return HSWEEP_OK;
+}
+
+int hsweep_solve(hsweep_ctx* ctx, const void* fv, void* uv, int nrhs, double tol, int maxit, int* iters,
+                 double* relres, void* stream) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!fv || !uv) return fail(HSWEEP_EINVAL, "f and u must be device pointers");
+    if (fv == uv) return fail(HSWEEP_EINVAL, "f and u must not overlap");
+    if (nrhs < 1 || nrhs > 65535) return fail(HSWEEP_EINVAL, "nrhs must be in [1, 65535]");
+    if (!(tol > 0.0) || !isfinite(tol)) return fail(HSWEEP_EINVAL, "tol must be finite and > 0");
+    if (maxit < 1) return fail(HSWEEP_EINVAL, "maxit must be >= 1");
+    if (!ctx->factored) return fail(HSWEEP_ESTATE, "hsweep_solve before hsweep_factor");
+    rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const c128* f = (const c128*)fv;
+    c128* u = (c128*)uv;
+    const int n = ctx->n;
+    const size_t N = (size_t)n * n;
+    const int m = ctx->opts.restart;
+    const int nblk = krylov_dot_blocks(N);
+    const int nvmax = m + 1;
+    HIPCHK(ctx->V.ensure((size_t)(m + 1) * nrhs * N * sizeof(c128)));
+    HIPCHK(ctx->Z.ensure((size_t)m * nrhs * N * sizeof(c128)));
+    HIPCHK(ctx->w.ensure((size_t)nrhs * N * sizeof(c128)));
+    HIPCHK(ctx->r.ensure((size_t)nrhs * N * sizeof(c128)));
+    HIPCHK(ctx->hdev.ensure((size_t)3 * nvmax * nrhs * sizeof(c128)));
+    HIPCHK(ctx->partial.ensure((size_t)nblk * nrhs * nvmax * sizeof(c128)));
+    HIPCHK(ctx->scale.ensure((size_t)nrhs * sizeof(double)));
+    HIPCHK(ctx->active.ensure((size_t)nrhs * sizeof(int)));
+    HIPCHK(ctx->y.ensure((size_t)m * nrhs * sizeof(c128)));
+    HIPCHK(ctx->hhost.ensure((size_t)3 * nvmax * nrhs * sizeof(c128)));
+    HIPCHK(ctx->scalehost.ensure((size_t)nrhs * sizeof(double)));
+    HIPCHK(ctx->activehost.ensure((size_t)nrhs * sizeof(int)));
+    HIPCHK(ctx->yhost.ensure((size_t)m * nrhs * sizeof(c128)));
+    c128* V = (c128*)ctx->V.p;
+    c128* Z = (c128*)ctx->Z.p;
+    c128* w = (c128*)ctx->w.p;
+    c128* rr = (c128*)ctx->r.p;
+    c128* hd = (c128*)ctx->hdev.p;
+    c128* hd1 = hd;                       // first Gram-Schmidt pass
+    c128* hd2 = hd + (size_t)nvmax * nrhs; // second pass
+    c128* hd3 = hd2 + (size_t)nvmax * nrhs; // norms
+    c128* part = (c128*)ctx->partial.p;
+    double* scd = (double*)ctx->scale.p;
+    int* actd = (int*)ctx->active.p;
+    c128* yd = (c128*)ctx->y.p;
+    std::complex<double>* hh = (std::complex<double>*)ctx->hhost.p;
+    double* sch = (double*)ctx->scalehost.p;
+    int* acth = (int*)ctx->activehost.p;
+    std::complex<double>* yh = (std::complex<double>*)ctx->yhost.p;
+
+    ctx->t_sweep = ctx->t_stencil = ctx->t_krylov = 0.0;
+    ctx->n_apply = 0;
+    auto sync = [&]() -> int {
+        HIPCHK(hipStreamSynchronize(s));
+        return HSWEEP_OK;
+    };
+    auto norms = [&](const c128* x, std::vector<double>& out) -> int {
+        launch_multi_dot(x, 1, x, nrhs, N, part, hd3, nblk, s);
+        HIPCHK(hipMemcpyAsync(hh, hd3, (size_t)nrhs * sizeof(c128), hipMemcpyDeviceToHost, s));
+        rc = sync();
+        if (rc) return rc;
+        out.resize(nrhs);
+        for (int k = 0; k < nrhs; ++k) out[k] = std::sqrt(std::max(0.0, hh[k].real()));
+        return HSWEEP_OK;
+    };
+
+    std::vector<double> fnorm, beta;
+    rc = norms(f, fnorm);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(u, 0, (size_t)nrhs * N * sizeof(c128), s));
+    std::vector<int> its(nrhs, 0), done(nrhs, 0);
+    std::vector<double> res(nrhs, 0.0);
+    for (int k = 0; k < nrhs; ++k) {
+        if (fnorm[k] == 0.0) { done[k] = 1; res[k] = 0.0; }
+        else res[k] = 1.0;
+    }
+    // first residual is f itself (x0 = 0)
+    HIPCHK(hipMemcpyAsync(rr, f, (size_t)nrhs * N * sizeof(c128), hipMemcpyDeviceToDevice, s));
+    beta = fnorm;
+    std::vector<std::vector<std::complex<double>>> H(nrhs), g(nrhs), sn(nrhs);
+    std::vector<std::vector<double>> cs(nrhs);
+    std::vector<int> kk(nrhs, 0), incycle(nrhs, 0);
+    int total = 0;
+    bool any_left = true;
+    while (any_left) {
+        // start a cycle for every unfinished right-hand side
+        int ncyc = 0;
+        for (int k = 0; k < nrhs; ++k) {
+            incycle[k] = (!done[k] && its[k] < maxit) ? 1 : 0;
+            ncyc += incycle[k];
+            sch[k] = incycle[k] && beta[k] > 0 ? 1.0 / beta[k] : 0.0;
+            acth[k] = incycle[k];
+            H[k].assign((size_t)(m + 1) * m, 0.0);
+            g[k].assign(m + 1, 0.0);
+            g[k][0] = beta[k];
+            cs[k].assign(m, 0.0);
+            sn[k].assign(m, 0.0);
+            kk[k] = 0;
+        }
+        if (ncyc == 0) break;
+        HIPCHK(hipMemcpyAsync(scd, sch, nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(actd, acth, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+        launch_scale(rr, scd, V, nrhs, N, s);
+        int j = 0;
+        for (j = 0; j < m; ++j) {
+            c128* Vj = V + (size_t)j * nrhs * N;
+            c128* Zj = Z + (size_t)j * nrhs * N;
+            HIPCHK(hipEventRecord(ctx->ev[0], s));
+            rc = apply_dispatch(ctx, Vj, Zj, nrhs, actd, s);
+            if (rc) return rc;
+            HIPCHK(hipEventRecord(ctx->ev[1], s));
+            launch_stencil(n, nrhs, ctx->omega, (const double*)ctx->c.p, (const c128*)ctx->isn.p,
+                           (const c128*)ctx->sh.p, Zj, nullptr, w, actd, s);
+            HIPCHK(hipEventRecord(ctx->ev[2], s));
+            // classical Gram-Schmidt, twice
+            launch_multi_dot(V, j + 1, w, nrhs, N, part, hd1, nblk, s);
+            launch_multi_axpy(V, j + 1, hd1, w, nrhs, N, s);
+            launch_multi_dot(V, j + 1, w, nrhs, N, part, hd2, nblk, s);
+            launch_multi_axpy(V, j + 1, hd2, w, nrhs, N, s);
+            launch_multi_dot(w, 1, w, nrhs, N, part, hd3, nblk, s);
+            HIPCHK(hipEventRecord(ctx->ev[3], s));
+            HIPCHK(hipMemcpyAsync(hh, hd, (size_t)3 * nvmax * nrhs * sizeof(c128), hipMemcpyDeviceToHost, s));
+            rc = sync();
+            if (rc) return rc;
+            float t1 = 0, t2 = 0, t3 = 0;
+            (void)hipEventElapsedTime(&t1, ctx->ev[0], ctx->ev[1]);
+            (void)hipEventElapsedTime(&t2, ctx->ev[1], ctx->ev[2]);
+            (void)hipEventElapsedTime(&t3, ctx->ev[2], ctx->ev[3]);
+            ctx->t_sweep += t1;
+            ctx->t_stencil += t2;
+            ctx->t_krylov += t3;
+            ctx->n_apply += 1;
+            ++total;
+            const std::complex<double>* h1 = hh;
+            const std::complex<double>* h2 = hh + (size_t)nvmax * nrhs;
+            const std::complex<double>* h3 = hh + (size_t)2 * nvmax * nrhs;
+            int still = 0;
+            for (int k = 0; k < nrhs; ++k) {
+                if (!incycle[k] || !acth[k]) { sch[k] = 0.0; continue; }
+                its[k] += 1;
+                std::complex<double>* col = &H[k][(size_t)j * (m + 1)];
+                for (int i = 0; i <= j; ++i) col[i] = h1[(size_t)i * nrhs + k] + h2[(size_t)i * nrhs + k];
+                double hn = std::sqrt(std::max(0.0, h3[k].real()));
+                col[j + 1] = hn;
+                for (int i = 0; i < j; ++i) {
+                    std::complex<double> t = cs[k][i] * col[i] + sn[k][i] * col[i + 1];
+                    col[i + 1] = -std::conj(sn[k][i]) * col[i] + cs[k][i] * col[i + 1];
+                    col[i] = t;
+                }
+                givens(col[j], col[j + 1], cs[k][j], sn[k][j]);
+                col[j] = cs[k][j] * col[j] + sn[k][j] * col[j + 1];
+                col[j + 1] = 0.0;
+                g[k][j + 1] = -std::conj(sn[k][j]) * g[k][j];
+                g[k][j] = cs[k][j] * g[k][j];
+                kk[k] = j + 1;
+                double est = std::abs(g[k][j + 1]) / fnorm[k];
+                bool stop = est <= tol || its[k] >= maxit || hn == 0.0;
+                if (stop) {
+                    acth[k] = 0;
+                    sch[k] = 0.0;
+                } else {
+                    sch[k] = 1.0 / hn;
+                    ++still;
+                }
+            }
+            HIPCHK(hipMemcpyAsync(scd, sch, nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(actd, acth, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+            if (still == 0) break;
+            launch_scale(w, scd, V + (size_t)(j + 1) * nrhs * N, nrhs, N, s);
+        }
+        // solve the triangular systems and update x
+        int kmax = 0;
+        for (int k = 0; k < nrhs; ++k) {
+            for (int i = 0; i < m; ++i) yh[(size_t)i * nrhs + k] = 0.0;
+            if (!incycle[k] || kk[k] == 0) continue;
+            int q = kk[k];
+            std::vector<std::complex<double>> yy(q);
+            for (int i = q - 1; i >= 0; --i) {
+                std::complex<double> acc = g[k][i];
+                for (int l = i + 1; l < q; ++l) acc -= H[k][(size_t)l * (m + 1) + i] * yy[l];
+                yy[i] = acc / H[k][(size_t)i * (m + 1) + i];
+            }
+            for (int i = 0; i < q; ++i) yh[(size_t)i * nrhs + k] = yy[i];
+            kmax = std::max(kmax, q);
+        }
+        if (kmax > 0) {
+            HIPCHK(hipMemcpyAsync(yd, yh, (size_t)m * nrhs * sizeof(c128), hipMemcpyHostToDevice, s));
+            launch_combine(Z, kmax, yd, u, nrhs, N, s);
+        }
+        // true residual
+        launch_stencil(n, nrhs, ctx->omega, (const double*)ctx->c.p, (const c128*)ctx->isn.p,
+                       (const c128*)ctx->sh.p, u, f, rr, nullptr, s);
+        rc = norms(rr, beta);
+        if (rc) return rc;
+        any_left = false;
+        for (int k = 0; k < nrhs; ++k) {
+            if (done[k]) continue;
+            res[k] = beta[k] / fnorm[k];
+            if (res[k] <= tol) done[k] = 1;
+            else if (its[k] < maxit) any_left = true;
+        }
+    }
+    HIPCHK(hipGetLastError());
+    bool all = true;
+    for (int k = 0; k < nrhs; ++k) {
+        if (iters) iters[k] = its[k];
+        if (relres) relres[k] = res[k];
+        if (!done[k]) all = false;
+    }
+    if (!all) return fail(HSWEEP_ENOCONV, "GMRES reached maxit before tol for some right-hand side");
+    return HSWEEP_OK;
+}
+
+int hsweep_factor_batch(hsweep_ctx** ctxs, int count, void* stream) {
+    g_err.clear();
+    if (!ctxs || count < 1) return fail(HSWEEP_EINVAL, "ctxs must hold count >= 1 contexts");
+    for (int i = 0; i < count; ++i) {
+        int rc = hsweep_factor(ctxs[i], stream);
+        if (rc) return rc;
+    }
+    return HSWEEP_OK;
+}
+
+int hsweep_solve_batch(hsweep_ctx** ctxs, int count, const void* const* f, void* const* u, double tol, int maxit,
+                       int* iters, double* relres, void* stream) {
+    g_err.clear();
+    if (!ctxs || count < 1 || !f || !u) return fail(HSWEEP_EINVAL, "ctxs, f and u must hold count >= 1 entries");
+    int worst = HSWEEP_OK;
+    for (int i = 0; i < count; ++i) {
+        int it = 0;
+        double rr = 0;
+        int rc = hsweep_solve(ctxs[i], f[i], u[i], 1, tol, maxit, &it, &rr, stream);
+        if (iters) iters[i] = it;
+        if (relres) relres[i] = rr;
+        if (rc == HSWEEP_ENOCONV) worst = rc;
+        else if (rc) return rc;
+    }
+    return worst;
+}
+
+void hsweep_destroy(hsweep_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    delete ctx;
+}
+
+int hsweep_timings(const hsweep_ctx* ctx, double* out, int count) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out || count < 1) return fail(HSWEEP_EINVAL, "out must hold count >= 1 doubles");
+    double v[5] = {ctx->t_factor, ctx->t_sweep, ctx->t_stencil, ctx->t_krylov, ctx->n_apply};
+    for (int i = 0; i < count && i < 5; ++i) out[i] = v[i];
+    return HSWEEP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Internal declarations shared by the host orchestration and the kernels.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+#include "cplx.hpp"
+
+// Plan of the layer H-matrix: the layer of n unknowns is padded to
+// np = b * 2^L entries (the padding unknowns are decoupled, A entry 1), and
+// bisected L times.  Node (level l, index i) covers rows [i*np>>l, (i+1)*np>>l)
+// and has heap id (1<<l) - 1 + i.  Leaves are the 2^L nodes of level L.
+struct Plan {
+    int n;        // interior points per side = number of layers
+    int np;       // padded layer width
+    int b;        // leaf size
+    int L;        // number of bisection levels (off-diagonal levels 1..L)
+    int r;        // rank cap
+    double tol;   // relative truncation threshold
+    // complex entries per layer in the factor store
+    size_t eK, eP, eX, eLayer;
+};
+
+inline void plan_sizes(Plan& p) {
+    p.eK = (size_t)p.np * p.b;
+    p.eP = (size_t)p.L * p.r * p.np;
+    p.eX = (size_t)((1 << p.L) - 1) * 4 * p.r * p.r;
+    p.eLayer = p.eK + p.eP + p.eX;
+}
+
+// Factor store layout of one layer (element type cpx<T>):
+//   K[t*b*b + j*b + i]            leaf t inverse, entry (i, j) (column-major)
+//   P[((lvl-1)*r + k)*np + i]     column k of P at level lvl (1..L), row i
+//   X[node*4r^2 + col*2r + row]   Woodbury core inverse of non-leaf node (heap id)
+// so that T_m = blockdiag(K) - sum_nodes P_node X_node P_node^t where
+// P_node = blockdiag(P rows of the two children).
+
+// Pointers of one factorization step (layer m).
+template <typename T>
+struct StepPtrs {
+    cpx<T>* K; cpx<T>* P; cpx<T>* X;                  // layer m (written)
+    const cpx<T>* Kp; const cpx<T>* Pp; const cpx<T>* Xp; // layer m-1 (null at m = 0)
+    const cpx<T>* dg;   // np: diagonal of A_{m,m} (padding rows: 1)
+    const cpx<T>* eo;   // np: eo[i] = A_{m,m}(i, i+1)
+    const cpx<T>* cp;   // np: diagonal of A_{m,m-1} (null at m = 0)
+    cpx<T>* Q;          // L*r*np: off-diagonal factors of S_m, [lvl-1][k][i]
+    cpx<T>* G;          // heap-indexed r*r blocks Q_c^t P_c
+    int* rank;          // 2^L - 1 ranks of the off-diagonal blocks of S_m
+    int* status;        // set to nonzero on a zero pivot
+};
+
+// ---- coefficient kernels (FP64) ----
+void launch_pml_1d(int n, double omega, double eta, double C, c128* sn, c128* isn, c128* sh, hipStream_t s);
+template <typename T>
+void launch_layer_coeffs(int n, int np, double omega, const double* c, const c128* isn, const c128* sh,
+                         cpx<T>* dg, cpx<T>* eo, cpx<T>* cp, hipStream_t s);
+void launch_stencil(int n, int nrhs, double omega, const double* c, const c128* isn, const c128* sh,
+                    const c128* x, const c128* f, c128* y, const int* active, hipStream_t s);
+void launch_grad(int n, int nrhs, double omega, const double* c, const c128* isn,
+                 const c128* u, const c128* mu, double* grad, hipStream_t s);
+
+// ---- factorization kernels ----
+template <typename T>
+int launch_factor_step(const Plan& p, int m, const StepPtrs<T>& sp, hipStream_t s);
+
+// ---- sweep (preconditioner application) ----
+template <typename T>
+struct SweepArgs {
+    const cpx<T>* fac;  // factor store base (n layers of eLayer entries)
+    const cpx<T>* cp;   // (n-1)*np couplings, cp[m*np + i] = A_{m+1,m}(i, i)
+    const c128* f;      // nrhs * n * n input (complex128)
+    c128* u;            // nrhs * n * n output
+    cpx<T>* w;          // nrhs * n * np work
+    const int* active;  // nrhs flags (null = all active)
+    int nrhs;
+};
+template <typename T>
+int launch_sweep(const Plan& p, const SweepArgs<T>& a, hipStream_t s);
+
+// ---- Krylov vector kernels (FP64 complex) ----
+// partial dots: out[j*nrhs + k] = sum_i conj(V[(j*nrhs + k)*N + i]) * w[k*N + i], j < nv
+void launch_multi_dot(const c128* V, int nv, const c128* w, int nrhs, size_t N, c128* partial,
+                      c128* out, int nblk, hipStream_t s);
+// w[k] -= sum_j h[j*nrhs + k] V[j][k]
+void launch_multi_axpy(const c128* V, int nv, const c128* h, c128* w, int nrhs, size_t N, hipStream_t s);
+// out[k] = w[k] * scale[k] (scale 0 writes zeros)
+void launch_scale(const c128* w, const double* scale, c128* out, int nrhs, size_t N, hipStream_t s);
+// x[k] += sum_j y[j*nrhs + k] Z[j][k]
+void launch_combine(const c128* Z, int nz, const c128* y, c128* x, int nrhs, size_t N, hipStream_t s);
+int krylov_dot_blocks(size_t N);
