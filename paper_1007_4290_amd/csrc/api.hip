@@ -16,6 +16,8 @@
 
 size_t factor_lds_bytes(const Plan& p, size_t elem);
 size_t sweep_lds_bytes(const Plan& p, size_t elem);
+bool factor_supported(const Plan& p);
+bool sweep_supported(const Plan& p);
 
 namespace {
 
@@ -34,7 +36,7 @@ int fail(int code, const std::string& msg) {
                         std::string(#expr) + ": " + hipGetErrorString(e_));            \
     } while (0)
 
-constexpr size_t kMaxLds = 160 * 1024;
+constexpr size_t kMaxLds = 152 * 1024;   // dynamic LDS budget: 160 KiB minus static shared variables
 
 struct DevBuf {
     void* p = nullptr;
@@ -121,8 +123,8 @@ int validate_opts(const hsweep_opts* o, int n) {
     if (!o->dense) {
         if (!is_pow2(o->leaf) || o->leaf < 4 || o->leaf > 64)
             return fail(HSWEEP_EINVAL, "leaf must be a power of two in [4, 64]");
-        if (!is_pow2(o->rank) || o->rank < 2 || o->rank > 32)
-            return fail(HSWEEP_EINVAL, "rank must be a power of two in [2, 32]");
+        if (!is_pow2(o->rank) || o->rank < 2 || o->rank > 16)
+            return fail(HSWEEP_EINVAL, "rank must be a power of two in [2, 16]");
     }
     if (!(o->rank_tol >= 0.0) || !isfinite(o->rank_tol) || o->rank_tol >= 1.0)
         return fail(HSWEEP_EINVAL, "rank_tol must be in [0, 1)");
@@ -150,12 +152,12 @@ int make_plan(hsweep_ctx* ctx, Plan& p) {
         p.tol = o.rank_tol;
     }
     if (p.np > 1024) return fail(HSWEEP_EINVAL, "padded layer width above 1024 (n > 1024) is not supported");
-    for (int lam = 1; lam <= p.L; ++lam) {
-        int s = p.np >> lam, k = 1 + p.r * lam;
-        if ((s < k ? s : k) > 64)
-            return fail(HSWEEP_EINVAL, "rank * level too large for the in-block SVD (reduce rank or leaf)");
-    }
+    if (1 + p.r * p.L > 64)
+        return fail(HSWEEP_EINVAL, "rank * levels too large for the in-block recompression (reduce rank or raise leaf)");
     plan_sizes(p);
+    if (!factor_supported(p)) return fail(HSWEEP_EINVAL, "unsupported leaf size or rank");
+    if (!sweep_supported(p))
+        return fail(HSWEEP_EINVAL, "no compiled sweep for this (leaf, rank, levels) combination");
     size_t elem = o.precision == HSWEEP_C64 ? sizeof(c64) : sizeof(c128);
     if (factor_lds_bytes(p, elem) > kMaxLds)
         return fail(HSWEEP_EINVAL, "layer too wide for this precision (LDS of the factorization kernels)");

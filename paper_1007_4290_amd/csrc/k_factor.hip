@@ -127,6 +127,10 @@ __device__ __forceinline__ void gj_invert(cpx<T> (&M)[Tile<B>::TS][Tile<B>::TS],
 
 // ----------------------------------------------------------------------------
 // Leaf: S leaf of layer m, then its inverse K (column-major b x b).
+//   S_leaf = A_leaf - D (K_prev - sum_lvl P_lvl X_lvl P_lvl^t) D   on the leaf rows.
+// All factor data of the previous layer that the leaf needs is loaded in one
+// phase (every load independent), then the update and the inverse run from
+// registers and LDS.
 template <typename T, int B>
 __global__ __launch_bounds__(NT) void leaf_kernel(Plan p, StepPtrs<T> sp, int m) {
     constexpr int TS = Tile<B>::TS, G = Tile<B>::G;
@@ -138,9 +142,9 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Plan p, StepPtrs<T> sp, int m)
     const int tr = tid % G, tc = tid / G;
     const int base = t * B;
     const int r = p.r, L = p.L, np = p.np;
-    cpx<T>* Pl = (cpx<T>*)smem;   // B x r, [i*r + k]
-    cpx<T>* Wl = Pl + B * r;      // B x r
-    cpx<T>* Xb = Wl + B * r;      // r x r, [k1*r + k2]
+    cpx<T>* Pl = (cpx<T>*)smem;            // [lvl][i][k], L x B x r
+    cpx<T>* Xb = Pl + (size_t)L * B * r;   // [lvl][k1][k2], L x r x r
+    cpx<T>* Wl = Xb + (size_t)L * r * r;   // [lvl][i][k2], L x B x r
 
     cpx<T> M[TS][TS];
 #pragma unroll
@@ -150,40 +154,42 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Plan p, StepPtrs<T> sp, int m)
             int i = tr * TS + a, j = tc * TS + bb;
             M[a][bb] = (m > 0 && act) ? sp.Kp[(size_t)t * B * B + (size_t)j * B + i] : czero<T>();
         }
-    if (m > 0) {
-        for (int lvl = 1; lvl <= L; ++lvl) {
-            int anc = t >> (L - lvl);
+    if (m > 0 && L > 0) {
+        for (int e = tid; e < L * B * r; e += NT) {
+            int i = e % B, k = (e / B) % r, l = e / (B * r);
+            Pl[((size_t)l * B + i) * r + k] = sp.Pp[((size_t)l * r + k) * np + base + i];
+        }
+        for (int e = tid; e < L * r * r; e += NT) {
+            int k1 = e % r, k2 = (e / r) % r, l = e / (r * r);
+            int anc = t >> (L - 1 - l);
             int q = anc >> 1, sg = anc & 1;
-            const cpx<T>* Pv = sp.Pp + (size_t)(lvl - 1) * r * np;
-            const cpx<T>* Xq = sp.Xp + (size_t)heap_id(lvl - 1, q) * 4 * r * r;
-            for (int e = tid; e < B * r; e += NT) {
-                int i = e % B, k = e / B;
-                Pl[i * r + k] = Pv[(size_t)k * np + base + i];
-            }
-            for (int e = tid; e < r * r; e += NT) {
-                int k1 = e % r, k2 = e / r;
-                Xb[k1 * r + k2] = Xq[(size_t)(sg * r + k2) * 2 * r + sg * r + k1];
-            }
-            __syncthreads();
-            for (int e = tid; e < B * r; e += NT) {
-                int i = e / r, k2 = e % r;
-                cpx<T> acc = czero<T>();
-                for (int k1 = 0; k1 < r; ++k1) cfma(acc, Pl[i * r + k1], Xb[k1 * r + k2]);
-                Wl[i * r + k2] = acc;
-            }
-            __syncthreads();
-            if (act) {
+            const cpx<T>* Xq = sp.Xp + (size_t)heap_id(l, q) * 4 * r * r;
+            Xb[((size_t)l * r + k1) * r + k2] = Xq[(size_t)(sg * r + k2) * 2 * r + sg * r + k1];
+        }
+        __syncthreads();
+        for (int e = tid; e < L * B * r; e += NT) {
+            int k2 = e % r, i = (e / r) % B, l = e / (B * r);
+            const cpx<T>* pr = Pl + ((size_t)l * B + i) * r;
+            const cpx<T>* xc = Xb + (size_t)l * r * r + k2;
+            cpx<T> acc = czero<T>();
+            for (int k1 = 0; k1 < r; ++k1) cfma(acc, pr[k1], xc[(size_t)k1 * r]);
+            Wl[((size_t)l * B + i) * r + k2] = acc;
+        }
+        __syncthreads();
+        if (act) {
 #pragma unroll
-                for (int a = 0; a < TS; ++a)
+            for (int a = 0; a < TS; ++a)
 #pragma unroll
-                    for (int bb = 0; bb < TS; ++bb) {
-                        int i = tr * TS + a, j = tc * TS + bb;
-                        cpx<T> acc = czero<T>();
-                        for (int k = 0; k < r; ++k) cfma(acc, Wl[i * r + k], Pl[j * r + k]);
-                        M[a][bb] -= acc;
+                for (int bb = 0; bb < TS; ++bb) {
+                    int i = tr * TS + a, j = tc * TS + bb;
+                    cpx<T> acc = czero<T>();
+                    for (int l = 0; l < L; ++l) {
+                        const cpx<T>* wr = Wl + ((size_t)l * B + i) * r;
+                        const cpx<T>* pr = Pl + ((size_t)l * B + j) * r;
+                        for (int k = 0; k < r; ++k) cfma(acc, wr[k], pr[k]);
                     }
-            }
-            __syncthreads();
+                    M[a][bb] -= acc;
+                }
         }
     }
     if (act) {
@@ -213,108 +219,191 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Plan p, StepPtrs<T> sp, int m)
 }
 
 // ----------------------------------------------------------------------------
-// Block-level helpers for the recompression (all operands in LDS).
+// Wave-level helpers.  A wavefront executes in lockstep; wave_sync orders its
+// LDS traffic (and stops the compiler from moving memory operations across).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T>
-__device__ T block_sum(T v, T* red) {
+__device__ __forceinline__ T wave_sum(T v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) red[wv] = v;
-    __syncthreads();
-    T s = T(0);
-    for (int q = 0; q < NT / 64; ++q) s += red[q];
-    __syncthreads();
-    return s;
+    return v;
 }
 
-// dots[c - c0] = v^H A[j:, c] for c in [c0, ncol), where v = (v0, A[j+1:, j]).
-// Work split: tasks (column, row-phase) with the rows of one task strided.
+// Householder QR with column pivoting of the s x k column-major matrix A in
+// LDS, run by one wavefront.  Hermitian reflectors H_j = I - tau_j v_j v_j^H,
+// v_j = (v0_j, A[j+1:, j]); on exit A's upper triangle holds R (diagonal
+// beta_j), perm[c] is the original index of column c, and
+// A_in[:, perm] = H_0 ... H_{kr-1} R.  The factorization stops at step kr
+// when every remaining column norm is below delta times the largest initial
+// column norm (the dropped trailing block is that small).
 template <typename T>
-__device__ void reflector_dots(const cpx<T>* A, int lda, int s, int j, cpx<T> v0, const cpx<T>* Y, int ldy,
-                               int c0, int ncol, cpx<T>* part, cpx<T>* dots) {
-    int nc = ncol - c0;
-    if (nc <= 0) return;
-    int nph = NT / nc;
-    if (nph < 1) nph = 1;
-    if (nph > 64) nph = 64;
-    for (int task = threadIdx.x; task < nc * nph; task += NT) {
-        int c = c0 + task % nc, ph = task / nc;
-        cpx<T> acc = czero<T>();
-        for (int i = j + ph; i < s; i += nph) {
-            cpx<T> vi = (i == j) ? v0 : A[(size_t)j * lda + i];
-            cfma_conj(acc, vi, Y[(size_t)c * ldy + i]);
-        }
-        part[task] = acc;
+__device__ int wave_qrcp(cpx<T>* A, int s, int k, int* perm, cpx<T>* v0, T* tau, T* nrm, T* nref,
+                         cpx<T>* part, cpx<T>* dots, T delta) {
+    const int lane = threadIdx.x & 63;
+    for (int c = lane; c < k; c += 64) {
+        T acc = T(0);
+        for (int i = 0; i < s; ++i) acc += abs2(A[(size_t)c * s + i]);
+        nrm[c] = acc;
+        nref[c] = acc;
+        perm[c] = c;
     }
-    __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += NT) {
-        cpx<T> acc = czero<T>();
-        for (int ph = 0; ph < nph; ++ph) acc += part[ph * nc + c];
-        dots[c] = acc;
+    wave_sync();
+    T mx = T(0);
+    for (int c = lane; c < k; c += 64) mx = nrm[c] > mx ? nrm[c] : mx;
+    for (int off = 32; off > 0; off >>= 1) {
+        T o = __shfl_xor(mx, off, 64);
+        mx = o > mx ? o : mx;
     }
-    __syncthreads();
-}
-
-// Y[j:, c] -= tau * v * dots[c - c0] for c in [c0, ncol).
-template <typename T>
-__device__ void reflector_update(const cpx<T>* A, int lda, int s, int j, cpx<T> v0, T tau, cpx<T>* Y, int ldy,
-                                 int c0, int ncol, const cpx<T>* dots) {
-    int nc = ncol - c0, nr = s - j;
-    for (int e = threadIdx.x; e < nc * nr; e += NT) {
-        int i = j + e % nr, c = c0 + e / nr;
-        cpx<T> vi = (i == j) ? v0 : A[(size_t)j * lda + i];
-        Y[(size_t)c * ldy + i] -= (tau * vi) * dots[c - c0];
-    }
-    __syncthreads();
-}
-
-// Householder QR of the s x k column-major matrix A (in LDS).  Hermitian
-// reflectors H_j = I - tau_j v_j v_j^H with v_j = (v0_j, A[j+1:, j]); on exit
-// A's upper triangle holds R (diagonal = beta_j) and Q = H_0 H_1 ... H_{kk-1}.
-template <typename T>
-__device__ void house_qr(cpx<T>* A, int s, int k, cpx<T>* v0, T* tau, T* redr, cpx<T>* part, cpx<T>* dots) {
-    int kk = s < k ? s : k;
+    const T stop = delta * delta * mx;
+    const int kk = s < k ? s : k;
+    int kr = kk;
     for (int j = 0; j < kk; ++j) {
+        // pivot: the remaining column of largest norm (ties -> lowest index)
+        T best = T(-1);
+        int bi = j;
+        for (int c = j + lane; c < k; c += 64)
+            if (nrm[c] > best) { best = nrm[c]; bi = c; }
+        for (int off = 32; off > 0; off >>= 1) {
+            T ob = __shfl_xor(best, off, 64);
+            int oi = __shfl_xor(bi, off, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (!(best > stop)) { kr = j; break; }
+        if (bi != j) {
+            for (int i = lane; i < s; i += 64) {
+                cpx<T> a = A[(size_t)j * s + i];
+                A[(size_t)j * s + i] = A[(size_t)bi * s + i];
+                A[(size_t)bi * s + i] = a;
+            }
+            if (lane == 0) {
+                T tn = nrm[j]; nrm[j] = nrm[bi]; nrm[bi] = tn;
+                tn = nref[j]; nref[j] = nref[bi]; nref[bi] = tn;
+                int tp = perm[j]; perm[j] = perm[bi]; perm[bi] = tp;
+            }
+            wave_sync();
+        }
         T pr = T(0);
-        for (int i = j + threadIdx.x; i < s; i += NT) pr += abs2(A[(size_t)j * s + i]);
-        T nx2 = block_sum(pr, redr);
-        cpx<T> x0 = A[(size_t)j * s + j];
-        T nx = rsq(nx2), ax0 = rsq(abs2(x0));
-        cpx<T> ph = ax0 > T(0) ? (T(1) / ax0) * x0 : mk<T>(T(1), T(0));
-        cpx<T> vv0 = (ax0 + nx) * ph;
-        T tj = nx > T(0) ? T(1) / (nx * (nx + ax0)) : T(0);
-        reflector_dots(A, s, s, j, vv0, A, s, j + 1, k, part, dots);
-        reflector_update(A, s, s, j, vv0, tj, A, s, j + 1, k, dots);
-        if (threadIdx.x == 0) {
+        for (int i = j + lane; i < s; i += 64) pr += abs2(A[(size_t)j * s + i]);
+        const T nx2 = wave_sum(pr);
+        const cpx<T> x0 = A[(size_t)j * s + j];
+        const T nx = rsq(nx2), ax0 = rsq(abs2(x0));
+        const cpx<T> ph = ax0 > T(0) ? (T(1) / ax0) * x0 : mk<T>(T(1), T(0));
+        const cpx<T> vv0 = (ax0 + nx) * ph;
+        const T tj = nx > T(0) ? T(1) / (nx * (nx + ax0)) : T(0);
+        // dots[c] = v^H A[j:, c] for the columns right of j
+        const int nc = k - j - 1;
+        if (nc > 0) {
+            int nph = 64 / nc;
+            if (nph < 1) nph = 1;
+            for (int task = lane; task < nc * nph; task += 64) {
+                const int c = j + 1 + task % nc, ph2 = task / nc;
+                cpx<T> acc = czero<T>();
+                for (int i = j + ph2; i < s; i += nph) {
+                    cpx<T> vi = (i == j) ? vv0 : A[(size_t)j * s + i];
+                    cfma_conj(acc, vi, A[(size_t)c * s + i]);
+                }
+                part[task] = acc;
+            }
+            wave_sync();
+            for (int c = lane; c < nc; c += 64) {
+                cpx<T> acc = czero<T>();
+                for (int q = 0; q < nph; ++q) acc += part[q * nc + c];
+                dots[c] = acc;
+            }
+            wave_sync();
+            for (int i = j + lane; i < s; i += 64) {
+                const cpx<T> vi = (i == j) ? vv0 : A[(size_t)j * s + i];
+                const cpx<T> tv = tj * vi;
+                for (int c = 0; c < nc; ++c) A[(size_t)(j + 1 + c) * s + i] -= tv * dots[c];
+            }
+            wave_sync();
+        }
+        if (lane == 0) {
             A[(size_t)j * s + j] = -nx * ph;
             v0[j] = vv0;
             tau[j] = tj;
         }
+        // downdate the remaining column norms by the new row j of R
+        for (int c = j + 1 + lane; c < k; c += 64) {
+            T v = nrm[c] - abs2(A[(size_t)c * s + j]);
+            if (v < T(1e-2) * nref[c]) {
+                v = T(0);
+                for (int i = j + 1; i < s; ++i) v += abs2(A[(size_t)c * s + i]);
+                nref[c] = v;
+            }
+            nrm[c] = v > T(0) ? v : T(0);
+        }
+        wave_sync();
+    }
+    return kr;
+}
+
+// Y <- H_0 ... H_{kr-1} Y for the reflectors of wave_qrcp (Y: s x ncol,
+// column-major), run by one wavefront.
+template <typename T>
+__device__ void wave_apply_q(const cpx<T>* A, int s, int kr, const cpx<T>* v0, const T* tau, cpx<T>* Y, int ncol,
+                             cpx<T>* part, cpx<T>* dots) {
+    const int lane = threadIdx.x & 63;
+    if (ncol <= 0) return;
+    int nph = 64 / ncol;
+    if (nph < 1) nph = 1;
+    for (int j = kr - 1; j >= 0; --j) {
+        const T tj = tau[j];
+        if (tj == T(0)) continue;
+        const cpx<T> vv0 = v0[j];
+        for (int task = lane; task < ncol * nph; task += 64) {
+            const int c = task % ncol, ph2 = task / ncol;
+            cpx<T> acc = czero<T>();
+            for (int i = j + ph2; i < s; i += nph) {
+                cpx<T> vi = (i == j) ? vv0 : A[(size_t)j * s + i];
+                cfma_conj(acc, vi, Y[(size_t)c * s + i]);
+            }
+            part[task] = acc;
+        }
+        wave_sync();
+        for (int c = lane; c < ncol; c += 64) {
+            cpx<T> acc = czero<T>();
+            for (int q = 0; q < nph; ++q) acc += part[q * ncol + c];
+            dots[c] = acc;
+        }
+        wave_sync();
+        for (int i = j + lane; i < s; i += 64) {
+            const cpx<T> vi = (i == j) ? vv0 : A[(size_t)j * s + i];
+            const cpx<T> tv = tj * vi;
+            for (int c = 0; c < ncol; ++c) Y[(size_t)c * s + i] -= tv * dots[c];
+        }
+        wave_sync();
+    }
+}
+
+// One-sided Jacobi SVD (FP64) of the nr x P column-major matrix N in LDS
+// (P even; zero padding columns allowed) by the whole workgroup.  Rotations
+// of a round act on disjoint column pairs (round-robin ordering); J
+// accumulates them so that N_in J = N_out, whose columns are mutually
+// orthogonal.  A pair is rotated when |a^H b| > thr sqrt(|a|^2 |b|^2) and
+// both columns are above the negligible level; sweeps stop when none is.
+__device__ void jacobi_svd64(c128* N, int nr, c128* J, int P, int* flag, double* fro /* [NT/64] */) {
+    const int npair = P / 2;
+    int gsz = NT / (npair > 0 ? npair : 1);
+    int g2 = 1;
+    while (g2 * 2 <= gsz && g2 < 64) g2 *= 2;
+    gsz = g2;
+    const int grp = threadIdx.x / gsz, gl = threadIdx.x % gsz;
+    const double thr = 4.0 * P * 2.220446049250313e-16;
+    for (int e = threadIdx.x; e < P * P; e += NT) J[e] = (e % P == e / P) ? mk(1.0, 0.0) : czero<double>();
+    {
+        double f = 0.0;
+        for (int e = threadIdx.x; e < nr * P; e += NT) f += abs2(N[e]);
+        for (int off = 32; off > 0; off >>= 1) f += __shfl_xor(f, off, 64);
+        if ((threadIdx.x & 63) == 0) fro[threadIdx.x >> 6] = f;   // fixed-order sum below
         __syncthreads();
     }
-}
-
-// Y <- Q Y for the Q of house_qr (Y: s x ncol, column-major, ld s).
-template <typename T>
-__device__ void apply_q(const cpx<T>* A, int s, int kk, const cpx<T>* v0, const T* tau, cpx<T>* Y, int ncol,
-                        cpx<T>* part, cpx<T>* dots) {
-    for (int j = kk - 1; j >= 0; --j) {
-        if (tau[j] == T(0)) continue;
-        reflector_dots(A, s, s, j, v0[j], Y, s, 0, ncol, part, dots);
-        reflector_update(A, s, s, j, v0[j], tau[j], Y, s, 0, ncol, dots);
-    }
-}
-
-// One-sided Jacobi SVD of the P x P column-major matrix Mx (P even, columns
-// beyond the true size are zero).  On exit the columns of Mx are W_c sigma_c
-// and Z holds the accumulated unitary rotations (Mx_in Z = Mx_out).
-template <typename T>
-__device__ void jacobi_svd(cpx<T>* Mx, cpx<T>* Z, int P, int* flag) {
-    const int npair = P / 2;
-    const int grp = threadIdx.x >> 3, gl = threadIdx.x & 7;
-    const T thr = T(P) * eps_of<T>();
-    for (int e = threadIdx.x; e < P * P; e += NT) Z[e] = (e % P == e / P) ? mk<T>(T(1), T(0)) : czero<T>();
-    __syncthreads();
-    for (int sweep = 0; sweep < 60; ++sweep) {
+    const double tiny = (fro[0] + fro[1] + fro[2] + fro[3]) * 1e-30 + 1e-300;
+    for (int sweep = 0; sweep < 40; ++sweep) {
         if (threadIdx.x == 0) *flag = 0;
         __syncthreads();
         for (int rd = 0; rd < P - 1; ++rd) {
@@ -322,44 +411,46 @@ __device__ void jacobi_svd(cpx<T>* Mx, cpx<T>* Z, int P, int* flag) {
                 int a, b;
                 if (grp == 0) { a = rd; b = P - 1; }
                 else { a = (rd + grp) % (P - 1); b = (rd - grp + P - 1) % (P - 1); }
-                cpx<T>* ca = Mx + (size_t)a * P;
-                cpx<T>* cb = Mx + (size_t)b * P;
-                T al = T(0), be = T(0);
-                cpx<T> ga = czero<T>();
-                for (int i = gl; i < P; i += 8) {
+                c128* ca = N + (size_t)a * nr;
+                c128* cb = N + (size_t)b * nr;
+                double al = 0.0, be = 0.0;
+                c128 ga = czero<double>();
+                for (int i = gl; i < nr; i += gsz) {
                     al += abs2(ca[i]);
                     be += abs2(cb[i]);
                     cfma_conj(ga, ca[i], cb[i]);
                 }
-                for (int off = 1; off < 8; off <<= 1) {
-                    al += __shfl_xor(al, off, 8);
-                    be += __shfl_xor(be, off, 8);
-                    ga.re += __shfl_xor(ga.re, off, 8);
-                    ga.im += __shfl_xor(ga.im, off, 8);
+                for (int off = 1; off < gsz; off <<= 1) {
+                    al += __shfl_xor(al, off, gsz);
+                    be += __shfl_xor(be, off, gsz);
+                    ga.re += __shfl_xor(ga.re, off, gsz);
+                    ga.im += __shfl_xor(ga.im, off, gsz);
                 }
-                T ag = rsq(abs2(ga));
-                if (ag > thr * rsq(al * be) && ag > T(0)) {
-                    T zeta = (be - al) / (T(2) * ag);
-                    T t = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + rsq(T(1) + zeta * zeta));
-                    T c = T(1) / rsq(T(1) + t * t);
-                    T sn = c * t;
-                    cpx<T> em = (T(1) / ag) * conj(ga);   // e^{-i phi}
-                    for (int i = gl; i < P; i += 8) {
-                        cpx<T> xa = ca[i], xb = cb[i];
-                        ca[i] = c * xa - sn * (em * xb);
-                        cb[i] = sn * xa + c * (em * xb);
-                        cpx<T>* za = Z + (size_t)a * P;
-                        cpx<T>* zb = Z + (size_t)b * P;
-                        cpx<T> ya = za[i], yb = zb[i];
-                        za[i] = c * ya - sn * (em * yb);
-                        zb[i] = sn * ya + c * (em * yb);
+                const double ag = sqrt(abs2(ga));
+                if (al > tiny && be > tiny && ag > thr * sqrt(al * be)) {
+                    const double zeta = (be - al) / (2.0 * ag);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double c = 1.0 / sqrt(1.0 + t * t);
+                    const double sn = c * t;
+                    const c128 em = (1.0 / ag) * conj(ga);   // e^{-i phi}
+                    for (int i = gl; i < nr; i += gsz) {
+                        const c128 xa = ca[i], xb = em * cb[i];
+                        ca[i] = c * xa - sn * xb;
+                        cb[i] = sn * xa + c * xb;
+                    }
+                    c128* ja = J + (size_t)a * P;
+                    c128* jb = J + (size_t)b * P;
+                    for (int i = gl; i < P; i += gsz) {
+                        const c128 ya = ja[i], yb = em * jb[i];
+                        ja[i] = c * ya - sn * yb;
+                        jb[i] = sn * ya + c * yb;
                     }
                     if (gl == 0) *flag = 1;
                 }
             }
             __syncthreads();
         }
-        int f = *flag;
+        const int f = *flag;
         __syncthreads();
         if (!f) break;
     }
@@ -368,168 +459,212 @@ __device__ void jacobi_svd(cpx<T>* Mx, cpx<T>* Z, int P, int* flag) {
 // ----------------------------------------------------------------------------
 // Recompression of the off-diagonal blocks of S_m.
 struct RecompLayout {
-    // element offsets (in cpx<T> units) inside dynamic LDS
-    int s, k, kk, P, r;
-    size_t oU, oV, oM, oZ, oY, oPart, oDots, oV0u, oV0v, oEnd;
+    int s, k, kk, r;
+    size_t oU, oV, oY1, oY2, oPartU, oPartV, oDotsU, oDotsV, oV0u, oV0v, oEnd;   // cpx<T> units
+    size_t dN, dJ, dEnd;                                                         // c128 units (after oEnd)
 };
 
-__host__ __device__ inline RecompLayout recomp_layout(int s, int k, int r) {
+__host__ __device__ inline RecompLayout recomp_layout(int s, int k, int r, int Xblocks, size_t elem) {
     RecompLayout l;
     l.s = s; l.k = k; l.r = r;
     l.kk = s < k ? s : k;
-    l.P = l.kk + (l.kk & 1);
     size_t o = 0;
     l.oU = o; o += (size_t)s * k;
     l.oV = o; o += (size_t)s * k;
-    l.oM = o; o += (size_t)l.P * l.P;
-    l.oZ = o; o += (size_t)l.P * l.P;
-    l.oY = o; o += (size_t)s * r;
-    l.oPart = o; o += NT;
-    l.oDots = o; o += (k > r ? k : r);
+    l.oY1 = o; o += (size_t)s * r;
+    l.oY2 = o; o += (size_t)s * r;
+    l.oPartU = o; o += 64;
+    l.oPartV = o; o += 64;
+    l.oDotsU = o; o += (k > r ? k : r);
+    l.oDotsV = o; o += (k > r ? k : r);
     l.oV0u = o; o += l.kk;
     l.oV0v = o; o += l.kk;
+    o += (size_t)Xblocks;                  // staged X blocks
     l.oEnd = o;
+    // FP64 core (N: kk x P, J: P x P with P <= kk + 1), placed after the cpx<T> area
+    size_t bytes = o * elem;
+    bytes = (bytes + 15) / 16 * 16;
+    int P = l.kk + 1;
+    l.dN = bytes / sizeof(c128);
+    l.dJ = l.dN + (size_t)l.kk * P;
+    l.dEnd = l.dJ + (size_t)P * P;
     return l;
 }
 
-template <typename T>
+template <typename T, int R>
 __global__ __launch_bounds__(NT) void recompress_kernel(Plan p, StepPtrs<T> sp, int m) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ T tau_u[64 * 2 + 8], tau_v[64 * 2 + 8], redr[NT / 64], sig[72];
+    __shared__ T tau_u[72], tau_v[72], nrm_u[72], nrm_v[72], nref_u[72], nref_v[72];
+    __shared__ int perm_u[72], perm_v[72], pinv_u[72], pinv_v[72];
+    __shared__ double sig[72];
     __shared__ int order[72];
-    __shared__ int flag, rank_s;
+    __shared__ int flag, rank_s, kr_u, kr_v;
+    __shared__ double fro[NT / 64];
     const int pj = blockIdx.x;                   // heap id of the parent node
     const int lp = 31 - __clz(pj + 1);
     const int j = pj - ((1 << lp) - 1);
     const int lam = lp + 1;
     const int s = p.np >> lam;
-    const int r = p.r, np = p.np;
-    const int k = 1 + (m > 0 ? r * lam : 0);
+    const int np = p.np;
+    const int k = 1 + (m > 0 ? R * lam : 0);
     const int lo1 = 2 * j * s, lo2 = (2 * j + 1) * s;
-    RecompLayout ly = recomp_layout(s, k, r);
+    const int nX = m > 0 ? lam * R * R : 0;
+    RecompLayout ly = recomp_layout(s, k, R, nX, sizeof(cpx<T>));
     cpx<T>* base = (cpx<T>*)smem;
     cpx<T>* Ut = base + ly.oU;
     cpx<T>* Vt = base + ly.oV;
-    cpx<T>* Mx = base + ly.oM;
-    cpx<T>* Z = base + ly.oZ;
-    cpx<T>* Y = base + ly.oY;
-    cpx<T>* part = base + ly.oPart;
-    cpx<T>* dots = base + ly.oDots;
-    cpx<T>* v0u = base + ly.oV0u;
-    cpx<T>* v0v = base + ly.oV0v;
-    const int tid = threadIdx.x;
+    cpx<T>* Y1 = base + ly.oY1;
+    cpx<T>* Y2 = base + ly.oY2;
+    cpx<T>* Xs = base + ly.oEnd - nX;          // [blk][k1][k2]
+    c128* Nm = (c128*)smem + ly.dN;
+    c128* Jm = (c128*)smem + ly.dJ;
+    const int tid = threadIdx.x, wv = tid >> 6;
 
     // Stacked factors: S_m(c1, c2) = Ut Vt^t.
-    //   column 0:        A_{m,m}(last of c1, first of c2) e_last e_first^t
-    //   columns 1..r:    D P_lam[c1] X_pj(0-block row, 1-block col) | D P_lam[c2]
-    //   then for each ancestor level l' = lam-1 .. 1:
-    //                    D P_l'[c1] X_q'(sigma, sigma)              | D P_l'[c2]
+    //   column 0:          A_{m,m}(last of c1, first of c2) e_last e_first^t
+    //   block 0 (cols 1..r): D P_lam[c1] X_pj(first block row, second block col) | D P_lam[c2]
+    //   block b >= 1:      ancestor level l' = lam - b:  D P_l'[c1] X_q'(sg, sg)  | D P_l'[c2]
+    for (int e = tid; e < nX; e += NT) {
+        const int k2 = e % R, k1 = (e / R) % R, blk = e / (R * R);
+        const cpx<T>* Xq;
+        int rowoff, coloff;
+        if (blk == 0) {
+            Xq = sp.Xp + (size_t)pj * 4 * R * R;
+            rowoff = 0; coloff = R;
+        } else {
+            const int lv = lam - blk;
+            const int a = (2 * j) >> (lam - lv);
+            Xq = sp.Xp + (size_t)heap_id(lv - 1, a >> 1) * 4 * R * R;
+            rowoff = (a & 1) * R; coloff = rowoff;
+        }
+        Xs[e] = Xq[(size_t)(coloff + k2) * 2 * R + rowoff + k1];
+    }
     for (int i = tid; i < s; i += NT) {
         Ut[i] = (i == s - 1) ? sp.eo[lo1 + s - 1] : czero<T>();
         Vt[i] = (i == 0) ? mk<T>(T(1), T(0)) : czero<T>();
     }
+    __syncthreads();
     if (m > 0) {
-        for (int e = tid; e < lam * s * r; e += NT) {
-            int i = e % s;
-            int k2 = (e / s) % r;
-            int blk = e / (s * r);          // 0: own pair, 1..lam-1: ancestors
-            int lv, rowoff, coloff;
-            const cpx<T>* Xq;
-            if (blk == 0) {
-                lv = lam;
-                Xq = sp.Xp + (size_t)pj * 4 * r * r;
-                rowoff = 0; coloff = r;
-            } else {
-                lv = lam - blk;
-                int a = (2 * j) >> (lam - lv);
-                int q = a >> 1, sg = a & 1;
-                Xq = sp.Xp + (size_t)heap_id(lv - 1, q) * 4 * r * r;
-                rowoff = sg * r; coloff = sg * r;
+        for (int e = tid; e < lam * s; e += NT) {
+            const int i = e % s, blk = e / s;
+            const int lv = lam - blk;
+            const cpx<T>* Pv = sp.Pp + (size_t)(lv - 1) * R * np;
+            cpx<T> pu[R], pv[R];
+#pragma unroll
+            for (int kk = 0; kk < R; ++kk) {
+                pu[kk] = Pv[(size_t)kk * np + lo1 + i];
+                pv[kk] = Pv[(size_t)kk * np + lo2 + i];
             }
-            const cpx<T>* Pv = sp.Pp + (size_t)(lv - 1) * r * np;
-            cpx<T> acc = czero<T>();
-            for (int k1 = 0; k1 < r; ++k1)
-                cfma(acc, Pv[(size_t)k1 * np + lo1 + i], Xq[(size_t)(coloff + k2) * 2 * r + rowoff + k1]);
-            int col = 1 + blk * r + k2;
-            Ut[(size_t)col * s + i] = sp.cp[lo1 + i] * acc;
-            Vt[(size_t)col * s + i] = sp.cp[lo2 + i] * Pv[(size_t)k2 * np + lo2 + i];
+            const cpx<T> d1 = sp.cp[lo1 + i], d2 = sp.cp[lo2 + i];
+            const cpx<T>* xb = Xs + (size_t)blk * R * R;
+#pragma unroll
+            for (int k2 = 0; k2 < R; ++k2) {
+                cpx<T> acc = czero<T>();
+#pragma unroll
+                for (int k1 = 0; k1 < R; ++k1) cfma(acc, pu[k1], xb[k1 * R + k2]);
+                const int col = 1 + blk * R + k2;
+                Ut[(size_t)col * s + i] = d1 * acc;
+                Vt[(size_t)col * s + i] = d2 * pv[k2];
+            }
         }
     }
     __syncthreads();
 
-    house_qr(Ut, s, k, v0u, tau_u, redr, part, dots);
-    house_qr(Vt, s, k, v0v, tau_v, redr, part, dots);
-
-    // core Mx = R1 R2^t (kk x kk), padded to P x P with zeros
-    const int kk = ly.kk, P = ly.P;
-    for (int e = tid; e < P * P; e += NT) {
-        int a = e % P, b = e / P;
-        cpx<T> acc = czero<T>();
-        if (a < kk && b < kk) {
-            int c0 = a > b ? a : b;
-            for (int c = c0; c < k; ++c) cfma(acc, Ut[(size_t)c * s + a], Vt[(size_t)c * s + b]);
-        }
-        Mx[(size_t)b * P + a] = acc;
+    // rank-revealing QR of both factors, one wavefront each, concurrently
+    // rank-revealing cut of the stacked factors: far below the truncation
+    // tolerance (none when nothing is truncated); in complex64 at the level
+    // of the factors' own rounding
+    const T delta = p.tol <= 0.0 ? T(0) : (sizeof(T) == 4 ? T(4.0e-7) : T(1.0e-5 * p.tol < 1.0e-11 ? 1.0e-5 * p.tol : 1.0e-11));
+    if (wv == 0) {
+        int kr = wave_qrcp(Ut, s, k, perm_u, base + ly.oV0u, tau_u, nrm_u, nref_u, base + ly.oPartU,
+                           base + ly.oDotsU, delta);
+        if ((tid & 63) == 0) kr_u = kr;
+    } else if (wv == 1) {
+        int kr = wave_qrcp(Vt, s, k, perm_v, base + ly.oV0v, tau_v, nrm_v, nref_v, base + ly.oPartV,
+                           base + ly.oDotsV, delta);
+        if ((tid & 63) == 0) kr_v = kr;
     }
     __syncthreads();
-    jacobi_svd(Mx, Z, P, &flag);
+    const int k1 = kr_u, k2 = kr_v;
+    for (int c = tid; c < k; c += NT) {
+        pinv_u[perm_u[c]] = c;
+        pinv_v[perm_v[c]] = c;
+    }
+    __syncthreads();
 
-    // singular values and truncation
+    // core M = R1 Pi1^t Pi2 R2^t (k1 x k2), in FP64.  Jacobi runs on the
+    // columns of the orientation with fewer columns: N = M (k2 <= k1) or
+    // N = M^H (k1 < k2).
+    const bool tr = k1 < k2;
+    const int nr = tr ? k2 : k1;
+    const int ncl = tr ? k1 : k2;
+    const int P = ncl + (ncl & 1);
+    for (int e = tid; e < nr * P; e += NT) {
+        const int row = e % nr, col = e / nr;
+        c128 v = czero<double>();
+        if (col < ncl) {
+            const int a = tr ? col : row;      // row of M (U side)
+            const int b = tr ? row : col;      // column of M (V side)
+            for (int c = 0; c < k; ++c) {
+                const int cu = pinv_u[c], cv = pinv_v[c];
+                if (cu >= a && cv >= b)
+                    cfma(v, ccast<double>(Ut[(size_t)cu * s + a]), ccast<double>(Vt[(size_t)cv * s + b]));
+            }
+            if (tr) v = conj(v);
+        }
+        Nm[(size_t)col * nr + row] = v;
+    }
+    __syncthreads();
+    if (ncl > 0) jacobi_svd64(Nm, nr, Jm, P, &flag, fro);
+    __syncthreads();
+
     for (int c = tid; c < P; c += NT) {
-        T ss = T(0);
-        for (int i = 0; i < P; ++i) ss += abs2(Mx[(size_t)c * P + i]);
-        sig[c] = rsq(ss);
+        double ss = 0.0;
+        for (int i = 0; i < nr; ++i) ss += abs2(Nm[(size_t)c * nr + i]);
+        sig[c] = sqrt(ss);
     }
     __syncthreads();
     if (tid == 0) {
+        // partial selection of the R largest singular values
         for (int c = 0; c < P; ++c) order[c] = c;
-        for (int a = 0; a < P; ++a) {
+        const int top = P < R ? P : R;
+        for (int a = 0; a < top; ++a) {
             int best = a;
             for (int b2 = a + 1; b2 < P; ++b2)
                 if (sig[order[b2]] > sig[order[best]]) best = b2;
-            int tmp = order[a]; order[a] = order[best]; order[best] = tmp;
+            const int tmp = order[a]; order[a] = order[best]; order[best] = tmp;
         }
-        T s1 = sig[order[0]];
+        const double s1 = P > 0 ? sig[order[0]] : 0.0;
         int rho = 0;
-        while (rho < P && rho < r && s1 > T(0) && sig[order[rho]] > T(p.tol) * s1 && sig[order[rho]] > T(0)) ++rho;
+        while (rho < top && s1 > 0.0 && sig[order[rho]] > p.tol * s1 && sig[order[rho]] > 0.0) ++rho;
         rank_s = rho;
     }
     __syncthreads();
     const int rho = rank_s;
 
-    // U = Q1 [W sqrt(S); 0]: W_c sqrt(s_c) = Mx_c / sqrt(s_c)
-    for (int e = tid; e < s * r; e += NT) {
-        int i = e % s, q = e / s;
-        cpx<T> v = czero<T>();
-        if (q < rho && i < kk) {
-            int c = order[q];
-            v = (T(1) / rsq(sig[c])) * Mx[(size_t)c * P + i];
+    // M = W S Z^H.  If N = M: N J = W S, Z = J.  If N = M^H: N J = Z S, W = J.
+    // U = Q1 [W sqrt(S); 0],  V = Q2 [conj(Z) sqrt(S); 0]
+    for (int e = tid; e < s * R; e += NT) {
+        const int i = e % s, q = e / s;
+        c128 u = czero<double>(), v = czero<double>();
+        if (q < rho) {
+            const int c = order[q];
+            const double sq = sqrt(sig[c]);
+            if (i < k1) u = tr ? sq * Jm[(size_t)c * P + i] : (1.0 / sq) * Nm[(size_t)c * nr + i];
+            if (i < k2) v = tr ? (1.0 / sq) * conj(Nm[(size_t)c * nr + i]) : sq * conj(Jm[(size_t)c * P + i]);
         }
-        Y[(size_t)q * s + i] = v;
+        Y1[(size_t)q * s + i] = ccast<T>(u);
+        Y2[(size_t)q * s + i] = ccast<T>(v);
     }
     __syncthreads();
-    apply_q(Ut, s, kk, v0u, tau_u, Y, rho, part, dots);
-    cpx<T>* Qv = sp.Q + (size_t)(lam - 1) * r * np;
-    for (int e = tid; e < s * r; e += NT) {
-        int i = e % s, q = e / s;
-        Qv[(size_t)q * np + lo1 + i] = Y[(size_t)q * s + i];
-    }
+    if (wv == 0) wave_apply_q(Ut, s, k1, base + ly.oV0u, tau_u, Y1, rho, base + ly.oPartU, base + ly.oDotsU);
+    else if (wv == 1) wave_apply_q(Vt, s, k2, base + ly.oV0v, tau_v, Y2, rho, base + ly.oPartV, base + ly.oDotsV);
     __syncthreads();
-    // V = Q2 [conj(Z) sqrt(S); 0]
-    for (int e = tid; e < s * r; e += NT) {
-        int i = e % s, q = e / s;
-        cpx<T> v = czero<T>();
-        if (q < rho && i < kk) {
-            int c = order[q];
-            v = rsq(sig[c]) * conj(Z[(size_t)c * P + i]);
-        }
-        Y[(size_t)q * s + i] = v;
-    }
-    __syncthreads();
-    apply_q(Vt, s, kk, v0v, tau_v, Y, rho, part, dots);
-    for (int e = tid; e < s * r; e += NT) {
-        int i = e % s, q = e / s;
-        Qv[(size_t)q * np + lo2 + i] = Y[(size_t)q * s + i];
+    cpx<T>* Qv = sp.Q + (size_t)(lam - 1) * R * np;
+    for (int e = tid; e < s * R; e += NT) {
+        const int i = e % s, q = e / s;
+        Qv[(size_t)q * np + lo1 + i] = Y1[(size_t)q * s + i];
+        Qv[(size_t)q * np + lo2 + i] = Y2[(size_t)q * s + i];
     }
     if (tid == 0) sp.rank[pj] = rho;
 }
@@ -546,19 +681,20 @@ __host__ __device__ inline WoodLayout wood_layout(int s, int r, int b, int L, in
     w.oQ = o; o += (size_t)s * r;
     w.oY = o; o += (size_t)s * r;
     w.oPart = o; o += (size_t)(s / b > 0 ? s / b : 1) * r * r;
-    int nodes = lam < L ? (1 << (L - lam)) : 1;   // children at the finest level inside the node
+    const int nodes = lam < L ? (1 << (L - lam)) : 1;   // children at the finest level inside the node
     w.oYs = o; o += (size_t)nodes * r * r;
     w.oZs = o; o += (size_t)nodes * r * r;
     w.oEnd = o;
     return w;
 }
 
-template <typename T, int R2>
+template <typename T, int B, int R>
 __global__ __launch_bounds__(NT) void wood_kernel(Plan p, StepPtrs<T> sp, int lam) {
+    constexpr int R2 = 2 * R;
     constexpr int TS = Tile<R2>::TS, G = Tile<R2>::G;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ GJScratch<T, R2> gjs;
-    const int r = p.r, L = p.L, b = p.b, np = p.np;
+    const int L = p.L, np = p.np;
     const int ci = blockIdx.x;
     const int node = heap_id(lam, ci);
     const int s = p.np >> lam;
@@ -569,177 +705,232 @@ __global__ __launch_bounds__(NT) void wood_kernel(Plan p, StepPtrs<T> sp, int la
     if (lam < L) {
         const bool act = tid < G * G;
         const int tr = tid % G, tc = tid / G;
-        const cpx<T>* G1 = sp.G + (size_t)heap_id(lam + 1, 2 * ci) * r * r;
-        const cpx<T>* G2 = sp.G + (size_t)heap_id(lam + 1, 2 * ci + 1) * r * r;
+        const cpx<T>* G1 = sp.G + (size_t)heap_id(lam + 1, 2 * ci) * R * R;
+        const cpx<T>* G2 = sp.G + (size_t)heap_id(lam + 1, 2 * ci + 1) * R * R;
         cpx<T> M[TS][TS];
 #pragma unroll
         for (int a = 0; a < TS; ++a)
 #pragma unroll
             for (int bb = 0; bb < TS; ++bb) {
-                int i = tr * TS + a, j = tc * TS + bb;
+                const int i = tr * TS + a, jj = tc * TS + bb;
                 cpx<T> v = czero<T>();
                 if (act) {
-                    if (i < r && j < r) v = G1[i * r + j];
-                    else if (i >= r && j >= r) v = G2[(i - r) * r + (j - r)];
-                    else if (i - j == r || j - i == r) v = mk<T>(T(1), T(0));
+                    if (i < R && jj < R) v = G1[i * R + jj];
+                    else if (i >= R && jj >= R) v = G2[(i - R) * R + (jj - R)];
+                    else if (i - jj == R || jj - i == R) v = mk<T>(T(1), T(0));
                 }
                 M[a][bb] = v;
             }
         gj_invert<T, R2>(M, act, tr, tc, gjs, sp.status);
         if (act) {
-            cpx<T>* Xo = sp.X + (size_t)node * 4 * r * r;
+            cpx<T>* Xo = sp.X + (size_t)node * 4 * R * R;
 #pragma unroll
             for (int a = 0; a < TS; ++a)
 #pragma unroll
                 for (int bb = 0; bb < TS; ++bb) {
-                    int i = tr * TS + a, j = tc * TS + bb;
-                    Xo[(size_t)gjs.perm[j] * R2 + gjs.pinv[i]] = M[a][bb];
+                    const int i = tr * TS + a, jj = tc * TS + bb;
+                    Xo[(size_t)gjs.perm[jj] * R2 + gjs.pinv[i]] = M[a][bb];
                 }
         }
         __syncthreads();
     }
     if (lam == 0) return;
 
-    WoodLayout wl = wood_layout(s, r, b, L, lam);
+    WoodLayout wl = wood_layout(s, R, B, L, lam);
     cpx<T>* base = (cpx<T>*)smem;
-    cpx<T>* Qc = base + wl.oQ;     // [i*r + k]
-    cpx<T>* Y = base + wl.oY;      // [i*r + k]
+    cpx<T>* Qc = base + wl.oQ;     // [i*R + k]
+    cpx<T>* Y = base + wl.oY;      // [i*R + k]
     cpx<T>* part = base + wl.oPart;
     cpx<T>* ys = base + wl.oYs;
     cpx<T>* zs = base + wl.oZs;
-    const cpx<T>* Qv = sp.Q + (size_t)(lam - 1) * r * np;
-    for (int e = tid; e < s * r; e += NT) {
-        int i = e % s, k = e / s;
-        Qc[i * r + k] = Qv[(size_t)k * np + lo + i];
+    const cpx<T>* Qv = sp.Q + (size_t)(lam - 1) * R * np;
+    for (int i = tid; i < s; i += NT) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) Qc[i * R + k] = Qv[(size_t)k * np + lo + i];
     }
     __syncthreads();
-    // (b1) leaf part: Y = K Qc
-    for (int e = tid; e < s * r; e += NT) {
-        int i = e % s, k = e / s;
-        int gi = lo + i;
-        int t = gi / b, il = gi % b;
-        const cpx<T>* Kt = sp.K + (size_t)t * b * b;
-        int lb = (gi - il) - lo;
-        cpx<T> acc = czero<T>();
-        for (int jj = 0; jj < b; ++jj) cfma(acc, Kt[(size_t)jj * b + il], Qc[(lb + jj) * r + k]);
-        Y[i * r + k] = acc;
+    // (b1) leaf part: Y = K Qc, one row per thread
+    for (int i = tid; i < s; i += NT) {
+        const int gi = lo + i;
+        const int il = gi % B;
+        const cpx<T>* Kt = sp.K + (size_t)(gi / B) * B * B + il;
+        cpx<T> kr[B];
+#pragma unroll
+        for (int jj = 0; jj < B; ++jj) kr[jj] = Kt[(size_t)jj * B];
+        const cpx<T>* qb = Qc + (size_t)(i - il) * R;
+        cpx<T> acc[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = czero<T>();
+#pragma unroll
+        for (int jj = 0; jj < B; ++jj)
+#pragma unroll
+            for (int k = 0; k < R; ++k) cfma(acc[k], kr[jj], qb[jj * R + k]);
+#pragma unroll
+        for (int k = 0; k < R; ++k) Y[i * R + k] = acc[k];
     }
     __syncthreads();
-    // (b2) corrections of the nodes inside this node: levels lc = lam+1 .. L of children
-    const int nch = s / b;     // leaf-size chunks in the node
+    // (b2) corrections of the nodes inside this node: child levels lc = lam+1 .. L
+    const int nch = s / B;     // leaf-size chunks in the node
     for (int lc = lam + 1; lc <= L; ++lc) {
         const int sc = np >> lc;                  // child size
         const int ncn = s / sc;                   // children at level lc inside this node
-        const int cpn = sc / b;                   // chunks per child
-        const cpx<T>* Pv = sp.P + (size_t)(lc - 1) * r * np;
-        // chunk partials of P^t Qc
-        for (int e = tid; e < nch * r * r; e += NT) {
-            int ch = e % nch, k1 = (e / nch) % r, k2 = e / (nch * r);
-            cpx<T> acc = czero<T>();
-            for (int jj = 0; jj < b; ++jj) {
-                int i = ch * b + jj;
-                cfma(acc, Pv[(size_t)k1 * np + lo + i], Qc[i * r + k2]);
-            }
-            part[(k1 * r + k2) * nch + ch] = acc;
+        const int cpn = sc / B;                   // chunks per child
+        const cpx<T>* Pv = sp.P + (size_t)(lc - 1) * R * np;
+        // chunk partials of P^t Qc: task (chunk, k1) -> R outputs
+        for (int e = tid; e < nch * R; e += NT) {
+            const int ch = e % nch, k1 = e / nch;
+            const cpx<T>* pc = Pv + (size_t)k1 * np + lo + ch * B;
+            cpx<T> pv[B];
+#pragma unroll
+            for (int jj = 0; jj < B; ++jj) pv[jj] = pc[jj];
+            cpx<T> acc[R];
+#pragma unroll
+            for (int k2 = 0; k2 < R; ++k2) acc[k2] = czero<T>();
+#pragma unroll
+            for (int jj = 0; jj < B; ++jj)
+#pragma unroll
+                for (int k2 = 0; k2 < R; ++k2) cfma(acc[k2], pv[jj], Qc[(ch * B + jj) * R + k2]);
+#pragma unroll
+            for (int k2 = 0; k2 < R; ++k2) part[(k1 * R + k2) * nch + ch] = acc[k2];
         }
         __syncthreads();
-        for (int e = tid; e < ncn * r * r; e += NT) {
-            int c = e / (r * r), kk = e % (r * r);
+        for (int e = tid; e < ncn * R * R; e += NT) {
+            const int c = e / (R * R), kk = e % (R * R);
             cpx<T> acc = czero<T>();
             for (int q = 0; q < cpn; ++q) acc += part[kk * nch + c * cpn + q];
-            ys[c * r * r + kk] = acc;             // ys[c][k1][k2]
+            ys[c * R * R + kk] = acc;             // ys[c][k1][k2]
         }
         __syncthreads();
-        // z_parent = X_parent [y_left; y_right]  (2r x r) for the parents at level lc-1
+        // z_parent = X_parent [y_left; y_right]  (2R x R) for the parents at level lc-1
         const int npar = ncn / 2;
-        for (int e = tid; e < npar * 2 * r * r; e += NT) {
-            int q = e / (2 * r * r), o = (e / r) % (2 * r), k2 = e % r;
-            int gq = (lo / (2 * sc)) + q;         // parent index at level lc-1
-            const cpx<T>* Xq = sp.X + (size_t)heap_id(lc - 1, gq) * 4 * r * r;
+        for (int e = tid; e < npar * R2 * R; e += NT) {
+            const int q = e / (R2 * R), o = (e / R) % R2, k2 = e % R;
+            const int gq = (lo / (2 * sc)) + q;   // parent index at level lc-1
+            const cpx<T>* Xq = sp.X + (size_t)heap_id(lc - 1, gq) * 4 * R * R + o;
+            cpx<T> xr[R2];
+#pragma unroll
+            for (int c = 0; c < R2; ++c) xr[c] = Xq[(size_t)c * R2];
             cpx<T> acc = czero<T>();
-            for (int c = 0; c < 2 * r; ++c) {
-                cpx<T> yv = ys[(2 * q + c / r) * r * r + (c % r) * r + k2];
-                cfma(acc, Xq[(size_t)c * 2 * r + o], yv);
-            }
-            zs[(q * 2 * r + o) * r + k2] = acc;
+#pragma unroll
+            for (int c = 0; c < R2; ++c) cfma(acc, xr[c], ys[(2 * q + c / R) * R * R + (c % R) * R + k2]);
+            zs[(q * R2 + o) * R + k2] = acc;
         }
         __syncthreads();
-        for (int e = tid; e < s * r; e += NT) {
-            int i = e % s, k2 = e / s;
-            int c = i / sc;
-            int q = c >> 1, sg = c & 1;
-            cpx<T> acc = czero<T>();
-            for (int k1 = 0; k1 < r; ++k1)
-                cfma(acc, Pv[(size_t)k1 * np + lo + i], zs[(q * 2 * r + sg * r + k1) * r + k2]);
-            Y[i * r + k2] -= acc;
+        for (int i = tid; i < s; i += NT) {
+            const int c = i / sc;
+            const int q = c >> 1, sg = c & 1;
+            cpx<T> pr[R];
+#pragma unroll
+            for (int k1 = 0; k1 < R; ++k1) pr[k1] = Pv[(size_t)k1 * np + lo + i];
+            const cpx<T>* z = zs + (size_t)(q * R2 + sg * R) * R;
+#pragma unroll
+            for (int k2 = 0; k2 < R; ++k2) {
+                cpx<T> acc = czero<T>();
+#pragma unroll
+                for (int k1 = 0; k1 < R; ++k1) cfma(acc, pr[k1], z[k1 * R + k2]);
+                Y[i * R + k2] -= acc;
+            }
         }
         __syncthreads();
     }
     // (b3) P_c = Y ; G_c = Qc^t Y
-    cpx<T>* Pw = sp.P + (size_t)(lam - 1) * r * np;
-    for (int e = tid; e < s * r; e += NT) {
-        int i = e % s, k = e / s;
-        Pw[(size_t)k * np + lo + i] = Y[i * r + k];
+    cpx<T>* Pw = sp.P + (size_t)(lam - 1) * R * np;
+    for (int e = tid; e < s * R; e += NT) {
+        const int i = e % s, k = e / s;
+        Pw[(size_t)k * np + lo + i] = Y[i * R + k];
     }
-    for (int e = tid; e < nch * r * r; e += NT) {
-        int ch = e % nch, k1 = (e / nch) % r, k2 = e / (nch * r);
+    for (int e = tid; e < nch * R * R; e += NT) {
+        const int ch = e % nch, k1 = (e / nch) % R, k2 = e / (nch * R);
         cpx<T> acc = czero<T>();
-        for (int jj = 0; jj < b; ++jj) {
-            int i = ch * b + jj;
-            cfma(acc, Qc[i * r + k1], Y[i * r + k2]);
+#pragma unroll
+        for (int jj = 0; jj < B; ++jj) {
+            const int i = ch * B + jj;
+            cfma(acc, Qc[i * R + k1], Y[i * R + k2]);
         }
-        part[(k1 * r + k2) * nch + ch] = acc;
+        part[(k1 * R + k2) * nch + ch] = acc;
     }
     __syncthreads();
-    cpx<T>* Gw = sp.G + (size_t)node * r * r;
-    for (int e = tid; e < r * r; e += NT) {
+    cpx<T>* Gw = sp.G + (size_t)node * R * R;
+    for (int e = tid; e < R * R; e += NT) {
         cpx<T> acc = czero<T>();
         for (int ch = 0; ch < nch; ++ch) acc += part[e * nch + ch];
-        Gw[e] = acc;                               // G[k1*r + k2]
+        Gw[e] = acc;                               // G[k1*R + k2]
     }
 }
 
 template <typename T, int B>
 void launch_leaf(const Plan& p, int m, const StepPtrs<T>& sp, hipStream_t s) {
-    size_t lds = (size_t)(2 * B * p.r + p.r * p.r) * sizeof(cpx<T>);
+    size_t lds = (size_t)(2 * p.L * B * p.r + p.L * p.r * p.r + 1) * sizeof(cpx<T>);
     hipLaunchKernelGGL((leaf_kernel<T, B>), dim3(1 << p.L), dim3(NT), lds, s, p, sp, m);
 }
 
-template <typename T, int R2>
-void launch_wood(const Plan& p, int lam, const StepPtrs<T>& sp, hipStream_t s) {
-    size_t lds = 0;
-    if (lam > 0) lds = wood_layout(p.np >> lam, p.r, p.b, p.L, lam).oEnd * sizeof(cpx<T>);
-    hipLaunchKernelGGL((wood_kernel<T, R2>), dim3(1 << lam), dim3(NT), lds, s, p, sp, lam);
+template <typename T, int R>
+size_t recomp_lds(const Plan& p, int m) {
+    size_t mx = 0;
+    for (int lam = 1; lam <= p.L; ++lam) {
+        int k = 1 + (m > 0 ? R * lam : 0);
+        RecompLayout l = recomp_layout(p.np >> lam, k, R, m > 0 ? lam * R * R : 0, sizeof(cpx<T>));
+        size_t b = l.dEnd * sizeof(c128);
+        if (b > mx) mx = b;
+    }
+    return mx;
 }
 
+template <typename T, int R>
+void launch_recompress(const Plan& p, int m, const StepPtrs<T>& sp, hipStream_t s) {
+    const size_t lds = recomp_lds<T, R>(p, m);
+    hipLaunchKernelGGL((recompress_kernel<T, R>), dim3((1 << p.L) - 1), dim3(NT), lds, s, p, sp, m);
+}
+
+template <typename T, int B, int R>
+void launch_wood(const Plan& p, int lam, const StepPtrs<T>& sp, hipStream_t s) {
+    size_t lds = 0;
+    if (lam > 0) lds = wood_layout(p.np >> lam, R, B, p.L, lam).oEnd * sizeof(cpx<T>);
+    hipLaunchKernelGGL((wood_kernel<T, B, R>), dim3(1 << lam), dim3(NT), lds, s, p, sp, lam);
+}
+
+// Allow a kernel to use all LDS left after its static shared variables.
+template <typename K>
+void allow_lds(K kernel) {
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, (const void*)kernel) == hipSuccess) {
+        int dyn = 160 * 1024 - (int)a.sharedSizeBytes;
+        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    }
+    (void)hipGetLastError();   // a refused attribute must not surface as a later launch error
+}
+
+#define FOR_LEAVES(X) X(4) X(8) X(16) X(32) X(64)
+#define FOR_RANKS(X) X(2) X(4) X(8) X(16)
+#define FOR_WOOD(X) \
+    X(4, 2) X(4, 4) X(4, 8) X(4, 16) X(8, 2) X(8, 4) X(8, 8) X(8, 16) X(16, 2) X(16, 4) X(16, 8) X(16, 16) \
+    X(32, 2) X(32, 4) X(32, 8) X(32, 16) X(64, 2) X(64, 4) X(64, 8) X(64, 16)
+
 template <typename T>
-int set_lds_limits() {
+void set_lds_limits() {
     static bool done = false;
-    if (done) return 0;
+    if (done) return;
     done = true;
-    const int mx = 160 * 1024;
-    (void)hipFuncSetAttribute((const void*)recompress_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void*)leaf_kernel<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void*)leaf_kernel<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void*)leaf_kernel<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void*)leaf_kernel<T, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void*)leaf_kernel<T, 64>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void*)wood_kernel<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void*)wood_kernel<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void*)wood_kernel<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void*)wood_kernel<T, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void*)wood_kernel<T, 64>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    return 0;
+#define A_LEAF(BB) allow_lds(leaf_kernel<T, BB>);
+#define A_REC(RR) allow_lds(recompress_kernel<T, RR>);
+#define A_WOOD(BB, RR) allow_lds(wood_kernel<T, BB, RR>);
+    FOR_LEAVES(A_LEAF)
+    FOR_RANKS(A_REC)
+    FOR_WOOD(A_WOOD)
+#undef A_LEAF
+#undef A_REC
+#undef A_WOOD
 }
 
 }  // namespace
 
 // Largest dynamic LDS (bytes) any factorization kernel needs for this plan.
 size_t factor_lds_bytes(const Plan& p, size_t elem) {
-    size_t mx = (size_t)(2 * p.b * p.r + p.r * p.r) * elem;
+    size_t mx = (size_t)(2 * p.L * p.b * p.r + p.L * p.r * p.r + 1) * elem;
     for (int lam = 1; lam <= p.L; ++lam) {
         int s = p.np >> lam;
-        size_t a = recomp_layout(s, 1 + p.r * lam, p.r).oEnd * elem;
+        RecompLayout l = recomp_layout(s, 1 + p.r * lam, p.r, lam * p.r * p.r, elem);
+        size_t a = l.dEnd * sizeof(c128);
         size_t w = wood_layout(s, p.r, p.b, p.L, lam).oEnd * elem;
         if (a > mx) mx = a;
         if (w > mx) mx = w;
@@ -747,36 +938,36 @@ size_t factor_lds_bytes(const Plan& p, size_t elem) {
     return mx;
 }
 
+bool factor_supported(const Plan& p) {
+    bool leaf_ok = p.b == 4 || p.b == 8 || p.b == 16 || p.b == 32 || p.b == 64;
+    if (!leaf_ok) return false;
+    if (p.L == 0) return true;
+    return p.r == 2 || p.r == 4 || p.r == 8 || p.r == 16;
+}
+
 template <typename T>
 int launch_factor_step(const Plan& p, int m, const StepPtrs<T>& sp, hipStream_t s) {
     set_lds_limits<T>();
     if (p.L > 0) {
-        int kmax = 1 + (m > 0 ? p.r * 1 : 0);
-        (void)kmax;
-        size_t lds = 0;
-        for (int lam = 1; lam <= p.L; ++lam) {
-            size_t a = recomp_layout(p.np >> lam, 1 + (m > 0 ? p.r * lam : 0), p.r).oEnd;
-            if (a > lds) lds = a;
+        switch (p.r) {
+#define C_REC(RR) case RR: launch_recompress<T, RR>(p, m, sp, s); break;
+            FOR_RANKS(C_REC)
+#undef C_REC
+            default: return -1;
         }
-        hipLaunchKernelGGL(recompress_kernel<T>, dim3((1 << p.L) - 1), dim3(NT), lds * sizeof(cpx<T>), s, p, sp, m);
     }
     switch (p.b) {
-        case 4: launch_leaf<T, 4>(p, m, sp, s); break;
-        case 8: launch_leaf<T, 8>(p, m, sp, s); break;
-        case 16: launch_leaf<T, 16>(p, m, sp, s); break;
-        case 32: launch_leaf<T, 32>(p, m, sp, s); break;
-        case 64: launch_leaf<T, 64>(p, m, sp, s); break;
+#define C_LEAF(BB) case BB: launch_leaf<T, BB>(p, m, sp, s); break;
+        FOR_LEAVES(C_LEAF)
+#undef C_LEAF
         default: return -1;
     }
     for (int lam = p.L; lam >= 0 && p.L > 0; --lam) {
-        switch (2 * p.r) {
-            case 4: launch_wood<T, 4>(p, lam, sp, s); break;
-            case 8: launch_wood<T, 8>(p, lam, sp, s); break;
-            case 16: launch_wood<T, 16>(p, lam, sp, s); break;
-            case 32: launch_wood<T, 32>(p, lam, sp, s); break;
-            case 64: launch_wood<T, 64>(p, lam, sp, s); break;
-            default: return -1;
-        }
+        bool ok = false;
+#define C_WOOD(BB, RR) if (!ok && p.b == BB && p.r == RR) { launch_wood<T, BB, RR>(p, lam, sp, s); ok = true; }
+        FOR_WOOD(C_WOOD)
+#undef C_WOOD
+        if (!ok) return -1;
     }
     return 0;
 }
