@@ -165,8 +165,10 @@ int make_plan(hsweep_ctx* ctx, Plan& p) {
     return HSWEEP_OK;
 }
 
+// Allocate the factorization buffers of one context, build its layer
+// coefficients (Sec. 2.1) and describe it for the factorization kernels.
 template <typename T>
-int do_factor(hsweep_ctx* ctx, hipStream_t s) {
+int prepare_factor(hsweep_ctx* ctx, hipStream_t s, InstDesc<T>& d) {
     const Plan& p = ctx->plan;
     const int n = p.n, np = p.np;
     const size_t E = sizeof(cpx<T>);
@@ -183,28 +185,51 @@ int do_factor(hsweep_ctx* ctx, hipStream_t s) {
     launch_layer_coeffs<T>(n, np, ctx->omega, (const double*)ctx->c.p, (const c128*)ctx->isn.p,
                            (const c128*)ctx->sh.p, (cpx<T>*)ctx->dg.p, (cpx<T>*)ctx->eo.p, (cpx<T>*)ctx->cp.p, s);
     HIPCHK(hipGetLastError());
-    cpx<T>* fac = (cpx<T>*)ctx->fac.p;
-    for (int m = 0; m < n; ++m) {
-        StepPtrs<T> sp;
-        cpx<T>* cur = fac + (size_t)m * p.eLayer;
-        sp.K = cur; sp.P = cur + p.eK; sp.X = cur + p.eK + p.eP;
-        if (m > 0) {
-            const cpx<T>* prev = fac + (size_t)(m - 1) * p.eLayer;
-            sp.Kp = prev; sp.Pp = prev + p.eK; sp.Xp = prev + p.eK + p.eP;
-            sp.cp = (const cpx<T>*)ctx->cp.p + (size_t)(m - 1) * np;
-        } else {
-            sp.Kp = sp.Pp = sp.Xp = nullptr;
-            sp.cp = nullptr;
-        }
-        sp.dg = (const cpx<T>*)ctx->dg.p + (size_t)m * np;
-        sp.eo = (const cpx<T>*)ctx->eo.p + (size_t)m * np;
-        sp.Q = (cpx<T>*)ctx->Q.p;
-        sp.G = (cpx<T>*)ctx->G.p;
-        sp.rank = (int*)ctx->rank.p + (size_t)m * (1 << p.L);
-        sp.status = (int*)ctx->status.p;
-        if (launch_factor_step<T>(p, m, sp, s) != 0) return fail(HSWEEP_EINVAL, "unsupported leaf or rank");
+    d.p = p;
+    d.fac = (cpx<T>*)ctx->fac.p;
+    d.dg = (const cpx<T>*)ctx->dg.p;
+    d.eo = (const cpx<T>*)ctx->eo.p;
+    d.cp = (const cpx<T>*)ctx->cp.p;
+    d.Q = (cpx<T>*)ctx->Q.p;
+    d.G = (cpx<T>*)ctx->G.p;
+    d.rank = (int*)ctx->rank.p;
+    d.status = (int*)ctx->status.p;
+    return HSWEEP_OK;
+}
+
+// Run the layer loop of Alg. 2.3 for `count` contexts of the same element
+// type, leaf size and rank: layer step m of every context in one set of
+// launches.  Synchronizes `s` and checks every context's pivot status.
+template <typename T>
+int do_factor_many(hsweep_ctx** ctxs, int count, hipStream_t s) {
+    std::vector<InstDesc<T>> hd(count);
+    std::vector<Plan> plans(count);
+    int nmax = 0;
+    for (int q = 0; q < count; ++q) {
+        int rc = prepare_factor<T>(ctxs[q], s, hd[q]);
+        if (rc) return rc;
+        plans[q] = ctxs[q]->plan;
+        nmax = std::max(nmax, plans[q].n);
     }
-    HIPCHK(hipGetLastError());
+    DevBuf dd;
+    HIPCHK(dd.ensure(count * sizeof(InstDesc<T>)));
+    hipError_t e = hipMemcpyAsync(dd.p, hd.data(), count * sizeof(InstDesc<T>), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) { dd.release(); return fail(HSWEEP_EDEVICE, std::string("descriptor upload: ") + hipGetErrorString(e)); }
+    int rc = HSWEEP_OK;
+    for (int m = 0; m < nmax && rc == HSWEEP_OK; ++m)
+        if (launch_factor_layer<T>((const InstDesc<T>*)dd.p, plans.data(), count, m, s) != 0)
+            rc = fail(HSWEEP_EINVAL, "contexts of one batch need the same leaf size and rank");
+    e = hipGetLastError();
+    if (rc == HSWEEP_OK && e != hipSuccess) rc = fail(HSWEEP_EDEVICE, std::string("factor launch: ") + hipGetErrorString(e));
+    e = hipStreamSynchronize(s);   // also keeps dd alive until the kernels are done
+    dd.release();
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(HSWEEP_EDEVICE, std::string("factor: ") + hipGetErrorString(e));
+    for (int q = 0; q < count; ++q) {
+        int st = 0;
+        HIPCHK(hipMemcpy(&st, ctxs[q]->status.p, sizeof(int), hipMemcpyDeviceToHost));
+        if (st) return fail(HSWEEP_ESINGULAR, "zero pivot in a leaf or core inverse");
+    }
     return HSWEEP_OK;
 }
 
@@ -405,15 +430,13 @@ int hsweep_factor(hsweep_ctx* ctx, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     ctx->factored = false;
     HIPCHK(hipEventRecord(ctx->ev[0], s));
-    rc = ctx->opts.precision == HSWEEP_C64 ? do_factor<float>(ctx, s) : do_factor<double>(ctx, s);
+    hsweep_ctx* one[1] = {ctx};
+    rc = ctx->opts.precision == HSWEEP_C64 ? do_factor_many<float>(one, 1, s) : do_factor_many<double>(one, 1, s);
     if (rc) return rc;
     HIPCHK(hipEventRecord(ctx->ev[1], s));
-    int st = 0;
-    HIPCHK(hipMemcpyAsync(&st, ctx->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipEventSynchronize(ctx->ev[1]));
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->t_factor = ms;
-    if (st) return fail(HSWEEP_ESINGULAR, "zero pivot in a leaf or core inverse");
     ctx->factored = true;
     return HSWEEP_OK;
 }
@@ -677,9 +700,38 @@ int hsweep_solve(hsweep_ctx* ctx, const void* fv, void* uv, int nrhs, double tol
 int hsweep_factor_batch(hsweep_ctx** ctxs, int count, void* stream) {
     g_err.clear();
     if (!ctxs || count < 1) return fail(HSWEEP_EINVAL, "ctxs must hold count >= 1 contexts");
-    for (int i = 0; i < count; ++i) {
-        int rc = hsweep_factor(ctxs[i], stream);
+    for (int q = 0; q < count; ++q) {
+        int rc = check_ctx(ctxs[q]);
         if (rc) return rc;
+        if (!ctxs[q]->planned) {
+            Plan p;
+            rc = make_plan(ctxs[q], p);
+            if (rc) return rc;
+            ctxs[q]->plan = p;
+            ctxs[q]->planned = true;
+        }
+        if (ctxs[q]->opts.precision != ctxs[0]->opts.precision || ctxs[q]->device != ctxs[0]->device)
+            return fail(HSWEEP_EINVAL, "contexts of one batch need the same precision and device");
+        const Plan& a = ctxs[q]->plan;
+        const Plan& b0 = ctxs[0]->plan;
+        if (a.b != b0.b || (a.L > 0 ? a.r : 2) != (b0.L > 0 ? b0.r : 2))
+            return fail(HSWEEP_EINVAL, "contexts of one batch need the same leaf size and rank");
+    }
+    int rc = set_device(ctxs[0]);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    for (int q = 0; q < count; ++q) ctxs[q]->factored = false;
+    HIPCHK(hipEventRecord(ctxs[0]->ev[0], s));
+    rc = ctxs[0]->opts.precision == HSWEEP_C64 ? do_factor_many<float>(ctxs, count, s)
+                                               : do_factor_many<double>(ctxs, count, s);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(ctxs[0]->ev[1], s));
+    HIPCHK(hipEventSynchronize(ctxs[0]->ev[1]));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctxs[0]->ev[0], ctxs[0]->ev[1]);
+    for (int q = 0; q < count; ++q) {
+        ctxs[q]->t_factor = ms;
+        ctxs[q]->factored = true;
     }
     return HSWEEP_OK;
 }

@@ -57,9 +57,27 @@ void launch_stencil(int n, int nrhs, double omega, const double* c, const c128* 
 void launch_grad(int n, int nrhs, double omega, const double* c, const c128* isn,
                  const c128* u, const c128* mu, double* grad, hipStream_t s);
 
-// ---- factorization kernels ----
+// One problem instance of a (possibly batched) factorization: its plan and
+// the device buffers of its layer coefficients and factor store.
 template <typename T>
-int launch_factor_step(const Plan& p, int m, const StepPtrs<T>& sp, hipStream_t s);
+struct InstDesc {
+    Plan p;
+    cpx<T>* fac;        // n * eLayer
+    const cpx<T>* dg;   // n * np
+    const cpx<T>* eo;   // n * np
+    const cpx<T>* cp;   // (n-1) * np
+    cpx<T>* Q;          // L * r * np
+    cpx<T>* G;          // 2^(L+1) * r * r
+    int* rank;          // n * 2^L
+    int* status;
+};
+
+// ---- factorization kernels ----
+// Launches layer step m of every instance in `descs` (device array of ninst
+// descriptors; `plans` are host copies of their plans).  All instances share
+// the element type, leaf size and rank; instances with n <= m are skipped.
+template <typename T>
+int launch_factor_layer(const InstDesc<T>* descs, const Plan* plans, int ninst, int m, hipStream_t s);
 
 // ---- sweep (preconditioner application) ----
 template <typename T>

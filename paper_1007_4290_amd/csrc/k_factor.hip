@@ -42,6 +42,14 @@ template <> __device__ __forceinline__ double rsq<double>(double x) { return sqr
 
 __device__ __forceinline__ int heap_id(int lvl, int idx) { return (1 << lvl) - 1 + idx; }
 
+// A wavefront executes in lockstep; wave_sync orders its LDS traffic and
+// stops the compiler from moving memory operations across it.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ----------------------------------------------------------------------------
 // Gauss-Jordan inversion with partial pivoting of a B x B matrix held in
 // register tiles: thread (tr, tc) of a G x G grid (G = B / TS) owns rows
@@ -80,13 +88,27 @@ __device__ __forceinline__ void gj_invert(cpx<T> (&M)[Tile<B>::TS][Tile<B>::TS],
                     if (bb == kb) colk[tr * TS + a] = M[a][bb];
         }
         __syncthreads();
-        int p = 0;
-        T best = T(-1);
-        for (int i = 0; i < B; ++i) {
-            if (!g.used[i]) {
-                T v = abs2(colk[i]);
-                if (v > best) { best = v; p = i; }
+        // pivot: largest |colk[i]| over the unused rows, by a wavefront argmax
+        // (every wavefront computes the same result; ties -> lowest row)
+        int p;
+        T best;
+        {
+            const int lane = threadIdx.x & 63;
+            best = T(-1);
+            p = B;
+            for (int i = lane; i < B; i += 64) {
+                if (!g.used[i]) {
+                    const T v = abs2(colk[i]);
+                    if (v > best) { best = v; p = i; }
+                }
             }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const T ob = __shfl_xor(best, off, 64);
+                const int op = __shfl_xor(p, off, 64);
+                if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
+            }
+            if (p >= B) p = 0;
         }
         if (act && tr == p / TS) {
             const int pa = p % TS;
@@ -126,22 +148,96 @@ __device__ __forceinline__ void gj_invert(cpx<T> (&M)[Tile<B>::TS][Tile<B>::TS],
 }
 
 // ----------------------------------------------------------------------------
+// Gauss-Jordan inversion with partial pivoting of a B x B matrix held in the
+// registers of ONE wavefront (no LDS round trips, no workgroup barriers).
+// Lane l holds row i = l % B and the CPL columns g*CPL .. g*CPL+CPL-1 of
+// column group g = l / B.  Pivot rows are chosen among the rows not used yet
+// (no physical swaps); if row i was the pivot of step k_i and perm[k] is the
+// pivot row of step k, the inverse is inv(k_i, perm[j]) = M(i, j).
+template <int B> struct WaveTile {
+    static constexpr int NG = (64 / B) < B ? (64 / B) : B;   // column groups
+    static constexpr int CPL = B / NG;                         // columns per lane
+    static constexpr int LANES = B * NG;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> shfl_c(cpx<T> v, int src) {
+    return mk<T>(__shfl(v.re, src, 64), __shfl(v.im, src, 64));
+}
+
+// Runs on the lanes of one wavefront (all 64 must call it).  Min: column-major
+// B x B input (ldi); Out: column-major inverse (ldo).  perm: B ints of LDS.
+template <typename T, int B>
+__device__ __forceinline__ void gj_wave(const cpx<T>* Min, int ldi, cpx<T>* Out, int ldo, int* perm,
+                                        int* status) {
+    constexpr int NG = WaveTile<B>::NG, CPL = WaveTile<B>::CPL, LANES = WaveTile<B>::LANES;
+    const int lane = threadIdx.x & 63;
+    const bool act = lane < LANES;
+    const int i = lane % B, g = lane / B;
+    cpx<T> M[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) M[c] = act ? Min[(size_t)(g * CPL + c) * ldi + i] : czero<T>();
+    bool used = false;
+    int mystep = 0;
+    bool singular = false;
+    for (int k = 0; k < B; ++k) {
+        const int gk = k / CPL, kk = k % CPL;
+        cpx<T> mine = czero<T>();
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+            if (c == kk) mine = M[c];
+        const cpx<T> ci = shfl_c(mine, gk * B + i);          // this row's entry in column k
+        // argmax of |ci|^2 over the unused rows of this column group
+        T best = (act && !used) ? abs2(ci) : T(-1);
+        int pr = act ? i : B;
+#pragma unroll
+        for (int off = 1; off < B; off <<= 1) {
+            const T ob = __shfl_xor(best, off, 64);
+            const int op = __shfl_xor(pr, off, 64);
+            if (ob > best || (ob == best && op < pr)) { best = ob; pr = op; }
+        }
+        const int p = pr;                                    // same in every group
+        const cpx<T> cp = shfl_c(ci, g * B + p);             // pivot value
+        if (!(best > T(0))) singular = true;
+        const cpx<T> ipv = cinv(cp);
+        cpx<T> rowp[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) rowp[c] = shfl_c(M[c], g * B + p);
+        if (i == p) { used = true; mystep = k; }
+        if (lane == 0) perm[k] = p;
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int j = g * CPL + c;
+                if (i == p) M[c] = (j == k) ? ipv : rowp[c] * ipv;
+                else M[c] = (j == k) ? -(ci * ipv) : M[c] - ci * (rowp[c] * ipv);
+            }
+        }
+    }
+    wave_sync();
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) Out[(size_t)perm[g * CPL + c] * ldo + mystep] = M[c];
+    }
+    if (lane == 0 && singular) *status = 1;
+}
+
+// ----------------------------------------------------------------------------
 // Leaf: S leaf of layer m, then its inverse K (column-major b x b).
 //   S_leaf = A_leaf - D (K_prev - sum_lvl P_lvl X_lvl P_lvl^t) D   on the leaf rows.
 // All factor data of the previous layer that the leaf needs is loaded in one
 // phase (every load independent), then the update and the inverse run from
 // registers and LDS.
-template <typename T, int B>
-__global__ __launch_bounds__(NT) void leaf_kernel(Plan p, StepPtrs<T> sp, int m) {
+template <typename T, int B, int R>
+__device__ __forceinline__ void leaf_job(const Plan& p, const StepPtrs<T>& sp, int m, int t, unsigned char* smem) {
     constexpr int TS = Tile<B>::TS, G = Tile<B>::G;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ GJScratch<T, B> gjs;
-    const int t = blockIdx.x;
+    __shared__ int perm_w[B];
     const int tid = threadIdx.x;
     const bool act = tid < G * G;
     const int tr = tid % G, tc = tid / G;
     const int base = t * B;
-    const int r = p.r, L = p.L, np = p.np;
+    constexpr int r = R;
+    const int L = p.L, np = p.np;
     cpx<T>* Pl = (cpx<T>*)smem;            // [lvl][i][k], L x B x r
     cpx<T>* Xb = Pl + (size_t)L * B * r;   // [lvl][k1][k2], L x r x r
     cpx<T>* Wl = Xb + (size_t)L * r * r;   // [lvl][i][k2], L x B x r
@@ -172,6 +268,7 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Plan p, StepPtrs<T> sp, int m)
             const cpx<T>* pr = Pl + ((size_t)l * B + i) * r;
             const cpx<T>* xc = Xb + (size_t)l * r * r + k2;
             cpx<T> acc = czero<T>();
+#pragma unroll
             for (int k1 = 0; k1 < r; ++k1) cfma(acc, pr[k1], xc[(size_t)k1 * r]);
             Wl[((size_t)l * B + i) * r + k2] = acc;
         }
@@ -186,6 +283,7 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Plan p, StepPtrs<T> sp, int m)
                     for (int l = 0; l < L; ++l) {
                         const cpx<T>* wr = Wl + ((size_t)l * B + i) * r;
                         const cpx<T>* pr = Pl + ((size_t)l * B + j) * r;
+#pragma unroll
                         for (int k = 0; k < r; ++k) cfma(acc, wr[k], pr[k]);
                     }
                     M[a][bb] -= acc;
@@ -206,26 +304,21 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Plan p, StepPtrs<T> sp, int m)
                 M[a][bb] = (m > 0) ? aij - (sp.cp[gi] * sp.cp[gj]) * M[a][bb] : aij;
             }
     }
-    gj_invert<T, B>(M, act, tr, tc, gjs, sp.status);
+    // hand the leaf to one wavefront for the inverse (through LDS, column-major)
+    __syncthreads();                       // Pl / Wl are no longer read
+    cpx<T>* Ml = (cpx<T>*)smem;
     if (act) {
 #pragma unroll
         for (int a = 0; a < TS; ++a)
 #pragma unroll
-            for (int bb = 0; bb < TS; ++bb) {
-                int i = tr * TS + a, j = tc * TS + bb;
-                sp.K[(size_t)t * B * B + (size_t)gjs.perm[j] * B + gjs.pinv[i]] = M[a][bb];
-            }
+            for (int bb = 0; bb < TS; ++bb) Ml[(size_t)(tc * TS + bb) * B + tr * TS + a] = M[a][bb];
     }
+    __syncthreads();
+    if (threadIdx.x < 64) gj_wave<T, B>(Ml, B, sp.K + (size_t)t * B * B, B, perm_w, sp.status);
 }
 
 // ----------------------------------------------------------------------------
-// Wave-level helpers.  A wavefront executes in lockstep; wave_sync orders its
-// LDS traffic (and stops the compiler from moving memory operations across).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+// Wave-level helpers.
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -315,10 +408,12 @@ __device__ int wave_qrcp(cpx<T>* A, int s, int k, int* perm, cpx<T>* v0, T* tau,
                 dots[c] = acc;
             }
             wave_sync();
-            for (int i = j + lane; i < s; i += 64) {
+            // rank-1 update over all (row, column) pairs, spread across the lanes
+            const int nrw = s - j;
+            for (int e = lane; e < nrw * nc; e += 64) {
+                const int i = j + e % nrw, c = e / nrw;
                 const cpx<T> vi = (i == j) ? vv0 : A[(size_t)j * s + i];
-                const cpx<T> tv = tj * vi;
-                for (int c = 0; c < nc; ++c) A[(size_t)(j + 1 + c) * s + i] -= tv * dots[c];
+                A[(size_t)(j + 1 + c) * s + i] -= (tj * vi) * dots[c];
             }
             wave_sync();
         }
@@ -371,10 +466,11 @@ __device__ void wave_apply_q(const cpx<T>* A, int s, int kr, const cpx<T>* v0, c
             dots[c] = acc;
         }
         wave_sync();
-        for (int i = j + lane; i < s; i += 64) {
+        const int nrw = s - j;
+        for (int e = lane; e < nrw * ncol; e += 64) {
+            const int i = j + e % nrw, c = e / nrw;
             const cpx<T> vi = (i == j) ? vv0 : A[(size_t)j * s + i];
-            const cpx<T> tv = tj * vi;
-            for (int c = 0; c < ncol; ++c) Y[(size_t)c * s + i] -= tv * dots[c];
+            Y[(size_t)c * s + i] -= (tj * vi) * dots[c];
         }
         wave_sync();
     }
@@ -388,12 +484,13 @@ __device__ void wave_apply_q(const cpx<T>* A, int s, int kr, const cpx<T>* v0, c
 // both columns are above the negligible level; sweeps stop when none is.
 __device__ void jacobi_svd64(c128* N, int nr, c128* J, int P, int* flag, double* fro /* [NT/64] */) {
     const int npair = P / 2;
-    int gsz = NT / (npair > 0 ? npair : 1);
-    int g2 = 1;
-    while (g2 * 2 <= gsz && g2 < 64) g2 *= 2;
-    gsz = g2;
+    // 8 lanes per pair: three shuffle steps per reduction, rows strided by 8
+    const int gsz = 8;
     const int grp = threadIdx.x / gsz, gl = threadIdx.x % gsz;
-    const double thr = 4.0 * P * 2.220446049250313e-16;
+    // a pair counts as orthogonal below this cosine; far below the relative
+    // truncation thresholds used (the singular values are then accurate to
+    // about thr * sigma_1)
+    const double thr = 1.0e-12;
     for (int e = threadIdx.x; e < P * P; e += NT) J[e] = (e % P == e / P) ? mk(1.0, 0.0) : czero<double>();
     {
         double f = 0.0;
@@ -426,13 +523,14 @@ __device__ void jacobi_svd64(c128* N, int nr, c128* J, int P, int* flag, double*
                     ga.re += __shfl_xor(ga.re, off, gsz);
                     ga.im += __shfl_xor(ga.im, off, gsz);
                 }
-                const double ag = sqrt(abs2(ga));
-                if (al > tiny && be > tiny && ag > thr * sqrt(al * be)) {
-                    const double zeta = (be - al) / (2.0 * ag);
+                const double ag2 = abs2(ga);
+                if (al > tiny && be > tiny && ag2 > thr * thr * al * be) {
+                    const double iag = rsqrt(ag2);                  // 1 / |gamma|
+                    const double zeta = 0.5 * (be - al) * iag;
                     const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + t * t);
+                    const double c = rsqrt(1.0 + t * t);
                     const double sn = c * t;
-                    const c128 em = (1.0 / ag) * conj(ga);   // e^{-i phi}
+                    const c128 em = iag * conj(ga);                 // e^{-i phi}
                     for (int i = gl; i < nr; i += gsz) {
                         const c128 xa = ca[i], xb = em * cb[i];
                         ca[i] = c * xa - sn * xb;
@@ -492,16 +590,15 @@ __host__ __device__ inline RecompLayout recomp_layout(int s, int k, int r, int X
 }
 
 template <typename T, int R>
-__global__ __launch_bounds__(NT) void recompress_kernel(Plan p, StepPtrs<T> sp, int m) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>& sp, int m, int pj,
+                                               unsigned char* smem) {
     __shared__ T tau_u[72], tau_v[72], nrm_u[72], nrm_v[72], nref_u[72], nref_v[72];
     __shared__ int perm_u[72], perm_v[72], pinv_u[72], pinv_v[72];
     __shared__ double sig[72];
     __shared__ int order[72];
     __shared__ int flag, rank_s, kr_u, kr_v;
     __shared__ double fro[NT / 64];
-    const int pj = blockIdx.x;                   // heap id of the parent node
-    const int lp = 31 - __clz(pj + 1);
+    const int lp = 31 - __clz(pj + 1);           // pj: heap id of the parent node
     const int j = pj - ((1 << lp) - 1);
     const int lam = lp + 1;
     const int s = p.np >> lam;
@@ -669,6 +766,48 @@ __global__ __launch_bounds__(NT) void recompress_kernel(Plan p, StepPtrs<T> sp, 
     if (tid == 0) sp.rank[pj] = rho;
 }
 
+// One launch per layer for the two independent parts of forming S_m: blocks
+// [0, 2^L - 1) recompress the off-diagonal blocks, the next 2^L blocks form
+// and invert the dense leaves.
+template <typename T>
+__device__ __forceinline__ StepPtrs<T> step_ptrs(const InstDesc<T>& d, int m) {
+    const Plan& p = d.p;
+    StepPtrs<T> sp;
+    cpx<T>* cur = d.fac + (size_t)m * p.eLayer;
+    sp.K = cur; sp.P = cur + p.eK; sp.X = cur + p.eK + p.eP;
+    if (m > 0) {
+        const cpx<T>* prev = d.fac + (size_t)(m - 1) * p.eLayer;
+        sp.Kp = prev; sp.Pp = prev + p.eK; sp.Xp = prev + p.eK + p.eP;
+        sp.cp = d.cp + (size_t)(m - 1) * p.np;
+    } else {
+        sp.Kp = sp.Pp = sp.Xp = nullptr;
+        sp.cp = nullptr;
+    }
+    sp.dg = d.dg + (size_t)m * p.np;
+    sp.eo = d.eo + (size_t)m * p.np;
+    sp.Q = d.Q;
+    sp.G = d.G;
+    sp.rank = d.rank + (size_t)m * (1 << p.L);
+    sp.status = d.status;
+    return sp;
+}
+
+template <typename T, int B, int R>
+__global__ __launch_bounds__(NT) void layer_kernel(const InstDesc<T>* __restrict__ descs, int m) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const InstDesc<T> d = descs[blockIdx.y];
+    const Plan& p = d.p;
+    if (m >= p.n) return;
+    const int nrec = p.L > 0 ? (1 << p.L) - 1 : 0;
+    if ((int)blockIdx.x >= nrec + (1 << p.L)) return;
+    const StepPtrs<T> sp = step_ptrs(d, m);
+    if ((int)blockIdx.x < nrec) {
+        if constexpr (R >= 2) recompress_job<T, R>(p, sp, m, blockIdx.x, smem);
+    } else {
+        leaf_job<T, B, R>(p, sp, m, blockIdx.x - nrec, smem);
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Woodbury step for the nodes of level lam (lam = 0: root core only).
 struct WoodLayout {
@@ -689,11 +828,14 @@ __host__ __device__ inline WoodLayout wood_layout(int s, int r, int b, int L, in
 }
 
 template <typename T, int B, int R>
-__global__ __launch_bounds__(NT) void wood_kernel(Plan p, StepPtrs<T> sp, int lam) {
+__global__ __launch_bounds__(NT) void wood_kernel(const InstDesc<T>* __restrict__ descs, int m, int lam) {
     constexpr int R2 = 2 * R;
-    constexpr int TS = Tile<R2>::TS, G = Tile<R2>::G;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ GJScratch<T, R2> gjs;
+    __shared__ int perm_w[R2];
+    const InstDesc<T> d = descs[blockIdx.y];
+    const Plan& p = d.p;
+    if (m >= p.n || p.L == 0 || lam > p.L || (int)blockIdx.x >= (1 << lam)) return;
+    const StepPtrs<T> sp = step_ptrs(d, m);
     const int L = p.L, np = p.np;
     const int ci = blockIdx.x;
     const int node = heap_id(lam, ci);
@@ -701,37 +843,21 @@ __global__ __launch_bounds__(NT) void wood_kernel(Plan p, StepPtrs<T> sp, int la
     const int lo = ci * s;
     const int tid = threadIdx.x;
 
-    // (a) core inverse of this node from its children's G blocks
+    // (a) core inverse of this node from its children's G blocks, by wavefront 0
     if (lam < L) {
-        const bool act = tid < G * G;
-        const int tr = tid % G, tc = tid / G;
         const cpx<T>* G1 = sp.G + (size_t)heap_id(lam + 1, 2 * ci) * R * R;
         const cpx<T>* G2 = sp.G + (size_t)heap_id(lam + 1, 2 * ci + 1) * R * R;
-        cpx<T> M[TS][TS];
-#pragma unroll
-        for (int a = 0; a < TS; ++a)
-#pragma unroll
-            for (int bb = 0; bb < TS; ++bb) {
-                const int i = tr * TS + a, jj = tc * TS + bb;
-                cpx<T> v = czero<T>();
-                if (act) {
-                    if (i < R && jj < R) v = G1[i * R + jj];
-                    else if (i >= R && jj >= R) v = G2[(i - R) * R + (jj - R)];
-                    else if (i - jj == R || jj - i == R) v = mk<T>(T(1), T(0));
-                }
-                M[a][bb] = v;
-            }
-        gj_invert<T, R2>(M, act, tr, tc, gjs, sp.status);
-        if (act) {
-            cpx<T>* Xo = sp.X + (size_t)node * 4 * R * R;
-#pragma unroll
-            for (int a = 0; a < TS; ++a)
-#pragma unroll
-                for (int bb = 0; bb < TS; ++bb) {
-                    const int i = tr * TS + a, jj = tc * TS + bb;
-                    Xo[(size_t)gjs.perm[jj] * R2 + gjs.pinv[i]] = M[a][bb];
-                }
+        cpx<T>* Cl = (cpx<T>*)smem;        // column-major 2R x 2R
+        for (int e = tid; e < R2 * R2; e += NT) {
+            const int i = e % R2, jj = e / R2;
+            cpx<T> v = czero<T>();
+            if (i < R && jj < R) v = G1[i * R + jj];
+            else if (i >= R && jj >= R) v = G2[(i - R) * R + (jj - R)];
+            else if (i - jj == R || jj - i == R) v = mk<T>(T(1), T(0));
+            Cl[e] = v;
         }
+        __syncthreads();
+        if (tid < 64) gj_wave<T, R2>(Cl, R2, sp.X + (size_t)node * 4 * R * R, R2, perm_w, sp.status);
         __syncthreads();
     }
     if (lam == 0) return;
@@ -858,12 +984,6 @@ __global__ __launch_bounds__(NT) void wood_kernel(Plan p, StepPtrs<T> sp, int la
     }
 }
 
-template <typename T, int B>
-void launch_leaf(const Plan& p, int m, const StepPtrs<T>& sp, hipStream_t s) {
-    size_t lds = (size_t)(2 * p.L * B * p.r + p.L * p.r * p.r + 1) * sizeof(cpx<T>);
-    hipLaunchKernelGGL((leaf_kernel<T, B>), dim3(1 << p.L), dim3(NT), lds, s, p, sp, m);
-}
-
 template <typename T, int R>
 size_t recomp_lds(const Plan& p, int m) {
     size_t mx = 0;
@@ -876,17 +996,57 @@ size_t recomp_lds(const Plan& p, int m) {
     return mx;
 }
 
-template <typename T, int R>
-void launch_recompress(const Plan& p, int m, const StepPtrs<T>& sp, hipStream_t s) {
-    const size_t lds = recomp_lds<T, R>(p, m);
-    hipLaunchKernelGGL((recompress_kernel<T, R>), dim3((1 << p.L) - 1), dim3(NT), lds, s, p, sp, m);
+template <typename T, int B, int R>
+size_t layer_lds(const Plan& p, int m) {
+    size_t lds = (size_t)(2 * p.L * B * R + p.L * R * R + 1);
+    if (lds < (size_t)B * B) lds = (size_t)B * B;
+    lds *= sizeof(cpx<T>);
+    if (p.L > 0) {
+        size_t a = recomp_lds<T, R>(p, m);
+        if (a > lds) lds = a;
+    }
+    return lds;
 }
 
 template <typename T, int B, int R>
-void launch_wood(const Plan& p, int lam, const StepPtrs<T>& sp, hipStream_t s) {
+size_t wood_lds(const Plan& p, int lam) {
+    size_t lds = (size_t)4 * R * R;
+    if (lam > 0 && lam <= p.L) {
+        const size_t w = wood_layout(p.np >> lam, R, B, p.L, lam).oEnd;
+        if (w > lds) lds = w;
+    }
+    return lds * sizeof(cpx<T>);
+}
+
+template <typename T, int B, int R>
+void launch_layer(const InstDesc<T>* descs, const Plan* plans, int ninst, int m, hipStream_t s) {
     size_t lds = 0;
-    if (lam > 0) lds = wood_layout(p.np >> lam, R, B, p.L, lam).oEnd * sizeof(cpx<T>);
-    hipLaunchKernelGGL((wood_kernel<T, B, R>), dim3(1 << lam), dim3(NT), lds, s, p, sp, lam);
+    int nblk = 0;
+    for (int q = 0; q < ninst; ++q) {
+        const Plan& p = plans[q];
+        if (m >= p.n) continue;
+        const size_t l = layer_lds<T, B, R>(p, m);
+        if (l > lds) lds = l;
+        const int nb = (p.L > 0 ? (1 << p.L) - 1 : 0) + (1 << p.L);
+        if (nb > nblk) nblk = nb;
+    }
+    if (nblk == 0) return;
+    hipLaunchKernelGGL((layer_kernel<T, B, R>), dim3(nblk, ninst), dim3(NT), lds, s, descs, m);
+}
+
+template <typename T, int B, int R>
+void launch_wood(const InstDesc<T>* descs, const Plan* plans, int ninst, int m, int lam, hipStream_t s) {
+    size_t lds = 0;
+    bool any = false;
+    for (int q = 0; q < ninst; ++q) {
+        const Plan& p = plans[q];
+        if (m >= p.n || p.L == 0 || lam > p.L) continue;
+        any = true;
+        const size_t l = wood_lds<T, B, R>(p, lam);
+        if (l > lds) lds = l;
+    }
+    if (!any) return;
+    hipLaunchKernelGGL((wood_kernel<T, B, R>), dim3(1 << lam, ninst), dim3(NT), lds, s, descs, m, lam);
 }
 
 // Allow a kernel to use all LDS left after its static shared variables.
@@ -911,14 +1071,8 @@ void set_lds_limits() {
     static bool done = false;
     if (done) return;
     done = true;
-#define A_LEAF(BB) allow_lds(leaf_kernel<T, BB>);
-#define A_REC(RR) allow_lds(recompress_kernel<T, RR>);
-#define A_WOOD(BB, RR) allow_lds(wood_kernel<T, BB, RR>);
-    FOR_LEAVES(A_LEAF)
-    FOR_RANKS(A_REC)
+#define A_WOOD(BB, RR) allow_lds(wood_kernel<T, BB, RR>); allow_lds(layer_kernel<T, BB, RR>);
     FOR_WOOD(A_WOOD)
-#undef A_LEAF
-#undef A_REC
 #undef A_WOOD
 }
 
@@ -926,7 +1080,10 @@ void set_lds_limits() {
 
 // Largest dynamic LDS (bytes) any factorization kernel needs for this plan.
 size_t factor_lds_bytes(const Plan& p, size_t elem) {
-    size_t mx = (size_t)(2 * p.L * p.b * p.r + p.L * p.r * p.r + 1) * elem;
+    size_t mx = (size_t)(2 * p.L * p.b * p.r + p.L * p.r * p.r + 1);
+    if (mx < (size_t)p.b * p.b) mx = (size_t)p.b * p.b;
+    if (mx < (size_t)4 * p.r * p.r) mx = (size_t)4 * p.r * p.r;
+    mx *= elem;
     for (int lam = 1; lam <= p.L; ++lam) {
         int s = p.np >> lam;
         RecompLayout l = recomp_layout(s, 1 + p.r * lam, p.r, lam * p.r * p.r, elem);
@@ -946,31 +1103,27 @@ bool factor_supported(const Plan& p) {
 }
 
 template <typename T>
-int launch_factor_step(const Plan& p, int m, const StepPtrs<T>& sp, hipStream_t s) {
+int launch_factor_layer(const InstDesc<T>* descs, const Plan* plans, int ninst, int m, hipStream_t s) {
     set_lds_limits<T>();
-    if (p.L > 0) {
-        switch (p.r) {
-#define C_REC(RR) case RR: launch_recompress<T, RR>(p, m, sp, s); break;
-            FOR_RANKS(C_REC)
-#undef C_REC
-            default: return -1;
-        }
+    const int b = plans[0].b, L0 = plans[0].L;
+    const int rr = L0 > 0 ? plans[0].r : 2;   // dense leaves: no low-rank data
+    int Lmax = 0;
+    for (int q = 0; q < ninst; ++q) {
+        if (plans[q].b != b || (plans[q].L > 0 ? plans[q].r : 2) != rr) return -1;
+        if (plans[q].L > Lmax) Lmax = plans[q].L;
     }
-    switch (p.b) {
-#define C_LEAF(BB) case BB: launch_leaf<T, BB>(p, m, sp, s); break;
-        FOR_LEAVES(C_LEAF)
-#undef C_LEAF
-        default: return -1;
+    bool ok = false;
+#define C_LAYER(BB, RR)                                                               \
+    if (!ok && b == BB && rr == RR) {                                                 \
+        launch_layer<T, BB, RR>(descs, plans, ninst, m, s);                           \
+        for (int lam = Lmax; lam >= 0 && Lmax > 0; --lam)                             \
+            launch_wood<T, BB, RR>(descs, plans, ninst, m, lam, s);                   \
+        ok = true;                                                                    \
     }
-    for (int lam = p.L; lam >= 0 && p.L > 0; --lam) {
-        bool ok = false;
-#define C_WOOD(BB, RR) if (!ok && p.b == BB && p.r == RR) { launch_wood<T, BB, RR>(p, lam, sp, s); ok = true; }
-        FOR_WOOD(C_WOOD)
-#undef C_WOOD
-        if (!ok) return -1;
-    }
-    return 0;
+    FOR_WOOD(C_LAYER)
+#undef C_LAYER
+    return ok ? 0 : -1;
 }
 
-template int launch_factor_step<float>(const Plan&, int, const StepPtrs<float>&, hipStream_t);
-template int launch_factor_step<double>(const Plan&, int, const StepPtrs<double>&, hipStream_t);
+template int launch_factor_layer<float>(const InstDesc<float>*, const Plan*, int, int, hipStream_t);
+template int launch_factor_layer<double>(const InstDesc<double>*, const Plan*, int, int, hipStream_t);

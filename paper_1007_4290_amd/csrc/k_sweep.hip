@@ -31,9 +31,7 @@ void call_sweep(const Plan& p, const SweepArgs<double>& a, size_t lds, int th, h
 }  // namespace
 
 size_t sweep_lds_bytes(const Plan& p, size_t elem) {
-    int ch = p.b < p.r ? p.b : p.r;
-    size_t e = (size_t)p.np + (size_t)p.L * p.r * (p.np / ch) + (size_t)((1 << (p.L + 1)) - 1) * p.r +
-               (size_t)((1 << p.L) - 1) * 2 * p.r;
+    size_t e = (size_t)p.np + (size_t)((1 << (p.L + 1)) - 1) * p.r + (size_t)((1 << p.L) - 1) * 2 * p.r;
     return e * elem;
 }
 

@@ -78,18 +78,21 @@ __device__ __forceinline__ void load_layer(const Plan& p, const cpx<T>* __restri
 template <typename T>
 struct SweepShared {
     cpx<T>* xs;    // np
-    cpx<T>* part;  // L * r * np / CH  (per level: r columns x np/CH chunks)
     cpx<T>* gs;    // heap-indexed node reductions, (2^(L+1) - 1) * r
     cpx<T>* zs;    // (2^L - 1) * 2r
 };
 
+// y = T_m x for the row owned by this thread.  Three workgroup barriers per
+// call when L > 0: after the vector is published, after the node reductions,
+// after the cores.  The node reductions are segmented wavefront reductions of
+// the per-thread chunk sums (each node's chunks are consecutive lanes).
 template <typename T, int B, int R, int L>
 __device__ __forceinline__ cpx<T> apply_T(const Plan& p, const LayerRegs<T, B, R, L>& g, cpx<T> x,
                                           const SweepShared<T>& sh) {
     const int np = p.np;
     const int i = threadIdx.x;
     const bool row = i < np;
-    __syncthreads();   // the previous step may still read xs / zs
+    if constexpr (L == 0) __syncthreads();   // the previous step may still read xs
     if (row) sh.xs[i] = x;
     __syncthreads();
     cpx<T> y = czero<T>();
@@ -98,54 +101,48 @@ __device__ __forceinline__ cpx<T> apply_T(const Plan& p, const LayerRegs<T, B, R
         const cpx<T>* xl = sh.xs + t * B;
 #pragma unroll
         for (int j = 0; j < B; ++j) cfma(y, g.k[j], xl[j]);
+    }
+    if constexpr (L > 0) {
         constexpr int CH = Chunk<B, R>::CH, NTQ = Chunk<B, R>::NTQ;
         const int nch = np / CH;
 #pragma unroll
         for (int l = 0; l < L; ++l) {
-            {
+            const int lvl = l + 1;
+            const int cpn = nch >> lvl;           // chunks per node of this level
 #pragma unroll
-                for (int tq = 0; tq < NTQ; ++tq) {
-                    const int e = i + tq * np;
+            for (int tq = 0; tq < NTQ; ++tq) {
+                const int e = i + tq * np;        // (column kc, chunk ch) = (e / nch, e % nch)
+                cpx<T> acc = czero<T>();
+                if (row) {
                     const cpx<T>* xc = sh.xs + (e % nch) * CH;
-                    cpx<T> acc = czero<T>();
 #pragma unroll
                     for (int j = 0; j < CH; ++j) cfma(acc, g.pc[l][tq * CH + j], xc[j]);
-                    sh.part[(size_t)l * R * nch + e] = acc;   // entry (kc * nch + ch) of level l
+                }
+                for (int off = 1; off < cpn; off <<= 1) {
+                    acc.re += __shfl_xor(acc.re, off, 64);
+                    acc.im += __shfl_xor(acc.im, off, 64);
+                }
+                if (row && (e % cpn) == 0) {
+                    const int idx = (e % nch) / cpn, k = e / nch;
+                    sh.gs[((1 << lvl) - 1 + idx) * R + k] = acc;
                 }
             }
         }
-    }
-    if constexpr (L == 0) return y;
-    __syncthreads();
-    // node sums g_c for the nodes of levels 1..L (heap ids 1 .. 2^(L+1)-2)
-    const int nch = np / Chunk<B, R>::CH;
-    const int nnode = (1 << (L + 1)) - 2;
-    for (int e = i; e < nnode * R; e += blockDim.x) {
-        const int h = 1 + e / R, k = e % R;
-        const int lvl = 31 - __clz(h + 1);
-        const int idx = h - ((1 << lvl) - 1);
-        const int cpn = nch >> lvl;   // chunks per node
-        const cpx<T>* pp = sh.part + (size_t)(lvl - 1) * R * nch + k * nch + idx * cpn;
-        cpx<T> acc = czero<T>();
-        for (int q = 0; q < cpn; ++q) acc += pp[q];
-        sh.gs[h * R + k] = acc;
-    }
-    __syncthreads();
-    const int npar = (1 << L) - 1;
-    if (i < npar * 2 * R) {
-        const int q = i / (2 * R);
-        const cpx<T>* gq = sh.gs + (size_t)(2 * q + 1) * R;   // children 2q+1, 2q+2 are contiguous
-        cpx<T> acc = czero<T>();
+        __syncthreads();
+        const int npar = (1 << L) - 1;
+        if (i < npar * 2 * R) {
+            const int q = i / (2 * R);
+            const cpx<T>* gq = sh.gs + (size_t)(2 * q + 1) * R;   // children 2q+1, 2q+2 are contiguous
+            cpx<T> acc = czero<T>();
 #pragma unroll
-        for (int c = 0; c < 2 * R; ++c) cfma(acc, g.x[c], gq[c]);
-        sh.zs[i] = acc;
-    }
-    __syncthreads();
-    if (row) {
-        const int lnp = 31 - __clz(np);
+            for (int c = 0; c < 2 * R; ++c) cfma(acc, g.x[c], gq[c]);
+            sh.zs[i] = acc;
+        }
+        __syncthreads();
+        if (row) {
+            const int lnp = 31 - __clz(np);
 #pragma unroll
-        for (int l = 0; l < L; ++l) {
-            {
+            for (int l = 0; l < L; ++l) {
                 const int lvl = l + 1;
                 const int c = i >> (lnp - lvl);   // node index at lvl
                 const int q = (1 << (lvl - 1)) - 1 + (c >> 1);
@@ -160,6 +157,47 @@ __device__ __forceinline__ cpx<T> apply_T(const Plan& p, const LayerRegs<T, B, R
     return y;
 }
 
+// State carried between the 2n-1 layer steps of one sweep.
+template <typename T>
+struct SweepState {
+    const c128* f;
+    c128* u;
+    cpx<T>* w;
+    const cpx<T>* cp;
+    cpx<T> carry;      // forward: w_{m-1}; backward: u_{m+1}
+};
+
+// Step s of the sweep: s < n is forward layer m = s, otherwise backward
+// layer m = 2n-2-s.
+template <typename T, int B, int R, int L>
+__device__ __forceinline__ void sweep_step(const Plan& p, int s, const LayerRegs<T, B, R, L>& g,
+                                           SweepState<T>& st, const SweepShared<T>& sh) {
+    const int n = p.n, np = p.np;
+    const int i = threadIdx.x;
+    const bool row = i < np, real_row = i < n;
+    if (s < n) {
+        const int m = s;
+        cpx<T> x = czero<T>();
+        if (real_row) x = ccast<T>(st.f[(size_t)m * n + i]);
+        if (m > 0 && row) x -= st.cp[(size_t)(m - 1) * np + i] * st.carry;
+        cpx<T> y = apply_T<T, B, R, L>(p, g, x, sh);
+        if (row) st.w[(size_t)m * np + i] = y;
+        st.carry = y;
+        if (m == n - 1 && real_row) st.u[(size_t)m * n + i] = ccast<double>(y);
+    } else {
+        const int m = 2 * n - 2 - s;
+        cpx<T> x = czero<T>();
+        if (row) x = st.cp[(size_t)m * np + i] * st.carry;
+        cpx<T> y = apply_T<T, B, R, L>(p, g, x, sh);
+        cpx<T> um = czero<T>();
+        if (row) um = st.w[(size_t)m * np + i] - y;
+        if (real_row) st.u[(size_t)m * n + i] = ccast<double>(um);
+        st.carry = um;
+    }
+}
+
+__device__ __forceinline__ int layer_of_step(int s, int n) { return s < n ? s : 2 * n - 2 - s; }
+
 template <typename T, int B, int R, int L, int NTHR>
 __global__ __launch_bounds__(NTHR) void sweep_kernel(Plan p, SweepArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -167,79 +205,47 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(Plan p, SweepArgs<T> a) {
     const int rhs = blockIdx.x;
     const int i = threadIdx.x;
     const size_t N = (size_t)n * n;
-    const c128* f = a.f + rhs * N;
-    c128* u = a.u + rhs * N;
+    SweepState<T> st;
+    st.f = a.f + rhs * N;
+    st.u = a.u + rhs * N;
+    st.w = a.w + (size_t)rhs * n * np;
+    st.cp = a.cp;
+    st.carry = czero<T>();
     if (a.active && !a.active[rhs]) {
-        for (size_t e = i; e < N; e += blockDim.x) u[e] = czero<double>();
+        for (size_t e = i; e < N; e += blockDim.x) st.u[e] = czero<double>();
         return;
     }
     SweepShared<T> sh;
     cpx<T>* base = (cpx<T>*)smem;
     sh.xs = base;
-    sh.part = sh.xs + np;
-    sh.gs = sh.part + (size_t)L * R * (np / Chunk<B, R>::CH);
+    sh.gs = sh.xs + np;
     sh.zs = sh.gs + (size_t)((1 << (L + 1)) - 1) * R;
-    cpx<T>* w = a.w + (size_t)rhs * n * np;
-    const bool row = i < np;
-    const bool real_row = i < n;
+    const int steps = 2 * n - 1;
     // Double buffering when two layers of register tiles fit the registers a
     // thread has at this block size (512 per SIMD lane shared by the waves).
     constexpr int FOOT = (B + 2 * (L > 0 ? L : 1) * R + 2 * R) * (int)(2 * sizeof(T) / 4);
     constexpr int BUDGET = 131072 / NTHR < 512 ? 131072 / NTHR : 512;
     constexpr bool DB = 2 * FOOT + 48 <= BUDGET;
-    LayerRegs<T, B, R, L> cur, nxt;
-    if constexpr (DB) load_layer<T, B, R, L>(p, a.fac, cur);
-    cpx<T> prev = czero<T>();
-    for (int m = 0; m < n; ++m) {
-        if constexpr (DB) {
-            // next layer of the forward loop, or the first layer of the backward loop
-            const int mn = (m + 1 < n) ? m + 1 : n - 2;
-            load_layer<T, B, R, L>(p, a.fac + (size_t)mn * p.eLayer, nxt);
-        } else {
-            load_layer<T, B, R, L>(p, a.fac + (size_t)m * p.eLayer, cur);
+    if constexpr (DB) {
+        // two register sets used alternately: no copies between steps
+        LayerRegs<T, B, R, L> ga, gb;
+        load_layer<T, B, R, L>(p, a.fac, ga);
+        for (int s = 0; s < steps; s += 2) {
+            if (s + 1 < steps) load_layer<T, B, R, L>(p, a.fac + (size_t)layer_of_step(s + 1, n) * p.eLayer, gb);
+            sweep_step<T, B, R, L>(p, s, ga, st, sh);
+            if (s + 1 < steps) {
+                if (s + 2 < steps) load_layer<T, B, R, L>(p, a.fac + (size_t)layer_of_step(s + 2, n) * p.eLayer, ga);
+                sweep_step<T, B, R, L>(p, s + 1, gb, st, sh);
+            }
         }
-        cpx<T> x = czero<T>();
-        if (real_row) x = ccast<T>(f[(size_t)m * n + i]);
-        if (m > 0 && row) x -= a.cp[(size_t)(m - 1) * np + i] * prev;
-        cpx<T> y = apply_T<T, B, R, L>(p, cur, x, sh);
-        if (row) w[(size_t)m * np + i] = y;
-        prev = y;
-        if constexpr (DB) cur = nxt;
-    }
-    cpx<T> next = prev;
-    if (real_row) u[(size_t)(n - 1) * n + i] = ccast<double>(next);
-    for (int m = n - 2; m >= 0; --m) {
-        if constexpr (DB) {
-            if (m >= 1) load_layer<T, B, R, L>(p, a.fac + (size_t)(m - 1) * p.eLayer, nxt);
-        } else {
-            load_layer<T, B, R, L>(p, a.fac + (size_t)m * p.eLayer, cur);
+    } else {
+        LayerRegs<T, B, R, L> g;
+        for (int s = 0; s < steps; ++s) {
+            load_layer<T, B, R, L>(p, a.fac + (size_t)layer_of_step(s, n) * p.eLayer, g);
+            sweep_step<T, B, R, L>(p, s, g, st, sh);
         }
-        cpx<T> x = czero<T>();
-        if (row) x = a.cp[(size_t)m * np + i] * next;
-        cpx<T> y = apply_T<T, B, R, L>(p, cur, x, sh);
-        cpx<T> um = czero<T>();
-        if (row) um = w[(size_t)m * np + i] - y;
-        if (real_row) u[(size_t)m * n + i] = ccast<double>(um);
-        next = um;
-        if constexpr (DB) cur = nxt;
     }
 }
-
-template <typename T, int B, int R>
-void launch_one(const Plan& p, const SweepArgs<T>& a, size_t lds, int threads, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        hipFuncAttributes fa;
-        if (hipFuncGetAttributes(&fa, (const void*)sweep_kernel<T, B, R>) == hipSuccess)
-            (void)hipFuncSetAttribute((const void*)sweep_kernel<T, B, R>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      160 * 1024 - (int)fa.sharedSizeBytes);
-        (void)hipGetLastError();
-        attr = true;
-    }
-    hipLaunchKernelGGL((sweep_kernel<T, B, R>), dim3(a.nrhs), dim3(threads), lds, s, p, a);
-}
-
 
 // Launch one instantiation; the block has max(64, n_p, core rows) threads,
 // rounded to whole wavefronts (NTHR is its upper bound).
