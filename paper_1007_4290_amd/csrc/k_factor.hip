@@ -27,6 +27,7 @@
 //                      children's G, then P_c = T_c Q_c and G_c = Q_c^t P_c.
 //   wood_kernel(0)     the root core X_0.
 #include "internal.hpp"
+#include "wave_ops.hpp"
 
 namespace {
 
@@ -318,251 +319,439 @@ __device__ __forceinline__ void leaf_job(const Plan& p, const StepPtrs<T>& sp, i
 }
 
 // ----------------------------------------------------------------------------
-// Wave-level helpers.
+// Wavefront routines of the recompression.  One wavefront owns a problem; its
+// 64 lanes form groups of G consecutive lanes (G a power of two), one group
+// per column (or column pair), and lane g of a group handles the rows g,
+// g + G, g + 2G, ...  Column sums are butterflies inside the group (DPP lane
+// moves).  In the QR and in the application of Q each lane keeps its rows in
+// registers (the first RROWS of them; further rows stay in LDS and are
+// streamed in chunks), so the only LDS traffic of a step is the reflector,
+// which every group reads at the same addresses (broadcast, no conflicts).
+// Pointers are cast to the LDS address space so that every access is a ds_*
+// instruction; loads use clamped indices and selects instead of per-row
+// branches, and the group geometry is kept in scalar registers.
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+template <typename X> using lds = __attribute__((address_space(3))) X;
+template <typename X> __device__ __forceinline__ lds<X>* to_lds(X* p) { return (lds<X>*)p; }
+template <typename X> __device__ __forceinline__ lds<X>* to_lds(const X* p) { return (lds<X>*)const_cast<X*>(p); }
+template <typename T> __device__ __forceinline__ cpx<T> ldc(const lds<cpx<T>>* p) { return mk<T>(p->re, p->im); }
+template <typename T> __device__ __forceinline__ void stc(lds<cpx<T>>* p, cpx<T> v) { p->re = v.re; p->im = v.im; }
+
+constexpr int RROWS = 32;   // rows per lane held in registers
+constexpr int CHUNK = 8;    // rows per lane per chunk of LDS-resident rows
+
+// Lane geometry for groups of G = 64 / 2^ceil(log2(ngroups)) lanes.
+struct Groups {
+    int lgG, G;   // log2 of the group size, group size (wave-uniform)
+    int id, g;    // group index and lane within the group
+};
+__device__ __forceinline__ Groups make_groups(int ngroups) {
+    Groups q;
+    const int lgn = ngroups > 1 ? 32 - __clz(ngroups - 1) : 0;     // ceil(log2(ngroups))
+    q.lgG = __builtin_amdgcn_readfirstlane(6 - lgn);
+    q.G = 1 << q.lgG;
+    const int lane = threadIdx.x & 63;
+    q.id = lane >> q.lgG;
+    q.g = lane & (q.G - 1);
+    return q;
+}
+// rows g, g + G, ... below s: count for lane g, and for lane 0 (wave-uniform)
+__device__ __forceinline__ int lane_rows(int s, const Groups& q) { return q.g < s ? ((s - 1 - q.g) >> q.lgG) + 1 : 0; }
+__device__ __forceinline__ int max_rows(int s, const Groups& q) {
+    return __builtin_amdgcn_readfirstlane((s + q.G - 1) >> q.lgG);
 }
 
-// Householder QR with column pivoting of the s x k column-major matrix A in
-// LDS, run by one wavefront.  Hermitian reflectors H_j = I - tau_j v_j v_j^H,
-// v_j = (v0_j, A[j+1:, j]); on exit A's upper triangle holds R (diagonal
-// beta_j), perm[c] is the original index of column c, and
-// A_in[:, perm] = H_0 ... H_{kr-1} R.  The factorization stops at step kr
-// when every remaining column norm is below delta times the largest initial
-// column norm (the dropped trailing block is that small).
-template <typename T>
-__device__ int wave_qrcp(cpx<T>* A, int s, int k, int* perm, cpx<T>* v0, T* tau, T* nrm, T* nref,
-                         cpx<T>* part, cpx<T>* dots, T delta) {
+// Householder QR with column pivoting of the s x k column-major matrix A
+// (leading dimension lda, k <= 64) in LDS, by one wavefront.  Columns stay in
+// place: step j takes the remaining column p = perm[j] of largest norm, and
+// the Hermitian reflector H_j = I - tau_j v_j v_j^H with
+// v_j = (v0[j], A[j+1:, p]) maps it to beta_j e_j, stored in A[j, p].  Row j
+// of every column not yet chosen then holds row j of R; pos[c] is the step at
+// which column c was chosen (k if never), so R Pi^t has entry (j, c) equal to
+// A[j, c] when j <= pos[c] and 0 otherwise.  Column norms are recomputed
+// exactly from the updated rows at every step (no downdating).  The
+// factorization stops at step kr when every remaining column norm is at most
+// delta times the largest initial one.
+template <typename T, int NR>
+__device__ __forceinline__ int wave_qrcp_n(cpx<T>* Ag, int lda, int s, int k, int* permg, int* posg, cpx<T>* v0g,
+                                           T* taug, T delta) {
+    lds<cpx<T>>* A = to_lds(Ag);
+    lds<int>* perm = to_lds(permg);
+    lds<int>* pos = to_lds(posg);
+    lds<cpx<T>>* v0 = to_lds(v0g);
+    lds<T>* tau = to_lds(taug);
     const int lane = threadIdx.x & 63;
-    for (int c = lane; c < k; c += 64) {
-        T acc = T(0);
-        for (int i = 0; i < s; ++i) acc += abs2(A[(size_t)c * s + i]);
-        nrm[c] = acc;
-        nref[c] = acc;
-        perm[c] = c;
+    const Groups gq = make_groups(k);
+    const int G = gq.G, c = gq.id, g = gq.g;
+    const bool col = c < k;
+    lds<cpx<T>>* Ac = A + (size_t)(col ? c : 0) * lda;
+    const int nrl = col ? lane_rows(s, gq) : 0;
+    const int nmax = max_rows(s, gq);
+    cpx<T> a[NR];
+    T acc = T(0);
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        const int i = g + G * u;
+        a[u] = ldc(Ac + (i < s ? i : s - 1));
     }
-    wave_sync();
-    T mx = T(0);
-    for (int c = lane; c < k; c += 64) mx = nrm[c] > mx ? nrm[c] : mx;
-    for (int off = 32; off > 0; off >>= 1) {
-        T o = __shfl_xor(mx, off, 64);
-        mx = o > mx ? o : mx;
+    __builtin_amdgcn_sched_barrier(0);        // all loads in flight before the first use
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        a[u] = u < nrl ? a[u] : czero<T>();
+        acc += abs2(a[u]);
     }
+    for (int u0 = NR; u0 < nmax; u0 += CHUNK) {
+#pragma unroll
+        for (int u = 0; u < CHUNK; ++u) {
+            const int i = g + G * (u0 + u);
+            const cpx<T> x = ldc(Ac + (i < s ? i : s - 1));
+            acc += u0 + u < nrl ? abs2(x) : T(0);
+        }
+    }
+    T nrm = wops::gsum(acc, G);
+    T mx = col ? nrm : T(0);
+    int unused = lane;
+    wops::argmax(mx, unused);
     const T stop = delta * delta * mx;
+    bool chosen = !col;
     const int kk = s < k ? s : k;
     int kr = kk;
     for (int j = 0; j < kk; ++j) {
-        // pivot: the remaining column of largest norm (ties -> lowest index)
-        T best = T(-1);
-        int bi = j;
-        for (int c = j + lane; c < k; c += 64)
-            if (nrm[c] > best) { best = nrm[c]; bi = c; }
-        for (int off = 32; off > 0; off >>= 1) {
-            T ob = __shfl_xor(best, off, 64);
-            int oi = __shfl_xor(bi, off, 64);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        if (!(best > stop)) { kr = j; break; }
-        if (bi != j) {
-            for (int i = lane; i < s; i += 64) {
-                cpx<T> a = A[(size_t)j * s + i];
-                A[(size_t)j * s + i] = A[(size_t)bi * s + i];
-                A[(size_t)bi * s + i] = a;
-            }
-            if (lane == 0) {
-                T tn = nrm[j]; nrm[j] = nrm[bi]; nrm[bi] = tn;
-                tn = nref[j]; nref[j] = nref[bi]; nref[bi] = tn;
-                int tp = perm[j]; perm[j] = perm[bi]; perm[bi] = tp;
-            }
-            wave_sync();
-        }
-        T pr = T(0);
-        for (int i = j + lane; i < s; i += 64) pr += abs2(A[(size_t)j * s + i]);
-        const T nx2 = wave_sum(pr);
-        const cpx<T> x0 = A[(size_t)j * s + j];
-        const T nx = rsq(nx2), ax0 = rsq(abs2(x0));
-        const cpx<T> ph = ax0 > T(0) ? (T(1) / ax0) * x0 : mk<T>(T(1), T(0));
-        const cpx<T> vv0 = (ax0 + nx) * ph;
-        const T tj = nx > T(0) ? T(1) / (nx * (nx + ax0)) : T(0);
-        // dots[c] = v^H A[j:, c] for the columns right of j
-        const int nc = k - j - 1;
-        if (nc > 0) {
-            int nph = 64 / nc;
-            if (nph < 1) nph = 1;
-            for (int task = lane; task < nc * nph; task += 64) {
-                const int c = j + 1 + task % nc, ph2 = task / nc;
-                cpx<T> acc = czero<T>();
-                for (int i = j + ph2; i < s; i += nph) {
-                    cpx<T> vi = (i == j) ? vv0 : A[(size_t)j * s + i];
-                    cfma_conj(acc, vi, A[(size_t)c * s + i]);
-                }
-                part[task] = acc;
-            }
-            wave_sync();
-            for (int c = lane; c < nc; c += 64) {
-                cpx<T> acc = czero<T>();
-                for (int q = 0; q < nph; ++q) acc += part[q * nc + c];
-                dots[c] = acc;
-            }
-            wave_sync();
-            // rank-1 update over all (row, column) pairs, spread across the lanes
-            const int nrw = s - j;
-            for (int e = lane; e < nrw * nc; e += 64) {
-                const int i = j + e % nrw, c = e / nrw;
-                const cpx<T> vi = (i == j) ? vv0 : A[(size_t)j * s + i];
-                A[(size_t)(j + 1 + c) * s + i] -= (tj * vi) * dots[c];
-            }
-            wave_sync();
-        }
-        if (lane == 0) {
-            A[(size_t)j * s + j] = -nx * ph;
-            v0[j] = vv0;
-            tau[j] = tj;
-        }
-        // downdate the remaining column norms by the new row j of R
-        for (int c = j + 1 + lane; c < k; c += 64) {
-            T v = nrm[c] - abs2(A[(size_t)c * s + j]);
-            if (v < T(1e-2) * nref[c]) {
-                v = T(0);
-                for (int i = j + 1; i < s; ++i) v += abs2(A[(size_t)c * s + i]);
-                nref[c] = v;
-            }
-            nrm[c] = v > T(0) ? v : T(0);
+        T key = chosen ? T(-1) : nrm;
+        int p = c;
+        wops::argmax(key, p);
+        if (!(key > stop)) { kr = j; break; }
+        // the pivot group publishes its register rows (rows beyond them are in LDS already)
+        if (c == p) {
+#pragma unroll
+            for (int u = 0; u < NR; ++u)
+                if (u < nrl) stc(Ac + (g + G * u), a[u]);
         }
         wave_sync();
+        lds<cpx<T>>* Ap = A + (size_t)p * lda;
+        const cpx<T> x0 = ldc(Ap + j);
+        const T nx = sqrt(key), ax0 = sqrt(abs2(x0));
+        const cpx<T> ph = ax0 > T(0) ? (T(1) / ax0) * x0 : mk<T>(T(1), T(0));
+        const cpx<T> vv0 = (ax0 + nx) * ph;
+        const T tj = T(1) / (nx * (nx + ax0));
+        const bool act = !chosen && c != p;
+        const int n_act = act ? nrl : 0;
+        // reflector entries of this lane's rows: zero above row j, past the
+        // column and on lanes that do not update
+        cpx<T> d = czero<T>();
+        cpx<T> v[NR];
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int i = g + G * u;
+            v[u] = ldc(Ap + (i < s ? i : s - 1));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int i = g + G * u;
+            v[u] = (u < n_act && i >= j) ? (i == j ? vv0 : v[u]) : czero<T>();
+            cfma_conj(d, v[u], a[u]);
+        }
+        for (int u0 = NR; u0 < nmax; u0 += CHUNK) {
+#pragma unroll
+            for (int u = 0; u < CHUNK; ++u) {
+                const int i = g + G * (u0 + u);
+                const int ic = i < s ? i : s - 1;
+                const cpx<T> lv = ldc(Ap + ic), x = ldc(Ac + ic);
+                const bool in = u0 + u < n_act && i >= j;
+                cfma_conj(d, in ? (i == j ? vv0 : lv) : czero<T>(), x);
+            }
+        }
+        d = wops::gsum(d, G);
+        const cpx<T> td = tj * d;
+        T nn = T(0);
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int i = g + G * u;
+            a[u] -= v[u] * td;
+            nn += i > j ? abs2(a[u]) : T(0);
+        }
+        for (int u0 = NR; u0 < nmax; u0 += CHUNK) {
+            cpx<T> an[CHUNK];
+#pragma unroll
+            for (int u = 0; u < CHUNK; ++u) {
+                const int i = g + G * (u0 + u);
+                const int ic = i < s ? i : s - 1;
+                const cpx<T> lv = ldc(Ap + ic), x = ldc(Ac + ic);
+                an[u] = x - (i == j ? vv0 : lv) * td;
+            }
+#pragma unroll
+            for (int u = 0; u < CHUNK; ++u) {
+                const int i = g + G * (u0 + u);
+                if (u0 + u < n_act && i >= j) {
+                    stc(Ac + i, an[u]);
+                    if (i > j) nn += abs2(an[u]);
+                }
+            }
+        }
+        nn = wops::gsum(nn, G);
+        if (act) nrm = nn;
+        if (c == p && g == (j & (G - 1))) stc(Ap + j, -nx * ph);
+        if (lane == 0) {
+            stc(v0 + j, vv0);
+            tau[j] = tj;
+            perm[j] = p;
+            pos[p] = j;
+        }
+        if (c == p) chosen = true;
+        wave_sync();
     }
+    // columns never chosen: rows < kr hold R, the rest the dropped remainder
+    if (!chosen) {
+#pragma unroll
+        for (int u = 0; u < NR; ++u)
+            if (u < nrl) stc(Ac + (g + G * u), a[u]);
+        if (g == 0) pos[c] = k;
+    }
+    wave_sync();
     return kr;
 }
 
-// Y <- H_0 ... H_{kr-1} Y for the reflectors of wave_qrcp (Y: s x ncol,
-// column-major), run by one wavefront.
+// Rows per lane held in registers: 4, 16 or 32 (beyond 32 they are streamed).
 template <typename T>
-__device__ void wave_apply_q(const cpx<T>* A, int s, int kr, const cpx<T>* v0, const T* tau, cpx<T>* Y, int ncol,
-                             cpx<T>* part, cpx<T>* dots) {
-    const int lane = threadIdx.x & 63;
-    if (ncol <= 0) return;
-    int nph = 64 / ncol;
-    if (nph < 1) nph = 1;
-    for (int j = kr - 1; j >= 0; --j) {
-        const T tj = tau[j];
-        if (tj == T(0)) continue;
-        const cpx<T> vv0 = v0[j];
-        for (int task = lane; task < ncol * nph; task += 64) {
-            const int c = task % ncol, ph2 = task / ncol;
-            cpx<T> acc = czero<T>();
-            for (int i = j + ph2; i < s; i += nph) {
-                cpx<T> vi = (i == j) ? vv0 : A[(size_t)j * s + i];
-                cfma_conj(acc, vi, Y[(size_t)c * s + i]);
-            }
-            part[task] = acc;
-        }
-        wave_sync();
-        for (int c = lane; c < ncol; c += 64) {
-            cpx<T> acc = czero<T>();
-            for (int q = 0; q < nph; ++q) acc += part[q * ncol + c];
-            dots[c] = acc;
-        }
-        wave_sync();
-        const int nrw = s - j;
-        for (int e = lane; e < nrw * ncol; e += 64) {
-            const int i = j + e % nrw, c = e / nrw;
-            const cpx<T> vi = (i == j) ? vv0 : A[(size_t)j * s + i];
-            Y[(size_t)c * s + i] -= (tj * vi) * dots[c];
-        }
-        wave_sync();
-    }
+__device__ __forceinline__ int wave_qrcp(cpx<T>* A, int lda, int s, int k, int* perm, int* pos, cpx<T>* v0, T* tau,
+                                         T delta) {
+    const int nmax = max_rows(s, make_groups(k));
+    if (nmax <= 4) return wave_qrcp_n<T, 4>(A, lda, s, k, perm, pos, v0, tau, delta);
+    if (nmax <= 16) return wave_qrcp_n<T, 16>(A, lda, s, k, perm, pos, v0, tau, delta);
+    return wave_qrcp_n<T, RROWS>(A, lda, s, k, perm, pos, v0, tau, delta);
 }
 
-// One-sided Jacobi SVD (FP64) of the nr x P column-major matrix N in LDS
-// (P even; zero padding columns allowed) by the whole workgroup.  Rotations
-// of a round act on disjoint column pairs (round-robin ordering); J
-// accumulates them so that N_in J = N_out, whose columns are mutually
-// orthogonal.  A pair is rotated when |a^H b| > thr sqrt(|a|^2 |b|^2) and
-// both columns are above the negligible level; sweeps stop when none is.
-__device__ void jacobi_svd64(c128* N, int nr, c128* J, int P, int* flag, double* fro /* [NT/64] */) {
-    const int npair = P / 2;
-    // 8 lanes per pair: three shuffle steps per reduction, rows strided by 8
-    const int gsz = 8;
-    const int grp = threadIdx.x / gsz, gl = threadIdx.x % gsz;
-    // a pair counts as orthogonal below this cosine; far below the relative
-    // truncation thresholds used (the singular values are then accurate to
-    // about thr * sigma_1)
-    const double thr = 1.0e-12;
-    for (int e = threadIdx.x; e < P * P; e += NT) J[e] = (e % P == e / P) ? mk(1.0, 0.0) : czero<double>();
-    {
-        double f = 0.0;
-        for (int e = threadIdx.x; e < nr * P; e += NT) f += abs2(N[e]);
-        for (int off = 32; off > 0; off >>= 1) f += __shfl_xor(f, off, 64);
-        if ((threadIdx.x & 63) == 0) fro[threadIdx.x >> 6] = f;   // fixed-order sum below
-        __syncthreads();
+// Y <- H_0 ... H_{kr-1} Y for the reflectors left in A by wave_qrcp (Y: s x
+// ncol column-major, leading dimension ldy, ncol <= 64), by one wavefront.
+template <typename T, int NR>
+__device__ __forceinline__ void wave_apply_q_n(const cpx<T>* Ag, int lda, int s, int kr, const int* permg,
+                                               const cpx<T>* v0g, const T* taug, cpx<T>* Yg, int ldy, int ncol) {
+    lds<cpx<T>>* A = to_lds(Ag);
+    lds<int>* perm = to_lds(permg);
+    lds<cpx<T>>* v0 = to_lds(v0g);
+    lds<T>* tau = to_lds(taug);
+    const Groups gq = make_groups(ncol);
+    const int G = gq.G, c = gq.id, g = gq.g;
+    const bool act = c < ncol;
+    lds<cpx<T>>* Yc = to_lds(Yg) + (size_t)(act ? c : 0) * ldy;
+    const int nrl = act ? lane_rows(s, gq) : 0;
+    const int nmax = max_rows(s, gq);
+    cpx<T> y[NR];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        const int i = g + G * u;
+        y[u] = ldc(Yc + (i < s ? i : s - 1));
     }
-    const double tiny = (fro[0] + fro[1] + fro[2] + fro[3]) * 1e-30 + 1e-300;
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        if (threadIdx.x == 0) *flag = 0;
-        __syncthreads();
-        for (int rd = 0; rd < P - 1; ++rd) {
-            if (grp < npair) {
-                int a, b;
-                if (grp == 0) { a = rd; b = P - 1; }
-                else { a = (rd + grp) % (P - 1); b = (rd - grp + P - 1) % (P - 1); }
-                c128* ca = N + (size_t)a * nr;
-                c128* cb = N + (size_t)b * nr;
-                double al = 0.0, be = 0.0;
-                c128 ga = czero<double>();
-                for (int i = gl; i < nr; i += gsz) {
-                    al += abs2(ca[i]);
-                    be += abs2(cb[i]);
-                    cfma_conj(ga, ca[i], cb[i]);
-                }
-                for (int off = 1; off < gsz; off <<= 1) {
-                    al += __shfl_xor(al, off, gsz);
-                    be += __shfl_xor(be, off, gsz);
-                    ga.re += __shfl_xor(ga.re, off, gsz);
-                    ga.im += __shfl_xor(ga.im, off, gsz);
-                }
-                const double ag2 = abs2(ga);
-                if (al > tiny && be > tiny && ag2 > thr * thr * al * be) {
-                    const double iag = rsqrt(ag2);                  // 1 / |gamma|
-                    const double zeta = 0.5 * (be - al) * iag;
-                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = rsqrt(1.0 + t * t);
-                    const double sn = c * t;
-                    const c128 em = iag * conj(ga);                 // e^{-i phi}
-                    for (int i = gl; i < nr; i += gsz) {
-                        const c128 xa = ca[i], xb = em * cb[i];
-                        ca[i] = c * xa - sn * xb;
-                        cb[i] = sn * xa + c * xb;
-                    }
-                    c128* ja = J + (size_t)a * P;
-                    c128* jb = J + (size_t)b * P;
-                    for (int i = gl; i < P; i += gsz) {
-                        const c128 ya = ja[i], yb = em * jb[i];
-                        ja[i] = c * ya - sn * yb;
-                        jb[i] = sn * ya + c * yb;
-                    }
-                    if (gl == 0) *flag = 1;
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < NR; ++u) y[u] = u < nrl ? y[u] : czero<T>();
+    for (int j = kr - 1; j >= 0; --j) {
+        const T tj = tau[j];
+        lds<cpx<T>>* Ap = A + (size_t)perm[j] * lda;
+        const cpx<T> vv0 = ldc(v0 + j);
+        cpx<T> d = czero<T>();
+        cpx<T> v[NR];
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int i = g + G * u;
+            v[u] = ldc(Ap + (i < s ? i : s - 1));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int i = g + G * u;
+            v[u] = (u < nrl && i >= j) ? (i == j ? vv0 : v[u]) : czero<T>();
+            cfma_conj(d, v[u], y[u]);
+        }
+        for (int u0 = NR; u0 < nmax; u0 += CHUNK) {
+#pragma unroll
+            for (int u = 0; u < CHUNK; ++u) {
+                const int i = g + G * (u0 + u);
+                const int ic = i < s ? i : s - 1;
+                const cpx<T> lv = ldc(Ap + ic), x = ldc(Yc + ic);
+                const bool in = u0 + u < nrl && i >= j;
+                cfma_conj(d, in ? (i == j ? vv0 : lv) : czero<T>(), x);
+            }
+        }
+        d = wops::gsum(d, G);
+        const cpx<T> td = tj * d;
+#pragma unroll
+        for (int u = 0; u < NR; ++u) y[u] -= v[u] * td;
+        for (int u0 = NR; u0 < nmax; u0 += CHUNK) {
+            cpx<T> yn[CHUNK];
+#pragma unroll
+            for (int u = 0; u < CHUNK; ++u) {
+                const int i = g + G * (u0 + u);
+                const int ic = i < s ? i : s - 1;
+                const cpx<T> lv = ldc(Ap + ic), x = ldc(Yc + ic);
+                yn[u] = x - (i == j ? vv0 : lv) * td;
+            }
+#pragma unroll
+            for (int u = 0; u < CHUNK; ++u) {
+                const int i = g + G * (u0 + u);
+                if (u0 + u < nrl && i >= j) stc(Yc + i, yn[u]);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NR; ++u)
+        if (u < nrl) stc(Yc + (g + G * u), y[u]);
+    wave_sync();
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_apply_q(const cpx<T>* A, int lda, int s, int kr, const int* perm,
+                                             const cpx<T>* v0, const T* tau, cpx<T>* Y, int ldy, int ncol) {
+    if (ncol <= 0) return;
+    const int nmax = max_rows(s, make_groups(ncol));
+    if (nmax <= 4) wave_apply_q_n<T, 4>(A, lda, s, kr, perm, v0, tau, Y, ldy, ncol);
+    else if (nmax <= 16) wave_apply_q_n<T, 16>(A, lda, s, kr, perm, v0, tau, Y, ldy, ncol);
+    else wave_apply_q_n<T, RROWS>(A, lda, s, kr, perm, v0, tau, Y, ldy, ncol);
+}
+
+// One-sided Jacobi SVD by one wavefront of the P columns of N in LDS (P even,
+// P <= 64; zero columns allowed).  The rotations of a round act on disjoint
+// column pairs (round-robin order), one lane group of G lanes per pair.  N
+// (nr rows) and J (P rows) are stored with NR * G rows per column, the rows
+// past nr (past P for J) zero, so every lane loads and stores exactly NR rows
+// of each column without predicates; a pair that needs no rotation applies the
+// identity.  A pair is rotated when |a^H b| > thr |a| |b| and both columns are
+// above the negligible level tiny (squared norm); sweeps stop when no pair is.
+// J (column-major, leading dimension NR * G) starts as the identity and
+// accumulates the rotations, so that N_in J = N_out with mutually orthogonal
+// columns; nrm2[c] is the squared norm of column c.
+// Reciprocal and reciprocal square root for the rotation parameters: the
+// hardware approximations (about 1 ulp) in single precision, correctly
+// rounded operations in double precision.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double fast_rsq(double x) { return 1.0 / sqrt(x); }
+
+template <typename CT, int NR>
+__device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, CT* nrm2g, CT thr, CT tiny,
+                                              int max_sweeps) {
+    lds<cpx<CT>>* N = to_lds(Ng);
+    lds<cpx<CT>>* J = to_lds(Jg);
+    lds<CT>* nrm2 = to_lds(nrm2g);
+    const int lane = threadIdx.x & 63;
+    const int npair = P / 2;
+    const Groups gq = make_groups(npair);
+    const int G = gq.G, q = gq.id, g = gq.g;
+    const int ld = NR * G;
+    const bool act = q < npair;
+    for (int e = lane; e < ld * P; e += 64) {
+        const int r = e % ld;
+        stc(J + e, r == e / ld ? mk<CT>(CT(1), CT(0)) : czero<CT>());
+    }
+    wave_sync();
+    const int P1 = P - 1;
+    for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
+        const bool last = sweep == max_sweeps;
+        bool rot = false;
+        for (int rd = 0; rd < P1; ++rd) {
+            // round-robin pairs: (rd, P-1) and ((rd + q) mod (P-1), (rd - q) mod (P-1))
+            int a = rd + q, b = rd - q + P1;
+            a = a >= P1 ? a - P1 : a;
+            b = b >= P1 ? b - P1 : b;
+            if (q == 0) { a = rd; b = P1; }
+            if (!act) { a = 0; b = 0; }
+            lds<cpx<CT>>* ca = N + (size_t)a * ld + g;
+            lds<cpx<CT>>* cb = N + (size_t)b * ld + g;
+            lds<cpx<CT>>* ja = J + (size_t)a * ld + g;
+            lds<cpx<CT>>* jb = J + (size_t)b * ld + g;
+            cpx<CT> xa[NR], xb[NR], ya[NR], yb[NR];
+#pragma unroll
+            for (int u = 0; u < NR; ++u) {
+                xa[u] = ldc(ca + G * u);
+                xb[u] = ldc(cb + G * u);
+                ya[u] = ldc(ja + G * u);
+                yb[u] = ldc(jb + G * u);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            CT al = CT(0), be = CT(0);
+            cpx<CT> ga = czero<CT>();
+#pragma unroll
+            for (int u = 0; u < NR; ++u) {
+                al += abs2(xa[u]);
+                be += abs2(xb[u]);
+                cfma_conj(ga, xa[u], xb[u]);
+            }
+            al = wops::gsum(al, G);
+            be = wops::gsum(be, G);
+            ga = wops::gsum(ga, G);
+            const CT ag2 = abs2(ga);
+            const bool doit = !last && act && al > tiny && be > tiny && ag2 > thr * thr * al * be;
+            // rotation (identity when the pair is left alone)
+            const CT iag = doit ? fast_rsq(ag2) : CT(0);              // 1 / |gamma|
+            const CT zeta = CT(0.5) * (be - al) * iag;
+            const CT tm = fast_rcp(fabs(zeta) + sqrt(CT(1) + zeta * zeta));
+            const CT t = doit ? (zeta >= CT(0) ? tm : -tm) : CT(0);
+            const CT cs = fast_rsq(CT(1) + t * t);
+            const CT sn = cs * t;
+            const cpx<CT> em = doit ? iag * conj(ga) : mk<CT>(CT(1), CT(0));   // e^{-i phi}
+            if (act && !last) {
+#pragma unroll
+                for (int u = 0; u < NR; ++u) {
+                    const cpx<CT> x2 = em * xb[u], y2 = em * yb[u];
+                    stc(ca + G * u, cs * xa[u] - sn * x2);
+                    stc(cb + G * u, sn * xa[u] + cs * x2);
+                    stc(ja + G * u, cs * ya[u] - sn * y2);
+                    stc(jb + G * u, sn * ya[u] + cs * y2);
                 }
             }
-            __syncthreads();
+            if (last && act && g == 0) {
+                nrm2[a] = al;
+                nrm2[b] = be;
+            }
+            rot = rot || doit;
+            wave_sync();
+            if (last) break;
         }
-        const int f = *flag;
-        __syncthreads();
-        if (!f) break;
+        if (last) break;
+        if (!__any(rot)) sweep = max_sweeps - 1;   // converged: one more pass for the norms
     }
+    wave_sync();
+}
+
+// Rows per lane (4, 8, 16 or 32) and leading dimension of N and J in the
+// Jacobi for P columns of at most nr rows.
+__host__ __device__ inline int jacobi_group(int P) {
+    int np2 = 1;
+    while (np2 < (P / 2 > 0 ? P / 2 : 1)) np2 <<= 1;
+    return 64 / np2;
+}
+__host__ __device__ inline int jacobi_rows(int nr, int P) {
+    const int G = jacobi_group(P);
+    const int need = ((nr > P ? nr : P) + G - 1) / G;
+    int r = 1;
+    while (r < need) r <<= 1;
+    return r;
+}
+__host__ __device__ inline int jacobi_ld(int nr, int P) { return jacobi_rows(nr, P) * jacobi_group(P); }
+
+template <typename CT>
+__device__ __forceinline__ void wave_jacobi(cpx<CT>* N, int P, int NRr, cpx<CT>* J, CT* nrm2, CT thr, CT tiny,
+                                            int max_sweeps) {
+    if (NRr == 1) wave_jacobi_n<CT, 1>(N, P, J, nrm2, thr, tiny, max_sweeps);
+    else if (NRr == 2) wave_jacobi_n<CT, 2>(N, P, J, nrm2, thr, tiny, max_sweeps);
+    else if (NRr == 4) wave_jacobi_n<CT, 4>(N, P, J, nrm2, thr, tiny, max_sweeps);
+    else if (NRr == 8) wave_jacobi_n<CT, 8>(N, P, J, nrm2, thr, tiny, max_sweeps);
+    else if (NRr == 16) wave_jacobi_n<CT, 16>(N, P, J, nrm2, thr, tiny, max_sweeps);
+    else wave_jacobi_n<CT, 32>(N, P, J, nrm2, thr, tiny, max_sweeps);
 }
 
 // ----------------------------------------------------------------------------
 // Recompression of the off-diagonal blocks of S_m.
 struct RecompLayout {
     int s, k, kk, r;
-    size_t oU, oV, oY1, oY2, oPartU, oPartV, oDotsU, oDotsV, oV0u, oV0v, oEnd;   // cpx<T> units
-    size_t dN, dJ, dEnd;                                                         // c128 units (after oEnd)
+    size_t oU, oV, oY1, oY2, oV0u, oV0v, oEnd;   // cpx<T> units
+    size_t dN, dJ, dS, dEnd;                     // cpx<CT> units (after oEnd)
 };
 
-__host__ __device__ inline RecompLayout recomp_layout(int s, int k, int r, int Xblocks, size_t elem) {
+// elem = sizeof(cpx<T>), celem = sizeof(cpx<CT>) of the core's type
+__host__ __device__ inline RecompLayout recomp_layout(int s, int k, int r, int Xblocks, size_t elem, size_t celem) {
     RecompLayout l;
     l.s = s; l.k = k; l.r = r;
     l.kk = s < k ? s : k;
@@ -571,33 +760,34 @@ __host__ __device__ inline RecompLayout recomp_layout(int s, int k, int r, int X
     l.oV = o; o += (size_t)s * k;
     l.oY1 = o; o += (size_t)s * r;
     l.oY2 = o; o += (size_t)s * r;
-    l.oPartU = o; o += 64;
-    l.oPartV = o; o += 64;
-    l.oDotsU = o; o += (k > r ? k : r);
-    l.oDotsV = o; o += (k > r ? k : r);
     l.oV0u = o; o += l.kk;
     l.oV0v = o; o += l.kk;
     o += (size_t)Xblocks;                  // staged X blocks
     l.oEnd = o;
-    // FP64 core (N: kk x P, J: P x P with P <= kk + 1), placed after the cpx<T> area
+    // core N (nr <= kk rows) and rotations J, both P columns of jacobi_ld(nr, P)
+    // entries (P <= kk + 1), then P squared norms
     size_t bytes = o * elem;
     bytes = (bytes + 15) / 16 * 16;
-    int P = l.kk + 1;
-    l.dN = bytes / sizeof(c128);
-    l.dJ = l.dN + (size_t)l.kk * P;
-    l.dEnd = l.dJ + (size_t)P * P;
+    size_t nj = 0;
+    for (int P = 2; P <= l.kk + 1; P += 2) {
+        const size_t e = (size_t)jacobi_ld(l.kk, P) * P;
+        nj = e > nj ? e : nj;
+    }
+    l.dN = bytes / celem;
+    l.dJ = l.dN + nj;
+    l.dS = l.dJ + nj;
+    l.dEnd = l.dS + (size_t)(l.kk + 2);
     return l;
 }
 
 template <typename T, int R>
 __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>& sp, int m, int pj,
                                                unsigned char* smem) {
-    __shared__ T tau_u[72], tau_v[72], nrm_u[72], nrm_v[72], nref_u[72], nref_v[72];
-    __shared__ int perm_u[72], perm_v[72], pinv_u[72], pinv_v[72];
-    __shared__ double sig[72];
+    using CT = T;                                // core SVD in the factor precision
+    __shared__ T tau_u[72], tau_v[72];
+    __shared__ int perm_u[72], perm_v[72], pos_u[72], pos_v[72];
     __shared__ int order[72];
-    __shared__ int flag, rank_s, kr_u, kr_v;
-    __shared__ double fro[NT / 64];
+    __shared__ int rank_s, kr_u, kr_v;
     const int lp = 31 - __clz(pj + 1);           // pj: heap id of the parent node
     const int j = pj - ((1 << lp) - 1);
     const int lam = lp + 1;
@@ -606,15 +796,16 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
     const int k = 1 + (m > 0 ? R * lam : 0);
     const int lo1 = 2 * j * s, lo2 = (2 * j + 1) * s;
     const int nX = m > 0 ? lam * R * R : 0;
-    RecompLayout ly = recomp_layout(s, k, R, nX, sizeof(cpx<T>));
+    RecompLayout ly = recomp_layout(s, k, R, nX, sizeof(cpx<T>), sizeof(cpx<CT>));
     cpx<T>* base = (cpx<T>*)smem;
     cpx<T>* Ut = base + ly.oU;
     cpx<T>* Vt = base + ly.oV;
     cpx<T>* Y1 = base + ly.oY1;
     cpx<T>* Y2 = base + ly.oY2;
     cpx<T>* Xs = base + ly.oEnd - nX;          // [blk][k1][k2]
-    c128* Nm = (c128*)smem + ly.dN;
-    c128* Jm = (c128*)smem + ly.dJ;
+    cpx<CT>* Nm = (cpx<CT>*)smem + ly.dN;
+    cpx<CT>* Jm = (cpx<CT>*)smem + ly.dJ;
+    CT* nrm2 = (CT*)((cpx<CT>*)smem + ly.dS);
     const int tid = threadIdx.x, wv = tid >> 6;
 
     // Stacked factors: S_m(c1, c2) = Ut Vt^t.
@@ -667,74 +858,74 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
     }
     __syncthreads();
 
-    // rank-revealing QR of both factors, one wavefront each, concurrently
-    // rank-revealing cut of the stacked factors: far below the truncation
-    // tolerance (none when nothing is truncated); in complex64 at the level
-    // of the factors' own rounding
+    // rank-revealing QR of both factors, one wavefront each, concurrently.
+    // The cut is far below the truncation tolerance (none when nothing is
+    // truncated); in complex64 at the level of the factors' own rounding.
     const T delta = p.tol <= 0.0 ? T(0) : (sizeof(T) == 4 ? T(4.0e-7) : T(1.0e-5 * p.tol < 1.0e-11 ? 1.0e-5 * p.tol : 1.0e-11));
-    if (wv == 0) {
-        int kr = wave_qrcp(Ut, s, k, perm_u, base + ly.oV0u, tau_u, nrm_u, nref_u, base + ly.oPartU,
-                           base + ly.oDotsU, delta);
-        if ((tid & 63) == 0) kr_u = kr;
-    } else if (wv == 1) {
-        int kr = wave_qrcp(Vt, s, k, perm_v, base + ly.oV0v, tau_v, nrm_v, nref_v, base + ly.oPartV,
-                           base + ly.oDotsV, delta);
-        if ((tid & 63) == 0) kr_v = kr;
+    if (wv < 2) {                               // one call site: wave 0 on Ut, wave 1 on Vt
+        const bool w1 = wv == 1;
+        const int kr = wave_qrcp(w1 ? Vt : Ut, s, s, k, w1 ? perm_v : perm_u, w1 ? pos_v : pos_u,
+                                 base + (w1 ? ly.oV0v : ly.oV0u), w1 ? tau_v : tau_u, delta);
+        if ((tid & 63) == 0) (w1 ? kr_v : kr_u) = kr;
     }
     __syncthreads();
     const int k1 = kr_u, k2 = kr_v;
-    for (int c = tid; c < k; c += NT) {
-        pinv_u[perm_u[c]] = c;
-        pinv_v[perm_v[c]] = c;
-    }
-    __syncthreads();
 
-    // core M = R1 Pi1^t Pi2 R2^t (k1 x k2), in FP64.  Jacobi runs on the
-    // columns of the orientation with fewer columns: N = M (k2 <= k1) or
-    // N = M^H (k1 < k2).
+    // core M = (R1 Pi1^t)(R2 Pi2^t)^t (k1 x k2).  The SVD works on the
+    // orientation with fewer columns: N = M (k2 <= k1) or N = M^H (k1 < k2).
     const bool tr = k1 < k2;
     const int nr = tr ? k2 : k1;
     const int ncl = tr ? k1 : k2;
     const int P = ncl + (ncl & 1);
-    for (int e = tid; e < nr * P; e += NT) {
-        const int row = e % nr, col = e / nr;
-        c128 v = czero<double>();
-        if (col < ncl) {
+    const int ldn = P > 0 ? jacobi_ld(nr, P) : 0;   // rows nr.. ldn-1 are zero padding
+    for (int e = tid; e < ldn * P; e += NT) {
+        const int row = e % ldn, col = e / ldn;
+        cpx<CT> v = czero<CT>();
+        if (col < ncl && row < nr) {
             const int a = tr ? col : row;      // row of M (U side)
             const int b = tr ? row : col;      // column of M (V side)
-            for (int c = 0; c < k; ++c) {
-                const int cu = pinv_u[c], cv = pinv_v[c];
-                if (cu >= a && cv >= b)
-                    cfma(v, ccast<double>(Ut[(size_t)cu * s + a]), ccast<double>(Vt[(size_t)cv * s + b]));
+            const lds<cpx<T>>* Ua = to_lds(Ut) + a;
+            const lds<cpx<T>>* Vb = to_lds(Vt) + b;
+#pragma unroll 8
+            for (int c = 0; c < k; ++c) {            // branch-free so the loads pipeline
+                const cpx<T> x = ldc(Ua + (size_t)c * s), y = ldc(Vb + (size_t)c * s);
+                const bool on = pos_u[c] >= a && pos_v[c] >= b;
+                cfma(v, on ? ccast<CT>(x) : czero<CT>(), ccast<CT>(y));
             }
             if (tr) v = conj(v);
         }
-        Nm[(size_t)col * nr + row] = v;
+        Nm[(size_t)col * ldn + row] = v;
     }
     __syncthreads();
-    if (ncl > 0) jacobi_svd64(Nm, nr, Jm, P, &flag, fro);
-    __syncthreads();
-
-    for (int c = tid; c < P; c += NT) {
-        double ss = 0.0;
-        for (int i = 0; i < nr; ++i) ss += abs2(Nm[(size_t)c * nr + i]);
-        sig[c] = sqrt(ss);
-    }
-    __syncthreads();
-    if (tid == 0) {
-        // partial selection of the R largest singular values
-        for (int c = 0; c < P; ++c) order[c] = c;
-        const int top = P < R ? P : R;
-        for (int a = 0; a < top; ++a) {
-            int best = a;
-            for (int b2 = a + 1; b2 < P; ++b2)
-                if (sig[order[b2]] > sig[order[best]]) best = b2;
-            const int tmp = order[a]; order[a] = order[best]; order[best] = tmp;
+    if (wv == 0) {
+        // Frobenius norm (fixed-order wave sum), then Jacobi
+        CT f = CT(0);
+        for (int e = tid; e < ldn * P; e += 64) f += abs2(Nm[e]);
+        f = wops::sum(f);
+        const CT eps = eps_of<CT>();
+        const CT thr = sizeof(CT) == 4 ? CT(1.0e-6) : CT(1.0e-12);
+        const CT tiny = f * eps * eps * CT(1e-2) + (sizeof(CT) == 4 ? CT(1e-37) : CT(1e-300));
+        if (P > 0) wave_jacobi<CT>(Nm, P, jacobi_rows(nr, P), Jm, nrm2, thr, tiny, 40);
+        // selection: rank of each column by decreasing norm (ties: lower index first)
+        const int lane = tid;
+        CT mine = CT(-1);
+        int rk = 64;
+        if (lane < P) {
+            mine = nrm2[lane];
+            rk = 0;
+            for (int c = 0; c < P; ++c) {
+                const CT o = nrm2[c];
+                rk += (o > mine || (o == mine && c < lane)) ? 1 : 0;
+            }
+            if (rk < R) order[rk] = lane;
         }
-        const double s1 = P > 0 ? sig[order[0]] : 0.0;
-        int rho = 0;
-        while (rho < top && s1 > 0.0 && sig[order[rho]] > p.tol * s1 && sig[order[rho]] > 0.0) ++rho;
-        rank_s = rho;
+        CT s1 = mine;
+        int unused = lane;
+        wops::argmax(s1, unused);
+        const CT t2 = CT(p.tol) * CT(p.tol);
+        const bool keep = lane < P && rk < R && s1 > CT(0) && mine > t2 * s1 && mine > CT(0);
+        const unsigned long long bal = __ballot(keep);
+        if (lane == 0) rank_s = __popcll(bal);
     }
     __syncthreads();
     const int rho = rank_s;
@@ -743,19 +934,28 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
     // U = Q1 [W sqrt(S); 0],  V = Q2 [conj(Z) sqrt(S); 0]
     for (int e = tid; e < s * R; e += NT) {
         const int i = e % s, q = e / s;
-        c128 u = czero<double>(), v = czero<double>();
-        if (q < rho) {
+        cpx<CT> u = czero<CT>(), v = czero<CT>();
+        if (q < rho && (i < k1 || i < k2)) {
             const int c = order[q];
-            const double sq = sqrt(sig[c]);
-            if (i < k1) u = tr ? sq * Jm[(size_t)c * P + i] : (1.0 / sq) * Nm[(size_t)c * nr + i];
-            if (i < k2) v = tr ? (1.0 / sq) * conj(Nm[(size_t)c * nr + i]) : sq * conj(Jm[(size_t)c * P + i]);
+            const CT sq = sqrt(sqrt(nrm2[c]));            // sqrt of the singular value
+            const CT isq = CT(1) / sq;
+            if (i < k1) u = tr ? sq * Jm[(size_t)c * ldn + i] : isq * Nm[(size_t)c * ldn + i];
+            if (i < k2) v = tr ? isq * conj(Nm[(size_t)c * ldn + i]) : sq * conj(Jm[(size_t)c * ldn + i]);
         }
         Y1[(size_t)q * s + i] = ccast<T>(u);
         Y2[(size_t)q * s + i] = ccast<T>(v);
     }
     __syncthreads();
-    if (wv == 0) wave_apply_q(Ut, s, k1, base + ly.oV0u, tau_u, Y1, rho, base + ly.oPartU, base + ly.oDotsU);
-    else if (wv == 1) wave_apply_q(Vt, s, k2, base + ly.oV0v, tau_v, Y2, rho, base + ly.oPartV, base + ly.oDotsV);
+    {
+        // waves 0, 1: Q1 on the two halves of Y1's columns; waves 2, 3: Q2 on Y2
+        constexpr int H = R / 2 > 0 ? R / 2 : 1;
+        const int c0 = (wv & 1) * H;
+        int nc = rho - c0;
+        nc = nc < 0 ? 0 : (nc > H ? H : nc);
+        const bool sv = wv >= 2;
+        wave_apply_q(sv ? Vt : Ut, s, s, sv ? k2 : k1, sv ? perm_v : perm_u, base + (sv ? ly.oV0v : ly.oV0u),
+                     sv ? tau_v : tau_u, (sv ? Y2 : Y1) + (size_t)c0 * s, s, nc);
+    }
     __syncthreads();
     cpx<T>* Qv = sp.Q + (size_t)(lam - 1) * R * np;
     for (int e = tid; e < s * R; e += NT) {
@@ -989,8 +1189,8 @@ size_t recomp_lds(const Plan& p, int m) {
     size_t mx = 0;
     for (int lam = 1; lam <= p.L; ++lam) {
         int k = 1 + (m > 0 ? R * lam : 0);
-        RecompLayout l = recomp_layout(p.np >> lam, k, R, m > 0 ? lam * R * R : 0, sizeof(cpx<T>));
-        size_t b = l.dEnd * sizeof(c128);
+        RecompLayout l = recomp_layout(p.np >> lam, k, R, m > 0 ? lam * R * R : 0, sizeof(cpx<T>), sizeof(cpx<T>));
+        size_t b = l.dEnd * sizeof(cpx<T>);
         if (b > mx) mx = b;
     }
     return mx;
@@ -1086,8 +1286,8 @@ size_t factor_lds_bytes(const Plan& p, size_t elem) {
     mx *= elem;
     for (int lam = 1; lam <= p.L; ++lam) {
         int s = p.np >> lam;
-        RecompLayout l = recomp_layout(s, 1 + p.r * lam, p.r, lam * p.r * p.r, elem);
-        size_t a = l.dEnd * sizeof(c128);
+        RecompLayout l = recomp_layout(s, 1 + p.r * lam, p.r, lam * p.r * p.r, elem, elem);
+        size_t a = l.dEnd * elem;
         size_t w = wood_layout(s, p.r, p.b, p.L, lam).oEnd * elem;
         if (a > mx) mx = a;
         if (w > mx) mx = w;
