@@ -324,7 +324,7 @@ __device__ __forceinline__ void leaf_job(const Plan& p, const StepPtrs<T>& sp, i
 // per column (or column pair), and lane g of a group handles the rows g,
 // g + G, g + 2G, ...  Column sums are butterflies inside the group (DPP lane
 // moves).  In the QR and in the application of Q each lane keeps its rows in
-// registers (the first RROWS of them; further rows stay in LDS and are
+// registers (the first rrows of them; further rows stay in LDS and are
 // streamed in chunks), so the only LDS traffic of a step is the reflector,
 // which every group reads at the same addresses (broadcast, no conflicts).
 // Pointers are cast to the LDS address space so that every access is a ds_*
@@ -337,7 +337,9 @@ template <typename X> __device__ __forceinline__ lds<X>* to_lds(const X* p) { re
 template <typename T> __device__ __forceinline__ cpx<T> ldc(const lds<cpx<T>>* p) { return mk<T>(p->re, p->im); }
 template <typename T> __device__ __forceinline__ void stc(lds<cpx<T>>* p, cpx<T> v) { p->re = v.re; p->im = v.im; }
 
-constexpr int RROWS = 32;   // rows per lane held in registers
+// rows per lane held in registers (fewer in double precision, whose rows take
+// twice the registers)
+template <typename T> constexpr int rrows() { return sizeof(T) == 4 ? 32 : 16; }
 constexpr int CHUNK = 8;    // rows per lane per chunk of LDS-resident rows
 
 // Lane geometry for groups of G = 64 / 2^ceil(log2(ngroups)) lanes.
@@ -512,14 +514,14 @@ __device__ __forceinline__ int wave_qrcp_n(cpx<T>* Ag, int lda, int s, int k, in
     return kr;
 }
 
-// Rows per lane held in registers: 4, 16 or 32 (beyond 32 they are streamed).
+// Rows per lane held in registers: 4, 16 or rrows (beyond that they are streamed).
 template <typename T>
 __device__ __forceinline__ int wave_qrcp(cpx<T>* A, int lda, int s, int k, int* perm, int* pos, cpx<T>* v0, T* tau,
                                          T delta) {
     const int nmax = max_rows(s, make_groups(k));
     if (nmax <= 4) return wave_qrcp_n<T, 4>(A, lda, s, k, perm, pos, v0, tau, delta);
     if (nmax <= 16) return wave_qrcp_n<T, 16>(A, lda, s, k, perm, pos, v0, tau, delta);
-    return wave_qrcp_n<T, RROWS>(A, lda, s, k, perm, pos, v0, tau, delta);
+    return wave_qrcp_n<T, rrows<T>()>(A, lda, s, k, perm, pos, v0, tau, delta);
 }
 
 // Y <- H_0 ... H_{kr-1} Y for the reflectors left in A by wave_qrcp (Y: s x
@@ -607,7 +609,7 @@ __device__ __forceinline__ void wave_apply_q(const cpx<T>* A, int lda, int s, in
     const int nmax = max_rows(s, make_groups(ncol));
     if (nmax <= 4) wave_apply_q_n<T, 4>(A, lda, s, kr, perm, v0, tau, Y, ldy, ncol);
     else if (nmax <= 16) wave_apply_q_n<T, 16>(A, lda, s, kr, perm, v0, tau, Y, ldy, ncol);
-    else wave_apply_q_n<T, RROWS>(A, lda, s, kr, perm, v0, tau, Y, ldy, ncol);
+    else wave_apply_q_n<T, rrows<T>()>(A, lda, s, kr, perm, v0, tau, Y, ldy, ncol);
 }
 
 // One-sided Jacobi SVD by one wavefront of the P columns of N in LDS (P even,
@@ -616,11 +618,15 @@ __device__ __forceinline__ void wave_apply_q(const cpx<T>* A, int lda, int s, in
 // (nr rows) and J (P rows) are stored with NR * G rows per column, the rows
 // past nr (past P for J) zero, so every lane loads and stores exactly NR rows
 // of each column without predicates; a pair that needs no rotation applies the
-// identity.  A pair is rotated when |a^H b| > thr |a| |b| and both columns are
-// above the negligible level tiny (squared norm); sweeps stop when no pair is.
-// J (column-major, leading dimension NR * G) starts as the identity and
-// accumulates the rotations, so that N_in J = N_out with mutually orthogonal
-// columns; nrm2[c] is the squared norm of column c.
+// identity.  A pair is rotated when |a^H b| > thr |a| |b|, |a^H b| > gabs and
+// both columns are above the negligible level tiny (squared norm).  Sweeps
+// stop after one in which no pair was rotated by more than cos = sqrt(thr)
+// (the next sweep, converging quadratically, would rotate none).  J
+// (column-major, leading dimension NR * G) starts as the identity and
+// accumulates the rotations, so that N_in J = N_out with nearly orthogonal
+// columns; nrm2[c] is the squared norm of column c.  Since J is unitary,
+// dropping columns of N_out changes N by exactly their norms, whatever their
+// residual inner products.
 // Reciprocal and reciprocal square root for the rotation parameters: the
 // hardware approximations (about 1 ulp) in single precision, correctly
 // rounded operations in double precision.
@@ -630,7 +636,7 @@ __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsq
 __device__ __forceinline__ double fast_rsq(double x) { return 1.0 / sqrt(x); }
 
 template <typename CT, int NR>
-__device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, CT* nrm2g, CT thr, CT tiny,
+__device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, CT* nrm2g, CT thr, CT gabs, CT tiny,
                                               int max_sweeps) {
     lds<cpx<CT>>* N = to_lds(Ng);
     lds<cpx<CT>>* J = to_lds(Jg);
@@ -640,6 +646,8 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
     const Groups gq = make_groups(npair);
     const int G = gq.G, q = gq.id, g = gq.g;
     const int ld = NR * G;
+    constexpr int CH = NR < 8 ? NR : 8;
+    constexpr bool ONE = NR <= 8;
     const bool act = q < npair;
     for (int e = lane; e < ld * P; e += 64) {
         const int r = e % ld;
@@ -649,7 +657,7 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
     const int P1 = P - 1;
     for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
         const bool last = sweep == max_sweeps;
-        bool rot = false;
+        CT mxc = CT(0);                       // largest squared cosine rotated in this sweep
         for (int rd = 0; rd < P1; ++rd) {
             // round-robin pairs: (rd, P-1) and ((rd + q) mod (P-1), (rd - q) mod (P-1))
             int a = rd + q, b = rd - q + P1;
@@ -661,28 +669,35 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
             lds<cpx<CT>>* cb = N + (size_t)b * ld + g;
             lds<cpx<CT>>* ja = J + (size_t)a * ld + g;
             lds<cpx<CT>>* jb = J + (size_t)b * ld + g;
-            cpx<CT> xa[NR], xb[NR], ya[NR], yb[NR];
-#pragma unroll
-            for (int u = 0; u < NR; ++u) {
-                xa[u] = ldc(ca + G * u);
-                xb[u] = ldc(cb + G * u);
-                ya[u] = ldc(ja + G * u);
-                yb[u] = ldc(jb + G * u);
-            }
-            __builtin_amdgcn_sched_barrier(0);
+            // rows in chunks of CH; with a single chunk the rows stay in registers
+            cpx<CT> xa[CH], xb[CH], ya[CH], yb[CH];
             CT al = CT(0), be = CT(0);
             cpx<CT> ga = czero<CT>();
 #pragma unroll
-            for (int u = 0; u < NR; ++u) {
-                al += abs2(xa[u]);
-                be += abs2(xb[u]);
-                cfma_conj(ga, xa[u], xb[u]);
+            for (int u0 = 0; u0 < NR; u0 += CH) {
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    xa[u] = ldc(ca + G * (u0 + u));
+                    xb[u] = ldc(cb + G * (u0 + u));
+                    if (ONE) {
+                        ya[u] = ldc(ja + G * u);
+                        yb[u] = ldc(jb + G * u);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);     // all loads in flight before the first use
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    al += abs2(xa[u]);
+                    be += abs2(xb[u]);
+                    cfma_conj(ga, xa[u], xb[u]);
+                }
             }
             al = wops::gsum(al, G);
             be = wops::gsum(be, G);
             ga = wops::gsum(ga, G);
             const CT ag2 = abs2(ga);
-            const bool doit = !last && act && al > tiny && be > tiny && ag2 > thr * thr * al * be;
+            const CT ab = al * be;
+            const bool doit = !last && act && al > tiny && be > tiny && ag2 > thr * thr * ab && ag2 > gabs * gabs;
             // rotation (identity when the pair is left alone)
             const CT iag = doit ? fast_rsq(ag2) : CT(0);              // 1 / |gamma|
             const CT zeta = CT(0.5) * (be - al) * iag;
@@ -693,24 +708,40 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
             const cpx<CT> em = doit ? iag * conj(ga) : mk<CT>(CT(1), CT(0));   // e^{-i phi}
             if (act && !last) {
 #pragma unroll
-                for (int u = 0; u < NR; ++u) {
-                    const cpx<CT> x2 = em * xb[u], y2 = em * yb[u];
-                    stc(ca + G * u, cs * xa[u] - sn * x2);
-                    stc(cb + G * u, sn * xa[u] + cs * x2);
-                    stc(ja + G * u, cs * ya[u] - sn * y2);
-                    stc(jb + G * u, sn * ya[u] + cs * y2);
+                for (int u0 = 0; u0 < NR; u0 += CH) {
+                    if (!ONE) {
+                        // reload the chunk (the fence keeps the compiler from reusing pass-1 values)
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                        for (int u = 0; u < CH; ++u) {
+                            xa[u] = ldc(ca + G * (u0 + u));
+                            xb[u] = ldc(cb + G * (u0 + u));
+                            ya[u] = ldc(ja + G * (u0 + u));
+                            yb[u] = ldc(jb + G * (u0 + u));
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        const cpx<CT> x2 = em * xb[u], y2 = em * yb[u];
+                        stc(ca + G * (u0 + u), cs * xa[u] - sn * x2);
+                        stc(cb + G * (u0 + u), sn * xa[u] + cs * x2);
+                        stc(ja + G * (u0 + u), cs * ya[u] - sn * y2);
+                        stc(jb + G * (u0 + u), sn * ya[u] + cs * y2);
+                    }
                 }
             }
             if (last && act && g == 0) {
                 nrm2[a] = al;
                 nrm2[b] = be;
             }
-            rot = rot || doit;
+            if (doit) mxc = fmax(mxc, ag2 / ab);
             wave_sync();
             if (last) break;
         }
         if (last) break;
-        if (!__any(rot)) sweep = max_sweeps - 1;   // converged: one more pass for the norms
+        int unused = 0;
+        wops::argmax(mxc, unused);
+        if (!(mxc > thr)) sweep = max_sweeps - 1;   // converged: one more pass for the norms
     }
     wave_sync();
 }
@@ -732,14 +763,14 @@ __host__ __device__ inline int jacobi_rows(int nr, int P) {
 __host__ __device__ inline int jacobi_ld(int nr, int P) { return jacobi_rows(nr, P) * jacobi_group(P); }
 
 template <typename CT>
-__device__ __forceinline__ void wave_jacobi(cpx<CT>* N, int P, int NRr, cpx<CT>* J, CT* nrm2, CT thr, CT tiny,
-                                            int max_sweeps) {
-    if (NRr == 1) wave_jacobi_n<CT, 1>(N, P, J, nrm2, thr, tiny, max_sweeps);
-    else if (NRr == 2) wave_jacobi_n<CT, 2>(N, P, J, nrm2, thr, tiny, max_sweeps);
-    else if (NRr == 4) wave_jacobi_n<CT, 4>(N, P, J, nrm2, thr, tiny, max_sweeps);
-    else if (NRr == 8) wave_jacobi_n<CT, 8>(N, P, J, nrm2, thr, tiny, max_sweeps);
-    else if (NRr == 16) wave_jacobi_n<CT, 16>(N, P, J, nrm2, thr, tiny, max_sweeps);
-    else wave_jacobi_n<CT, 32>(N, P, J, nrm2, thr, tiny, max_sweeps);
+__device__ __forceinline__ void wave_jacobi(cpx<CT>* N, int P, int NRr, cpx<CT>* J, CT* nrm2, CT thr, CT gabs,
+                                            CT tiny, int max_sweeps) {
+    if (NRr == 1) wave_jacobi_n<CT, 1>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else if (NRr == 2) wave_jacobi_n<CT, 2>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else if (NRr == 4) wave_jacobi_n<CT, 4>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else if (NRr == 8) wave_jacobi_n<CT, 8>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else if (NRr == 16) wave_jacobi_n<CT, 16>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else wave_jacobi_n<CT, 32>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
 }
 
 // ----------------------------------------------------------------------------
@@ -905,7 +936,10 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
         const CT eps = eps_of<CT>();
         const CT thr = sizeof(CT) == 4 ? CT(1.0e-6) : CT(1.0e-12);
         const CT tiny = f * eps * eps * CT(1e-2) + (sizeof(CT) == 4 ? CT(1e-37) : CT(1e-300));
-        if (P > 0) wave_jacobi<CT>(Nm, P, jacobi_rows(nr, P), Jm, nrm2, thr, tiny, 40);
+        // inner products below a tenth of the truncation level of the squared
+        // norms are left alone: they move no column norm by more than that
+        const CT gabs = CT(0.1 * (p.tol > 0.0 ? p.tol : 0.0)) * f;
+        if (P > 0) wave_jacobi<CT>(Nm, P, jacobi_rows(nr, P), Jm, nrm2, thr, gabs, tiny, 40);
         // selection: rank of each column by decreasing norm (ties: lower index first)
         const int lane = tid;
         CT mine = CT(-1);
