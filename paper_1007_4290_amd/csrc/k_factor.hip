@@ -42,6 +42,18 @@ template <> __device__ __forceinline__ float rsq<float>(float x) { return sqrtf(
 template <> __device__ __forceinline__ double rsq<double>(double x) { return sqrt(x); }
 
 __device__ __forceinline__ int heap_id(int lvl, int idx) { return (1 << lvl) - 1 + idx; }
+// Reciprocal and reciprocal square root: the hardware approximations (about
+// 1 ulp) in single precision, correctly rounded operations in double precision.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double fast_rsq(double x) { return 1.0 / sqrt(x); }
+// 1 / a through one reciprocal of |a|^2 (pivots here are far from the
+// overflow and underflow limits of |a|^2)
+template <typename T> __device__ __forceinline__ cpx<T> cinv_fast(cpx<T> a) {
+    const T r = fast_rcp(a.re * a.re + a.im * a.im);
+    return mk<T>(a.re * r, -a.im * r);
+}
 
 // A wavefront executes in lockstep; wave_sync orders its LDS traffic and
 // stops the compiler from moving memory operations across it.
@@ -223,6 +235,96 @@ __device__ __forceinline__ void gj_wave(const cpx<T>* Min, int ldi, cpx<T>* Out,
     if (lane == 0 && singular) *status = 1;
 }
 
+// Gauss-Jordan inversion with partial pivoting of a B x B matrix (B = 8, 16
+// or 32) by one wavefront.  Lane l owns column j = l % B and the RPL = B*B/64
+// rows rg*RPL .. rg*RPL + RPL-1 of row group rg = l / B.  A step fetches the
+// pivot column's entries of its rows and, after a wave argmax, the pivot
+// row's entry of its column, each with one ds_bpermute round trip.  Same
+// pivot bookkeeping as gj_wave (no physical row swaps).
+template <typename T>
+__device__ __forceinline__ T bperm(T v, int src_lane);
+template <>
+__device__ __forceinline__ float bperm<float>(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+template <>
+__device__ __forceinline__ double bperm<double>(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> bperm_c(cpx<T> v, int src) { return mk<T>(bperm(v.re, src), bperm(v.im, src)); }
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane_f(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> readlane_c(cpx<T> v, int l) { return mk<T>(readlane_f(v.re, l), readlane_f(v.im, l)); }
+
+template <typename T, int B>
+__device__ __forceinline__ void gj_cols(const cpx<T>* Min, int ldi, cpx<T>* Out, int ldo, int* status) {
+    static_assert(B == 8 || B == 16 || B == 32, "B * B must be a multiple of 64 lanes");
+    constexpr int RPL = B * B / 64;
+    const int lane = threadIdx.x & 63;
+    const int j = lane % B, rg = lane / B;
+    const int r0 = rg * RPL;
+    cpx<T> M[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) M[t] = Min[(size_t)j * ldi + r0 + t];
+    unsigned used = 0;              // rows of this lane already used as pivots (bit t)
+    int mystep[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) mystep[t] = 0;
+    int myperm = 0;                 // pivot row of step j
+    bool singular = false;
+    for (int k = 0; k < B; ++k) {
+        // multipliers: column k's entries of this lane's rows
+        cpx<T> ci[RPL];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) ci[t] = bperm_c(M[t], k + rg * B);
+        // pivot: unused row of largest |entry| (lowest index among ties)
+        T key = T(-1);
+        int pr = 0x7fffffff;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+            const T a = ((used >> t) & 1u) ? T(-1) : abs2(ci[t]);
+            if (a > key) { key = a; pr = r0 + t; }
+        }
+        // lanes of a row group hold the same candidate: combine the groups only
+        wops::argmax_groups<B>(key, pr);
+        const int p = __builtin_amdgcn_readfirstlane(pr);
+        if (!(key > T(0))) singular = true;
+        const int tp = p % RPL, gp = p / RPL;           // pivot row's slot and row group
+        // pivot row entry of this lane's column, and the pivot itself
+        cpx<T> mine = M[0];
+#pragma unroll
+        for (int t = 1; t < RPL; ++t) mine = t == tp ? M[t] : mine;
+        const cpx<T> rowp = bperm_c(mine, j + gp * B);
+        const cpx<T> cp = readlane_c(rowp, k);          // pivot: column k's lane
+        const cpx<T> ipv = cinv_fast(cp);
+        const cpx<T> rs = rowp * ipv;                   // scaled pivot row entry
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+            const bool isp = r0 + t == p;
+            if (j == k) M[t] = isp ? ipv : -(ci[t] * ipv);
+            else M[t] = isp ? rs : M[t] - ci[t] * rs;
+            if (isp) { used |= 1u << t; mystep[t] = k; }
+        }
+        if (j == k) myperm = p;
+    }
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) Out[(size_t)myperm * ldo + mystep[t]] = M[t];
+    if (lane == 0 && singular) *status = 1;
+}
+
 // ----------------------------------------------------------------------------
 // Leaf: S leaf of layer m, then its inverse K (column-major b x b).
 //   S_leaf = A_leaf - D (K_prev - sum_lvl P_lvl X_lvl P_lvl^t) D   on the leaf rows.
@@ -315,7 +417,10 @@ __device__ __forceinline__ void leaf_job(const Plan& p, const StepPtrs<T>& sp, i
             for (int bb = 0; bb < TS; ++bb) Ml[(size_t)(tc * TS + bb) * B + tr * TS + a] = M[a][bb];
     }
     __syncthreads();
-    if (threadIdx.x < 64) gj_wave<T, B>(Ml, B, sp.K + (size_t)t * B * B, B, perm_w, sp.status);
+    if (threadIdx.x < 64) {
+        if constexpr (B == 8 || B == 16 || B == 32) gj_cols<T, B>(Ml, B, sp.K + (size_t)t * B * B, B, sp.status);
+        else gj_wave<T, B>(Ml, B, sp.K + (size_t)t * B * B, B, perm_w, sp.status);
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -627,14 +732,6 @@ __device__ __forceinline__ void wave_apply_q(const cpx<T>* A, int lda, int s, in
 // columns; nrm2[c] is the squared norm of column c.  Since J is unitary,
 // dropping columns of N_out changes N by exactly their norms, whatever their
 // residual inner products.
-// Reciprocal and reciprocal square root for the rotation parameters: the
-// hardware approximations (about 1 ulp) in single precision, correctly
-// rounded operations in double precision.
-__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
-__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double fast_rsq(double x) { return 1.0 / sqrt(x); }
-
 template <typename CT, int NR>
 __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, CT* nrm2g, CT thr, CT gabs, CT tiny,
                                               int max_sweeps) {
@@ -1091,7 +1188,11 @@ __global__ __launch_bounds__(NT) void wood_kernel(const InstDesc<T>* __restrict_
             Cl[e] = v;
         }
         __syncthreads();
-        if (tid < 64) gj_wave<T, R2>(Cl, R2, sp.X + (size_t)node * 4 * R * R, R2, perm_w, sp.status);
+        if (tid < 64) {
+            if constexpr (R2 == 8 || R2 == 16 || R2 == 32)
+                gj_cols<T, R2>(Cl, R2, sp.X + (size_t)node * 4 * R * R, R2, sp.status);
+            else gj_wave<T, R2>(Cl, R2, sp.X + (size_t)node * 4 * R * R, R2, perm_w, sp.status);
+        }
         __syncthreads();
     }
     if (lam == 0) return;

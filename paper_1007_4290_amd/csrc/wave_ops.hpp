@@ -148,4 +148,23 @@ __device__ __forceinline__ void argmax(T& v, int& idx) {
     idx = readlane63_i(idx);
 }
 
+// argmax as above when every lane of each aligned group of G lanes (G = 8, 16
+// or 32) holds the same candidate: only the steps that combine groups run.
+template <int G, typename T>
+__device__ __forceinline__ void argmax_groups(T& v, int& idx) {
+    const T lo = -__builtin_huge_val();
+#define WOPS_STEP(CTRL, RM)                                                                  \
+    {                                                                                        \
+        const T ov = dpp<CTRL, RM>(v, lo);                                                   \
+        const int oi = dpp_i32<CTRL, RM>(idx, 0x7fffffff);                                   \
+        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }                           \
+    }
+    if constexpr (G <= 8) WOPS_STEP(ROW_MIRROR, 0xf)
+    if constexpr (G <= 16) WOPS_STEP(ROW_BCAST15, 0xa)
+    WOPS_STEP(ROW_BCAST31, 0xc)
+#undef WOPS_STEP
+    v = readlane63(v);
+    idx = readlane63_i(idx);
+}
+
 }  // namespace wops
