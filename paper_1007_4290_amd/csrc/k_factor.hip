@@ -495,7 +495,9 @@ __device__ __forceinline__ int wave_qrcp_n(cpx<T>* Ag, int lda, int s, int k, in
     const int nrl = col ? lane_rows(s, gq) : 0;
     const int nmax = max_rows(s, gq);
     cpx<T> a[NR];
-    T acc = T(0);
+    // sums use four independent accumulators: with one wavefront per SIMD
+    // nothing else hides the latency of a dependent chain
+    T acc4[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int u = 0; u < NR; ++u) {
         const int i = g + G * u;
@@ -505,8 +507,9 @@ __device__ __forceinline__ int wave_qrcp_n(cpx<T>* Ag, int lda, int s, int k, in
 #pragma unroll
     for (int u = 0; u < NR; ++u) {
         a[u] = u < nrl ? a[u] : czero<T>();
-        acc += abs2(a[u]);
+        acc4[u & 3] += abs2(a[u]);
     }
+    T acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
     for (int u0 = NR; u0 < nmax; u0 += CHUNK) {
 #pragma unroll
         for (int u = 0; u < CHUNK; ++u) {
@@ -553,12 +556,14 @@ __device__ __forceinline__ int wave_qrcp_n(cpx<T>* Ag, int lda, int s, int k, in
             v[u] = ldc(Ap + (i < s ? i : s - 1));
         }
         __builtin_amdgcn_sched_barrier(0);
+        cpx<T> d4[4] = {czero<T>(), czero<T>(), czero<T>(), czero<T>()};
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
             const int i = g + G * u;
             v[u] = (u < n_act && i >= j) ? (i == j ? vv0 : v[u]) : czero<T>();
-            cfma_conj(d, v[u], a[u]);
+            cfma_conj(d4[u & 3], v[u], a[u]);
         }
+        d = (d4[0] + d4[1]) + (d4[2] + d4[3]);
         for (int u0 = NR; u0 < nmax; u0 += CHUNK) {
 #pragma unroll
             for (int u = 0; u < CHUNK; ++u) {
@@ -571,13 +576,14 @@ __device__ __forceinline__ int wave_qrcp_n(cpx<T>* Ag, int lda, int s, int k, in
         }
         d = wops::gsum(d, G);
         const cpx<T> td = tj * d;
-        T nn = T(0);
+        T nn4[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
             const int i = g + G * u;
             a[u] -= v[u] * td;
-            nn += i > j ? abs2(a[u]) : T(0);
+            nn4[u & 3] += i > j ? abs2(a[u]) : T(0);
         }
+        T nn = (nn4[0] + nn4[1]) + (nn4[2] + nn4[3]);
         for (int u0 = NR; u0 < nmax; u0 += CHUNK) {
             cpx<T> an[CHUNK];
 #pragma unroll
@@ -665,12 +671,14 @@ __device__ __forceinline__ void wave_apply_q_n(const cpx<T>* Ag, int lda, int s,
             v[u] = ldc(Ap + (i < s ? i : s - 1));
         }
         __builtin_amdgcn_sched_barrier(0);
+        cpx<T> d4[4] = {czero<T>(), czero<T>(), czero<T>(), czero<T>()};
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
             const int i = g + G * u;
             v[u] = (u < nrl && i >= j) ? (i == j ? vv0 : v[u]) : czero<T>();
-            cfma_conj(d, v[u], y[u]);
+            cfma_conj(d4[u & 3], v[u], y[u]);
         }
+        d = (d4[0] + d4[1]) + (d4[2] + d4[3]);
         for (int u0 = NR; u0 < nmax; u0 += CHUNK) {
 #pragma unroll
             for (int u = 0; u < CHUNK; ++u) {
@@ -870,16 +878,113 @@ __device__ __forceinline__ void wave_jacobi(cpx<CT>* N, int P, int NRr, cpx<CT>*
     else wave_jacobi_n<CT, 32>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
 }
 
+// Gram matrices GA = A^H A and GB = B^H B (k x k, both triangles stored,
+// column-major) of the s x k column-major A and B in LDS, accumulated in FP64
+// (products of single-precision entries are exact), by all threads.
+template <typename T>
+__device__ __forceinline__ void gram_pair(const cpx<T>* A, const cpx<T>* B, int s, int k, c128* GA, c128* GB) {
+    const int nt = k * (k + 1) / 2;
+    for (int e = threadIdx.x; e < 2 * nt; e += NT) {
+        const bool second = e >= nt;
+        int q = second ? e - nt : e;
+        int b = 0;                                   // column b, row a <= b
+        while (q > b) { q -= b + 1; ++b; }
+        const int a = q;
+        const lds<cpx<T>>* X = to_lds(second ? B : A);
+        const lds<cpx<T>>* xa = X + (size_t)a * s;
+        const lds<cpx<T>>* xb = X + (size_t)b * s;
+        c128 g0 = czero<double>(), g1 = g0, g2 = g0, g3 = g0;     // independent chains
+        int i = 0;
+        for (; i + 4 <= s; i += 4) {
+            cfma_conj(g0, ccast<double>(ldc(xa + i)), ccast<double>(ldc(xb + i)));
+            cfma_conj(g1, ccast<double>(ldc(xa + i + 1)), ccast<double>(ldc(xb + i + 1)));
+            cfma_conj(g2, ccast<double>(ldc(xa + i + 2)), ccast<double>(ldc(xb + i + 2)));
+            cfma_conj(g3, ccast<double>(ldc(xa + i + 3)), ccast<double>(ldc(xb + i + 3)));
+        }
+        for (; i < s; ++i) cfma_conj(g0, ccast<double>(ldc(xa + i)), ccast<double>(ldc(xb + i)));
+        const c128 g = (g0 + g1) + (g2 + g3);
+        c128* G = second ? GB : GA;
+        G[(size_t)b * k + a] = g;
+        G[(size_t)a * k + b] = conj(g);
+    }
+}
+
+// Pivoted Cholesky (Crout form) of the k x k Hermitian positive semidefinite
+// G (column-major, k <= 64) by one wavefront; lane c owns column c.  Step j
+// takes the column p of largest Schur-complement diagonal d_p and forms row j
+// of R:  R[j][c] = (G[p][c] - sum_{t<j} conj(R[t][p]) R[t][c]) / sqrt(d_p)
+// for the columns not chosen yet, 0 for the others (so R holds R Pi^t, as the
+// QR path's row j).  With G = A^H A this is the R of A's Householder QR with
+// column pivoting (in exact arithmetic).  It stops at kr when every remaining
+// d is at most delta^2 times the largest initial one; pos[c] is the step at
+// which c was chosen (k if never), perm[j] the column of step j.
+__device__ __forceinline__ int wave_pchol(const c128* Gg, int k, int kmax, c128* Rg, int* permg, int* posg,
+                                          double delta) {
+    lds<c128>* G = to_lds(const_cast<c128*>(Gg));
+    lds<c128>* Rr = to_lds(Rg);
+    lds<int>* perm = to_lds(permg);
+    lds<int>* pos = to_lds(posg);
+    const int c = threadIdx.x & 63;
+    const bool col = c < k;
+    const int cc = col ? c : 0;
+    double d = col ? ldc(G + (size_t)cc * k + cc).re : -1.0;
+    double mx = d;
+    int unused = c;
+    wops::argmax(mx, unused);
+    const double stop = delta * delta * mx;
+    bool chosen = !col;
+    int kr = kmax;
+    for (int j = 0; j < kmax; ++j) {
+        double key = chosen ? -1.0 : d;
+        int p = c;
+        wops::argmax(key, p);
+        if (!(key > stop)) { kr = j; break; }
+        const double rpp = sqrt(key);
+        c128 val = ldc(G + (size_t)cc * k + p);          // G[p][c]
+        c128 s0 = czero<double>(), s1 = s0;
+        int t = 0;
+        for (; t + 2 <= j; t += 2) {
+            cfma_conj(s0, ldc(Rr + (size_t)t * k + p), ldc(Rr + (size_t)t * k + cc));
+            cfma_conj(s1, ldc(Rr + (size_t)(t + 1) * k + p), ldc(Rr + (size_t)(t + 1) * k + cc));
+        }
+        if (t < j) cfma_conj(s0, ldc(Rr + (size_t)t * k + p), ldc(Rr + (size_t)t * k + cc));
+        val -= s0 + s1;
+        const double ir = 1.0 / rpp;
+        c128 r = chosen ? czero<double>() : (c == p ? mk(rpp, 0.0) : ir * val);
+        if (!chosen && c != p) d -= abs2(r);
+        if (col) stc(Rr + (size_t)j * k + c, r);
+        if (c == 0) {
+            perm[j] = p;
+            pos[p] = j;
+        }
+        if (c == p) chosen = true;
+        wave_sync();
+    }
+    if (col && !chosen) pos[c] = k;
+    wave_sync();
+    return kr;
+}
+
 // ----------------------------------------------------------------------------
 // Recompression of the off-diagonal blocks of S_m.
 struct RecompLayout {
     int s, k, kk, r;
     size_t oU, oV, oY1, oY2, oV0u, oV0v, oEnd;   // cpx<T> units
     size_t dN, dJ, dS, dEnd;                     // cpx<CT> units (after oEnd)
+    size_t gGu, gGv, gRu, gRv, gYu, gYv, gEnd;   // c128 units (after dEnd; Gram path only)
 };
 
+// The Gram path (complex64 factors, truncation on, k <= GRAM_KMAX) replaces
+// the Householder QR of the stacked factors by a pivoted Cholesky of their
+// FP64 Gram matrices.
+constexpr int GRAM_KMAX = 40;
+__host__ __device__ inline bool gram_path(size_t elem, double tol, int k) {
+    return elem == sizeof(c64) && tol > 0.0 && k <= GRAM_KMAX;
+}
+
 // elem = sizeof(cpx<T>), celem = sizeof(cpx<CT>) of the core's type
-__host__ __device__ inline RecompLayout recomp_layout(int s, int k, int r, int Xblocks, size_t elem, size_t celem) {
+__host__ __device__ inline RecompLayout recomp_layout(int s, int k, int r, int Xblocks, size_t elem, size_t celem,
+                                                      bool gram) {
     RecompLayout l;
     l.s = s; l.k = k; l.r = r;
     l.kk = s < k ? s : k;
@@ -905,6 +1010,24 @@ __host__ __device__ inline RecompLayout recomp_layout(int s, int k, int r, int X
     l.dJ = l.dN + nj;
     l.dS = l.dJ + nj;
     l.dEnd = l.dS + (size_t)(l.kk + 2);
+    // Gram path: the Gram matrices (k x k each) are dead once the Cholesky is
+    // done and overlay the core area (N, J), which is written after it; the
+    // dense pivot-ordered R11 blocks of the back substitution (kk x kk each)
+    // overlay it again once the core is read.  Then Cholesky rows (kk x k)
+    // and FP64 output blocks (kk x r).
+    const size_t g0 = (bytes + 15) / 16;                          // start of the core area, c128 units
+    size_t g = (l.dEnd * celem + 15) / 16;
+    l.gGu = g0;
+    l.gGv = g0 + (size_t)k * k;
+    if (gram) {
+        const size_t over = g0 + 2 * (size_t)k * k;
+        g = over > g ? over : g;
+    }
+    l.gRu = g; if (gram) g += (size_t)l.kk * k;
+    l.gRv = g; if (gram) g += (size_t)l.kk * k;
+    l.gYu = g; if (gram) g += (size_t)l.kk * r;
+    l.gYv = g; if (gram) g += (size_t)l.kk * r;
+    l.gEnd = g;
     return l;
 }
 
@@ -924,7 +1047,8 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
     const int k = 1 + (m > 0 ? R * lam : 0);
     const int lo1 = 2 * j * s, lo2 = (2 * j + 1) * s;
     const int nX = m > 0 ? lam * R * R : 0;
-    RecompLayout ly = recomp_layout(s, k, R, nX, sizeof(cpx<T>), sizeof(cpx<CT>));
+    const bool gram = gram_path(sizeof(cpx<T>), p.tol, k);
+    RecompLayout ly = recomp_layout(s, k, R, nX, sizeof(cpx<T>), sizeof(cpx<CT>), gram);
     cpx<T>* base = (cpx<T>*)smem;
     cpx<T>* Ut = base + ly.oU;
     cpx<T>* Vt = base + ly.oV;
@@ -934,6 +1058,12 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
     cpx<CT>* Nm = (cpx<CT>*)smem + ly.dN;
     cpx<CT>* Jm = (cpx<CT>*)smem + ly.dJ;
     CT* nrm2 = (CT*)((cpx<CT>*)smem + ly.dS);
+    c128* GU = (c128*)smem + ly.gGu;
+    c128* GV = (c128*)smem + ly.gGv;
+    c128* RU = (c128*)smem + ly.gRu;
+    c128* RV = (c128*)smem + ly.gRv;
+    c128* YU = (c128*)smem + ly.gYu;
+    c128* YV = (c128*)smem + ly.gYv;
     const int tid = threadIdx.x, wv = tid >> 6;
 
     // Stacked factors: S_m(c1, c2) = Ut Vt^t.
@@ -990,7 +1120,17 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
     // The cut is far below the truncation tolerance (none when nothing is
     // truncated); in complex64 at the level of the factors' own rounding.
     const T delta = p.tol <= 0.0 ? T(0) : (sizeof(T) == 4 ? T(4.0e-7) : T(1.0e-5 * p.tol < 1.0e-11 ? 1.0e-5 * p.tol : 1.0e-11));
-    if (wv < 2) {                               // one call site: wave 0 on Ut, wave 1 on Vt
+    if (gram) {
+        // Gram path: FP64 Gram matrices, then pivoted Cholesky (waves 0 and 1)
+        gram_pair(Ut, Vt, s, k, GU, GV);
+        __syncthreads();
+        if (wv < 2) {
+            const bool w1 = wv == 1;
+            const int kr = wave_pchol(w1 ? GV : GU, k, ly.kk, w1 ? RV : RU, w1 ? perm_v : perm_u,
+                                      w1 ? pos_v : pos_u, (double)delta);
+            if ((tid & 63) == 0) (w1 ? kr_v : kr_u) = kr;
+        }
+    } else if (wv < 2) {                        // one call site: wave 0 on Ut, wave 1 on Vt
         const bool w1 = wv == 1;
         const int kr = wave_qrcp(w1 ? Vt : Ut, s, s, k, w1 ? perm_v : perm_u, w1 ? pos_v : pos_u,
                                  base + (w1 ? ly.oV0v : ly.oV0u), w1 ? tau_v : tau_u, delta);
@@ -1009,7 +1149,21 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
     for (int e = tid; e < ldn * P; e += NT) {
         const int row = e % ldn, col = e / ldn;
         cpx<CT> v = czero<CT>();
-        if (col < ncl && row < nr) {
+        if (gram && col < ncl && row < nr) {
+            const int a = tr ? col : row;
+            const int b = tr ? row : col;
+            const lds<c128>* ra = to_lds(RU) + (size_t)a * k;
+            const lds<c128>* rb = to_lds(RV) + (size_t)b * k;
+            c128 w0 = czero<double>(), w1 = w0;
+            int c = 0;
+            for (; c + 2 <= k; c += 2) {
+                cfma(w0, ldc(ra + c), ldc(rb + c));
+                cfma(w1, ldc(ra + c + 1), ldc(rb + c + 1));
+            }
+            if (c < k) cfma(w0, ldc(ra + c), ldc(rb + c));
+            const c128 w = w0 + w1;
+            v = ccast<CT>(tr ? conj(w) : w);
+        } else if (col < ncl && row < nr) {
             const int a = tr ? col : row;      // row of M (U side)
             const int b = tr ? row : col;      // column of M (V side)
             const lds<cpx<T>>* Ua = to_lds(Ut) + a;
@@ -1073,11 +1227,77 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
             if (i < k1) u = tr ? sq * Jm[(size_t)c * ldn + i] : isq * Nm[(size_t)c * ldn + i];
             if (i < k2) v = tr ? isq * conj(Nm[(size_t)c * ldn + i]) : sq * conj(Jm[(size_t)c * ldn + i]);
         }
-        Y1[(size_t)q * s + i] = ccast<T>(u);
-        Y2[(size_t)q * s + i] = ccast<T>(v);
+        if (gram) {
+            if (i < ly.kk) {
+                YU[(size_t)q * ly.kk + i] = ccast<double>(u);
+                YV[(size_t)q * ly.kk + i] = ccast<double>(v);
+            }
+        } else {
+            Y1[(size_t)q * s + i] = ccast<T>(u);
+            Y2[(size_t)q * s + i] = ccast<T>(v);
+        }
     }
     __syncthreads();
-    {
+    if (gram) {
+        // U_new = U Pi[:, :k1] R11^-1 Y: back substitution in place, then the
+        // product with FP64 accumulation, which cancels the conditioning of R11
+        // (U_new = Q1 Y with Q1 orthonormal).  R11 is first gathered densely in
+        // pivot order (over the dead core area) so every load is independent.
+        c128* D1 = GU;                                   // k1 x k1, row-major [jj][t]
+        c128* D2 = GU + (size_t)ly.kk * ly.kk;           // k2 x k2
+        for (int e = tid; e < k1 * k1 + k2 * k2; e += NT) {
+            const bool sv = e >= k1 * k1;
+            const int ee = sv ? e - k1 * k1 : e, kr = sv ? k2 : k1;
+            const int jj = ee / kr, t = ee % kr;
+            const int* pm = sv ? perm_v : perm_u;
+            (sv ? D2 : D1)[(size_t)jj * kr + t] = (sv ? RV : RU)[(size_t)jj * k + pm[t]];
+        }
+        __syncthreads();
+        if (tid < 2 * R) {
+            const bool sv = tid >= R;
+            const int q = tid % R;
+            const int kr = sv ? k2 : k1;
+            const lds<c128>* Dm = to_lds(sv ? D2 : D1);
+            lds<c128>* z = to_lds((sv ? YV : YU) + (size_t)q * ly.kk);
+            if (q < rho) {
+                for (int jj = kr - 1; jj >= 0; --jj) {
+                    c128 a0 = ldc(z + jj), a1 = czero<double>();
+                    int t = jj + 1;
+                    for (; t + 2 <= kr; t += 2) {
+                        const c128 r0 = ldc(Dm + (size_t)jj * kr + t), r1 = ldc(Dm + (size_t)jj * kr + t + 1);
+                        const c128 z0 = ldc(z + t), z1 = ldc(z + t + 1);
+                        a0 -= r0 * z0;
+                        a1 -= r1 * z1;
+                    }
+                    if (t < kr) a0 -= ldc(Dm + (size_t)jj * kr + t) * ldc(z + t);
+                    stc(z + jj, (1.0 / ldc(Dm + (size_t)jj * kr + jj).re) * (a0 + a1));
+                }
+            }
+        }
+        __syncthreads();
+        // one thread per row and side, all output columns: the Z entries are
+        // broadcast loads, the row's U entries one load per pivot
+        for (int e = tid; e < 2 * s; e += NT) {
+            const bool sv = e >= s;
+            const int i = sv ? e - s : e;
+            const int kr = sv ? k2 : k1;
+            const int* pm = sv ? perm_v : perm_u;
+            const lds<cpx<T>>* X = to_lds(sv ? Vt : Ut) + i;
+            const lds<c128>* z = to_lds(sv ? YV : YU);
+            c128 acc[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = czero<double>();
+            for (int t = 0; t < kr; ++t) {
+                const c128 x = ccast<double>(ldc(X + (size_t)pm[t] * s));
+#pragma unroll
+                for (int q = 0; q < R; ++q) cfma(acc[q], x, ldc(z + (size_t)q * ly.kk + t));
+            }
+            cpx<T>* Yo = sv ? Y2 : Y1;
+#pragma unroll
+            for (int q = 0; q < R; ++q) Yo[(size_t)q * s + i] = q < rho ? ccast<T>(acc[q]) : czero<T>();
+        }
+        __syncthreads();
+    } else {
         // waves 0, 1: Q1 on the two halves of Y1's columns; waves 2, 3: Q2 on Y2
         constexpr int H = R / 2 > 0 ? R / 2 : 1;
         const int c0 = (wv & 1) * H;
@@ -1086,8 +1306,8 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
         const bool sv = wv >= 2;
         wave_apply_q(sv ? Vt : Ut, s, s, sv ? k2 : k1, sv ? perm_v : perm_u, base + (sv ? ly.oV0v : ly.oV0u),
                      sv ? tau_v : tau_u, (sv ? Y2 : Y1) + (size_t)c0 * s, s, nc);
+        __syncthreads();
     }
-    __syncthreads();
     cpx<T>* Qv = sp.Q + (size_t)(lam - 1) * R * np;
     for (int e = tid; e < s * R; e += NT) {
         const int i = e % s, q = e / s;
@@ -1324,8 +1544,9 @@ size_t recomp_lds(const Plan& p, int m) {
     size_t mx = 0;
     for (int lam = 1; lam <= p.L; ++lam) {
         int k = 1 + (m > 0 ? R * lam : 0);
-        RecompLayout l = recomp_layout(p.np >> lam, k, R, m > 0 ? lam * R * R : 0, sizeof(cpx<T>), sizeof(cpx<T>));
-        size_t b = l.dEnd * sizeof(cpx<T>);
+        RecompLayout l = recomp_layout(p.np >> lam, k, R, m > 0 ? lam * R * R : 0, sizeof(cpx<T>), sizeof(cpx<T>),
+                                       gram_path(sizeof(cpx<T>), p.tol, k));
+        size_t b = l.gEnd * sizeof(c128);
         if (b > mx) mx = b;
     }
     return mx;
@@ -1421,8 +1642,9 @@ size_t factor_lds_bytes(const Plan& p, size_t elem) {
     mx *= elem;
     for (int lam = 1; lam <= p.L; ++lam) {
         int s = p.np >> lam;
-        RecompLayout l = recomp_layout(s, 1 + p.r * lam, p.r, lam * p.r * p.r, elem, elem);
-        size_t a = l.dEnd * elem;
+        RecompLayout l = recomp_layout(s, 1 + p.r * lam, p.r, lam * p.r * p.r, elem, elem,
+                                       gram_path(elem, p.tol, 1 + p.r * lam));
+        size_t a = l.gEnd * sizeof(c128);
         size_t w = wood_layout(s, p.r, p.b, p.L, lam).oEnd * elem;
         if (a > mx) mx = a;
         if (w > mx) mx = w;
