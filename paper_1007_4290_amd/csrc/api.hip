@@ -95,7 +95,24 @@ struct hsweep_ctx {
     HostBuf hhost, scalehost, activehost, yhost;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     double t_factor = 0, t_sweep = 0, t_stencil = 0, t_krylov = 0, n_apply = 0;
+    // the layer loop of a single-context factorization, captured once as a
+    // HIP graph (kernel nodes only) and replayed while its descriptor holds
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    DevBuf gdesc;
+    std::vector<unsigned char> gkey;
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        gkey.clear();
+    }
     ~hsweep_ctx() {
+        drop_graph();
+        if (cap) (void)hipStreamDestroy(cap);
+        gdesc.release();
         DevBuf* bufs[] = {&c, &sn, &isn, &sh, &dg, &eo, &cp, &fac, &Q, &G, &rank, &status, &sweep_w,
                           &V, &Z, &w, &r, &hdev, &partial, &scale, &active, &y};
         for (DevBuf* b : bufs) b->release();
@@ -230,6 +247,52 @@ int do_factor_many(hsweep_ctx** ctxs, int count, hipStream_t s) {
         HIPCHK(hipMemcpy(&st, ctxs[q]->status.p, sizeof(int), hipMemcpyDeviceToHost));
         if (st) return fail(HSWEEP_ESINGULAR, "zero pivot in a leaf or core inverse");
     }
+    return HSWEEP_OK;
+}
+
+// Single context: the coefficients are rebuilt on `s` (plain launches and
+// memsets), then the layer loop runs as a HIP graph on `s`.  The graph holds
+// kernel nodes only; it is captured on a private stream the first time and
+// again whenever the descriptor (plan and buffers) changes.
+template <typename T>
+int do_factor_one(hsweep_ctx* ctx, hipStream_t s) {
+    InstDesc<T> d;
+    int rc = prepare_factor<T>(ctx, s, d);
+    if (rc) return rc;
+    const unsigned char* kb = reinterpret_cast<const unsigned char*>(&d);
+    std::vector<unsigned char> key(kb, kb + sizeof(d));
+    if (!ctx->gexec || key != ctx->gkey) {
+        ctx->drop_graph();
+        HIPCHK(ctx->gdesc.ensure(sizeof(d)));
+        HIPCHK(hipMemcpy(ctx->gdesc.p, &d, sizeof(d), hipMemcpyHostToDevice));
+        factor_kernels_init<T>();               // kernel attributes are set outside the capture
+        if (!ctx->cap) HIPCHK(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+        const Plan plan = ctx->plan;
+        bool ok = true;
+        for (int m = 0; m < plan.n && ok; ++m)
+            ok = launch_factor_layer<T>((const InstDesc<T>*)ctx->gdesc.p, &plan, 1, m, ctx->cap) == 0;
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ctx->cap, &g);
+        if (!ok || ec != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            return fail(HSWEEP_EDEVICE, std::string("factor graph capture: ") + hipGetErrorString(ec));
+        }
+        ctx->graph = g;
+        const hipError_t ei = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            ctx->drop_graph();
+            return fail(HSWEEP_EDEVICE, std::string("factor graph instantiate: ") + hipGetErrorString(ei));
+        }
+        ctx->gkey = key;
+    }
+    HIPCHK(hipGraphLaunch(ctx->gexec, s));
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(HSWEEP_EDEVICE, std::string("factor: ") + hipGetErrorString(e));
+    int st = 0;
+    HIPCHK(hipMemcpy(&st, ctx->status.p, sizeof(int), hipMemcpyDeviceToHost));
+    if (st) return fail(HSWEEP_ESINGULAR, "zero pivot in a leaf or core inverse");
     return HSWEEP_OK;
 }
 
@@ -431,7 +494,8 @@ int hsweep_factor(hsweep_ctx* ctx, void* stream) {
     ctx->factored = false;
     HIPCHK(hipEventRecord(ctx->ev[0], s));
     hsweep_ctx* one[1] = {ctx};
-    rc = ctx->opts.precision == HSWEEP_C64 ? do_factor_many<float>(one, 1, s) : do_factor_many<double>(one, 1, s);
+    (void)one;
+    rc = ctx->opts.precision == HSWEEP_C64 ? do_factor_one<float>(ctx, s) : do_factor_one<double>(ctx, s);
     if (rc) return rc;
     HIPCHK(hipEventRecord(ctx->ev[1], s));
     HIPCHK(hipEventSynchronize(ctx->ev[1]));

@@ -78,6 +78,9 @@ struct InstDesc {
 // the element type, leaf size and rank; instances with n <= m are skipped.
 template <typename T>
 int launch_factor_layer(const InstDesc<T>* descs, const Plan* plans, int ninst, int m, hipStream_t s);
+// Sets the kernels' LDS limits (done once; must precede a stream capture).
+template <typename T>
+void factor_kernels_init();
 
 // ---- sweep (preconditioner application) ----
 template <typename T>

@@ -750,7 +750,7 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
     const int npair = P / 2;
     const Groups gq = make_groups(npair);
     const int G = gq.G, q = gq.id, g = gq.g;
-    const int ld = NR * G;
+    const int ld = (NR + 1) * G;                 // as jacobi_ld: one group of padding rows
     constexpr int CH = NR < 8 ? NR : 8;
     constexpr bool ONE = NR <= 8;
     const bool act = q < npair;
@@ -865,7 +865,8 @@ __host__ __device__ inline int jacobi_rows(int nr, int P) {
     while (r < need) r <<= 1;
     return r;
 }
-__host__ __device__ inline int jacobi_ld(int nr, int P) { return jacobi_rows(nr, P) * jacobi_group(P); }
+// (padded by one group so that columns do not start on the same LDS bank)
+__host__ __device__ inline int jacobi_ld(int nr, int P) { return (jacobi_rows(nr, P) + 1) * jacobi_group(P); }
 
 template <typename CT>
 __device__ __forceinline__ void wave_jacobi(cpx<CT>* N, int P, int NRr, cpx<CT>* J, CT* nrm2, CT thr, CT gabs,
@@ -882,7 +883,8 @@ __device__ __forceinline__ void wave_jacobi(cpx<CT>* N, int P, int NRr, cpx<CT>*
 // column-major) of the s x k column-major A and B in LDS, accumulated in FP64
 // (products of single-precision entries are exact), by all threads.
 template <typename T>
-__device__ __forceinline__ void gram_pair(const cpx<T>* A, const cpx<T>* B, int s, int k, c128* GA, c128* GB) {
+__device__ __forceinline__ void gram_pair(const cpx<T>* A, const cpx<T>* B, int s, int lda, int k, c128* GA,
+                                          c128* GB) {
     const int nt = k * (k + 1) / 2;
     for (int e = threadIdx.x; e < 2 * nt; e += NT) {
         const bool second = e >= nt;
@@ -891,8 +893,8 @@ __device__ __forceinline__ void gram_pair(const cpx<T>* A, const cpx<T>* B, int 
         while (q > b) { q -= b + 1; ++b; }
         const int a = q;
         const lds<cpx<T>>* X = to_lds(second ? B : A);
-        const lds<cpx<T>>* xa = X + (size_t)a * s;
-        const lds<cpx<T>>* xb = X + (size_t)b * s;
+        const lds<cpx<T>>* xa = X + (size_t)a * lda;
+        const lds<cpx<T>>* xb = X + (size_t)b * lda;
         c128 g0 = czero<double>(), g1 = g0, g2 = g0, g3 = g0;     // independent chains
         int i = 0;
         for (; i + 4 <= s; i += 4) {
@@ -969,6 +971,7 @@ __device__ __forceinline__ int wave_pchol(const c128* Gg, int k, int kmax, c128*
 // Recompression of the off-diagonal blocks of S_m.
 struct RecompLayout {
     int s, k, kk, r;
+    int lda, ldy;                                // padded leading dimensions of U, V and Y1, Y2
     size_t oU, oV, oY1, oY2, oV0u, oV0v, oEnd;   // cpx<T> units
     size_t dN, dJ, dS, dEnd;                     // cpx<CT> units (after oEnd)
     size_t gGu, gGv, gRu, gRv, gYu, gYv, gEnd;   // c128 units (after dEnd; Gram path only)
@@ -988,11 +991,18 @@ __host__ __device__ inline RecompLayout recomp_layout(int s, int k, int r, int X
     RecompLayout l;
     l.s = s; l.k = k; l.r = r;
     l.kk = s < k ? s : k;
+    // columns padded by the lane-group size of the wavefront routines, so the
+    // groups' loads of one row fall on different LDS banks
+    int pk = 1, pr = 1;
+    while (pk < k) pk <<= 1;
+    while (pr < (r / 2 > 0 ? r / 2 : 1)) pr <<= 1;
+    l.lda = s + 64 / pk;
+    l.ldy = s + 64 / pr;
     size_t o = 0;
-    l.oU = o; o += (size_t)s * k;
-    l.oV = o; o += (size_t)s * k;
-    l.oY1 = o; o += (size_t)s * r;
-    l.oY2 = o; o += (size_t)s * r;
+    l.oU = o; o += (size_t)l.lda * k;
+    l.oV = o; o += (size_t)l.lda * k;
+    l.oY1 = o; o += (size_t)l.ldy * r;
+    l.oY2 = o; o += (size_t)l.ldy * r;
     l.oV0u = o; o += l.kk;
     l.oV0v = o; o += l.kk;
     o += (size_t)Xblocks;                  // staged X blocks
@@ -1065,6 +1075,7 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
     c128* YU = (c128*)smem + ly.gYu;
     c128* YV = (c128*)smem + ly.gYv;
     const int tid = threadIdx.x, wv = tid >> 6;
+    const int lda = ly.lda, ldy = ly.ldy;
 
     // Stacked factors: S_m(c1, c2) = Ut Vt^t.
     //   column 0:          A_{m,m}(last of c1, first of c2) e_last e_first^t
@@ -1109,8 +1120,8 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
 #pragma unroll
                 for (int k1 = 0; k1 < R; ++k1) cfma(acc, pu[k1], xb[k1 * R + k2]);
                 const int col = 1 + blk * R + k2;
-                Ut[(size_t)col * s + i] = d1 * acc;
-                Vt[(size_t)col * s + i] = d2 * pv[k2];
+                Ut[(size_t)col * lda + i] = d1 * acc;
+                Vt[(size_t)col * lda + i] = d2 * pv[k2];
             }
         }
     }
@@ -1122,7 +1133,7 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
     const T delta = p.tol <= 0.0 ? T(0) : (sizeof(T) == 4 ? T(4.0e-7) : T(1.0e-5 * p.tol < 1.0e-11 ? 1.0e-5 * p.tol : 1.0e-11));
     if (gram) {
         // Gram path: FP64 Gram matrices, then pivoted Cholesky (waves 0 and 1)
-        gram_pair(Ut, Vt, s, k, GU, GV);
+        gram_pair(Ut, Vt, s, lda, k, GU, GV);
         __syncthreads();
         if (wv < 2) {
             const bool w1 = wv == 1;
@@ -1132,7 +1143,7 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
         }
     } else if (wv < 2) {                        // one call site: wave 0 on Ut, wave 1 on Vt
         const bool w1 = wv == 1;
-        const int kr = wave_qrcp(w1 ? Vt : Ut, s, s, k, w1 ? perm_v : perm_u, w1 ? pos_v : pos_u,
+        const int kr = wave_qrcp(w1 ? Vt : Ut, lda, s, k, w1 ? perm_v : perm_u, w1 ? pos_v : pos_u,
                                  base + (w1 ? ly.oV0v : ly.oV0u), w1 ? tau_v : tau_u, delta);
         if ((tid & 63) == 0) (w1 ? kr_v : kr_u) = kr;
     }
@@ -1170,7 +1181,7 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
             const lds<cpx<T>>* Vb = to_lds(Vt) + b;
 #pragma unroll 8
             for (int c = 0; c < k; ++c) {            // branch-free so the loads pipeline
-                const cpx<T> x = ldc(Ua + (size_t)c * s), y = ldc(Vb + (size_t)c * s);
+                const cpx<T> x = ldc(Ua + (size_t)c * lda), y = ldc(Vb + (size_t)c * lda);
                 const bool on = pos_u[c] >= a && pos_v[c] >= b;
                 cfma(v, on ? ccast<CT>(x) : czero<CT>(), ccast<CT>(y));
             }
@@ -1233,8 +1244,8 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
                 YV[(size_t)q * ly.kk + i] = ccast<double>(v);
             }
         } else {
-            Y1[(size_t)q * s + i] = ccast<T>(u);
-            Y2[(size_t)q * s + i] = ccast<T>(v);
+            Y1[(size_t)q * ldy + i] = ccast<T>(u);
+            Y2[(size_t)q * ldy + i] = ccast<T>(v);
         }
     }
     __syncthreads();
@@ -1288,13 +1299,13 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
 #pragma unroll
             for (int q = 0; q < R; ++q) acc[q] = czero<double>();
             for (int t = 0; t < kr; ++t) {
-                const c128 x = ccast<double>(ldc(X + (size_t)pm[t] * s));
+                const c128 x = ccast<double>(ldc(X + (size_t)pm[t] * lda));
 #pragma unroll
                 for (int q = 0; q < R; ++q) cfma(acc[q], x, ldc(z + (size_t)q * ly.kk + t));
             }
             cpx<T>* Yo = sv ? Y2 : Y1;
 #pragma unroll
-            for (int q = 0; q < R; ++q) Yo[(size_t)q * s + i] = q < rho ? ccast<T>(acc[q]) : czero<T>();
+            for (int q = 0; q < R; ++q) Yo[(size_t)q * ldy + i] = q < rho ? ccast<T>(acc[q]) : czero<T>();
         }
         __syncthreads();
     } else {
@@ -1304,15 +1315,15 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
         int nc = rho - c0;
         nc = nc < 0 ? 0 : (nc > H ? H : nc);
         const bool sv = wv >= 2;
-        wave_apply_q(sv ? Vt : Ut, s, s, sv ? k2 : k1, sv ? perm_v : perm_u, base + (sv ? ly.oV0v : ly.oV0u),
-                     sv ? tau_v : tau_u, (sv ? Y2 : Y1) + (size_t)c0 * s, s, nc);
+        wave_apply_q(sv ? Vt : Ut, lda, s, sv ? k2 : k1, sv ? perm_v : perm_u, base + (sv ? ly.oV0v : ly.oV0u),
+                     sv ? tau_v : tau_u, (sv ? Y2 : Y1) + (size_t)c0 * ldy, ldy, nc);
         __syncthreads();
     }
     cpx<T>* Qv = sp.Q + (size_t)(lam - 1) * R * np;
     for (int e = tid; e < s * R; e += NT) {
         const int i = e % s, q = e / s;
-        Qv[(size_t)q * np + lo1 + i] = Y1[(size_t)q * s + i];
-        Qv[(size_t)q * np + lo2 + i] = Y2[(size_t)q * s + i];
+        Qv[(size_t)q * np + lo1 + i] = Y1[(size_t)q * ldy + i];
+        Qv[(size_t)q * np + lo2 + i] = Y2[(size_t)q * ldy + i];
     }
     if (tid == 0) sp.rank[pj] = rho;
 }
@@ -1681,6 +1692,13 @@ int launch_factor_layer(const InstDesc<T>* descs, const Plan* plans, int ninst, 
 #undef C_LAYER
     return ok ? 0 : -1;
 }
+
+template <typename T>
+void factor_kernels_init() {
+    set_lds_limits<T>();
+}
+template void factor_kernels_init<float>();
+template void factor_kernels_init<double>();
 
 template int launch_factor_layer<float>(const InstDesc<float>*, const Plan*, int, int, hipStream_t);
 template int launch_factor_layer<double>(const InstDesc<double>*, const Plan*, int, int, hipStream_t);
