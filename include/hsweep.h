@@ -32,9 +32,10 @@
  * the context, the coefficient arrays, the factor store and its work
  * buffers (device memory, freed by hsweep_destroy).
  *
- * Streams.  `stream` is a hipStream_t (NULL = the default stream).  factor
- * and apply are asynchronous on that stream; solve, solve_batch and grad
- * synchronize on it before returning (they read scalars back to the host).
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  apply,
+ * stencil and grad are asynchronous on that stream; factor, factor_batch,
+ * solve and solve_batch synchronize on it before returning (they read pivot
+ * status or residuals back to the host).
  *
  * Errors.  Every function returns HSWEEP_OK (0) or a negative code; no
  * exception crosses this interface.  Arguments are validated on the host
@@ -68,7 +69,8 @@ typedef struct hsweep_ctx hsweep_ctx;
 typedef struct hsweep_opts {
     int    leaf;        /* dense leaf size b (power of two, 4..64); the padded
                            layer width is n_p = b * 2^L >= n */
-    int    rank;        /* maximum rank r of every off-diagonal block (1..32) */
+    int    rank;        /* maximum rank r of every off-diagonal block: 2, 4, 8
+                           or 16, with 1 + r * levels <= 64 */
     double rank_tol;    /* keep singular values > rank_tol * sigma_1 of the block
                            (0 keeps all up to `rank`) */
     double pml_C;       /* PML constant C of eq. sigma (> 0); default 20 */
@@ -100,7 +102,9 @@ int hsweep_plan_info(const hsweep_ctx* ctx, int* n_p, int* levels, size_t* facto
 
 /* Alg. 2.3 on the device: for m = 1..n form S_m = A_{m,m} - D_m T_{m-1} D_m
  * in H-form (recompressed to rank <= r), invert it, and keep T_m in the
- * factor store.  Asynchronous on `stream`. */
+ * factor store.  The layer loop is captured once as a HIP graph and
+ * replayed on later calls.  Synchronizes `stream`; ESINGULAR on a zero
+ * pivot. */
 int hsweep_factor(hsweep_ctx* ctx, void* stream);
 
 /* u = M f for nrhs right-hand sides (Alg. 2.4): f, u are device
@@ -131,12 +135,13 @@ int hsweep_grad_c(hsweep_ctx* ctx, const void* u, const void* mu, int nrhs,
 
 /* Several independent problems factored together: every step of the
  * factorization is launched once for all contexts whose layer loop has
- * not finished.  All contexts must have the same precision. */
+ * not finished.  All contexts must have the same precision, leaf size and
+ * rank.  Synchronizes `stream`. */
 int hsweep_factor_batch(hsweep_ctx** ctxs, int count, void* stream);
 
-/* One flexible-GMRES solve per context (one right-hand side each), the
- * sweeps of all contexts launched together.  f[k], u[k]: device
- * complex128 fields of context k.  iters, relres: host arrays of count. */
+/* One flexible-GMRES solve per context (one right-hand side each), run
+ * one context after the other on `stream`.  f[k], u[k]: device complex128
+ * fields of context k.  iters, relres: host arrays of count. */
 int hsweep_solve_batch(hsweep_ctx** ctxs, int count, const void* const* f, void* const* u,
                        double tol, int maxit, int* iters, double* relres, void* stream);
 

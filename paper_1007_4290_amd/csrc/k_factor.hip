@@ -17,12 +17,14 @@
 // inverse; truncation happens once per block when S_{m+1} is formed.
 //
 // Launches per layer (all on one stream):
-//   recompress_kernel  one block per off-diagonal pair: build the stacked
-//                      factors of S_m(c1, c2) (rank 1 + r*level), Householder
-//                      QR of both, one-sided Jacobi SVD of the small core,
+//   layer_kernel       blocks [0, 2^L - 1): one per off-diagonal pair, build
+//                      the stacked factors of S_m(c1, c2) (rank 1 + r*level),
+//                      column-pivoted triangular factors of both (Householder
+//                      QR, or in complex64 a pivoted Cholesky of the FP64 Gram
+//                      matrix), one-sided Jacobi SVD of the small core,
 //                      truncate (sigma > tol*sigma_1, at most r), write Q.
-//   leaf_kernel        one block per leaf: S_m leaf = A - D T_{m-1} D, then
-//                      Gauss-Jordan inverse with partial pivoting -> K.
+//                      blocks [2^L - 1, 2^(L+1) - 1): one per leaf, S_m leaf =
+//                      A - D T_{m-1} D, Gauss-Jordan inverse -> K.
 //   wood_kernel(l)     levels l = L..1, one block per node: X_c from the
 //                      children's G, then P_c = T_c Q_c and G_c = Q_c^t P_c.
 //   wood_kernel(0)     the root core X_0.
@@ -298,10 +300,8 @@ __device__ __forceinline__ void gj_cols(const cpx<T>* Min, int ldi, cpx<T>* Out,
             const T a = ((used >> t) & 1u) ? T(-1) : abs2(ci[t]);
             if (a > key) { key = a; pr = r0 + t; }
         }
-        // lanes of a row group hold the same candidate: combine the groups only
-        wops::argmax_groups<B>(key, pr);
-        const int p = __builtin_amdgcn_readfirstlane(pr);
-        if (!(key > T(0))) singular = true;
+        int p = wops::argmax_nonneg((float)key, pr & 63, key >= T(0));
+        p = p < 0 ? 0 : p;                              // no unused row left: singular, flagged below
         const int tp = p % RPL, gp = p / RPL;           // pivot row's slot and row group
         // pivot row entry of this lane's column, and the pivot itself
         cpx<T> mine = M[0];
@@ -309,6 +309,7 @@ __device__ __forceinline__ void gj_cols(const cpx<T>* Min, int ldi, cpx<T>* Out,
         for (int t = 1; t < RPL; ++t) mine = t == tp ? M[t] : mine;
         const cpx<T> rowp = bperm_c(mine, j + gp * B);
         const cpx<T> cp = readlane_c(rowp, k);          // pivot: column k's lane
+        if (!(abs2(cp) > T(0))) singular = true;
         const cpx<T> ipv = cinv_fast(cp);
         const cpx<T> rs = rowp * ipv;                   // scaled pivot row entry
 #pragma unroll
@@ -527,9 +528,8 @@ __device__ __forceinline__ int wave_qrcp_n(cpx<T>* Ag, int lda, int s, int k, in
     const int kk = s < k ? s : k;
     int kr = kk;
     for (int j = 0; j < kk; ++j) {
-        T key = chosen ? T(-1) : nrm;
-        int p = c;
-        wops::argmax(key, p);
+        int p = wops::argmax_nonneg((float)nrm, c, !chosen);
+        const T key = p >= 0 ? readlane_f(nrm, p * G) : T(-1);    // exact norm of the pivot column
         if (!(key > stop)) { kr = j; break; }
         // the pivot group publishes its register rows (rows beyond them are in LDS already)
         if (c == p) {
@@ -937,9 +937,8 @@ __device__ __forceinline__ int wave_pchol(const c128* Gg, int k, int kmax, c128*
     bool chosen = !col;
     int kr = kmax;
     for (int j = 0; j < kmax; ++j) {
-        double key = chosen ? -1.0 : d;
-        int p = c;
-        wops::argmax(key, p);
+        const int p = wops::argmax_nonneg((float)d, c, !chosen);
+        const double key = p >= 0 ? readlane_f(d, p) : -1.0;     // exact Schur diagonal of the pivot
         if (!(key > stop)) { kr = j; break; }
         const double rpp = sqrt(key);
         c128 val = ldc(G + (size_t)cc * k + p);          // G[p][c]

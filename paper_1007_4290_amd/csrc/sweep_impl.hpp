@@ -21,8 +21,23 @@
 // memory latency of a layer step hides behind the previous step.
 #pragma once
 #include "internal.hpp"
+#include "wave_ops.hpp"
 
 namespace hsweep_sweep {
+
+// Sum over aligned groups of G consecutive lanes (G a compile-time power of
+// two up to 64), returned to every lane of the group: DPP butterflies inside
+// rows of 16 lanes, the LDS crossbar only across rows.
+template <int G, typename T>
+__device__ __forceinline__ T seg_sum(T v) {
+    if constexpr (G >= 2) v += wops::dpp<wops::QP_XOR1>(v, T(0));
+    if constexpr (G >= 4) v += wops::dpp<wops::QP_XOR2>(v, T(0));
+    if constexpr (G >= 8) v += wops::dpp<wops::ROW_HALF_MIRROR>(v, T(0));
+    if constexpr (G >= 16) v += wops::dpp<wops::ROW_MIRROR>(v, T(0));
+    if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
 
 template <int B, int R> struct Chunk {
     static constexpr int CH = B < R ? B : R;   // chunk length (never longer than a leaf)
@@ -82,6 +97,20 @@ struct SweepShared {
     cpx<T>* zs;    // (2^L - 1) * 2r
 };
 
+// Segmented sum for level l (0-based) of a node tree whose level-1 nodes
+// span C1 lanes: segments of C1 >> l lanes.
+template <int C1, typename T>
+__device__ __forceinline__ T seg_sum_level(T v, int l) {
+    if constexpr (C1 >= 64) { if (l == 0) return seg_sum<64>(v); }
+    if constexpr (C1 >= 32) { if (l == (C1 >= 64 ? 1 : 0)) return seg_sum<32>(v); }
+    const int g = C1 >> l;
+    if (g >= 16) return seg_sum<16>(v);
+    if (g >= 8) return seg_sum<8>(v);
+    if (g >= 4) return seg_sum<4>(v);
+    if (g >= 2) return seg_sum<2>(v);
+    return v;
+}
+
 // y = T_m x for the row owned by this thread.  Three workgroup barriers per
 // call when L > 0: after the vector is published, after the node reductions,
 // after the cores.  The node reductions are segmented wavefront reductions of
@@ -118,10 +147,11 @@ __device__ __forceinline__ cpx<T> apply_T(const Plan& p, const LayerRegs<T, B, R
 #pragma unroll
                     for (int j = 0; j < CH; ++j) cfma(acc, g.pc[l][tq * CH + j], xc[j]);
                 }
-                for (int off = 1; off < cpn; off <<= 1) {
-                    acc.re += __shfl_xor(acc.re, off, 64);
-                    acc.im += __shfl_xor(acc.im, off, 64);
-                }
+                // cpn = (B << L) / CH >> lvl is a compile-time power of two
+                constexpr int NCH = (B << L) / CH;
+                constexpr int CPN = (NCH >> 1) > 0 ? (NCH >> 1) : 1;
+                acc.re = seg_sum_level<CPN>(acc.re, l);
+                acc.im = seg_sum_level<CPN>(acc.im, l);
                 if (row && (e % cpn) == 0) {
                     const int idx = (e % nch) / cpn, k = e / nch;
                     sh.gs[((1 << lvl) - 1 + idx) * R + k] = acc;
@@ -157,6 +187,16 @@ __device__ __forceinline__ cpx<T> apply_T(const Plan& p, const LayerRegs<T, B, R
     return y;
 }
 
+// Vector inputs of one layer step, loaded one step ahead: the loads are
+// issued before the current step's stores, so waiting for them never waits
+// for those stores (the vector memory counter retires in order).
+template <typename T>
+struct StepIn {
+    c128 f;            // forward: f_m
+    cpx<T> c;          // forward: A_{m,m-1} diagonal entry; backward: A_{m,m+1}
+    cpx<T> w;          // backward: w_m
+};
+
 // State carried between the 2n-1 layer steps of one sweep.
 template <typename T>
 struct SweepState {
@@ -165,7 +205,31 @@ struct SweepState {
     cpx<T>* w;
     const cpx<T>* cp;
     cpx<T> carry;      // forward: w_{m-1}; backward: u_{m+1}
+    StepIn<T> pre;     // inputs of the next step
 };
+
+template <typename T>
+__device__ __forceinline__ StepIn<T> fetch_in(const Plan& p, int s, const SweepState<T>& st) {
+    const int n = p.n, np = p.np;
+    const int i = threadIdx.x;
+    const bool row = i < np, real_row = i < n;
+    StepIn<T> in;
+    in.f = czero<double>();
+    in.c = czero<T>();
+    in.w = czero<T>();
+    if (s < n) {
+        const int m = s;
+        if (real_row) in.f = st.f[(size_t)m * n + i];
+        if (m > 0 && row) in.c = st.cp[(size_t)(m - 1) * np + i];
+    } else if (s < 2 * n - 1) {
+        const int m = 2 * n - 2 - s;
+        if (row) {
+            in.c = st.cp[(size_t)m * np + i];
+            in.w = st.w[(size_t)m * np + i];
+        }
+    }
+    return in;
+}
 
 // Step s of the sweep: s < n is forward layer m = s, otherwise backward
 // layer m = 2n-2-s.
@@ -175,22 +239,21 @@ __device__ __forceinline__ void sweep_step(const Plan& p, int s, const LayerRegs
     const int n = p.n, np = p.np;
     const int i = threadIdx.x;
     const bool row = i < np, real_row = i < n;
+    const StepIn<T> in = st.pre;
+    st.pre = fetch_in<T>(p, s + 1, st);          // before this step's stores
     if (s < n) {
         const int m = s;
-        cpx<T> x = czero<T>();
-        if (real_row) x = ccast<T>(st.f[(size_t)m * n + i]);
-        if (m > 0 && row) x -= st.cp[(size_t)(m - 1) * np + i] * st.carry;
+        cpx<T> x = ccast<T>(in.f);
+        if (m > 0) x -= in.c * st.carry;
         cpx<T> y = apply_T<T, B, R, L>(p, g, x, sh);
         if (row) st.w[(size_t)m * np + i] = y;
         st.carry = y;
         if (m == n - 1 && real_row) st.u[(size_t)m * n + i] = ccast<double>(y);
     } else {
         const int m = 2 * n - 2 - s;
-        cpx<T> x = czero<T>();
-        if (row) x = st.cp[(size_t)m * np + i] * st.carry;
+        const cpx<T> x = in.c * st.carry;
         cpx<T> y = apply_T<T, B, R, L>(p, g, x, sh);
-        cpx<T> um = czero<T>();
-        if (row) um = st.w[(size_t)m * np + i] - y;
+        const cpx<T> um = row ? in.w - y : czero<T>();
         if (real_row) st.u[(size_t)m * n + i] = ccast<double>(um);
         st.carry = um;
     }
@@ -215,6 +278,7 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(Plan p, SweepArgs<T> a) {
         for (size_t e = i; e < N; e += blockDim.x) st.u[e] = czero<double>();
         return;
     }
+    st.pre = fetch_in<T>(p, 0, st);
     SweepShared<T> sh;
     cpx<T>* base = (cpx<T>*)smem;
     sh.xs = base;

@@ -167,4 +167,31 @@ __device__ __forceinline__ void argmax_groups(T& v, int& idx) {
     idx = readlane63_i(idx);
 }
 
+// Unsigned maximum over all 64 lanes, returned to every lane.
+__device__ __forceinline__ unsigned umax(unsigned v) {
+    int x = (int)v;
+#define WOPS_UMAX(CTRL, RM) x = (int)max((unsigned)x, (unsigned)dpp_i32<CTRL, RM>(x, 0));
+    WOPS_UMAX(ROW_SHR1, 0xf)
+    WOPS_UMAX(ROW_SHR2, 0xf)
+    WOPS_UMAX(ROW_SHR4, 0xf)
+    WOPS_UMAX(ROW_SHR8, 0xf)
+    WOPS_UMAX(ROW_BCAST15, 0xa)
+    WOPS_UMAX(ROW_BCAST31, 0xc)
+#undef WOPS_UMAX
+    return (unsigned)readlane63_i(x);
+}
+
+// Pivot search on non-negative keys: the lane of largest key (ties: lowest
+// idx, 0 <= idx < 64) among the lanes with eligible set.  The key and index
+// are packed into one word (top bit: eligible; then the float key without its
+// lowest mantissa bits; then 63 - idx), so the search is a single unsigned
+// maximum.  Keys closer than about 2^-17 relative count as ties.  Returns the
+// winning idx, or -1 when no lane is eligible.
+__device__ __forceinline__ int argmax_nonneg(float key, int idx, bool eligible) {
+    const unsigned kb = (__float_as_uint(key > 0.0f ? key : 0.0f) >> 1) & ~63u;
+    const unsigned u = eligible ? (0x80000000u | kb | (unsigned)(63 - idx)) : 0u;
+    const unsigned m = umax(u);
+    return (m & 0x80000000u) ? 63 - (int)(m & 63u) : -1;
+}
+
 }  // namespace wops
