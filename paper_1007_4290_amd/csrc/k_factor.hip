@@ -740,7 +740,9 @@ __device__ __forceinline__ void wave_apply_q(const cpx<T>* A, int lda, int s, in
 // columns; nrm2[c] is the squared norm of column c.  Since J is unitary,
 // dropping columns of N_out changes N by exactly their norms, whatever their
 // residual inner products.
-template <typename CT, int NR>
+// GT: the lane-group size when known at compile time (then the butterflies
+// and the lane geometry are constants), 0 to take it from P at run time.
+template <typename CT, int NR, int GT>
 __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, CT* nrm2g, CT thr, CT gabs, CT tiny,
                                               int max_sweeps) {
     lds<cpx<CT>>* N = to_lds(Ng);
@@ -749,7 +751,9 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
     const int lane = threadIdx.x & 63;
     const int npair = P / 2;
     const Groups gq = make_groups(npair);
-    const int G = gq.G, q = gq.id, g = gq.g;
+    const int G = GT > 0 ? GT : gq.G;
+    const int q = GT > 0 ? lane / GT : gq.id, g = GT > 0 ? lane % GT : gq.g;
+    auto gs = [&](auto v) { if constexpr (GT > 0) return wops::gsum_ct<GT>(v); else return wops::gsum(v, G); };
     const int ld = (NR + 1) * G;                 // as jacobi_ld: one group of padding rows
     constexpr int CH = NR < 8 ? NR : 8;
     constexpr bool ONE = NR <= 8;
@@ -797,9 +801,9 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
                     cfma_conj(ga, xa[u], xb[u]);
                 }
             }
-            al = wops::gsum(al, G);
-            be = wops::gsum(be, G);
-            ga = wops::gsum(ga, G);
+            al = gs(al);
+            be = gs(be);
+            ga = gs(ga);
             const CT ag2 = abs2(ga);
             const CT ab = al * be;
             const bool doit = !last && act && al > tiny && be > tiny && ag2 > thr * thr * ab && ag2 > gabs * gabs;
@@ -868,15 +872,26 @@ __host__ __device__ inline int jacobi_rows(int nr, int P) {
 // (padded by one group so that columns do not start on the same LDS bank)
 __host__ __device__ inline int jacobi_ld(int nr, int P) { return (jacobi_rows(nr, P) + 1) * jacobi_group(P); }
 
+template <typename CT, int GT>
+__device__ __forceinline__ void wave_jacobi_g(cpx<CT>* N, int P, int NRr, cpx<CT>* J, CT* nrm2, CT thr, CT gabs,
+                                              CT tiny, int max_sweeps) {
+    if (NRr == 1) wave_jacobi_n<CT, 1, GT>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else if (NRr == 2) wave_jacobi_n<CT, 2, GT>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else if (NRr == 4) wave_jacobi_n<CT, 4, GT>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else if (NRr == 8) wave_jacobi_n<CT, 8, GT>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else if (NRr == 16) wave_jacobi_n<CT, 16, GT>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else wave_jacobi_n<CT, 32, GT>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+}
+
+// Group sizes 4, 8 and 16 (P from 7 to 32 columns) are compiled as constants.
 template <typename CT>
 __device__ __forceinline__ void wave_jacobi(cpx<CT>* N, int P, int NRr, cpx<CT>* J, CT* nrm2, CT thr, CT gabs,
                                             CT tiny, int max_sweeps) {
-    if (NRr == 1) wave_jacobi_n<CT, 1>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
-    else if (NRr == 2) wave_jacobi_n<CT, 2>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
-    else if (NRr == 4) wave_jacobi_n<CT, 4>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
-    else if (NRr == 8) wave_jacobi_n<CT, 8>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
-    else if (NRr == 16) wave_jacobi_n<CT, 16>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
-    else wave_jacobi_n<CT, 32>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+    const int G = jacobi_group(P);
+    if (G == 4 && NRr <= 16) wave_jacobi_g<CT, 4>(N, P, NRr, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else if (G == 8 && NRr <= 8) wave_jacobi_g<CT, 8>(N, P, NRr, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else if (G == 16 && NRr <= 4) wave_jacobi_g<CT, 16>(N, P, NRr, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else wave_jacobi_g<CT, 0>(N, P, NRr, J, nrm2, thr, gabs, tiny, max_sweeps);
 }
 
 // Gram matrices GA = A^H A and GB = B^H B (k x k, both triangles stored,

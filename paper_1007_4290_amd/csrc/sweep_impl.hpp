@@ -25,19 +25,8 @@
 
 namespace hsweep_sweep {
 
-// Sum over aligned groups of G consecutive lanes (G a compile-time power of
-// two up to 64), returned to every lane of the group: DPP butterflies inside
-// rows of 16 lanes, the LDS crossbar only across rows.
 template <int G, typename T>
-__device__ __forceinline__ T seg_sum(T v) {
-    if constexpr (G >= 2) v += wops::dpp<wops::QP_XOR1>(v, T(0));
-    if constexpr (G >= 4) v += wops::dpp<wops::QP_XOR2>(v, T(0));
-    if constexpr (G >= 8) v += wops::dpp<wops::ROW_HALF_MIRROR>(v, T(0));
-    if constexpr (G >= 16) v += wops::dpp<wops::ROW_MIRROR>(v, T(0));
-    if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
-    if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
-    return v;
-}
+__device__ __forceinline__ T seg_sum(T v) { return wops::gsum_ct<G>(v); }
 
 template <int B, int R> struct Chunk {
     static constexpr int CH = B < R ? B : R;   // chunk length (never longer than a leaf)

@@ -120,6 +120,23 @@ __device__ __forceinline__ cpx<T> gsum(cpx<T> v, int G) {
     return mk<T>(gsum(v.re, G), gsum(v.im, G));
 }
 
+// As gsum with a compile-time group size: no selects or branches.
+template <int G, typename T>
+__device__ __forceinline__ T gsum_ct(T v) {
+    if constexpr (G >= 2) v += dpp<QP_XOR1>(v, T(0));
+    if constexpr (G >= 4) v += dpp<QP_XOR2>(v, T(0));
+    if constexpr (G >= 8) v += dpp<ROW_HALF_MIRROR>(v, T(0));
+    if constexpr (G >= 16) v += dpp<ROW_MIRROR>(v, T(0));
+    if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+template <int G, typename T>
+__device__ __forceinline__ cpx<T> gsum_ct(cpx<T> v) {
+    return mk<T>(gsum_ct<G>(v.re), gsum_ct<G>(v.im));
+}
+
 __device__ __forceinline__ int pow2_at_least(int x) {
     int p = 1;
     while (p < x) p <<= 1;
