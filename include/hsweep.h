@@ -151,6 +151,15 @@ void hsweep_destroy(hsweep_ctx* ctx);
 /* Message for the last error on this thread ("" if none). */
 const char* hsweep_last_error(void);
 
+/* Factor as hsweep_factor does, but with plain launches (no graph) and HIP
+ * events recorded on `stream` around each kernel class, every layer queued
+ * before one synchronization.  out[0]: total milliseconds of the layer
+ * kernels (recompression and leaves, one launch per layer), out[1]: total
+ * milliseconds of the Woodbury kernels (L+1 launches per layer), out[2]:
+ * number of layers.  count >= 3.  The factor is usable afterwards.
+ * For measurement (Alg. 2.3 timed per kernel); synchronizes `stream`. */
+int hsweep_factor_profile(hsweep_ctx* ctx, void* stream, double* out, int count);
+
 /* Per-phase device times in milliseconds of the last factor and solve on
  * this context, measured with HIP events: out[0] factor, out[1] sweep
  * (all applies of the last solve), out[2] stencil, out[3] Krylov vector

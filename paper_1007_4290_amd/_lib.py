@@ -29,6 +29,7 @@ EXPORTED = [
     "hsweep_default_opts", "hsweep_setup", "hsweep_set_opts", "hsweep_get_opts", "hsweep_plan_info",
     "hsweep_factor", "hsweep_apply", "hsweep_stencil", "hsweep_solve", "hsweep_grad_c",
     "hsweep_factor_batch", "hsweep_solve_batch", "hsweep_destroy", "hsweep_last_error", "hsweep_timings",
+    "hsweep_factor_profile",
 ]
 
 
@@ -81,6 +82,7 @@ def load():
         "hsweep_destroy": (None, [vp]),
         "hsweep_last_error": (ctypes.c_char_p, []),
         "hsweep_timings": (i, [vp, dp, i]),
+        "hsweep_factor_profile": (i, [vp, vp, dp, i]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

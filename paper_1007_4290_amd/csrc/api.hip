@@ -296,6 +296,58 @@ int do_factor_one(hsweep_ctx* ctx, hipStream_t s) {
     return HSWEEP_OK;
 }
 
+// The factorization with HIP events around each kernel class, all layers
+// queued before one synchronization (so no launch latency falls inside an
+// interval): layer_ms sums the layer kernels (recompression and leaves),
+// wood_ms the Woodbury kernels of every level.
+template <typename T>
+int do_factor_profile(hsweep_ctx* ctx, hipStream_t s, double* layer_ms, double* wood_ms) {
+    InstDesc<T> d;
+    int rc = prepare_factor<T>(ctx, s, d);
+    if (rc) return rc;
+    const Plan plan = ctx->plan;
+    DevBuf dd;
+    HIPCHK(dd.ensure(sizeof(d)));
+    HIPCHK(hipMemcpyAsync(dd.p, &d, sizeof(d), hipMemcpyHostToDevice, s));
+    factor_kernels_init<T>();
+    std::vector<hipEvent_t> ev((size_t)3 * plan.n, nullptr);
+    for (auto& e : ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& x : ev)
+                if (x) (void)hipEventDestroy(x);
+            dd.release();
+            return fail(HSWEEP_EDEVICE, "event creation failed");
+        }
+    }
+    for (int m = 0; m < plan.n && rc == HSWEEP_OK; ++m) {
+        (void)hipEventRecord(ev[3 * m], s);
+        if (launch_factor_layer<T>((const InstDesc<T>*)dd.p, &plan, 1, m, s, ev[3 * m + 1]) != 0)
+            rc = fail(HSWEEP_EINVAL, "no factorization kernels for this plan");
+        (void)hipEventRecord(ev[3 * m + 2], s);
+    }
+    const hipError_t e = hipStreamSynchronize(s);
+    double tl = 0.0, tw = 0.0;
+    if (rc == HSWEEP_OK && e == hipSuccess) {
+        for (int m = 0; m < plan.n; ++m) {
+            float a = 0.f, b = 0.f;
+            (void)hipEventElapsedTime(&a, ev[3 * m], ev[3 * m + 1]);
+            (void)hipEventElapsedTime(&b, ev[3 * m + 1], ev[3 * m + 2]);
+            tl += a;
+            tw += b;
+        }
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    dd.release();
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(HSWEEP_EDEVICE, std::string("factor: ") + hipGetErrorString(e));
+    int st = 0;
+    HIPCHK(hipMemcpy(&st, ctx->status.p, sizeof(int), hipMemcpyDeviceToHost));
+    if (st) return fail(HSWEEP_ESINGULAR, "zero pivot in a leaf or core inverse");
+    *layer_ms = tl;
+    *wood_ms = tw;
+    return HSWEEP_OK;
+}
+
 template <typename T>
 int do_apply(hsweep_ctx* ctx, const c128* f, c128* u, int nrhs, const int* active, hipStream_t s) {
     const Plan& p = ctx->plan;
@@ -822,6 +874,33 @@ void hsweep_destroy(hsweep_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     delete ctx;
+}
+
+int hsweep_factor_profile(hsweep_ctx* ctx, void* stream, double* out, int count) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out || count < 3) return fail(HSWEEP_EINVAL, "out must hold count >= 3 doubles");
+    if (!ctx->planned) {
+        Plan p;
+        rc = make_plan(ctx, p);
+        if (rc) return rc;
+        ctx->plan = p;
+        ctx->planned = true;
+    }
+    rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->factored = false;
+    double tl = 0.0, tw = 0.0;
+    rc = ctx->opts.precision == HSWEEP_C64 ? do_factor_profile<float>(ctx, s, &tl, &tw)
+                                           : do_factor_profile<double>(ctx, s, &tl, &tw);
+    if (rc) return rc;
+    ctx->factored = true;
+    out[0] = tl;
+    out[1] = tw;
+    out[2] = (double)ctx->plan.n;
+    return HSWEEP_OK;
 }
 
 int hsweep_timings(const hsweep_ctx* ctx, double* out, int count) {

@@ -76,8 +76,11 @@ struct InstDesc {
 // Launches layer step m of every instance in `descs` (device array of ninst
 // descriptors; `plans` are host copies of their plans).  All instances share
 // the element type, leaf size and rank; instances with n <= m are skipped.
+// If `after_layer` is given it is recorded on `s` between the layer kernel
+// and the Woodbury kernels (for per-kernel timing).
 template <typename T>
-int launch_factor_layer(const InstDesc<T>* descs, const Plan* plans, int ninst, int m, hipStream_t s);
+int launch_factor_layer(const InstDesc<T>* descs, const Plan* plans, int ninst, int m, hipStream_t s,
+                        hipEvent_t after_layer = nullptr);
 // Sets the kernels' LDS limits (done once; must precede a stream capture).
 template <typename T>
 void factor_kernels_init();

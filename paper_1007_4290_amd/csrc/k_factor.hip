@@ -1685,7 +1685,8 @@ bool factor_supported(const Plan& p) {
 }
 
 template <typename T>
-int launch_factor_layer(const InstDesc<T>* descs, const Plan* plans, int ninst, int m, hipStream_t s) {
+int launch_factor_layer(const InstDesc<T>* descs, const Plan* plans, int ninst, int m, hipStream_t s,
+                        hipEvent_t after_layer) {
     set_lds_limits<T>();
     const int b = plans[0].b, L0 = plans[0].L;
     const int rr = L0 > 0 ? plans[0].r : 2;   // dense leaves: no low-rank data
@@ -1698,6 +1699,7 @@ int launch_factor_layer(const InstDesc<T>* descs, const Plan* plans, int ninst, 
 #define C_LAYER(BB, RR)                                                               \
     if (!ok && b == BB && rr == RR) {                                                 \
         launch_layer<T, BB, RR>(descs, plans, ninst, m, s);                           \
+        if (after_layer) (void)hipEventRecord(after_layer, s);                        \
         for (int lam = Lmax; lam >= 0 && Lmax > 0; --lam)                             \
             launch_wood<T, BB, RR>(descs, plans, ninst, m, lam, s);                   \
         ok = true;                                                                    \
@@ -1714,5 +1716,5 @@ void factor_kernels_init() {
 template void factor_kernels_init<float>();
 template void factor_kernels_init<double>();
 
-template int launch_factor_layer<float>(const InstDesc<float>*, const Plan*, int, int, hipStream_t);
-template int launch_factor_layer<double>(const InstDesc<double>*, const Plan*, int, int, hipStream_t);
+template int launch_factor_layer<float>(const InstDesc<float>*, const Plan*, int, int, hipStream_t, hipEvent_t);
+template int launch_factor_layer<double>(const InstDesc<double>*, const Plan*, int, int, hipStream_t, hipEvent_t);

@@ -88,6 +88,15 @@ class Solver:
         return {"factor_ms": out[0], "sweep_ms": out[1], "stencil_ms": out[2], "krylov_ms": out[3],
                 "applies": int(out[4])}
 
+    def profile_factor(self, stream=None):
+        """Factor with HIP events around each kernel class; returns the total
+        milliseconds of the layer kernels and of the Woodbury kernels and the
+        number of layers (one layer kernel launch each)."""
+        out = (ctypes.c_double * 3)()
+        _lib.check(_lib.load().hsweep_factor_profile(self._ctx, _stream_ptr(stream), out, 3))
+        self.factored = True
+        return {"layer_ms": out[0], "wood_ms": out[1], "layers": int(out[2])}
+
     # -- operations --------------------------------------------------------
     def factor(self, stream=None):
         _lib.check(_lib.load().hsweep_factor(self._ctx, _stream_ptr(stream)))

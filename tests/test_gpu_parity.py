@@ -228,3 +228,20 @@ def test_error_codes_on_device():
     with pytest.raises(_lib.HsweepError) as e:
         s.solve(f, tol=1e-14, maxit=1)
     assert e.value.code == _lib.ENOCONV
+
+
+def test_factor_profile_gives_the_same_factor():
+    # the per-kernel timed factorization (plain launches) and the graph replay
+    # must produce identical factors
+    _need_gpu()
+    c, omega, npml = _problem(127, 16, 8)
+    s = _Solver()(c, omega, npml, leaf=16, rank=8, rank_tol=1e-6, precision="c64")
+    f = _t(W.gaussian_source(127, (0.5, 0.5)).reshape(1, -1))
+    s.factor()
+    a = s.apply(f).cpu().numpy()
+    s.factor()                              # graph replay
+    b = s.apply(f).cpu().numpy()
+    prof = s.profile_factor()
+    c2 = s.apply(f).cpu().numpy()
+    assert np.array_equal(a, b) and np.array_equal(a, c2)
+    assert prof["layers"] == 127 and prof["layer_ms"] > 0 and prof["wood_ms"] > 0
