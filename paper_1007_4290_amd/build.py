@@ -17,8 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhsweep.so")
 
-SOURCES = ["api.hip", "k_coeff.hip", "k_factor.hip", "k_sweep.hip", "k_sweep_a.hip", "k_sweep_b.hip",
-           "k_sweep_c.hip", "k_krylov.hip"]
+SOURCES = ["api.hip", "k_coeff.hip", "k_factor.hip", "k_factor_f64.hip", "k_sweep.hip", "k_sweep_a.hip",
+           "k_sweep_b.hip", "k_sweep_c.hip", "k_krylov.hip"]
 
 ARCH = ["--offload-arch=gfx950"]
 FLAGS = ARCH + [
