@@ -992,7 +992,12 @@ struct RecompLayout {
     size_t oU, oV, oY1, oY2, oV0u, oV0v, oEnd;   // cpx<T> units
     size_t dN, dJ, dS, dEnd;                     // cpx<CT> units (after oEnd)
     size_t gGu, gGv, gRu, gRv, gYu, gYv, gEnd;   // c128 units (after dEnd; Gram path only)
+    size_t gTu, gTv;                             // inverses of R11 (Gram path, when they fit)
+    bool tinv;
 };
+
+// LDS bound up to which the Gram path also keeps the two R11 inverses
+constexpr size_t TINV_LDS_MAX = 150 * 1024;
 
 // The Gram path (complex64 factors, truncation on, k <= GRAM_KMAX) replaces
 // the Householder QR of the stacked factors by a pivoted Cholesky of their
@@ -1054,6 +1059,9 @@ __host__ __device__ inline RecompLayout recomp_layout(int s, int k, int r, int X
     l.gRv = g; if (gram) g += (size_t)l.kk * k;
     l.gYu = g; if (gram) g += (size_t)l.kk * r;
     l.gYv = g; if (gram) g += (size_t)l.kk * r;
+    l.tinv = gram && (g + 2 * (size_t)l.kk * l.kk) * sizeof(c128) <= TINV_LDS_MAX;
+    l.gTu = g; if (l.tinv) g += (size_t)l.kk * l.kk;
+    l.gTv = g; if (l.tinv) g += (size_t)l.kk * l.kk;
     l.gEnd = g;
     return l;
 }
@@ -1091,6 +1099,8 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
     c128* RV = (c128*)smem + ly.gRv;
     c128* YU = (c128*)smem + ly.gYu;
     c128* YV = (c128*)smem + ly.gYv;
+    c128* TU = (c128*)smem + ly.gTu;
+    c128* TV = (c128*)smem + ly.gTv;
     const int tid = threadIdx.x, wv = tid >> 6;
     const int lda = ly.lda, ldy = ly.ldy;
 
@@ -1239,6 +1249,30 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
         const bool keep = lane < P && rk < R && s1 > CT(0) && mine > t2 * s1 && mine > CT(0);
         const unsigned long long bal = __ballot(keep);
         if (lane == 0) rank_s = __popcll(bal);
+    } else if (ly.tinv && wv <= 2) {
+        // meanwhile waves 1 and 2 invert the triangular R11 of each side in
+        // FP64 (R11(j, t) = R(j, perm(t)), t >= j; inverse upper triangular,
+        // row-major, leading dimension kk): lane c forms column c, row by row
+        // upwards from the diagonal, from its own earlier entries
+        const bool sv = wv == 2;
+        const int kr = sv ? k2 : k1;
+        const int* pm = sv ? perm_v : perm_u;
+        const lds<c128>* Rm = to_lds(sv ? RV : RU);
+        lds<c128>* Tm = to_lds(sv ? TV : TU);
+        const int c = tid & 63, kk = ly.kk;
+        for (int jj = kr - 1; jj >= 0; --jj) {
+            const double idg = 1.0 / ldc(Rm + (size_t)jj * k + pm[jj]).re;
+            if (c >= jj && c < kr) {
+                c128 a0 = c == jj ? mk<double>(1.0, 0.0) : czero<double>(), a1 = czero<double>();
+                int mm = jj + 1;
+                for (; mm + 2 <= c + 1; mm += 2) {
+                    a0 -= ldc(Rm + (size_t)jj * k + pm[mm]) * ldc(Tm + (size_t)mm * kk + c);
+                    a1 -= ldc(Rm + (size_t)jj * k + pm[mm + 1]) * ldc(Tm + (size_t)(mm + 1) * kk + c);
+                }
+                if (mm <= c) a0 -= ldc(Rm + (size_t)jj * k + pm[mm]) * ldc(Tm + (size_t)mm * kk + c);
+                stc(Tm + (size_t)jj * kk + c, idg * (a0 + a1));
+            }
+        }
     }
     __syncthreads();
     const int rho = rank_s;
@@ -1266,7 +1300,29 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
         }
     }
     __syncthreads();
-    if (gram) {
+    if (gram && ly.tinv) {
+        // U_new = U Pi[:, :k1] (R11^-1 Y): Z = R11^-1 Y from the inverse formed
+        // during the Jacobi (over the dead core area, same layout as Y), then
+        // the product below
+        for (int e = tid; e < 2 * R * ly.kk; e += NT) {
+            const bool sv = e >= R * ly.kk;
+            const int ee = sv ? e - R * ly.kk : e;
+            const int q = ee / ly.kk, tt = ee % ly.kk;
+            const int kr = sv ? k2 : k1;
+            const lds<c128>* Tm = to_lds(sv ? TV : TU) + (size_t)tt * ly.kk;
+            const lds<c128>* y = to_lds(sv ? YV : YU) + (size_t)q * ly.kk;
+            c128 a0 = czero<double>(), a1 = czero<double>();
+            if (q < rho && tt < kr) {
+                int mm = tt;
+                for (; mm + 2 <= kr; mm += 2) {
+                    cfma(a0, ldc(Tm + mm), ldc(y + mm));
+                    cfma(a1, ldc(Tm + mm + 1), ldc(y + mm + 1));
+                }
+                if (mm < kr) cfma(a0, ldc(Tm + mm), ldc(y + mm));
+            }
+            stc(to_lds(GU + (sv ? (size_t)R * ly.kk : 0)) + ee, a0 + a1);
+        }
+    } else if (gram) {
         // U_new = U Pi[:, :k1] R11^-1 Y: back substitution in place, then the
         // product with FP64 accumulation, which cancels the conditioning of R11
         // (U_new = Q1 Y with Q1 orthonormal).  R11 is first gathered densely in
@@ -1302,6 +1358,8 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
                 }
             }
         }
+    }
+    if (gram) {
         __syncthreads();
         // one thread per row and side, all output columns: the Z entries are
         // broadcast loads, the row's U entries one load per pivot
@@ -1311,7 +1369,7 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
             const int kr = sv ? k2 : k1;
             const int* pm = sv ? perm_v : perm_u;
             const lds<cpx<T>>* X = to_lds(sv ? Vt : Ut) + i;
-            const lds<c128>* z = to_lds(sv ? YV : YU);
+            const lds<c128>* z = ly.tinv ? to_lds(GU + (sv ? (size_t)R * ly.kk : 0)) : to_lds(sv ? YV : YU);
             c128 acc[R];
 #pragma unroll
             for (int q = 0; q < R; ++q) acc[q] = czero<double>();
