@@ -960,14 +960,25 @@ __device__ __forceinline__ int wave_pchol(const c128* Gg, int k, int kmax, c128*
         if (!(key > stop)) { kr = j; break; }
         const double rpp = sqrt(key);
         c128 val = ldc(G + (size_t)cc * k + p);          // G[p][c]
-        c128 s0 = czero<double>(), s1 = s0;
-        int t = 0;
-        for (; t + 2 <= j; t += 2) {
-            cfma_conj(s0, ldc(Rr + (size_t)t * k + p), ldc(Rr + (size_t)t * k + cc));
-            cfma_conj(s1, ldc(Rr + (size_t)(t + 1) * k + p), ldc(Rr + (size_t)(t + 1) * k + cc));
+        // the dot over the rows so far in chunks of 4, one accumulator per
+        // chunk position (four independent FMA chains); all 8 loads are in
+        // flight before the first use (rows past j - 1 are clamped and zeroed)
+        c128 s0 = czero<double>(), s1 = s0, s2 = s0, s3 = s0;
+        for (int t0 = 0; t0 < j; t0 += 4) {
+            c128 ap[4], ac[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = min(t0 + u, j - 1);
+                ap[u] = ldc(Rr + (size_t)t * k + p);
+                ac[u] = ldc(Rr + (size_t)t * k + cc);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            cfma_conj(s0, ap[0], ac[0]);
+            cfma_conj(s1, t0 + 1 < j ? ap[1] : czero<double>(), ac[1]);
+            cfma_conj(s2, t0 + 2 < j ? ap[2] : czero<double>(), ac[2]);
+            cfma_conj(s3, t0 + 3 < j ? ap[3] : czero<double>(), ac[3]);
         }
-        if (t < j) cfma_conj(s0, ldc(Rr + (size_t)t * k + p), ldc(Rr + (size_t)t * k + cc));
-        val -= s0 + s1;
+        val -= (s0 + s1) + (s2 + s3);
         const double ir = 1.0 / rpp;
         c128 r = chosen ? czero<double>() : (c == p ? mk(rpp, 0.0) : ir * val);
         if (!chosen && c != p) d -= abs2(r);
@@ -1823,10 +1834,6 @@ __global__ __launch_bounds__(NT) void wood_pf_kernel(const InstDesc<T>* __restri
         }
     }
     __syncthreads();
-    if (has_core) {
-        gbl<cpx<T>>* Xg = to_gbl(sp.X) + (size_t)node * 4 * RR;
-        for (int e = tid; e < 4 * RR; e += NT) stg(Xg + e, ldc(Xo + e));
-    }
 
     // phase 1: K Q_c into registers; chunk partials of P_lc^t Q_c, all levels
     cpx<T> acc[KH];
@@ -1907,14 +1914,12 @@ __global__ __launch_bounds__(NT) void wood_pf_kernel(const InstDesc<T>* __restri
             }
         }
     }
-    // (b3) P_c = T_c Q_c ; G_c = Q_c^t P_c
+    // (b3) P_c = T_c Q_c ; G_c = Q_c^t P_c.  Every global store waits until
+    // the end: a store's data registers are not reused while it is in flight,
+    // so a store followed by more work would stall that work.
     if (rowt) {
-        gbl<cpx<T>>* Pw = to_gbl(sp.P) + (size_t)(lam - 1) * R * np + lo + i;
 #pragma unroll
-        for (int k = 0; k < KH; ++k) {
-            stc(Y + i * R + k0 + k, acc[k]);
-            stg(Pw + (size_t)(k0 + k) * np, acc[k]);
-        }
+        for (int k = 0; k < KH; ++k) stc(Y + i * R + k0 + k, acc[k]);
     }
     __syncthreads();
     for (int e = tid; e < nch * RR; e += NT) {
@@ -1933,6 +1938,15 @@ __global__ __launch_bounds__(NT) void wood_pf_kernel(const InstDesc<T>* __restri
         cpx<T> a = czero<T>();
         for (int ch = 0; ch < nch; ++ch) a += ldc(part + e * nch + ch);
         stg(Gw + e, a);
+    }
+    if (rowt) {
+        gbl<cpx<T>>* Pw = to_gbl(sp.P) + (size_t)(lam - 1) * R * np + lo + i;
+#pragma unroll
+        for (int k = 0; k < KH; ++k) stg(Pw + (size_t)(k0 + k) * np, acc[k]);
+    }
+    if (has_core) {
+        gbl<cpx<T>>* Xg = to_gbl(sp.X) + (size_t)node * 4 * RR;
+        for (int e = tid; e < 4 * RR; e += NT) stg(Xg + e, ldc(Xo + e));
     }
 }
 
