@@ -35,6 +35,11 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3      # MI355X vector FP32 (256 CUs at 2.4 GHz)
 FP64_PEAK_TFLOPS = 78.6
 METRIC = "2D Helmholtz solves/s at rel. residual 1e-6: complex64 vs FP64 sweep"
+# HBM bytes per launch of layer_kernel<float, 16, 8> on this workload: FETCH_SIZE
+# + WRITE_SIZE from two rocprofv3 counter passes, each scaled by what the counter
+# reads for a 1 GiB device-to-device copy (profiles/layer_kernel_pmc_helm255.md).
+# Counters cannot be read inside a timed run; a change to the kernel voids this.
+LAYER_KERNEL_HBM_BYTES = 1013233
 
 
 def sweep_bytes(plan, n, elem, nrhs=1):
@@ -150,12 +155,27 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (the "
+                         "calibration kernel for the HBM byte counters); not part of the timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import workloads as W
+
+    if args.copy_probe_mib > 0:
+        import torch
+        n4 = (args.copy_probe_mib << 20) // 4
+        src = torch.ones(n4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] copy probe: {args.copy_probe_mib} MiB read, {args.copy_probe_mib} MiB written",
+              file=sys.stderr, flush=True)
 
     tol = 1e-6
     wl = W.get("helm255_grf", precision="c64")
@@ -194,7 +214,8 @@ def main():
                  "gmres_iters": r128["iters"][0], "relres": r128["relres"]},
         "roofline": {"kernel": f"layer_kernel<float, {wl.leaf}, {wl.rank}>", "bound": "alu",
                      "achieved": l_ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": l_ach / FP32_PEAK_TFLOPS, "traffic": None, "flops_per_launch": lflops,
+                     "frac": l_ach / FP32_PEAK_TFLOPS, "traffic": LAYER_KERNEL_HBM_BYTES,
+                     "flops_per_launch": lflops,
                      "avg_launch_ms": r64["layer_kernel_ms_avg"],
                      "factor_share": r64["layer_kernel_ms_avg"] * wl.n / r64["factor_ms"],
                      "note": "latency bound: dependent steps on single wavefronts; Woodbury kernels "
