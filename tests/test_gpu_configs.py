@@ -96,6 +96,31 @@ def test_batched_factor_equals_single_factor():
         assert np.array_equal(a, b)
 
 
+def test_prefetching_and_plain_woodbury_kernels_agree():
+    # A batched launch takes the plain Woodbury kernel for a level when any
+    # instance cannot use the prefetching one there: nodes of more than 128
+    # rows (complex64, n = 1023, levels 1 and 2) or a prefetch layout over the
+    # LDS budget (complex128, n = 255, level 1).  The n = 127 instance alone
+    # takes the prefetching kernel at every level.  Both kernels sum in the
+    # same order, so the factors of the small instance agree to rounding.
+    _need_gpu()
+    from paper_1007_4290_amd.solver import Solver, factor_batch
+    c_small = W.random_field_medium(127, 11)
+    om_s = 2 * np.pi * 16
+    for prec, n_big, tol in (("c64", 1023, 1e-5), ("c128", 255, 1e-12)):
+        c_big = W.random_field_medium(n_big, 12)
+        om_b = 2 * np.pi * (n_big + 1) / 8
+        pair = [Solver(c_small, om_s, 16, leaf=16, rank=8, rank_tol=1e-6, precision=prec),
+                Solver(c_big, om_b, 24, leaf=16, rank=8, rank_tol=1e-6, precision=prec)]
+        factor_batch(pair)
+        alone = Solver(c_small, om_s, 16, leaf=16, rank=8, rank_tol=1e-6, precision=prec).factor()
+        rng = np.random.default_rng(5)
+        f = _t(rng.standard_normal(127 * 127) + 1j * rng.standard_normal(127 * 127))
+        a = pair[0].apply(f).cpu().numpy()
+        b = alone.apply(f).cpu().numpy()
+        assert _rel(a, b) < tol, (prec, _rel(a, b))
+
+
 def test_helm1023_lens_c64_residual():
     # n = 1023, omega = 2 pi 128, converging lens, PML 24, leaf 32, c64 factors and sweeps
     _need_gpu()
