@@ -27,8 +27,9 @@
 //                      truncate (sigma > tol*sigma_1, at most r), write Q.
 //                      blocks [2^L - 1, 2^(L+1) - 1): one per leaf, S_m leaf =
 //                      A - D T_{m-1} D, Gauss-Jordan inverse -> K.
-//   wood_kernel(l)     levels l = L..1, one block per node: X_c from the
-//                      children's G, then P_c = T_c Q_c and G_c = Q_c^t P_c.
+//   wood_pf_kernel(l)  levels l = L..1, one block per node: X_c from the
+//                      children's G, then P_c = T_c Q_c and G_c = Q_c^t P_c
+//                      (wood_kernel(l) where a node is too large for it).
 //   wood_kernel(0)     the root core X_0.
 #pragma once
 #include "internal.hpp"
