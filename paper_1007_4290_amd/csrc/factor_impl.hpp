@@ -746,9 +746,11 @@ __device__ __forceinline__ void wave_apply_q(const cpx<T>* A, int lda, int s, in
 // residual inner products.
 // GT: the lane-group size when known at compile time (then the butterflies
 // and the lane geometry are constants), 0 to take it from P at run time.
-template <typename CT, int NR, int GT>
+// NRJ: rows of J per lane (J has only P rows), at most NR.
+template <typename CT, int NR, int GT, int NRJ = NR>
 __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, CT* nrm2g, CT thr, CT gabs, CT tiny,
                                               int max_sweeps) {
+    static_assert(NRJ <= NR, "J has no more rows than N");
     lds<cpx<CT>>* N = to_lds(Ng);
     lds<cpx<CT>>* J = to_lds(Jg);
     lds<CT>* nrm2 = to_lds(nrm2g);
@@ -792,7 +794,7 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
                 for (int u = 0; u < CH; ++u) {
                     xa[u] = ldc(ca + G * (u0 + u));
                     xb[u] = ldc(cb + G * (u0 + u));
-                    if (ONE) {
+                    if (ONE && u < NRJ) {
                         ya[u] = ldc(ja + G * u);
                         yb[u] = ldc(jb + G * u);
                     }
@@ -829,17 +831,22 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
                         for (int u = 0; u < CH; ++u) {
                             xa[u] = ldc(ca + G * (u0 + u));
                             xb[u] = ldc(cb + G * (u0 + u));
-                            ya[u] = ldc(ja + G * (u0 + u));
-                            yb[u] = ldc(jb + G * (u0 + u));
+                            if (u0 + u < NRJ) {
+                                ya[u] = ldc(ja + G * (u0 + u));
+                                yb[u] = ldc(jb + G * (u0 + u));
+                            }
                         }
                     }
 #pragma unroll
                     for (int u = 0; u < CH; ++u) {
-                        const cpx<CT> x2 = em * xb[u], y2 = em * yb[u];
+                        const cpx<CT> x2 = em * xb[u];
                         stc(ca + G * (u0 + u), cs * xa[u] - sn * x2);
                         stc(cb + G * (u0 + u), sn * xa[u] + cs * x2);
-                        stc(ja + G * (u0 + u), cs * ya[u] - sn * y2);
-                        stc(jb + G * (u0 + u), sn * ya[u] + cs * y2);
+                        if (u0 + u < NRJ) {
+                            const cpx<CT> y2 = em * yb[u];
+                            stc(ja + G * (u0 + u), cs * ya[u] - sn * y2);
+                            stc(jb + G * (u0 + u), sn * ya[u] + cs * y2);
+                        }
                     }
                 }
             }
@@ -869,6 +876,7 @@ __host__ __device__ inline int jacobi_group(int P) {
 __host__ __device__ inline int jacobi_rows(int nr, int P) {
     const int G = jacobi_group(P);
     const int need = ((nr > P ? nr : P) + G - 1) / G;
+    if (need == 3) return 3;
     int r = 1;
     while (r < need) r <<= 1;
     return r;
@@ -881,6 +889,7 @@ __device__ __forceinline__ void wave_jacobi_g(cpx<CT>* N, int P, int NRr, cpx<CT
                                               CT tiny, int max_sweeps) {
     if (NRr == 1) wave_jacobi_n<CT, 1, GT>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
     else if (NRr == 2) wave_jacobi_n<CT, 2, GT>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else if (NRr == 3) wave_jacobi_n<CT, 3, GT>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
     else if (NRr == 4) wave_jacobi_n<CT, 4, GT>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
     else if (NRr == 8) wave_jacobi_n<CT, 8, GT>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
     else if (NRr == 16) wave_jacobi_n<CT, 16, GT>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps);
@@ -888,14 +897,26 @@ __device__ __forceinline__ void wave_jacobi_g(cpx<CT>* N, int P, int NRr, cpx<CT
 }
 
 // Group sizes 4, 8 and 16 (P from 7 to 32 columns) are compiled as constants.
+// With groups of 8 lanes (P from 9 to 16) J spans two rows per lane and with
+// groups of 16 (P from 5 to 8) one, however many rows N has.
 template <typename CT>
 __device__ __forceinline__ void wave_jacobi(cpx<CT>* N, int P, int NRr, cpx<CT>* J, CT* nrm2, CT thr, CT gabs,
                                             CT tiny, int max_sweeps) {
     const int G = jacobi_group(P);
+#define WJ(NRV, GV, NRJV) wave_jacobi_n<CT, NRV, GV, NRJV>(N, P, J, nrm2, thr, gabs, tiny, max_sweeps)
     if (G == 4 && NRr <= 16) wave_jacobi_g<CT, 4>(N, P, NRr, J, nrm2, thr, gabs, tiny, max_sweeps);
-    else if (G == 8 && NRr <= 8) wave_jacobi_g<CT, 8>(N, P, NRr, J, nrm2, thr, gabs, tiny, max_sweeps);
-    else if (G == 16 && NRr <= 4) wave_jacobi_g<CT, 16>(N, P, NRr, J, nrm2, thr, gabs, tiny, max_sweeps);
-    else wave_jacobi_g<CT, 0>(N, P, NRr, J, nrm2, thr, gabs, tiny, max_sweeps);
+    else if (G == 8 && NRr >= 2 && NRr <= 8) {
+        if (NRr == 2) WJ(2, 8, 2);
+        else if (NRr == 3) WJ(3, 8, 2);
+        else if (NRr == 4) WJ(4, 8, 2);
+        else WJ(8, 8, 2);
+    } else if (G == 16 && NRr <= 4) {
+        if (NRr == 1) WJ(1, 16, 1);
+        else if (NRr == 2) WJ(2, 16, 1);
+        else if (NRr == 3) WJ(3, 16, 1);
+        else WJ(4, 16, 1);
+    } else wave_jacobi_g<CT, 0>(N, P, NRr, J, nrm2, thr, gabs, tiny, max_sweeps);
+#undef WJ
 }
 
 // Gram matrices GA = A^H A and GB = B^H B (k x k, both triangles stored,
