@@ -952,7 +952,8 @@ __device__ __forceinline__ void gram_pair(const cpx<T>* A, const cpx<T>* B, int 
 }
 
 // Pivoted Cholesky (Crout form) of the k x k Hermitian positive semidefinite
-// G (column-major, k <= 64) by one wavefront; lane c owns column c.  Step j
+// G (column-major, k <= 64) by one wavefront; lane c owns column c (lanes
+// 2c and 2c + 1 when k <= 32).  Step j
 // takes the column p of largest Schur-complement diagonal d_p and forms row j
 // of R:  R[j][c] = (G[p][c] - sum_{t<j} conj(R[t][p]) R[t][c]) / sqrt(d_p)
 // for the columns not chosen yet, 0 for the others (so R holds R Pi^t, as the
@@ -966,53 +967,65 @@ __device__ __forceinline__ int wave_pchol(const c128* Gg, int k, int kmax, c128*
     lds<c128>* Rr = to_lds(Rg);
     lds<int>* perm = to_lds(permg);
     lds<int>* pos = to_lds(posg);
-    const int c = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
+    // with k <= 32 two lanes share a column and split its dot products
+    // (even and odd rows); both then hold the same values
+    const bool two = k <= 32;
+    const int c = two ? lane >> 1 : lane;
+    const int h = two ? lane & 1 : 0;
+    const int hs = two ? 2 : 1;
     const bool col = c < k;
     const int cc = col ? c : 0;
     double d = col ? ldc(G + (size_t)cc * k + cc).re : -1.0;
     double mx = d;
-    int unused = c;
+    int unused = lane;
     wops::argmax(mx, unused);
     const double stop = delta * delta * mx;
     bool chosen = !col;
     int kr = kmax;
     for (int j = 0; j < kmax; ++j) {
-        const int p = wops::argmax_nonneg((float)d, c, !chosen);
-        const double key = p >= 0 ? readlane_f(d, p) : -1.0;     // exact Schur diagonal of the pivot
+        const int p = wops::argmax_nonneg((float)d, c, !chosen && h == 0);
+        const double key = p >= 0 ? readlane_f(d, p * hs) : -1.0;   // exact Schur diagonal of the pivot
         if (!(key > stop)) { kr = j; break; }
         const double rpp = sqrt(key);
         c128 val = ldc(G + (size_t)cc * k + p);          // G[p][c]
-        // the dot over the rows so far in chunks of 4, one accumulator per
-        // chunk position (four independent FMA chains); all 8 loads are in
-        // flight before the first use (rows past j - 1 are clamped and zeroed)
+        // this lane's share of the dot over the rows so far (rows h, h + hs,
+        // ...) in chunks of 4, one accumulator per chunk position; all 8 loads
+        // are in flight before the first use (rows past j - 1 are zeroed)
         c128 s0 = czero<double>(), s1 = s0, s2 = s0, s3 = s0;
-        for (int t0 = 0; t0 < j; t0 += 4) {
+        for (int t0 = h; t0 < j; t0 += 4 * hs) {
             c128 ap[4], ac[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int t = min(t0 + u, j - 1);
+                const int t = min(t0 + u * hs, j - 1);
                 ap[u] = ldc(Rr + (size_t)t * k + p);
                 ac[u] = ldc(Rr + (size_t)t * k + cc);
             }
             __builtin_amdgcn_sched_barrier(0);
             cfma_conj(s0, ap[0], ac[0]);
-            cfma_conj(s1, t0 + 1 < j ? ap[1] : czero<double>(), ac[1]);
-            cfma_conj(s2, t0 + 2 < j ? ap[2] : czero<double>(), ac[2]);
-            cfma_conj(s3, t0 + 3 < j ? ap[3] : czero<double>(), ac[3]);
+            cfma_conj(s1, t0 + hs < j ? ap[1] : czero<double>(), ac[1]);
+            cfma_conj(s2, t0 + 2 * hs < j ? ap[2] : czero<double>(), ac[2]);
+            cfma_conj(s3, t0 + 3 * hs < j ? ap[3] : czero<double>(), ac[3]);
         }
-        val -= (s0 + s1) + (s2 + s3);
+        c128 sd = (s0 + s1) + (s2 + s3);
+        if (two) {
+            // add the partner lane's share (the sum is the same on both lanes)
+            sd.re += wops::dpp<wops::QP_XOR1>(sd.re, 0.0);
+            sd.im += wops::dpp<wops::QP_XOR1>(sd.im, 0.0);
+        }
+        val -= sd;
         const double ir = 1.0 / rpp;
         c128 r = chosen ? czero<double>() : (c == p ? mk(rpp, 0.0) : ir * val);
         if (!chosen && c != p) d -= abs2(r);
-        if (col) stc(Rr + (size_t)j * k + c, r);
-        if (c == 0) {
+        if (col && h == 0) stc(Rr + (size_t)j * k + c, r);
+        if (lane == 0) {
             perm[j] = p;
             pos[p] = j;
         }
         if (c == p) chosen = true;
         wave_sync();
     }
-    if (col && !chosen) pos[c] = k;
+    if (col && h == 0 && !chosen) pos[c] = k;
     wave_sync();
     return kr;
 }
