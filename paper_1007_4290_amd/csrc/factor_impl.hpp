@@ -1757,7 +1757,7 @@ __host__ __device__ inline WoodPfLayout wood_pf_layout(int s, int r, int b, int 
     size_t o = 0;
     w.oQ = o; o += (size_t)s * r;                                  // Q_c rows   [i][k]
     w.oY = o; o += (size_t)s * r;                                  // T_c Q_c    [i][k]
-    w.oP = o; o += (size_t)nl * r * s;                             // P levels lam+1..L  [l][k][i]
+    w.oP = o; o += (size_t)nl * r * (s + 2);                       // P levels lam+1..L  [l][k][i], ld s + 2
     w.oX = o; o += nl >= 1 ? ((size_t)(1 << nl) - 2) * 4 * rr : 0; // X of levels lam+1..L-1
     w.oC = o; o += nl >= 1 ? 5 * rr : 0;                           // core scratch
     w.oXo = o; o += nl >= 1 ? 4 * rr : 0;                          // core inverse X_c
@@ -1845,7 +1845,7 @@ __global__ __launch_bounds__(NT) void wood_pf_kernel(const InstDesc<T>* __restri
                 const int qi = e & (s - 1), qk = e >> ls;
                 // P entry f = (l*R + k)*s + row: contiguous rows of each column
                 const int f = e - nQ;
-                const int fr = f & (s - 1), fc = f >> ls;
+                const int fr = f & (s - 1), fc = f >> ls;        // stored with leading dimension s + 2
                 // X entry g: node group j (level lam + j, 2^j nodes) found from g / (4 R^2) + 2
                 const int g = e - nQ - nP;
                 const int gn = (g >= 0 ? g : 0) / (4 * RR) + 2;
@@ -1859,7 +1859,7 @@ __global__ __launch_bounds__(NT) void wood_pf_kernel(const InstDesc<T>* __restri
                 const uint64_t aP = (uint64_t)(Pv + (size_t)fc * np + fr);
                 const uint64_t aX = (uint64_t)(Xv + (size_t)first * 4 * RR + gl);
                 const gbl<cpx<T>>* src = (const gbl<cpx<T>>*)((aQ & mQ) | (aP & mP) | (aX & mX));
-                dst[u] = (((int)wl.oQ + qi * R + qk) & (int)mQ) | (((int)wl.oP + f) & (int)mP) |
+                dst[u] = (((int)wl.oQ + qi * R + qk) & (int)mQ) | (((int)wl.oP + fc * (s + 2) + fr) & (int)mP) |
                          (((int)wl.oX + g) & (int)mX);
                 v[u] = ldg(src);
             }
@@ -1881,14 +1881,17 @@ __global__ __launch_bounds__(NT) void wood_pf_kernel(const InstDesc<T>* __restri
 #pragma unroll
             for (int k = 0; k < KH; ++k) cfma(acc[k], kr[jj], ldc(qb + jj * R + k));
     }
-    // the partial tasks follow the row tasks in one list over the threads
+    // the partial tasks follow the row tasks in one list over the threads;
+    // neighbouring threads take the same chunk (broadcast Q_c reads) and
+    // different columns k1 (P rows padded to s + 2 entries: different banks)
+    const int ldp = s + 2;
     const int nrt = s * HPR, npt = nl * nch * R;
     for (int v = tid; v < nrt + npt; v += NT) {
         if (v < nrt) continue;
         const int pe = v - nrt;
         const int lI = pe >> (lnch + LR), rem = pe & ((nch << LR) - 1);
-        const int ch = rem & (nch - 1), k1 = rem >> lnch;
-        const lds<cpx<T>>* pc = Pc + ((size_t)lI * R + k1) * s + ch * B;
+        const int k1 = rem & (R - 1), ch = rem >> LR;
+        const lds<cpx<T>>* pc = Pc + ((size_t)lI * R + k1) * ldp + ch * B;
         const lds<cpx<T>>* qc = Qc + (size_t)ch * B * R;
         cpx<T> a2[R];
 #pragma unroll
@@ -1900,7 +1903,7 @@ __global__ __launch_bounds__(NT) void wood_pf_kernel(const InstDesc<T>* __restri
             for (int k2 = 0; k2 < R; ++k2) cfma(a2[k2], pv, ldc(qc + jj * R + k2));
         }
 #pragma unroll
-        for (int k2 = 0; k2 < R; ++k2) stc(part + ((size_t)lI * RR + k1 * R + k2) * nch + ch, a2[k2]);
+        for (int k2 = 0; k2 < R; ++k2) stc(part + ((size_t)lI * nch + ch) * RR + k1 * R + k2, a2[k2]);
     }
     if (nl >= 1) {
         __syncthreads();
@@ -1911,9 +1914,9 @@ __global__ __launch_bounds__(NT) void wood_pf_kernel(const InstDesc<T>* __restri
             const int el = e - ((2 << lI) - 2) * RR;
             const int c = el / RR, kk = el % RR;
             const int cpn = nch >> (lI + 1);
-            const lds<cpx<T>>* pp = part + ((size_t)lI * RR + kk) * nch + c * cpn;
+            const lds<cpx<T>>* pp = part + ((size_t)lI * nch + c * cpn) * RR + kk;
             cpx<T> a = czero<T>();
-            for (int q = 0; q < cpn; ++q) a += ldc(pp + q);
+            for (int q = 0; q < cpn; ++q) a += ldc(pp + (size_t)q * RR);
             stc(ys + e, a);
         }
         __syncthreads();
@@ -1938,7 +1941,7 @@ __global__ __launch_bounds__(NT) void wood_pf_kernel(const InstDesc<T>* __restri
                 const lds<cpx<T>>* z = zs + ((2 << lI) - 2) * RR + (size_t)(q * R2 + sg * R) * R + k0;
                 cpx<T> pr[R];
 #pragma unroll
-                for (int k1 = 0; k1 < R; ++k1) pr[k1] = ldc(Pc + ((size_t)lI * R + k1) * s + i);
+                for (int k1 = 0; k1 < R; ++k1) pr[k1] = ldc(Pc + ((size_t)lI * R + k1) * ldp + i);
 #pragma unroll
                 for (int k = 0; k < KH; ++k) {
                     cpx<T> a = czero<T>();
@@ -1958,20 +1961,21 @@ __global__ __launch_bounds__(NT) void wood_pf_kernel(const InstDesc<T>* __restri
     }
     __syncthreads();
     for (int e = tid; e < nch * RR; e += NT) {
-        const int ch = e & (nch - 1), k1 = (e >> lnch) & (R - 1), k2 = e >> (lnch + LR);
+        // neighbouring threads: same chunk and k1 (broadcast), consecutive k2
+        const int k2 = e & (R - 1), k1 = (e >> LR) & (R - 1), ch = e >> (2 * LR);
         cpx<T> a = czero<T>();
 #pragma unroll
         for (int jj = 0; jj < B; ++jj) {
             const int ii = ch * B + jj;
             cfma(a, ldc(Qc + ii * R + k1), ldc(Y + ii * R + k2));
         }
-        stc(part + (k1 * R + k2) * nch + ch, a);
+        stc(part + (size_t)ch * RR + k1 * R + k2, a);
     }
     __syncthreads();
     gbl<cpx<T>>* Gw = to_gbl(sp.G) + (size_t)node * RR;
     for (int e = tid; e < RR; e += NT) {
         cpx<T> a = czero<T>();
-        for (int ch = 0; ch < nch; ++ch) a += ldc(part + e * nch + ch);
+        for (int ch = 0; ch < nch; ++ch) a += ldc(part + (size_t)ch * RR + e);
         stg(Gw + e, a);
     }
     if (rowt) {
