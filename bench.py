@@ -39,7 +39,7 @@ METRIC = "2D Helmholtz solves/s at rel. residual 1e-6: complex64 vs FP64 sweep"
 # + WRITE_SIZE from two rocprofv3 counter passes, each scaled by what the counter
 # reads for a 1 GiB device-to-device copy (profiles/layer_kernel_pmc_helm255.md).
 # Counters cannot be read inside a timed run; a change to the kernel voids this.
-LAYER_KERNEL_HBM_BYTES = 944509
+LAYER_KERNEL_HBM_BYTES = 981244
 
 
 def sweep_bytes(plan, n, elem, nrhs=1):
