@@ -40,6 +40,8 @@ METRIC = "2D Helmholtz solves/s at rel. residual 1e-6: complex64 vs FP64 sweep"
 # reads for a 1 GiB device-to-device copy (profiles/layer_kernel_pmc_helm255.md).
 # Counters cannot be read inside a timed run; a change to the kernel voids this.
 LAYER_KERNEL_HBM_BYTES = 981244
+# The same two passes for one complex64 sweep launch (one right-hand side).
+SWEEP_KERNEL_HBM_BYTES = 66189250
 
 
 def sweep_bytes(plan, n, elem, nrhs=1):
@@ -222,7 +224,7 @@ def main():
                              f"{r64['wood_ms_per_factor']:.1f} ms per factorization"},
         "roofline_sweep": {"kernel": "sweep_kernel<float>", "bound": "hbm", "achieved": achieved,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": None, "bytes_per_launch": nbytes,
+                           "traffic": SWEEP_KERNEL_HBM_BYTES, "bytes_per_launch": nbytes,
                            "avg_launch_ms": r64["sweep_ms_avg"]},
     }
     if not args.no_cpu:
