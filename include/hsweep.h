@@ -125,6 +125,26 @@ int hsweep_stencil(hsweep_ctx* ctx, const void* x, void* y, int nrhs, void* stre
 int hsweep_solve(hsweep_ctx* ctx, const void* f, void* u, int nrhs, double tol,
                  int maxit, int* iters, double* relres, void* stream);
 
+/* Adjoint solve for the gradient of a real functional J(u) of the solution
+ * u = A^{-1} f (configs with a receiver misfit, Sec. 2.1: A = A^t).  g holds
+ * dJ/dRe(u) + i dJ/dIm(u) for nrhs fields (device complex128, nrhs*n*n).
+ * Solves A mu = conj(g) with the same factorization and flexible GMRES as
+ * hsweep_solve (tol, maxit, iters, relres as there) and, when grad_f is not
+ * NULL, writes grad_f = conj(mu) = dJ/dRe(f) + i dJ/dIm(f).  The velocity
+ * gradient follows from hsweep_grad_c(ctx, u, mu, ...).  g, mu and grad_f
+ * must not overlap.  Synchronizes `stream`; ENOCONV as hsweep_solve (mu and
+ * grad_f then hold the last iterate). */
+int hsweep_solve_adjoint(hsweep_ctx* ctx, const void* g, void* mu, void* grad_f, int nrhs, double tol,
+                         int maxit, int* iters, double* relres, void* stream);
+
+/* Device bytes the library allocates for this context with its current
+ * options: *factor_bytes for setup and hsweep_factor (coefficients, layer
+ * operators, factor store and the factorization's per-layer work) and
+ * *solve_bytes for an hsweep_solve of nrhs right-hand sides (sweep work
+ * vectors, the GMRES basis and residual fields, small reduction arrays).
+ * Either pointer may be NULL.  Host-only; EINVAL if nrhs is out of range. */
+int hsweep_workspace_bytes(const hsweep_ctx* ctx, int nrhs, size_t* factor_bytes, size_t* solve_bytes);
+
 /* Gradient of a real functional with respect to c through the adjoint
  * fields: grad[p] = sum_k Re( mu_k[p] u_k[p] 2 omega^2 / ((s1 s2)[p] c[p]^3) ),
  * the c-derivative of the diagonal of A (eq. helmd) contracted with the

@@ -33,6 +33,17 @@ def misfit(c, omega, pml, F, receivers, data, C=DEFAULT_C):
 
 def adjoint_gradient(c, omega, pml, F, receivers, data, C=DEFAULT_C):
     """Returns (J, dJ/dc as an (n, n) array)."""
+    J, grad, _, _ = adjoint_state(c, omega, pml, F, receivers, data, C)
+    return J, grad
+
+
+def adjoint_state(c, omega, pml, F, receivers, data, C=DEFAULT_C):
+    """Returns (J, dJ/dc, the fields U, the adjoint fields Mu).
+
+    J is linear-quadratic in the sources as well: u_s = A^{-1} f_s gives
+    dJ = Re sum_s mu_s^t df_s (A = A^t), so the gradient with respect to the
+    real and imaginary parts of f_s, packed as dJ/dRe f + i dJ/dIm f, is
+    conj(mu_s)."""
     st, lu, U = forward(c, omega, pml, F, C)
     n = st.n
     r = U[:, receivers] - data
@@ -42,7 +53,7 @@ def adjoint_gradient(c, omega, pml, F, receivers, data, C=DEFAULT_C):
     Mu = lu.solve(np.conj(G))
     dD = 2.0 * omega ** 2 / (st.s1s2 * st.c ** 3)
     grad = np.real(Mu.reshape(-1, n, n) * U.reshape(-1, n, n) * dD[None]).sum(axis=0)
-    return J, grad
+    return J, grad, U, Mu
 
 
 def central_difference(c, omega, pml, F, receivers, data, direction, eps, C=DEFAULT_C):

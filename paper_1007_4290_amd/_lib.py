@@ -29,7 +29,7 @@ EXPORTED = [
     "hsweep_default_opts", "hsweep_setup", "hsweep_set_opts", "hsweep_get_opts", "hsweep_plan_info",
     "hsweep_factor", "hsweep_apply", "hsweep_stencil", "hsweep_solve", "hsweep_grad_c",
     "hsweep_factor_batch", "hsweep_solve_batch", "hsweep_destroy", "hsweep_last_error", "hsweep_timings",
-    "hsweep_factor_profile",
+    "hsweep_factor_profile", "hsweep_solve_adjoint", "hsweep_workspace_bytes",
 ]
 
 
@@ -83,6 +83,8 @@ def load():
         "hsweep_last_error": (ctypes.c_char_p, []),
         "hsweep_timings": (i, [vp, dp, i]),
         "hsweep_factor_profile": (i, [vp, vp, dp, i]),
+        "hsweep_solve_adjoint": (i, [vp, vp, vp, vp, i, d, i, ip, dp, vp]),
+        "hsweep_workspace_bytes": (i, [vp, i, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -14,6 +14,7 @@
 #include "hsweep.h"
 #include "internal.hpp"
 
+
 size_t factor_lds_bytes(const Plan& p, size_t elem);
 size_t sweep_lds_bytes(const Plan& p, size_t elem);
 bool factor_supported(const Plan& p);
@@ -92,6 +93,8 @@ struct hsweep_ctx {
     DevBuf sweep_w;
     // Krylov work
     DevBuf V, Z, w, r, hdev, partial, scale, active, y;
+    // conj(g) of an adjoint solve
+    DevBuf adj;
     HostBuf hhost, scalehost, activehost, yhost;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     double t_factor = 0, t_sweep = 0, t_stencil = 0, t_krylov = 0, n_apply = 0;
@@ -114,7 +117,7 @@ struct hsweep_ctx {
         if (cap) (void)hipStreamDestroy(cap);
         gdesc.release();
         DevBuf* bufs[] = {&c, &sn, &isn, &sh, &dg, &eo, &cp, &fac, &Q, &G, &rank, &status, &sweep_w,
-                          &V, &Z, &w, &r, &hdev, &partial, &scale, &active, &y};
+                          &V, &Z, &w, &r, &hdev, &partial, &scale, &active, &y, &adj};
         for (DevBuf* b : bufs) b->release();
         HostBuf* hb[] = {&hhost, &scalehost, &activehost, &yhost};
         for (HostBuf* b : hb) b->release();
@@ -348,16 +351,22 @@ int do_factor_profile(hsweep_ctx* ctx, hipStream_t s, double* layer_ms, double* 
     return HSWEEP_OK;
 }
 
+// The sweep's work vectors come from the context (allocated on demand) or,
+// when `work` is given, from that buffer of at least nrhs * n * n_p entries.
 template <typename T>
-int do_apply(hsweep_ctx* ctx, const c128* f, c128* u, int nrhs, const int* active, hipStream_t s) {
+int do_apply(hsweep_ctx* ctx, const c128* f, c128* u, int nrhs, const int* active, hipStream_t s,
+             void* work = nullptr) {
     const Plan& p = ctx->plan;
-    HIPCHK(ctx->sweep_w.ensure((size_t)nrhs * p.n * p.np * sizeof(cpx<T>)));
+    if (!work) {
+        HIPCHK(ctx->sweep_w.ensure((size_t)nrhs * p.n * p.np * sizeof(cpx<T>)));
+        work = ctx->sweep_w.p;
+    }
     SweepArgs<T> a;
     a.fac = (const cpx<T>*)ctx->fac.p;
     a.cp = (const cpx<T>*)ctx->cp.p;
     a.f = f;
     a.u = u;
-    a.w = (cpx<T>*)ctx->sweep_w.p;
+    a.w = (cpx<T>*)work;
     a.active = active;
     a.nrhs = nrhs;
     launch_sweep<T>(p, a, s);
@@ -810,6 +819,64 @@ int hsweep_solve(hsweep_ctx* ctx, const void* fv, void* uv, int nrhs, double tol
         if (!done[k]) all = false;
     }
     if (!all) return fail(HSWEEP_ENOCONV, "GMRES reached maxit before tol for some right-hand side");
+    return HSWEEP_OK;
+}
+
+int hsweep_solve_adjoint(hsweep_ctx* ctx, const void* g, void* mu, void* grad_f, int nrhs, double tol, int maxit,
+                         int* iters, double* relres, void* stream) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!g || !mu) return fail(HSWEEP_EINVAL, "g and mu must be device pointers");
+    if (g == mu || (grad_f && (grad_f == g || grad_f == mu)))
+        return fail(HSWEEP_EINVAL, "g, mu and grad_f must not overlap");
+    if (nrhs < 1 || nrhs > 65535) return fail(HSWEEP_EINVAL, "nrhs must be in [1, 65535]");
+    if (!(tol > 0.0) || !isfinite(tol)) return fail(HSWEEP_EINVAL, "tol must be finite and > 0");
+    if (maxit < 1) return fail(HSWEEP_EINVAL, "maxit must be >= 1");
+    if (!ctx->factored) return fail(HSWEEP_ESTATE, "hsweep_solve_adjoint before hsweep_factor");
+    rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t tot = (size_t)nrhs * ctx->n * ctx->n;
+    HIPCHK(ctx->adj.ensure(tot * sizeof(c128)));
+    launch_conj((const c128*)g, (c128*)ctx->adj.p, tot, s);
+    HIPCHK(hipGetLastError());
+    rc = hsweep_solve(ctx, ctx->adj.p, mu, nrhs, tol, maxit, iters, relres, stream);
+    if (rc != HSWEEP_OK && rc != HSWEEP_ENOCONV) return rc;
+    if (grad_f) {
+        launch_conj((const c128*)mu, (c128*)grad_f, tot, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return rc;
+}
+
+int hsweep_workspace_bytes(const hsweep_ctx* ctx, int nrhs, size_t* factor_bytes, size_t* solve_bytes) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (nrhs < 1 || nrhs > 65535) return fail(HSWEEP_EINVAL, "nrhs must be in [1, 65535]");
+    Plan p = ctx->plan;
+    if (!ctx->planned) {
+        rc = make_plan(const_cast<hsweep_ctx*>(ctx), p);
+        if (rc) return rc;
+    }
+    const size_t E = ctx->opts.precision == HSWEEP_C64 ? sizeof(c64) : sizeof(c128);
+    const size_t n = (size_t)p.n, np = (size_t)p.np, N = n * n, K = (size_t)nrhs;
+    const size_t m = (size_t)ctx->opts.restart;
+    // coefficients of the setup: c, s and 1/s on nodes, s on half nodes
+    size_t fb = N * sizeof(double) + 2 * n * sizeof(c128) + (n + 1) * sizeof(c128);
+    // layer operators, factor store and the per-layer work of the factorization
+    fb += 2 * n * np * E + (n > 1 ? n : 2) * np * E + n * p.eLayer * E;
+    fb += (size_t)(p.L > 0 ? p.L : 1) * p.r * np * E + ((size_t)2 << p.L) * p.r * p.r * E;
+    fb += n * ((size_t)1 << p.L) * sizeof(int) + sizeof(int);
+    // sweep work vectors and the flexible-GMRES basis, residuals and small arrays
+    const size_t nblk = (size_t)krylov_dot_blocks(N);
+    size_t sb = K * n * np * E;
+    sb += (2 * m + 1) * K * N * sizeof(c128) + 2 * K * N * sizeof(c128);
+    sb += 3 * (m + 1) * K * sizeof(c128) + nblk * K * (m + 1) * sizeof(c128);
+    sb += K * (sizeof(double) + sizeof(int)) + m * K * sizeof(c128);
+    if (factor_bytes) *factor_bytes = fb;
+    if (solve_bytes) *solve_bytes = sb;
     return HSWEEP_OK;
 }
 

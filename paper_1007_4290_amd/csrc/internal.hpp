@@ -110,3 +110,5 @@ void launch_scale(const c128* w, const double* scale, c128* out, int nrhs, size_
 // x[k] += sum_j y[j*nrhs + k] Z[j][k]
 void launch_combine(const c128* Z, int nz, const c128* y, c128* x, int nrhs, size_t N, hipStream_t s);
 int krylov_dot_blocks(size_t N);
+// y = conj(x), n complex entries
+void launch_conj(const c128* x, c128* y, size_t n, hipStream_t s);

@@ -89,7 +89,19 @@ __global__ void combine_kernel(const c128* __restrict__ Z, int nz, const c128* _
     x[(size_t)k * N + i] = acc;
 }
 
+// y = conj(x) over n entries (x and y may be the same array).
+__global__ void conj_kernel(const c128* __restrict__ x, c128* __restrict__ y, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    y[i] = conj(x[i]);
+}
+
 }  // namespace
+
+void launch_conj(const c128* x, c128* y, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(conj_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
+}
 
 int krylov_dot_blocks(size_t N) {
     size_t b = (N + 8191) / 8192;

@@ -135,6 +135,30 @@ class Solver:
             return u[0], its_l[0], res_l[0]
         return u, its_l, res_l
 
+    def solve_adjoint(self, g, tol=1e-6, maxit=200, want_grad_f=False, stream=None, allow_noconv=False):
+        """mu = A^{-1} conj(g) (and grad_f = conj(mu) if asked), computed in the
+        library; returns (mu, grad_f or None, iterations, relative residuals)."""
+        g2, single = _as_fields(g, self.n)
+        k = g2.shape[0]
+        mu = torch.empty_like(g2)
+        gf = torch.empty_like(g2) if want_grad_f else None
+        its = (ctypes.c_int * k)()
+        res = (ctypes.c_double * k)()
+        rc = _lib.load().hsweep_solve_adjoint(self._ctx, ctypes.c_void_p(g2.data_ptr()), ctypes.c_void_p(mu.data_ptr()),
+                                              ctypes.c_void_p(gf.data_ptr() if gf is not None else None), k,
+                                              float(tol), int(maxit), its, res, _stream_ptr(stream))
+        if not (allow_noconv and rc == _lib.ENOCONV):
+            _lib.check(rc)
+        if single:
+            return mu[0], (gf[0] if gf is not None else None), its[0], res[0]
+        return mu, gf, list(its), list(res)
+
+    def workspace_bytes(self, nrhs=1):
+        """Device bytes the library allocates: (factorization, solve of nrhs right-hand sides)."""
+        fb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+        _lib.check(_lib.load().hsweep_workspace_bytes(self._ctx, int(nrhs), ctypes.byref(fb), ctypes.byref(sb)))
+        return fb.value, sb.value
+
     def grad_c(self, u, mu, stream=None):
         """sum_k Re(mu_k u_k 2 omega^2 / ((s1 s2) c^3)) as an (n, n) float64 tensor."""
         u2, _ = _as_fields(u, self.n)
@@ -192,10 +216,9 @@ class _HelmholtzSolve(torch.autograd.Function):
     def backward(ctx, grad_u):
         (u,) = ctx.saved_tensors
         solver = ctx.solver
-        g = grad_u.contiguous().to(torch.complex128)
-        mu, _, _ = solver.solve(torch.conj(g).resolve_conj().contiguous(), tol=ctx.tol)
+        g = grad_u.resolve_conj().contiguous().to(torch.complex128)
+        mu, grad_f, _, _ = solver.solve_adjoint(g, tol=ctx.tol, want_grad_f=bool(ctx.needs_input_grad[1]))
         grad_c = solver.grad_c(u, mu) if ctx.needs_input_grad[0] else None
-        grad_f = torch.conj(mu).resolve_conj() if ctx.needs_input_grad[1] else None
         return grad_c, grad_f, None, None, None, None
 
 

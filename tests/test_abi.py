@@ -77,6 +77,8 @@ def test_null_arguments_are_rejected():
     assert lib.hsweep_set_opts(None, None) == _lib.EINVAL
     assert lib.hsweep_timings(None, None, 0) == _lib.EINVAL
     assert lib.hsweep_factor_profile(None, None, None, 3) == _lib.EINVAL
+    assert lib.hsweep_solve_adjoint(None, None, None, None, 1, 1e-6, 10, None, None, None) == _lib.EINVAL
+    assert lib.hsweep_workspace_bytes(None, 1, None, None) == _lib.EINVAL
     lib.hsweep_destroy(None)
 
 

@@ -1,9 +1,13 @@
-"""Full-size workloads on the GPU: many right-hand sides, a mixed batch of
-instances, the n=1023 lens, and the misfit gradient at n=511.
+"""Full-size workloads on the GPU against the FP64 oracle: 64 right-hand
+sides on one medium, a mixed batch of 24 instances, the n=1023 lens, and
+the misfit gradient at n=511.
 
-Each test checks properties that hold at any size (the FP64 residual the
-library reports is recomputed here from the oracle's stencil) and compares
-sampled solutions with the oracle's sparse LU where that is affordable.
+Every solution is compared, element by element (relative L2 and relative
+max norm, `parity.assert_close`), with the oracle's sparse LU solution
+u = A^{-1} f.  The complex64 sweeps run inside FP64 flexible GMRES at
+tolerance 1e-10, and the bound on the solution error is 1e-5 (the stated
+target for complex64 sweeps after GMRES); the metric setting (residual
+1e-6) is checked on the FP64 residual recomputed with the oracle's stencil.
 """
 import numpy as np
 import pytest
@@ -12,6 +16,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import assemble, direct, gradient  # noqa: E402
 import workloads as W  # noqa: E402
+from parity import assert_close  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -26,10 +31,6 @@ def _t(x):
     return torch.as_tensor(np.ascontiguousarray(x), device=DEV)
 
 
-def _rel(a, b):
-    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
-
-
 def test_helm511_64_sources_c64():
     # n = 511, omega = 2 pi 64, GRF medium (seed 3), 64 sources (seed 4), c64 sweeps
     _need_gpu()
@@ -38,20 +39,22 @@ def test_helm511_64_sources_c64():
     c = wl.velocity()
     F = wl.sources()
     s = Solver(c, wl.omega, wl.pml, leaf=wl.leaf, rank=wl.rank, rank_tol=wl.rank_tol, precision="c64").factor()
-    U, its, res = s.solve(_t(F), tol=1e-6, maxit=100)
-    assert max(res) <= 1e-6
-    assert max(its) <= 10
+    U, its, res = s.solve(_t(F), tol=1e-10, maxit=200)
+    assert max(res) <= 1e-10
+    assert max(its) <= 20
     st = assemble.stencil(c, wl.omega, wl.pml)
+    Ue = direct.SparseLU(st).solve(F)
     Uh = U.cpu().numpy()
-    rr = direct.relative_residual(st, Uh, F)
-    assert np.max(rr) <= 1.0001e-6
-    lu = direct.SparseLU(st)
-    for k in (0, 31, 63):
-        ue = lu.solve(F[k])
-        assert _rel(Uh[k], ue) < 1e-4
+    for k in range(F.shape[0]):
+        assert_close(Uh[k], Ue[k], 1e-5, f"source {k}")
+    # metric setting: FP64 residual 1e-6 for all 64, recomputed by the oracle
+    U6, its6, res6 = s.solve(_t(F), tol=1e-6, maxit=100)
+    assert max(res6) <= 1e-6 and max(its6) <= 10
+    assert np.max(direct.relative_residual(st, U6.cpu().numpy(), F)) <= 1.0001e-6
 
 
 def test_mixed_batch_of_24_instances():
+    # 8 instances each of n = 127, 255, 511 (media seeds 100..123), c64 sweeps
     _need_gpu()
     from paper_1007_4290_amd.solver import Solver, factor_batch, solve_batch
     wls = W.configs.mixed_batch()
@@ -64,16 +67,14 @@ def test_mixed_batch_of_24_instances():
                    for wl in group]
         factor_batch(solvers)
         fs = [_t(wl.sources()[0]) for wl in group]
-        us, its, res = solve_batch(solvers, fs, tol=1e-6)
-        assert max(res) <= 1e-6
-        for k in (0, len(group) - 1):
-            wl = group[k]
+        us, its, res = solve_batch(solvers, fs, tol=1e-10, maxit=200)
+        assert max(res) <= 1e-10
+        for k, wl in enumerate(group):
             st = assemble.stencil(wl.velocity(), wl.omega, wl.pml)
-            f = wl.sources()[0]
-            ue = direct.solve_sparse(st, f)
-            assert _rel(us[k].cpu().numpy(), ue) < 1e-4
+            ue = direct.solve_sparse(st, wl.sources()[0])
+            assert_close(us[k].cpu().numpy(), ue, 1e-5, wl.name)
             checked += 1
-    assert checked >= 4
+    assert checked == 24
 
 
 def test_batched_factor_equals_single_factor():
@@ -118,10 +119,10 @@ def test_prefetching_and_plain_woodbury_kernels_agree():
         f = _t(rng.standard_normal(127 * 127) + 1j * rng.standard_normal(127 * 127))
         a = pair[0].apply(f).cpu().numpy()
         b = alone.apply(f).cpu().numpy()
-        assert _rel(a, b) < tol, (prec, _rel(a, b))
+        assert_close(a, b, tol, prec)
 
 
-def test_helm1023_lens_c64_residual():
+def test_helm1023_lens_c64_solution():
     # n = 1023, omega = 2 pi 128, converging lens, PML 24, leaf 32, c64 factors and sweeps
     _need_gpu()
     from paper_1007_4290_amd.solver import Solver
@@ -129,52 +130,66 @@ def test_helm1023_lens_c64_residual():
     c = wl.velocity()
     f = wl.sources()
     s = Solver(c, wl.omega, wl.pml, leaf=wl.leaf, rank=wl.rank, rank_tol=wl.rank_tol, precision="c64").factor()
-    u, its, res = s.solve(_t(f), tol=1e-6, maxit=100)
-    assert res[0] <= 1e-6
+    u, its, res = s.solve(_t(f), tol=1e-10, maxit=300)
+    assert res[0] <= 1e-10
     st = assemble.stencil(c, wl.omega, wl.pml)
-    assert direct.relative_residual(st, u.cpu().numpy()[0], f[0]) <= 1.0001e-6
-    # sampled check at points the oracle reaches cheaply: the residual of the
-    # 5-point equation at 64 random interior points is small relative to f
-    assert its[0] <= 15
+    ue = direct.solve_sparse(st, f[0])
+    assert_close(u.cpu().numpy()[0], ue, 1e-5, "helm1023 lens")
+    # metric setting: residual 1e-6, recomputed by the oracle's stencil
+    u6, its6, res6 = s.solve(_t(f), tol=1e-6, maxit=100)
+    assert res6[0] <= 1e-6 and its6[0] <= 15
+    assert direct.relative_residual(st, u6.cpu().numpy()[0], f[0]) <= 1.0001e-6
 
 
-def test_gradient_grad511_against_differences_and_oracle():
-    # n = 511, 32 bottom sources, 256 top receivers, data from c_true, gradient at c0 = 1
-    _need_gpu()
-    from paper_1007_4290_amd.solver import helmholtz_solve, Solver
+@pytest.fixture(scope="module")
+def grad511():
+    # oracle side of the gradient workload: data d_s from the true medium and
+    # the adjoint gradient at c0 = 1, both by sparse LU in FP64
     wl = W.get("grad511")
-    n, om, npml = wl.n, wl.omega, wl.pml
     c0 = wl.velocity()
     c_true = wl.extra["c_true"]()
     F = wl.sources()
     rec = wl.receivers
-    # synthetic data from the true medium, solved on the GPU to 1e-10
-    st_true = Solver(c_true, om, npml, leaf=32, rank=8, rank_tol=1e-6, precision="c64").factor()
-    Ut, _, res_t = st_true.solve(_t(F), tol=1e-10, maxit=200)
-    assert max(res_t) <= 1e-10
-    data = Ut[:, torch.as_tensor(rec, device=DEV)]
+    _, _, U_true = gradient.forward(c_true, wl.omega, wl.pml, F)
+    data = U_true[:, rec]
+    J_ref, g_ref, _, Mu_ref = gradient.adjoint_state(c0, wl.omega, wl.pml, F, rec, data)
+    return wl, c0, F, rec, data, J_ref, g_ref, Mu_ref
+
+
+def test_gradient_grad511_against_differences_and_oracle(grad511):
+    # n = 511, 32 bottom sources, 256 top receivers, data from c_true, gradient at c0 = 1,
+    # 16 central-difference directions
+    _need_gpu()
+    from paper_1007_4290_amd.solver import helmholtz_solve, Solver
+    wl, c0, F, rec, data_np, J_ref, g_ref, Mu_ref = grad511
+    n, om, npml = wl.n, wl.omega, wl.pml
+    data = _t(data_np)
+    rec_t = torch.as_tensor(rec, device=DEV)
 
     def misfit(c):
         s = Solver(c, om, npml, leaf=32, rank=8, rank_tol=1e-6, precision="c64").factor()
         U, _, res = s.solve(_t(F), tol=1e-12, maxit=300)
         assert max(res) <= 1e-12
-        r = U[:, torch.as_tensor(rec, device=DEV)] - data
+        r = U[:, rec_t] - data
         return 0.5 * float((r.abs() ** 2).sum())
 
     c_t = _t(c0).requires_grad_(True)
-    u = helmholtz_solve(c_t, _t(F), om, npml, tol=1e-12, leaf=32, rank=8, rank_tol=1e-6, precision="c64")
-    r = u[:, torch.as_tensor(rec, device=DEV)] - data
+    f_t = _t(F).requires_grad_(True)
+    u = helmholtz_solve(c_t, f_t, om, npml, tol=1e-12, leaf=32, rank=8, rank_tol=1e-6, precision="c64")
+    r = u[:, rec_t] - data
     J = 0.5 * (r.abs() ** 2).sum()
     J.backward()
     g = c_t.grad.detach().cpu().numpy()
+    # against the oracle's adjoint gradient (sparse LU, FP64)
+    assert float(J.detach()) == pytest.approx(J_ref, rel=1e-6)
+    assert_close(g, g_ref, 1e-4, "dJ/dc")
+    # dJ/df = conj(mu), the adjoint fields of the oracle conjugated
+    assert_close(f_t.grad.detach().cpu().numpy(), np.conj(Mu_ref), 1e-4, "dJ/df")
+    # central differences on 16 random smooth directions
     rng = np.random.default_rng(wl.extra["direction_seed"])
     eps = 2e-3 / om
-    for _ in range(4):
+    for d in range(16):
         v = W.random_field_medium(n, int(rng.integers(1 << 30)), amplitude=1.0) - 1.0
         fd = (misfit(c0 + eps * v) - misfit(c0 - eps * v)) / (2 * eps)
         ad = float(np.sum(g * v))
-        assert abs(fd - ad) <= 1e-4 * abs(ad)
-    # against the oracle's adjoint gradient (sparse LU, FP64)
-    J_ref, g_ref = gradient.adjoint_gradient(c0, om, npml, F, rec, data.cpu().numpy())
-    assert float(J.detach()) == pytest.approx(J_ref, rel=1e-6)
-    assert _rel(g, g_ref) < 1e-4
+        assert abs(fd - ad) <= 1e-4 * abs(ad), (d, fd, ad)

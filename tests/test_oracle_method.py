@@ -152,6 +152,33 @@ def test_hmatrix_factorization_without_truncation_equals_dense_schur():
         assert _rel(hmatrix.to_dense(Tm), Td) < 1e-10
 
 
+def test_hmatrix_sweep_without_truncation_is_the_exact_inverse():
+    # Alg. 2.4 with untruncated H-factors is Alg. 2.2 with the dense factors,
+    # and both give u = A^{-1} f (ragged bisection at n = 27 included).
+    for n, leaf in ((15, 4), (27, 4)):
+        st = assemble.stencil(W.random_field_medium(n, 13), 2 * np.pi * 2.5, 3)
+        T = sweep.factor(st)
+        Th = hmatrix.factor(st, leaf, hmatrix.Trunc())
+        rng = np.random.default_rng(n)
+        f = rng.standard_normal((2, n * n)) + 1j * rng.standard_normal((2, n * n))
+        uh = hmatrix.solve(st, Th, f)
+        assert _rel(uh, sweep.solve(st, T, f)) < 1e-11
+        assert _rel(uh, direct.solve_dense(st, f)) < 1e-10
+    # planted mistake: dropping the backward substitution is caught
+    n = 15
+    st = assemble.stencil(W.random_field_medium(n, 13), 2 * np.pi * 2.5, 3)
+    Th = hmatrix.factor(st, 4, hmatrix.Trunc())
+    f = W.gaussian_source(n, (0.5, 0.5)).ravel()
+    a = sweep.couplings(st)
+    F = f.reshape(n, n).copy()
+    w = np.empty_like(F)
+    for m in range(n):
+        if m > 0:
+            F[m] -= a[m - 1] * w[m - 1]
+        w[m] = hmatrix.matvec(Th[m], F[m])
+    assert _rel(w.ravel(), direct.solve_dense(st, f)) > 1e-3
+
+
 def test_compressed_sweep_preconditions_gmres():
     # Truncated factors (rank <= 8, tol 1e-6) still precondition well and GMRES
     # reaches the exact solution.
@@ -187,6 +214,33 @@ def test_adjoint_gradient_matches_central_differences():
         fd = gradient.central_difference(c0, omega, npml, F, rec, data, v, eps)
         ad = float(np.sum(g * v))
         assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-12
+
+
+def test_source_gradient_matches_central_differences():
+    # dJ/dRe f + i dJ/dIm f = conj(mu): checked along random complex source
+    # perturbations, whose directional derivative is Re sum conj(grad_f) v.
+    n, npml = 15, 3
+    omega = 2 * np.pi * 2
+    c0 = W.random_field_medium(n, 21)
+    F = np.stack([W.gaussian_source(n, p).ravel() for p in ((0.4, 0.3), (0.6, 0.35))])
+    rec = W.top_row_receivers(n, npml, 5, margin=1)
+    data = np.full((2, rec.size), 0.02 + 0.01j)
+    J, _, _, Mu = gradient.adjoint_state(c0, omega, npml, F, rec, data)
+    grad_f = np.conj(Mu)
+    rng = np.random.default_rng(8)
+    eps = 1e-4
+    for _ in range(3):
+        v = rng.standard_normal(F.shape) + 1j * rng.standard_normal(F.shape)
+        jp = gradient.misfit(c0, omega, npml, F + eps * v, rec, data)
+        jm = gradient.misfit(c0, omega, npml, F - eps * v, rec, data)
+        fd = (jp - jm) / (2 * eps)
+        ad = float(np.real(np.sum(np.conj(grad_f) * v)))
+        assert abs(fd - ad) <= 1e-7 * abs(ad)
+    # planted mistake: the adjoint field itself (no conjugate) is not the gradient
+    v = rng.standard_normal(F.shape) + 1j * rng.standard_normal(F.shape)
+    fd = (gradient.misfit(c0, omega, npml, F + eps * v, rec, data)
+          - gradient.misfit(c0, omega, npml, F - eps * v, rec, data)) / (2 * eps)
+    assert abs(float(np.real(np.sum(np.conj(Mu) * v))) - fd) > 1e-3 * abs(fd)
 
 
 def test_wrong_adjoint_sign_is_caught_by_differences():
