@@ -112,6 +112,22 @@ int hsweep_factor(hsweep_ctx* ctx, void* stream);
  * Asynchronous on `stream`.  ESTATE before hsweep_factor. */
 int hsweep_apply(hsweep_ctx* ctx, const void* f, void* u, int nrhs, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): u = M f as
+ * hsweep_apply computes it, with the same kernels, but the sweep's work
+ * vectors live in a static device array of HSWEEP_NOALLOC_SCRATCH_BYTES per
+ * GPU (its address is taken once per device by hsweep_setup) instead of
+ * context memory allocated on first use.  No hipMalloc, hipFree or other
+ * allocating call is made.  EINVAL if nrhs * n * n_p * (8 bytes for
+ * complex64 factors, 16 for complex128) exceeds HSWEEP_NOALLOC_SCRATCH_BYTES.
+ * Every call on one GPU shares that array: calls that overlap in time on
+ * one GPU (other streams, other threads, other contexts) race and must be
+ * serialized by the caller.  The kernels write every scratch entry they
+ * read, so no clearing is needed between calls.  Asynchronous on `stream`;
+ * ESTATE before hsweep_factor. */
+#define HSWEEP_NOALLOC_SCRATCH_BYTES (32u << 20)
+int hsweep_apply_noalloc(hsweep_ctx* ctx, const void* f, void* u, int nrhs, void* stream);
+
 /* y = A x for nrhs fields (the FP64 5-point operator, eq. helmd).  Device
  * complex128 arrays; asynchronous. */
 int hsweep_stencil(hsweep_ctx* ctx, const void* x, void* y, int nrhs, void* stream);

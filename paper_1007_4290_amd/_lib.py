@@ -29,8 +29,10 @@ EXPORTED = [
     "hsweep_default_opts", "hsweep_setup", "hsweep_set_opts", "hsweep_get_opts", "hsweep_plan_info",
     "hsweep_factor", "hsweep_apply", "hsweep_stencil", "hsweep_solve", "hsweep_grad_c",
     "hsweep_factor_batch", "hsweep_solve_batch", "hsweep_destroy", "hsweep_last_error", "hsweep_timings",
-    "hsweep_factor_profile", "hsweep_solve_adjoint", "hsweep_workspace_bytes",
+    "hsweep_factor_profile", "hsweep_solve_adjoint", "hsweep_workspace_bytes", "hsweep_apply_noalloc",
 ]
+# Size of the static device scratch of hsweep_apply_noalloc (HSWEEP_NOALLOC_SCRATCH_BYTES).
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class HsweepError(RuntimeError):
@@ -85,6 +87,7 @@ def load():
         "hsweep_factor_profile": (i, [vp, vp, dp, i]),
         "hsweep_solve_adjoint": (i, [vp, vp, vp, vp, i, d, i, ip, dp, vp]),
         "hsweep_workspace_bytes": (i, [vp, i, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+        "hsweep_apply_noalloc": (i, [vp, vp, vp, i, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

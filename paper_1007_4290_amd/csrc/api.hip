@@ -11,9 +11,16 @@
 #include <string>
 #include <vector>
 
+#include <mutex>
+
 #include "hsweep.h"
 #include "internal.hpp"
 
+// Device scratch of hsweep_apply_noalloc: the sweep's forward work vectors
+// w_m (nrhs * n * n_p entries of the factor precision).  One copy per GPU,
+// held until the process ends.  In host code `scratch` only names the
+// symbol; its device address is looked up once per device (scratch_init).
+static __device__ __align__(256) unsigned char scratch[HSWEEP_NOALLOC_SCRATCH_BYTES];
 
 size_t factor_lds_bytes(const Plan& p, size_t elem);
 size_t sweep_lds_bytes(const Plan& p, size_t elem);
@@ -127,6 +134,26 @@ struct hsweep_ctx {
 };
 
 namespace {
+
+// Per-device address of `scratch`, filled by scratch_init on the first
+// hsweep_setup with that device current.
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+int scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(HSWEEP_EDEVICE, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return HSWEEP_OK;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return fail(HSWEEP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = ptr;
+    return HSWEEP_OK;
+}
 
 int ilog2(int v) {
     int l = 0;
@@ -476,6 +503,8 @@ int hsweep_setup(const double* c, double omega, int pml, int n, hsweep_ctx** out
     SETUPCHK(ctx->sh.ensure((size_t)(n + 1) * sizeof(c128)));
     SETUPCHK(hipMemcpy(ctx->c.p, c, N * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
     for (int i = 0; i < 4; ++i) SETUPCHK(hipEventCreate(&ctx->ev[i]));
+    rc = scratch_init(ctx->device);
+    if (rc) return bail(rc);
     double h = 1.0 / (n + 1);
     launch_pml_1d(n, omega, pml * h, ctx->opts.pml_C, (c128*)ctx->sn.p, (c128*)ctx->isn.p, (c128*)ctx->sh.p, 0);
     SETUPCHK(hipGetLastError());
@@ -577,6 +606,30 @@ int hsweep_apply(hsweep_ctx* ctx, const void* f, void* u, int nrhs, void* stream
     rc = set_device(ctx);
     if (rc) return rc;
     return apply_dispatch(ctx, (const c128*)f, (c128*)u, nrhs, nullptr, (hipStream_t)stream);
+}
+
+int hsweep_apply_noalloc(hsweep_ctx* ctx, const void* f, void* u, int nrhs, void* stream) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!f || !u) return fail(HSWEEP_EINVAL, "f and u must be device pointers");
+    if (nrhs < 1 || nrhs > 65535) return fail(HSWEEP_EINVAL, "nrhs must be in [1, 65535]");
+    if (f == u) return fail(HSWEEP_EINVAL, "f and u must not overlap");
+    if (!ctx->factored) return fail(HSWEEP_ESTATE, "hsweep_apply_noalloc before hsweep_factor");
+    const Plan& p = ctx->plan;
+    const size_t elem = ctx->opts.precision == HSWEEP_C64 ? sizeof(c64) : sizeof(c128);
+    const size_t need = (size_t)nrhs * p.n * p.np * elem;
+    if (need > (size_t)HSWEEP_NOALLOC_SCRATCH_BYTES)
+        return fail(HSWEEP_EINVAL, "hsweep_apply_noalloc: nrhs * n * n_p work entries (" + std::to_string(need) +
+                                       " bytes) exceed the static scratch of " +
+                                       std::to_string((size_t)HSWEEP_NOALLOC_SCRATCH_BYTES) + " bytes");
+    rc = set_device(ctx);
+    if (rc) return rc;
+    void* work = ctx->device < kMaxDevices ? g_scratch_ptr[ctx->device] : nullptr;
+    if (!work) return fail(HSWEEP_EDEVICE, "scratch address of this device is unknown (no hsweep_setup on it)");
+    const hipStream_t s = (hipStream_t)stream;
+    if (ctx->opts.precision == HSWEEP_C64) return do_apply<float>(ctx, (const c128*)f, (c128*)u, nrhs, nullptr, s, work);
+    return do_apply<double>(ctx, (const c128*)f, (c128*)u, nrhs, nullptr, s, work);
 }
 
 int hsweep_stencil(hsweep_ctx* ctx, const void* x, void* y, int nrhs, void* stream) {
