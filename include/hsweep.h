@@ -78,10 +78,14 @@ typedef struct hsweep_opts {
     int    dense;       /* 1: dense uncompressed Schur complements (leaf = n_p,
                            no low-rank levels) -- the exact Alg. 2.1/2.2 */
     int    restart;     /* GMRES restart length (1..200) */
+    int    rhs_group;   /* right-hand sides per sweep workgroup, each layer's
+                           factors loaded once for the group: 1, 4 (where a
+                           grouped kernel exists for the plan, else 1), or
+                           0 = automatic */
 } hsweep_opts;
 
 /* Fill `o` with the defaults: leaf 16, rank 8, rank_tol 1e-6, C = 20,
- * complex128, compressed, restart 40. */
+ * complex128, compressed, restart 40, automatic right-hand-side groups. */
 void hsweep_default_opts(hsweep_opts* o);
 
 /* Create a context for velocity c (n*n doubles, layout above; every value
@@ -169,15 +173,23 @@ int hsweep_workspace_bytes(const hsweep_ctx* ctx, int nrhs, size_t* factor_bytes
 int hsweep_grad_c(hsweep_ctx* ctx, const void* u, const void* mu, int nrhs,
                   void* grad, void* stream);
 
-/* Several independent problems factored together: every step of the
- * factorization is launched once for all contexts whose layer loop has
- * not finished.  All contexts must have the same precision, leaf size and
- * rank.  Synchronizes `stream`. */
+/* Several independent problems factored together (Alg. 2.3 for each):
+ * contexts with the same leaf size and rank form a group, and every layer
+ * step of a group is launched once for all its contexts whose layer loop
+ * has not finished; groups run one after the other.  All contexts must
+ * have the same precision.  Synchronizes `stream`. */
 int hsweep_factor_batch(hsweep_ctx** ctxs, int count, void* stream);
 
-/* One flexible-GMRES solve per context (one right-hand side each), run
- * one context after the other on `stream`.  f[k], u[k]: device complex128
- * fields of context k.  iters, relres: host arrays of count. */
+/* One flexible-GMRES solve per context (one right-hand side each, Sec. 2.4
+ * preconditioned by each context's sweep, Alg. 2.4), all contexts in one
+ * iteration loop: every GMRES step launches the sweep once for all
+ * contexts with the same leaf size and rank (one workgroup per context),
+ * the FP64 vector kernels once for all, and the stencil once per context.
+ * Each right-hand side stops on its own true residual.  f[k], u[k]: device
+ * complex128 fields of context k (n_k * n_k entries).  iters, relres: host
+ * arrays of count.  All contexts factored, same precision and device, no
+ * context twice, count <= 4096.  The Krylov work buffers belong to
+ * ctxs[0] (its restart length applies).  Synchronizes `stream`. */
 int hsweep_solve_batch(hsweep_ctx** ctxs, int count, const void* const* f, void* const* u,
                        double tol, int maxit, int* iters, double* relres, void* stream);
 

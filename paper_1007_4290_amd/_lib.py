@@ -50,6 +50,7 @@ class Opts(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("dense", ctypes.c_int),
         ("restart", ctypes.c_int),
+        ("rhs_group", ctypes.c_int),
     ]
 
 

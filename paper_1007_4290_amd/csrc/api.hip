@@ -23,9 +23,7 @@
 static __device__ __align__(256) unsigned char scratch[HSWEEP_NOALLOC_SCRATCH_BYTES];
 
 size_t factor_lds_bytes(const Plan& p, size_t elem);
-size_t sweep_lds_bytes(const Plan& p, size_t elem);
 bool factor_supported(const Plan& p);
-bool sweep_supported(const Plan& p);
 
 namespace {
 
@@ -45,6 +43,7 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 constexpr size_t kMaxLds = 152 * 1024;   // dynamic LDS budget: 160 KiB minus static shared variables
+constexpr int kAutoGroupRhs = 1 << 30;   // automatic grouping: right-hand sides from which G = 4
 
 struct DevBuf {
     void* p = nullptr;
@@ -102,6 +101,10 @@ struct hsweep_ctx {
     DevBuf V, Z, w, r, hdev, partial, scale, active, y;
     // conj(g) of an adjoint solve
     DevBuf adj;
+    // system offsets of the Krylov vectors; batched solves: concatenated
+    // right-hand sides and solutions, sweep instance and task tables
+    DevBuf offd, bf, bu, sinst, stask;
+    HostBuf offh;
     HostBuf hhost, scalehost, activehost, yhost;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     double t_factor = 0, t_sweep = 0, t_stencil = 0, t_krylov = 0, n_apply = 0;
@@ -124,9 +127,10 @@ struct hsweep_ctx {
         if (cap) (void)hipStreamDestroy(cap);
         gdesc.release();
         DevBuf* bufs[] = {&c, &sn, &isn, &sh, &dg, &eo, &cp, &fac, &Q, &G, &rank, &status, &sweep_w,
-                          &V, &Z, &w, &r, &hdev, &partial, &scale, &active, &y, &adj};
+                          &V, &Z, &w, &r, &hdev, &partial, &scale, &active, &y, &adj,
+                          &offd, &bf, &bu, &sinst, &stask};
         for (DevBuf* b : bufs) b->release();
-        HostBuf* hb[] = {&hhost, &scalehost, &activehost, &yhost};
+        HostBuf* hb[] = {&hhost, &scalehost, &activehost, &yhost, &offh};
         for (HostBuf* b : hb) b->release();
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -177,6 +181,8 @@ int validate_opts(const hsweep_opts* o, int n) {
         return fail(HSWEEP_EINVAL, "rank_tol must be in [0, 1)");
     if (!(o->pml_C > 0.0) || !isfinite(o->pml_C)) return fail(HSWEEP_EINVAL, "pml_C must be finite and > 0");
     if (o->restart < 1 || o->restart > 200) return fail(HSWEEP_EINVAL, "restart must be in [1, 200]");
+    if (!(o->rhs_group == 0 || o->rhs_group == 1 || o->rhs_group == 4))
+        return fail(HSWEEP_EINVAL, "rhs_group must be 0 (automatic), 1 or 4");
     (void)n;
     return HSWEEP_OK;
 }
@@ -208,7 +214,7 @@ int make_plan(hsweep_ctx* ctx, Plan& p) {
     size_t elem = o.precision == HSWEEP_C64 ? sizeof(c64) : sizeof(c128);
     if (factor_lds_bytes(p, elem) > kMaxLds)
         return fail(HSWEEP_EINVAL, "layer too wide for this precision (LDS of the factorization kernels)");
-    if (sweep_lds_bytes(p, elem) > kMaxLds) return fail(HSWEEP_EINVAL, "layer too wide for the sweep kernel");
+    if (sweep_lds_bytes(p, elem, 1) > kMaxLds) return fail(HSWEEP_EINVAL, "layer too wide for the sweep kernel");
     return HSWEEP_OK;
 }
 
@@ -378,6 +384,31 @@ int do_factor_profile(hsweep_ctx* ctx, hipStream_t s, double* layer_ms, double* 
     return HSWEEP_OK;
 }
 
+// Right-hand sides per sweep workgroup: the option if set (4 only where a
+// grouped kernel exists for the plan), otherwise 4 for many right-hand sides.
+int sweep_group(const hsweep_ctx* ctx, int nrhs) {
+    const int o = ctx->opts.rhs_group;
+    const bool g4 = sweep_group_supported(ctx->plan);
+    if (o == 1) return 1;
+    if (o == 4) return g4 ? 4 : 1;
+    return (g4 && nrhs >= kAutoGroupRhs) ? 4 : 1;
+}
+
+// Descriptor of this context's sweep over nrhs fields f -> u.
+template <typename T>
+SweepInst<T> sweep_inst(const hsweep_ctx* ctx, const c128* f, c128* u, void* work, const int* active, int nrhs) {
+    const Plan& p = ctx->plan;
+    SweepInst<T> in{};
+    in.n = p.n; in.np = p.np; in.L = p.L; in.nrhs = nrhs;
+    in.eK = p.eK; in.eP = p.eP; in.eLayer = p.eLayer;
+    in.fac = (const cpx<T>*)ctx->fac.p;
+    in.cp = (const cpx<T>*)ctx->cp.p;
+    in.f = f; in.u = u; in.w = (cpx<T>*)work;
+    in.active = active;
+    in.fstride = 0; in.ustride = 0;
+    return in;
+}
+
 // The sweep's work vectors come from the context (allocated on demand) or,
 // when `work` is given, from that buffer of at least nrhs * n * n_p entries.
 template <typename T>
@@ -388,15 +419,10 @@ int do_apply(hsweep_ctx* ctx, const c128* f, c128* u, int nrhs, const int* activ
         HIPCHK(ctx->sweep_w.ensure((size_t)nrhs * p.n * p.np * sizeof(cpx<T>)));
         work = ctx->sweep_w.p;
     }
-    SweepArgs<T> a;
-    a.fac = (const cpx<T>*)ctx->fac.p;
-    a.cp = (const cpx<T>*)ctx->cp.p;
-    a.f = f;
-    a.u = u;
-    a.w = (cpx<T>*)work;
-    a.active = active;
-    a.nrhs = nrhs;
-    launch_sweep<T>(p, a, s);
+    SweepArgs<T> a{};
+    a.one = sweep_inst<T>(ctx, f, u, work, active, nrhs);
+    if (launch_sweep<T>(p, a, sweep_group(ctx, nrhs), s) != 0)
+        return fail(HSWEEP_EINVAL, "no compiled sweep for this plan");
     HIPCHK(hipGetLastError());
     return HSWEEP_OK;
 }
@@ -436,6 +462,352 @@ void givens(std::complex<double> a, std::complex<double> b, double& c, std::comp
     s = (a / std::abs(a)) * std::conj(b) / t;
 }
 
+// Host table of workgroup tasks for a multi-instance launch: group k of
+// instance q (first right-hand side k*G) runs on XCD (running task index) % 8;
+// table[slot * 8 + xcd] = (q << 16) | first right-hand side, -1 where idle.
+std::vector<int> sweep_task_table(const int* nrhs, int ninst, int G) {
+    std::vector<std::vector<int>> per(8);
+    int t = 0;
+    for (int q = 0; q < ninst; ++q)
+        for (int r0 = 0; r0 < nrhs[q]; r0 += G, ++t) per[t % 8].push_back((q << 16) | r0);
+    size_t slots = 0;
+    for (auto& v : per) slots = v.size() > slots ? v.size() : slots;
+    std::vector<int> table(8 * slots, -1);
+    for (int x = 0; x < 8; ++x)
+        for (size_t k = 0; k < per[x].size(); ++k) table[k * 8 + x] = per[x][k];
+    return table;
+}
+
+// Flexible GMRES (right-preconditioned, FP64 Arnoldi with classical
+// Gram-Schmidt applied twice, Givens rotations on the host) for the
+// right-hand sides of `count` contexts: nr[q] fields of context q, f[q] ->
+// u[q].  Every Krylov step is launched once for all of them: the vector
+// kernels over the concatenation of all systems, the sweep as one launch per
+// group of contexts with the same leaf size and rank (one launch for one
+// context), the stencil once per context.  Each system stops on its own
+// true residual ||f - A u|| <= tol ||f||.  The Krylov buffers live in
+// ctxs[0] (its restart length is used).  Synchronizes `s`.
+int solve_systems(hsweep_ctx** ctxs, int count, const int* nr, const c128* const* f_in, c128* const* u_out,
+                  double tol, int maxit, int* iters, double* relres, hipStream_t s) {
+    hsweep_ctx* c0 = ctxs[0];
+    int rc = HSWEEP_OK;
+    // systems and their offsets in the concatenated vectors
+    std::vector<int> first(count + 1, 0);
+    for (int q = 0; q < count; ++q) first[q + 1] = first[q] + nr[q];
+    const int S = first[count];
+    HIPCHK(c0->offh.ensure((size_t)(S + 1) * sizeof(size_t)));
+    size_t* offh = (size_t*)c0->offh.p;
+    size_t maxlen = 0;
+    offh[0] = 0;
+    for (int q = 0; q < count; ++q) {
+        const size_t Nq = (size_t)ctxs[q]->n * ctxs[q]->n;
+        maxlen = std::max(maxlen, Nq);
+        for (int k = 0; k < nr[q]; ++k) offh[first[q] + k + 1] = offh[first[q] + k] + Nq;
+    }
+    const size_t Ntot = offh[S];
+    const int m = c0->opts.restart;
+    const int nblk = krylov_dot_blocks(maxlen);
+    const int nvmax = m + 1;
+    HIPCHK(c0->offd.ensure((size_t)(S + 1) * sizeof(size_t)));
+    HIPCHK(c0->V.ensure((size_t)(m + 1) * Ntot * sizeof(c128)));
+    HIPCHK(c0->Z.ensure((size_t)m * Ntot * sizeof(c128)));
+    HIPCHK(c0->w.ensure(Ntot * sizeof(c128)));
+    HIPCHK(c0->r.ensure(Ntot * sizeof(c128)));
+    HIPCHK(c0->hdev.ensure((size_t)3 * nvmax * S * sizeof(c128)));
+    HIPCHK(c0->partial.ensure((size_t)nblk * S * nvmax * sizeof(c128)));
+    HIPCHK(c0->scale.ensure((size_t)S * sizeof(double)));
+    HIPCHK(c0->active.ensure((size_t)S * sizeof(int)));
+    HIPCHK(c0->y.ensure((size_t)m * S * sizeof(c128)));
+    HIPCHK(c0->hhost.ensure((size_t)3 * nvmax * S * sizeof(c128)));
+    HIPCHK(c0->scalehost.ensure((size_t)S * sizeof(double)));
+    HIPCHK(c0->activehost.ensure((size_t)S * sizeof(int)));
+    HIPCHK(c0->yhost.ensure((size_t)m * S * sizeof(c128)));
+    HIPCHK(hipMemcpyAsync(c0->offd.p, offh, (size_t)(S + 1) * sizeof(size_t), hipMemcpyHostToDevice, s));
+    const size_t* offd = (const size_t*)c0->offd.p;
+    c128* V = (c128*)c0->V.p;
+    c128* Z = (c128*)c0->Z.p;
+    c128* w = (c128*)c0->w.p;
+    c128* rr = (c128*)c0->r.p;
+    c128* hd = (c128*)c0->hdev.p;
+    c128* hd1 = hd;                          // first Gram-Schmidt pass
+    c128* hd2 = hd + (size_t)nvmax * S;      // second pass
+    c128* hd3 = hd2 + (size_t)nvmax * S;     // norms
+    c128* part = (c128*)c0->partial.p;
+    double* scd = (double*)c0->scale.p;
+    int* actd = (int*)c0->active.p;
+    c128* yd = (c128*)c0->y.p;
+    std::complex<double>* hh = (std::complex<double>*)c0->hhost.p;
+    double* sch = (double*)c0->scalehost.p;
+    int* acth = (int*)c0->activehost.p;
+    std::complex<double>* yh = (std::complex<double>*)c0->yhost.p;
+
+    // right-hand sides and solutions: the caller's arrays for one context,
+    // concatenated copies for several
+    const c128* f = f_in[0];
+    c128* u = u_out[0];
+    if (count > 1) {
+        HIPCHK(c0->bf.ensure(Ntot * sizeof(c128)));
+        HIPCHK(c0->bu.ensure(Ntot * sizeof(c128)));
+        for (int q = 0; q < count; ++q)
+            HIPCHK(hipMemcpyAsync((c128*)c0->bf.p + offh[first[q]], f_in[q],
+                                  (offh[first[q + 1]] - offh[first[q]]) * sizeof(c128), hipMemcpyDeviceToDevice, s));
+        f = (const c128*)c0->bf.p;
+        u = (c128*)c0->bu.p;
+    }
+
+    // sweep launches of a batch: one per (leaf, rank) group of contexts, with
+    // device tables of instances (fields of column j at V + j Ntot -> Z + j Ntot)
+    struct SweepGroup { std::vector<int> members; std::vector<Plan> plans; int G = 1, blocks = 0; size_t inst_off = 0, task_off = 0; };
+    std::vector<SweepGroup> groups;
+    const bool single_prec = c0->opts.precision == HSWEEP_C64;   // complex64 factors
+    if (count > 1) {
+        for (int q = 0; q < count; ++q) {
+            const Plan& p = ctxs[q]->plan;
+            const int rq = p.L > 0 ? p.r : 0;
+            int gi = -1;
+            for (size_t g = 0; g < groups.size(); ++g) {
+                const Plan& p0 = ctxs[groups[g].members[0]]->plan;
+                if (p0.b == p.b && (p0.L > 0 ? p0.r : 0) == rq) gi = (int)g;
+            }
+            if (gi < 0) { groups.emplace_back(); gi = (int)groups.size() - 1; }
+            groups[gi].members.push_back(q);
+            groups[gi].plans.push_back(p);
+        }
+        const size_t isz = single_prec ? sizeof(SweepInst<float>) : sizeof(SweepInst<double>);
+        std::vector<unsigned char> itab;
+        std::vector<int> ttab;
+        for (auto& g : groups) {
+            // the group's kernel: the largest level count of its members
+            int lmax = 0, nrmax = 0;
+            Plan pm = g.plans[0];
+            std::vector<int> gnr;
+            for (size_t k = 0; k < g.members.size(); ++k) {
+                if (g.plans[k].L > lmax) { lmax = g.plans[k].L; pm = g.plans[k]; }
+                nrmax = std::max(nrmax, nr[g.members[k]]);
+                gnr.push_back(nr[g.members[k]]);
+            }
+            g.G = sweep_group(ctxs[g.members[0]], nrmax);
+            if (g.G == 4 && !sweep_group_supported(pm)) g.G = 1;
+            if (!(g.G == 1 ? sweep_supported(pm) : true)) return fail(HSWEEP_EINVAL, "no compiled sweep for a batch group");
+            g.inst_off = itab.size();
+            for (int q : g.members) {
+                hsweep_ctx* cq = ctxs[q];
+                const Plan& p = cq->plan;
+                HIPCHK(cq->sweep_w.ensure((size_t)nr[q] * p.n * p.np * (single_prec ? sizeof(cpx<float>) : sizeof(cpx<double>))));
+                const size_t o = offh[first[q]];
+                if (single_prec) {
+                    SweepInst<float> in = sweep_inst<float>(cq, V + o, Z + o, cq->sweep_w.p, actd + first[q], nr[q]);
+                    in.fstride = Ntot; in.ustride = Ntot;
+                    const unsigned char* b = (const unsigned char*)&in;
+                    itab.insert(itab.end(), b, b + isz);
+                } else {
+                    SweepInst<double> in = sweep_inst<double>(cq, V + o, Z + o, cq->sweep_w.p, actd + first[q], nr[q]);
+                    in.fstride = Ntot; in.ustride = Ntot;
+                    const unsigned char* b = (const unsigned char*)&in;
+                    itab.insert(itab.end(), b, b + isz);
+                }
+            }
+            std::vector<int> t = sweep_task_table(gnr.data(), (int)gnr.size(), g.G);
+            g.task_off = ttab.size();
+            g.blocks = (int)t.size();
+            ttab.insert(ttab.end(), t.begin(), t.end());
+        }
+        HIPCHK(c0->sinst.ensure(itab.size()));
+        HIPCHK(c0->stask.ensure(ttab.size() * sizeof(int)));
+        HIPCHK(hipMemcpy(c0->sinst.p, itab.data(), itab.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c0->stask.p, ttab.data(), ttab.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    // u_j = M v_j for every active system: column j of V into column j of Z
+    auto sweep_column = [&](int j) -> int {
+        if (count == 1) return apply_dispatch(c0, V + (size_t)j * Ntot, Z + (size_t)j * Ntot, S, actd, s);
+        for (auto& g : groups) {
+            const int* tasks = (const int*)c0->stask.p + g.task_off;
+            int e;
+            if (single_prec)
+                e = launch_sweep_multi_col<float>(g.plans.data(), (int)g.plans.size(),
+                                                  (const SweepInst<float>*)((unsigned char*)c0->sinst.p + g.inst_off),
+                                                  tasks, g.blocks, g.G, j, j, s);
+            else
+                e = launch_sweep_multi_col<double>(g.plans.data(), (int)g.plans.size(),
+                                                   (const SweepInst<double>*)((unsigned char*)c0->sinst.p + g.inst_off),
+                                                   tasks, g.blocks, g.G, j, j, s);
+            if (e) return fail(HSWEEP_EINVAL, "no compiled sweep for a batch group");
+        }
+        HIPCHK(hipGetLastError());
+        return HSWEEP_OK;
+    };
+    // y = A x (or y = f - A x) for every system, one launch per context
+    auto stencil_all = [&](const c128* x, const c128* fv, c128* y, const int* act) {
+        for (int q = 0; q < count; ++q) {
+            hsweep_ctx* cq = ctxs[q];
+            const size_t o = offh[first[q]];
+            launch_stencil(cq->n, nr[q], cq->omega, (const double*)cq->c.p, (const c128*)cq->isn.p,
+                           (const c128*)cq->sh.p, x + o, fv ? fv + o : nullptr, y + o, act ? act + first[q] : nullptr, s);
+        }
+    };
+
+    c0->t_sweep = c0->t_stencil = c0->t_krylov = 0.0;
+    c0->n_apply = 0;
+    auto sync = [&]() -> int {
+        HIPCHK(hipStreamSynchronize(s));
+        return HSWEEP_OK;
+    };
+    auto norms = [&](const c128* x, std::vector<double>& out) -> int {
+        launch_multi_dot(x, 1, Ntot, x, offd, S, part, hd3, nblk, s);
+        HIPCHK(hipMemcpyAsync(hh, hd3, (size_t)S * sizeof(c128), hipMemcpyDeviceToHost, s));
+        rc = sync();
+        if (rc) return rc;
+        out.resize(S);
+        for (int k = 0; k < S; ++k) out[k] = std::sqrt(std::max(0.0, hh[k].real()));
+        return HSWEEP_OK;
+    };
+
+    std::vector<double> fnorm, beta;
+    rc = norms(f, fnorm);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(u, 0, Ntot * sizeof(c128), s));
+    std::vector<int> its(S, 0), done(S, 0);
+    std::vector<double> res(S, 0.0);
+    for (int k = 0; k < S; ++k) {
+        if (fnorm[k] == 0.0) { done[k] = 1; res[k] = 0.0; }
+        else res[k] = 1.0;
+    }
+    // first residual is f itself (x0 = 0)
+    HIPCHK(hipMemcpyAsync(rr, f, Ntot * sizeof(c128), hipMemcpyDeviceToDevice, s));
+    beta = fnorm;
+    std::vector<std::vector<std::complex<double>>> H(S), g(S), sn(S);
+    std::vector<std::vector<double>> cs(S);
+    std::vector<int> kk(S, 0), incycle(S, 0);
+    bool any_left = true;
+    while (any_left) {
+        // start a cycle for every unfinished right-hand side
+        int ncyc = 0;
+        for (int k = 0; k < S; ++k) {
+            incycle[k] = (!done[k] && its[k] < maxit) ? 1 : 0;
+            ncyc += incycle[k];
+            sch[k] = incycle[k] && beta[k] > 0 ? 1.0 / beta[k] : 0.0;
+            acth[k] = incycle[k];
+            H[k].assign((size_t)(m + 1) * m, 0.0);
+            g[k].assign(m + 1, 0.0);
+            g[k][0] = beta[k];
+            cs[k].assign(m, 0.0);
+            sn[k].assign(m, 0.0);
+            kk[k] = 0;
+        }
+        if (ncyc == 0) break;
+        HIPCHK(hipMemcpyAsync(scd, sch, S * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(actd, acth, S * sizeof(int), hipMemcpyHostToDevice, s));
+        launch_scale(rr, scd, V, offd, S, maxlen, s);
+        for (int j = 0; j < m; ++j) {
+            HIPCHK(hipEventRecord(c0->ev[0], s));
+            rc = sweep_column(j);
+            if (rc) return rc;
+            HIPCHK(hipEventRecord(c0->ev[1], s));
+            stencil_all(Z + (size_t)j * Ntot, nullptr, w, actd);
+            HIPCHK(hipEventRecord(c0->ev[2], s));
+            // classical Gram-Schmidt, twice
+            launch_multi_dot(V, j + 1, Ntot, w, offd, S, part, hd1, nblk, s);
+            launch_multi_axpy(V, j + 1, Ntot, hd1, w, offd, S, maxlen, s);
+            launch_multi_dot(V, j + 1, Ntot, w, offd, S, part, hd2, nblk, s);
+            launch_multi_axpy(V, j + 1, Ntot, hd2, w, offd, S, maxlen, s);
+            launch_multi_dot(w, 1, Ntot, w, offd, S, part, hd3, nblk, s);
+            HIPCHK(hipEventRecord(c0->ev[3], s));
+            HIPCHK(hipMemcpyAsync(hh, hd, (size_t)3 * nvmax * S * sizeof(c128), hipMemcpyDeviceToHost, s));
+            rc = sync();
+            if (rc) return rc;
+            float t1 = 0, t2 = 0, t3 = 0;
+            (void)hipEventElapsedTime(&t1, c0->ev[0], c0->ev[1]);
+            (void)hipEventElapsedTime(&t2, c0->ev[1], c0->ev[2]);
+            (void)hipEventElapsedTime(&t3, c0->ev[2], c0->ev[3]);
+            c0->t_sweep += t1;
+            c0->t_stencil += t2;
+            c0->t_krylov += t3;
+            c0->n_apply += 1;
+            const std::complex<double>* h1 = hh;
+            const std::complex<double>* h2 = hh + (size_t)nvmax * S;
+            const std::complex<double>* h3 = hh + (size_t)2 * nvmax * S;
+            int still = 0;
+            for (int k = 0; k < S; ++k) {
+                if (!incycle[k] || !acth[k]) { sch[k] = 0.0; continue; }
+                its[k] += 1;
+                std::complex<double>* col = &H[k][(size_t)j * (m + 1)];
+                for (int i = 0; i <= j; ++i) col[i] = h1[(size_t)i * S + k] + h2[(size_t)i * S + k];
+                double hn = std::sqrt(std::max(0.0, h3[k].real()));
+                col[j + 1] = hn;
+                for (int i = 0; i < j; ++i) {
+                    std::complex<double> t = cs[k][i] * col[i] + sn[k][i] * col[i + 1];
+                    col[i + 1] = -std::conj(sn[k][i]) * col[i] + cs[k][i] * col[i + 1];
+                    col[i] = t;
+                }
+                givens(col[j], col[j + 1], cs[k][j], sn[k][j]);
+                col[j] = cs[k][j] * col[j] + sn[k][j] * col[j + 1];
+                col[j + 1] = 0.0;
+                g[k][j + 1] = -std::conj(sn[k][j]) * g[k][j];
+                g[k][j] = cs[k][j] * g[k][j];
+                kk[k] = j + 1;
+                double est = std::abs(g[k][j + 1]) / fnorm[k];
+                bool stop = est <= tol || its[k] >= maxit || hn == 0.0;
+                if (stop) {
+                    acth[k] = 0;
+                    sch[k] = 0.0;
+                } else {
+                    sch[k] = 1.0 / hn;
+                    ++still;
+                }
+            }
+            HIPCHK(hipMemcpyAsync(scd, sch, S * sizeof(double), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(actd, acth, S * sizeof(int), hipMemcpyHostToDevice, s));
+            if (still == 0) break;
+            launch_scale(w, scd, V + (size_t)(j + 1) * Ntot, offd, S, maxlen, s);
+        }
+        // solve the triangular systems and update x
+        int kmax = 0;
+        for (int k = 0; k < S; ++k) {
+            for (int i = 0; i < m; ++i) yh[(size_t)i * S + k] = 0.0;
+            if (!incycle[k] || kk[k] == 0) continue;
+            int q = kk[k];
+            std::vector<std::complex<double>> yy(q);
+            for (int i = q - 1; i >= 0; --i) {
+                std::complex<double> acc = g[k][i];
+                for (int l = i + 1; l < q; ++l) acc -= H[k][(size_t)l * (m + 1) + i] * yy[l];
+                yy[i] = acc / H[k][(size_t)i * (m + 1) + i];
+            }
+            for (int i = 0; i < q; ++i) yh[(size_t)i * S + k] = yy[i];
+            kmax = std::max(kmax, q);
+        }
+        if (kmax > 0) {
+            HIPCHK(hipMemcpyAsync(yd, yh, (size_t)m * S * sizeof(c128), hipMemcpyHostToDevice, s));
+            launch_combine(Z, kmax, Ntot, yd, u, offd, S, maxlen, s);
+        }
+        // true residual
+        stencil_all(u, f, rr, nullptr);
+        rc = norms(rr, beta);
+        if (rc) return rc;
+        any_left = false;
+        for (int k = 0; k < S; ++k) {
+            if (done[k]) continue;
+            res[k] = beta[k] / fnorm[k];
+            if (res[k] <= tol) done[k] = 1;
+            else if (its[k] < maxit) any_left = true;
+        }
+    }
+    if (count > 1) {
+        for (int q = 0; q < count; ++q)
+            HIPCHK(hipMemcpyAsync(u_out[q], u + offh[first[q]], (offh[first[q + 1]] - offh[first[q]]) * sizeof(c128),
+                                  hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    HIPCHK(hipGetLastError());
+    bool all = true;
+    for (int k = 0; k < S; ++k) {
+        if (iters) iters[k] = its[k];
+        if (relres) relres[k] = res[k];
+        if (!done[k]) all = false;
+    }
+    if (!all) return fail(HSWEEP_ENOCONV, "GMRES reached maxit before tol for some right-hand side");
+    return HSWEEP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -449,6 +821,7 @@ void hsweep_default_opts(hsweep_opts* o) {
     o->precision = HSWEEP_C128;
     o->dense = 0;
     o->restart = 40;
+    o->rhs_group = 0;
 }
 
 const char* hsweep_last_error(void) { return g_err.c_str(); }
@@ -674,205 +1047,9 @@ int hsweep_solve(hsweep_ctx* ctx, const void* fv, void* uv, int nrhs, double tol
     if (!ctx->factored) return fail(HSWEEP_ESTATE, "hsweep_solve before hsweep_factor");
     rc = set_device(ctx);
     if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
     const c128* f = (const c128*)fv;
     c128* u = (c128*)uv;
-    const int n = ctx->n;
-    const size_t N = (size_t)n * n;
-    const int m = ctx->opts.restart;
-    const int nblk = krylov_dot_blocks(N);
-    const int nvmax = m + 1;
-    HIPCHK(ctx->V.ensure((size_t)(m + 1) * nrhs * N * sizeof(c128)));
-    HIPCHK(ctx->Z.ensure((size_t)m * nrhs * N * sizeof(c128)));
-    HIPCHK(ctx->w.ensure((size_t)nrhs * N * sizeof(c128)));
-    HIPCHK(ctx->r.ensure((size_t)nrhs * N * sizeof(c128)));
-    HIPCHK(ctx->hdev.ensure((size_t)3 * nvmax * nrhs * sizeof(c128)));
-    HIPCHK(ctx->partial.ensure((size_t)nblk * nrhs * nvmax * sizeof(c128)));
-    HIPCHK(ctx->scale.ensure((size_t)nrhs * sizeof(double)));
-    HIPCHK(ctx->active.ensure((size_t)nrhs * sizeof(int)));
-    HIPCHK(ctx->y.ensure((size_t)m * nrhs * sizeof(c128)));
-    HIPCHK(ctx->hhost.ensure((size_t)3 * nvmax * nrhs * sizeof(c128)));
-    HIPCHK(ctx->scalehost.ensure((size_t)nrhs * sizeof(double)));
-    HIPCHK(ctx->activehost.ensure((size_t)nrhs * sizeof(int)));
-    HIPCHK(ctx->yhost.ensure((size_t)m * nrhs * sizeof(c128)));
-    c128* V = (c128*)ctx->V.p;
-    c128* Z = (c128*)ctx->Z.p;
-    c128* w = (c128*)ctx->w.p;
-    c128* rr = (c128*)ctx->r.p;
-    c128* hd = (c128*)ctx->hdev.p;
-    c128* hd1 = hd;                       // first Gram-Schmidt pass
-    c128* hd2 = hd + (size_t)nvmax * nrhs; // second pass
-    c128* hd3 = hd2 + (size_t)nvmax * nrhs; // norms
-    c128* part = (c128*)ctx->partial.p;
-    double* scd = (double*)ctx->scale.p;
-    int* actd = (int*)ctx->active.p;
-    c128* yd = (c128*)ctx->y.p;
-    std::complex<double>* hh = (std::complex<double>*)ctx->hhost.p;
-    double* sch = (double*)ctx->scalehost.p;
-    int* acth = (int*)ctx->activehost.p;
-    std::complex<double>* yh = (std::complex<double>*)ctx->yhost.p;
-
-    ctx->t_sweep = ctx->t_stencil = ctx->t_krylov = 0.0;
-    ctx->n_apply = 0;
-    auto sync = [&]() -> int {
-        HIPCHK(hipStreamSynchronize(s));
-        return HSWEEP_OK;
-    };
-    auto norms = [&](const c128* x, std::vector<double>& out) -> int {
-        launch_multi_dot(x, 1, x, nrhs, N, part, hd3, nblk, s);
-        HIPCHK(hipMemcpyAsync(hh, hd3, (size_t)nrhs * sizeof(c128), hipMemcpyDeviceToHost, s));
-        rc = sync();
-        if (rc) return rc;
-        out.resize(nrhs);
-        for (int k = 0; k < nrhs; ++k) out[k] = std::sqrt(std::max(0.0, hh[k].real()));
-        return HSWEEP_OK;
-    };
-
-    std::vector<double> fnorm, beta;
-    rc = norms(f, fnorm);
-    if (rc) return rc;
-    HIPCHK(hipMemsetAsync(u, 0, (size_t)nrhs * N * sizeof(c128), s));
-    std::vector<int> its(nrhs, 0), done(nrhs, 0);
-    std::vector<double> res(nrhs, 0.0);
-    for (int k = 0; k < nrhs; ++k) {
-        if (fnorm[k] == 0.0) { done[k] = 1; res[k] = 0.0; }
-        else res[k] = 1.0;
-    }
-    // first residual is f itself (x0 = 0)
-    HIPCHK(hipMemcpyAsync(rr, f, (size_t)nrhs * N * sizeof(c128), hipMemcpyDeviceToDevice, s));
-    beta = fnorm;
-    std::vector<std::vector<std::complex<double>>> H(nrhs), g(nrhs), sn(nrhs);
-    std::vector<std::vector<double>> cs(nrhs);
-    std::vector<int> kk(nrhs, 0), incycle(nrhs, 0);
-    int total = 0;
-    bool any_left = true;
-    while (any_left) {
-        // start a cycle for every unfinished right-hand side
-        int ncyc = 0;
-        for (int k = 0; k < nrhs; ++k) {
-            incycle[k] = (!done[k] && its[k] < maxit) ? 1 : 0;
-            ncyc += incycle[k];
-            sch[k] = incycle[k] && beta[k] > 0 ? 1.0 / beta[k] : 0.0;
-            acth[k] = incycle[k];
-            H[k].assign((size_t)(m + 1) * m, 0.0);
-            g[k].assign(m + 1, 0.0);
-            g[k][0] = beta[k];
-            cs[k].assign(m, 0.0);
-            sn[k].assign(m, 0.0);
-            kk[k] = 0;
-        }
-        if (ncyc == 0) break;
-        HIPCHK(hipMemcpyAsync(scd, sch, nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(actd, acth, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
-        launch_scale(rr, scd, V, nrhs, N, s);
-        int j = 0;
-        for (j = 0; j < m; ++j) {
-            c128* Vj = V + (size_t)j * nrhs * N;
-            c128* Zj = Z + (size_t)j * nrhs * N;
-            HIPCHK(hipEventRecord(ctx->ev[0], s));
-            rc = apply_dispatch(ctx, Vj, Zj, nrhs, actd, s);
-            if (rc) return rc;
-            HIPCHK(hipEventRecord(ctx->ev[1], s));
-            launch_stencil(n, nrhs, ctx->omega, (const double*)ctx->c.p, (const c128*)ctx->isn.p,
-                           (const c128*)ctx->sh.p, Zj, nullptr, w, actd, s);
-            HIPCHK(hipEventRecord(ctx->ev[2], s));
-            // classical Gram-Schmidt, twice
-            launch_multi_dot(V, j + 1, w, nrhs, N, part, hd1, nblk, s);
-            launch_multi_axpy(V, j + 1, hd1, w, nrhs, N, s);
-            launch_multi_dot(V, j + 1, w, nrhs, N, part, hd2, nblk, s);
-            launch_multi_axpy(V, j + 1, hd2, w, nrhs, N, s);
-            launch_multi_dot(w, 1, w, nrhs, N, part, hd3, nblk, s);
-            HIPCHK(hipEventRecord(ctx->ev[3], s));
-            HIPCHK(hipMemcpyAsync(hh, hd, (size_t)3 * nvmax * nrhs * sizeof(c128), hipMemcpyDeviceToHost, s));
-            rc = sync();
-            if (rc) return rc;
-            float t1 = 0, t2 = 0, t3 = 0;
-            (void)hipEventElapsedTime(&t1, ctx->ev[0], ctx->ev[1]);
-            (void)hipEventElapsedTime(&t2, ctx->ev[1], ctx->ev[2]);
-            (void)hipEventElapsedTime(&t3, ctx->ev[2], ctx->ev[3]);
-            ctx->t_sweep += t1;
-            ctx->t_stencil += t2;
-            ctx->t_krylov += t3;
-            ctx->n_apply += 1;
-            ++total;
-            const std::complex<double>* h1 = hh;
-            const std::complex<double>* h2 = hh + (size_t)nvmax * nrhs;
-            const std::complex<double>* h3 = hh + (size_t)2 * nvmax * nrhs;
-            int still = 0;
-            for (int k = 0; k < nrhs; ++k) {
-                if (!incycle[k] || !acth[k]) { sch[k] = 0.0; continue; }
-                its[k] += 1;
-                std::complex<double>* col = &H[k][(size_t)j * (m + 1)];
-                for (int i = 0; i <= j; ++i) col[i] = h1[(size_t)i * nrhs + k] + h2[(size_t)i * nrhs + k];
-                double hn = std::sqrt(std::max(0.0, h3[k].real()));
-                col[j + 1] = hn;
-                for (int i = 0; i < j; ++i) {
-                    std::complex<double> t = cs[k][i] * col[i] + sn[k][i] * col[i + 1];
-                    col[i + 1] = -std::conj(sn[k][i]) * col[i] + cs[k][i] * col[i + 1];
-                    col[i] = t;
-                }
-                givens(col[j], col[j + 1], cs[k][j], sn[k][j]);
-                col[j] = cs[k][j] * col[j] + sn[k][j] * col[j + 1];
-                col[j + 1] = 0.0;
-                g[k][j + 1] = -std::conj(sn[k][j]) * g[k][j];
-                g[k][j] = cs[k][j] * g[k][j];
-                kk[k] = j + 1;
-                double est = std::abs(g[k][j + 1]) / fnorm[k];
-                bool stop = est <= tol || its[k] >= maxit || hn == 0.0;
-                if (stop) {
-                    acth[k] = 0;
-                    sch[k] = 0.0;
-                } else {
-                    sch[k] = 1.0 / hn;
-                    ++still;
-                }
-            }
-            HIPCHK(hipMemcpyAsync(scd, sch, nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(actd, acth, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
-            if (still == 0) break;
-            launch_scale(w, scd, V + (size_t)(j + 1) * nrhs * N, nrhs, N, s);
-        }
-        // solve the triangular systems and update x
-        int kmax = 0;
-        for (int k = 0; k < nrhs; ++k) {
-            for (int i = 0; i < m; ++i) yh[(size_t)i * nrhs + k] = 0.0;
-            if (!incycle[k] || kk[k] == 0) continue;
-            int q = kk[k];
-            std::vector<std::complex<double>> yy(q);
-            for (int i = q - 1; i >= 0; --i) {
-                std::complex<double> acc = g[k][i];
-                for (int l = i + 1; l < q; ++l) acc -= H[k][(size_t)l * (m + 1) + i] * yy[l];
-                yy[i] = acc / H[k][(size_t)i * (m + 1) + i];
-            }
-            for (int i = 0; i < q; ++i) yh[(size_t)i * nrhs + k] = yy[i];
-            kmax = std::max(kmax, q);
-        }
-        if (kmax > 0) {
-            HIPCHK(hipMemcpyAsync(yd, yh, (size_t)m * nrhs * sizeof(c128), hipMemcpyHostToDevice, s));
-            launch_combine(Z, kmax, yd, u, nrhs, N, s);
-        }
-        // true residual
-        launch_stencil(n, nrhs, ctx->omega, (const double*)ctx->c.p, (const c128*)ctx->isn.p,
-                       (const c128*)ctx->sh.p, u, f, rr, nullptr, s);
-        rc = norms(rr, beta);
-        if (rc) return rc;
-        any_left = false;
-        for (int k = 0; k < nrhs; ++k) {
-            if (done[k]) continue;
-            res[k] = beta[k] / fnorm[k];
-            if (res[k] <= tol) done[k] = 1;
-            else if (its[k] < maxit) any_left = true;
-        }
-    }
-    HIPCHK(hipGetLastError());
-    bool all = true;
-    for (int k = 0; k < nrhs; ++k) {
-        if (iters) iters[k] = its[k];
-        if (relres) relres[k] = res[k];
-        if (!done[k]) all = false;
-    }
-    if (!all) return fail(HSWEEP_ENOCONV, "GMRES reached maxit before tol for some right-hand side");
-    return HSWEEP_OK;
+    return solve_systems(&ctx, 1, &nrhs, &f, &u, tol, maxit, iters, relres, (hipStream_t)stream);
 }
 
 int hsweep_solve_adjoint(hsweep_ctx* ctx, const void* g, void* mu, void* grad_f, int nrhs, double tol, int maxit,
@@ -927,7 +1104,7 @@ int hsweep_workspace_bytes(const hsweep_ctx* ctx, int nrhs, size_t* factor_bytes
     size_t sb = K * n * np * E;
     sb += (2 * m + 1) * K * N * sizeof(c128) + 2 * K * N * sizeof(c128);
     sb += 3 * (m + 1) * K * sizeof(c128) + nblk * K * (m + 1) * sizeof(c128);
-    sb += K * (sizeof(double) + sizeof(int)) + m * K * sizeof(c128);
+    sb += K * (sizeof(double) + sizeof(int)) + m * K * sizeof(c128) + (K + 1) * sizeof(size_t);
     if (factor_bytes) *factor_bytes = fb;
     if (solve_bytes) *solve_bytes = sb;
     return HSWEEP_OK;
@@ -948,19 +1125,29 @@ int hsweep_factor_batch(hsweep_ctx** ctxs, int count, void* stream) {
         }
         if (ctxs[q]->opts.precision != ctxs[0]->opts.precision || ctxs[q]->device != ctxs[0]->device)
             return fail(HSWEEP_EINVAL, "contexts of one batch need the same precision and device");
-        const Plan& a = ctxs[q]->plan;
-        const Plan& b0 = ctxs[0]->plan;
-        if (a.b != b0.b || (a.L > 0 ? a.r : 2) != (b0.L > 0 ? b0.r : 2))
-            return fail(HSWEEP_EINVAL, "contexts of one batch need the same leaf size and rank");
     }
     int rc = set_device(ctxs[0]);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     for (int q = 0; q < count; ++q) ctxs[q]->factored = false;
     HIPCHK(hipEventRecord(ctxs[0]->ev[0], s));
-    rc = ctxs[0]->opts.precision == HSWEEP_C64 ? do_factor_many<float>(ctxs, count, s)
-                                               : do_factor_many<double>(ctxs, count, s);
-    if (rc) return rc;
+    // one layer loop per group of contexts with the same leaf size and rank;
+    // within a group every layer step is one set of launches for all of them
+    std::vector<std::vector<hsweep_ctx*>> groups;
+    for (int q = 0; q < count; ++q) {
+        const Plan& a = ctxs[q]->plan;
+        bool placed = false;
+        for (auto& g : groups) {
+            const Plan& b0 = g[0]->plan;
+            if (a.b == b0.b && (a.L > 0 ? a.r : 2) == (b0.L > 0 ? b0.r : 2)) { g.push_back(ctxs[q]); placed = true; break; }
+        }
+        if (!placed) groups.push_back({ctxs[q]});
+    }
+    for (auto& g : groups) {
+        rc = ctxs[0]->opts.precision == HSWEEP_C64 ? do_factor_many<float>(g.data(), (int)g.size(), s)
+                                                   : do_factor_many<double>(g.data(), (int)g.size(), s);
+        if (rc) return rc;
+    }
     HIPCHK(hipEventRecord(ctxs[0]->ev[1], s));
     HIPCHK(hipEventSynchronize(ctxs[0]->ev[1]));
     float ms = 0.f;
@@ -976,17 +1163,24 @@ int hsweep_solve_batch(hsweep_ctx** ctxs, int count, const void* const* f, void*
                        int* iters, double* relres, void* stream) {
     g_err.clear();
     if (!ctxs || count < 1 || !f || !u) return fail(HSWEEP_EINVAL, "ctxs, f and u must hold count >= 1 entries");
-    int worst = HSWEEP_OK;
-    for (int i = 0; i < count; ++i) {
-        int it = 0;
-        double rr = 0;
-        int rc = hsweep_solve(ctxs[i], f[i], u[i], 1, tol, maxit, &it, &rr, stream);
-        if (iters) iters[i] = it;
-        if (relres) relres[i] = rr;
-        if (rc == HSWEEP_ENOCONV) worst = rc;
-        else if (rc) return rc;
+    if (count > 4096) return fail(HSWEEP_EINVAL, "at most 4096 contexts per batch");
+    if (!(tol > 0.0) || !isfinite(tol)) return fail(HSWEEP_EINVAL, "tol must be finite and > 0");
+    if (maxit < 1) return fail(HSWEEP_EINVAL, "maxit must be >= 1");
+    for (int q = 0; q < count; ++q) {
+        int rc = check_ctx(ctxs[q]);
+        if (rc) return rc;
+        if (!f[q] || !u[q] || f[q] == u[q]) return fail(HSWEEP_EINVAL, "f[k] and u[k] must be distinct device pointers");
+        if (!ctxs[q]->factored) return fail(HSWEEP_ESTATE, "hsweep_solve_batch before the contexts are factored");
+        if (ctxs[q]->opts.precision != ctxs[0]->opts.precision || ctxs[q]->device != ctxs[0]->device)
+            return fail(HSWEEP_EINVAL, "contexts of one batch need the same precision and device");
+        for (int p = 0; p < q; ++p)
+            if (ctxs[p] == ctxs[q]) return fail(HSWEEP_EINVAL, "a context appears twice in the batch");
     }
-    return worst;
+    int rc = set_device(ctxs[0]);
+    if (rc) return rc;
+    std::vector<int> nr(count, 1);
+    return solve_systems(ctxs, count, nr.data(), (const c128* const*)f, (c128* const*)u, tol, maxit, iters, relres,
+                         (hipStream_t)stream);
 }
 
 void hsweep_destroy(hsweep_ctx* ctx) {

@@ -2,6 +2,7 @@
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
+#include <vector>
 #include "cplx.hpp"
 
 // Plan of the layer H-matrix: the layer of n unknowns is padded to
@@ -86,29 +87,59 @@ template <typename T>
 void factor_kernels_init();
 
 // ---- sweep (preconditioner application) ----
+// One instance of a sweep launch.  For call column j, right-hand side r
+// reads f + j*fstride + r*n*n and writes u + j*ustride + r*n*n; its forward
+// work vectors are w + r*n*np.
+template <typename T>
+struct SweepInst {
+    int n, np, L, nrhs;
+    size_t eK, eP, eLayer;
+    const cpx<T>* fac;   // factor store base (n layers of eLayer entries)
+    const cpx<T>* cp;    // (n-1)*np couplings, cp[m*np + i] = A_{m+1,m}(i, i)
+    const c128* f;       // complex128 input fields
+    c128* u;             // complex128 output fields
+    cpx<T>* w;           // nrhs * n * np work
+    const int* active;   // nrhs flags (null = all active); inactive ones get u = 0
+    size_t fstride, ustride;
+};
+// Kernel argument of a sweep launch: one instance by value (insts null), or
+// a device table of instances with a device table of workgroup tasks.
 template <typename T>
 struct SweepArgs {
-    const cpx<T>* fac;  // factor store base (n layers of eLayer entries)
-    const cpx<T>* cp;   // (n-1)*np couplings, cp[m*np + i] = A_{m+1,m}(i, i)
-    const c128* f;      // nrhs * n * n input (complex128)
-    c128* u;            // nrhs * n * n output
-    cpx<T>* w;          // nrhs * n * np work
-    const int* active;  // nrhs flags (null = all active)
-    int nrhs;
+    SweepInst<T> one;
+    const SweepInst<T>* insts;
+    const int* tasks;      // per workgroup: (instance << 16) | first right-hand side, -1 = idle
+    int ngroups, nxcd;     // one instance: its right-hand-side groups and the XCDs they use
+    int jf, ju;            // call column of the fields
 };
+// One instance, right-hand sides in groups of G (1 or 4) per workgroup.
 template <typename T>
-int launch_sweep(const Plan& p, const SweepArgs<T>& a, hipStream_t s);
+int launch_sweep(const Plan& p, SweepArgs<T> a, int G, hipStream_t s);
+// Several instances (same leaf size and rank) in one launch of `blocks`
+// workgroups; `tasks` is a device table of one entry per workgroup.
+template <typename T>
+int launch_sweep_multi_col(const Plan* plans, int ninst, const SweepInst<T>* insts, const int* tasks, int blocks,
+                           int G, int jf, int ju, hipStream_t s);
+size_t sweep_lds_bytes(const Plan& p, size_t elem, int G);
+bool sweep_supported(const Plan& p);
+bool sweep_group_supported(const Plan& p);
 
 // ---- Krylov vector kernels (FP64 complex) ----
-// partial dots: out[j*nrhs + k] = sum_i conj(V[(j*nrhs + k)*N + i]) * w[k*N + i], j < nv
-void launch_multi_dot(const c128* V, int nv, const c128* w, int nrhs, size_t N, c128* partial,
+// S systems of lengths off[k+1] - off[k] (off: device array of S+1 offsets);
+// system k occupies [off[k], off[k+1]) of every vector and vector j of a set
+// starts at j * ld.  maxlen: the longest system.
+// partial dots: out[j*S + k] = sum_i conj(V_j[i]) * w[i] over system k, j < nv
+void launch_multi_dot(const c128* V, int nv, size_t ld, const c128* w, const size_t* off, int S, c128* partial,
                       c128* out, int nblk, hipStream_t s);
-// w[k] -= sum_j h[j*nrhs + k] V[j][k]
-void launch_multi_axpy(const c128* V, int nv, const c128* h, c128* w, int nrhs, size_t N, hipStream_t s);
-// out[k] = w[k] * scale[k] (scale 0 writes zeros)
-void launch_scale(const c128* w, const double* scale, c128* out, int nrhs, size_t N, hipStream_t s);
-// x[k] += sum_j y[j*nrhs + k] Z[j][k]
-void launch_combine(const c128* Z, int nz, const c128* y, c128* x, int nrhs, size_t N, hipStream_t s);
+// w -= sum_j h[j*S + k] V_j on system k
+void launch_multi_axpy(const c128* V, int nv, size_t ld, const c128* h, c128* w, const size_t* off, int S,
+                       size_t maxlen, hipStream_t s);
+// out = w * scale[k] on system k (scale 0 writes zeros)
+void launch_scale(const c128* w, const double* scale, c128* out, const size_t* off, int S, size_t maxlen,
+                  hipStream_t s);
+// x += sum_j y[j*S + k] Z_j on system k
+void launch_combine(const c128* Z, int nz, size_t ld, const c128* y, c128* x, const size_t* off, int S, size_t maxlen,
+                    hipStream_t s);
 int krylov_dot_blocks(size_t N);
 // y = conj(x), n complex entries
 void launch_conj(const c128* x, c128* y, size_t n, hipStream_t s);

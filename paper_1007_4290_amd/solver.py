@@ -37,11 +37,12 @@ class Solver:
     c: velocity (n x n, indexed [j-1, i-1]) as numpy array or tensor;
     omega: angular frequency; pml: absorbing-layer width in grid points.
     Options: leaf, rank, rank_tol, precision ("c128" | "c64"), dense,
-    restart, pml_C.
+    restart, pml_C, rhs_group (right-hand sides per sweep workgroup:
+    0 automatic, 1 or 4).
     """
 
     def __init__(self, c, omega, pml, leaf=16, rank=8, rank_tol=1e-6, precision="c128", dense=False,
-                 restart=40, pml_C=20.0):
+                 restart=40, pml_C=20.0, rhs_group=0):
         lib = _lib.load()
         if isinstance(c, torch.Tensor):
             c_t = c.detach().to(torch.float64).contiguous()
@@ -60,6 +61,7 @@ class Solver:
         o = _lib.default_opts()
         o.leaf, o.rank, o.rank_tol = int(leaf), int(rank), float(rank_tol)
         o.pml_C, o.precision, o.dense, o.restart = float(pml_C), _PREC[precision], int(bool(dense)), int(restart)
+        o.rhs_group = int(rhs_group)
         _lib.check(lib.hsweep_set_opts(self._ctx, ctypes.byref(o)))
         self.precision = precision
         self.factored = False

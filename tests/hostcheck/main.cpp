@@ -1,0 +1,88 @@
+// Host-logic check of the C-ABI without a GPU: the library's host code runs
+// against a host-memory stand-in of the HIP runtime (fake_runtime.cpp), and
+// every kernel launcher is replaced by a check that the device ranges the
+// kernel would touch lie inside live allocations (stubs.cpp).  Covers the
+// batched factorization and FGMRES over mixed grid sizes and leaf sizes, a
+// multi-right-hand-side solve, the adjoint solve and the allocation-free
+// apply.  The stand-in dot products return 1, so GMRES runs to maxit: the
+// point is the ranges, not the numbers.
+#include <math.h>
+#include <stdio.h>
+#include <vector>
+#include "hsweep.h"
+#include <hip/hip_runtime.h>
+
+int multi_launches();
+
+static int expect(int rc, int want, const char* what) {
+    if (rc != want) {
+        printf("%s: rc %d (%s), expected %d\n", what, rc, hsweep_last_error(), want);
+        return 1;
+    }
+    return 0;
+}
+
+int main() {
+    int bad = 0;
+    // the mixed batch: 8 each of n = 127, 255 (leaf 16) and 511 (leaf 32)
+    std::vector<int> ns, leaves;
+    for (int k = 0; k < 8; ++k) { ns.push_back(127); leaves.push_back(16); }
+    for (int k = 0; k < 8; ++k) { ns.push_back(255); leaves.push_back(16); }
+    for (int k = 0; k < 8; ++k) { ns.push_back(511); leaves.push_back(32); }
+    std::vector<hsweep_ctx*> ctx(ns.size());
+    std::vector<void*> f(ns.size()), u(ns.size());
+    for (size_t q = 0; q < ns.size(); ++q) {
+        const int n = ns[q];
+        std::vector<double> c((size_t)n * n, 1.0);
+        if (expect(hsweep_setup(c.data(), 2 * M_PI * (n + 1) / 8, 16, n, &ctx[q]), 0, "setup")) return 1;
+        hsweep_opts o;
+        hsweep_default_opts(&o);
+        o.leaf = leaves[q];
+        o.precision = HSWEEP_C64;
+        if (expect(hsweep_set_opts(ctx[q], &o), 0, "set_opts")) return 1;
+        hipMalloc(&f[q], (size_t)n * n * 16);
+        hipMalloc(&u[q], (size_t)n * n * 16);
+    }
+    bad += expect(hsweep_factor_batch(ctx.data(), (int)ctx.size(), nullptr), 0, "factor_batch");
+    std::vector<int> its(ns.size());
+    std::vector<double> res(ns.size());
+    bad += expect(hsweep_solve_batch(ctx.data(), (int)ctx.size(), (const void* const*)f.data(), (void* const*)u.data(),
+                                     1e-10, 60, its.data(), res.data(), nullptr),
+                  HSWEEP_ENOCONV, "solve_batch");
+    if (multi_launches() < 2) { printf("expected one sweep launch per leaf group and step\n"); ++bad; }
+    // one context, 64 right-hand sides, then an adjoint solve and the allocation-free apply
+    void *F, *U, *G;
+    const size_t N = (size_t)511 * 511;
+    hipMalloc(&F, 64 * N * 16);
+    hipMalloc(&U, 64 * N * 16);
+    hipMalloc(&G, 64 * N * 16);
+    std::vector<int> it64(64);
+    std::vector<double> r64(64);
+    bad += expect(hsweep_solve(ctx[16], F, U, 64, 1e-10, 45, it64.data(), r64.data(), nullptr), HSWEEP_ENOCONV, "solve 64");
+    bad += expect(hsweep_solve_adjoint(ctx[16], F, U, G, 2, 1e-10, 45, it64.data(), r64.data(), nullptr), HSWEEP_ENOCONV,
+                  "adjoint");
+    bad += expect(hsweep_apply_noalloc(ctx[16], F, U, 4, nullptr), 0, "apply_noalloc");
+    bad += expect(hsweep_apply(ctx[0], F, U, 3, nullptr), 0, "apply");
+    // a complex128 batch of two grid sizes with one leaf size (one sweep launch per step)
+    std::vector<hsweep_ctx*> c2(2);
+    std::vector<void*> f2(2), u2(2);
+    const int n2[2] = {63, 31};
+    for (int q = 0; q < 2; ++q) {
+        std::vector<double> c((size_t)n2[q] * n2[q], 1.0);
+        if (expect(hsweep_setup(c.data(), 20.0, 4, n2[q], &c2[q]), 0, "setup c128")) return 1;
+        hsweep_opts o;
+        hsweep_default_opts(&o);
+        o.leaf = 8;
+        if (expect(hsweep_set_opts(c2[q], &o), 0, "set_opts c128")) return 1;
+        hipMalloc(&f2[q], (size_t)n2[q] * n2[q] * 16);
+        hipMalloc(&u2[q], (size_t)n2[q] * n2[q] * 16);
+    }
+    bad += expect(hsweep_factor_batch(c2.data(), 2, nullptr), 0, "factor_batch c128");
+    bad += expect(hsweep_solve_batch(c2.data(), 2, (const void* const*)f2.data(), (void* const*)u2.data(), 1e-10, 30,
+                                     its.data(), res.data(), nullptr),
+                  HSWEEP_ENOCONV, "solve_batch c128");
+    for (auto* c : c2) hsweep_destroy(c);
+    for (auto* c : ctx) hsweep_destroy(c);
+    printf(bad ? "HOSTCHECK FAILED\n" : "HOSTCHECK OK\n");
+    return bad ? 1 : 0;
+}

@@ -1,0 +1,102 @@
+// Stand-ins of the kernel launchers: each checks that every device range the
+// kernel would read or write lies inside a live allocation, and aborts with
+// the range otherwise.  The dot products return 1.
+#include <stdio.h>
+#include <stdlib.h>
+#include <complex>
+#include "internal.hpp"
+void fake_describe(const void* p);
+static void need(const void* p, size_t b, const char* what) {
+    if (b && !fake_in_alloc(p, b)) { fprintf(stderr, "OUT OF RANGE: %s %p %zu\n", what, p, b); fake_describe(p); abort(); }
+}
+void launch_pml_1d(int n, double, double, double, c128* sn, c128* isn, c128* sh, hipStream_t) {
+    need(sn, n * 16, "sn"); need(isn, n * 16, "isn"); need(sh, (n + 1) * 16, "sh");
+}
+template <typename T>
+void launch_layer_coeffs(int n, int np, double, const double* c, const c128* isn, const c128* sh, cpx<T>* dg,
+                         cpx<T>* eo, cpx<T>* cp, hipStream_t) {
+    need(c, (size_t)n * n * 8, "c"); need(dg, (size_t)n * np * sizeof(cpx<T>), "dg");
+    need(eo, (size_t)n * np * sizeof(cpx<T>), "eo"); need(cp, (size_t)(n - 1) * np * sizeof(cpx<T>), "cp");
+}
+template void launch_layer_coeffs<float>(int, int, double, const double*, const c128*, const c128*, c64*, c64*, c64*, hipStream_t);
+template void launch_layer_coeffs<double>(int, int, double, const double*, const c128*, const c128*, c128*, c128*, c128*, hipStream_t);
+void launch_stencil(int n, int nrhs, double, const double* c, const c128* isn, const c128* sh, const c128* x,
+                    const c128* f, c128* y, const int* active, hipStream_t) {
+    size_t N = (size_t)n * n;
+    need(c, N * 8, "st c"); need(isn, n * 16, "st isn"); need(sh, (n + 1) * 16, "st sh");
+    need(x, nrhs * N * 16, "st x"); if (f) need(f, nrhs * N * 16, "st f"); need(y, nrhs * N * 16, "st y");
+    if (active) need(active, nrhs * 4, "st active");
+}
+void launch_grad(int, int, double, const double*, const c128*, const c128*, const c128*, double*, hipStream_t) {}
+template <typename T> int launch_factor_layer(const InstDesc<T>*, const Plan*, int, int, hipStream_t, hipEvent_t) { return 0; }
+template int launch_factor_layer<float>(const InstDesc<float>*, const Plan*, int, int, hipStream_t, hipEvent_t);
+template int launch_factor_layer<double>(const InstDesc<double>*, const Plan*, int, int, hipStream_t, hipEvent_t);
+template <typename T> void factor_kernels_init() {}
+template void factor_kernels_init<float>();
+template void factor_kernels_init<double>();
+size_t factor_lds_bytes(const Plan&, size_t) { return 1024; }
+bool factor_supported(const Plan&) { return true; }
+size_t sweep_lds_bytes(const Plan& p, size_t elem, int G) {
+    size_t e = (size_t)p.np + (size_t)((1 << (p.L + 1)) - 1) * p.r + (size_t)((1 << p.L) - 1) * 2 * p.r;
+    return e * (size_t)G * elem;
+}
+bool sweep_supported(const Plan&) { return true; }
+bool sweep_group_supported(const Plan&) { return true; }
+template <typename T>
+static void check_inst(const SweepInst<T>& in, int jf, int ju, const char* tag) {
+    size_t N = (size_t)in.n * in.n;
+    need(in.fac, (size_t)in.n * in.eLayer * sizeof(cpx<T>), "fac");
+    if (in.n > 1) need(in.cp, (size_t)(in.n - 1) * in.np * sizeof(cpx<T>), "cp");
+    need(in.f + (size_t)jf * in.fstride, in.nrhs * N * 16, tag);
+    need(in.u + (size_t)ju * in.ustride, in.nrhs * N * 16, tag);
+    need(in.w, (size_t)in.nrhs * in.n * in.np * sizeof(cpx<T>), tag);
+    if (in.active) need(in.active, in.nrhs * 4, "active");
+}
+template <typename T> int launch_sweep(const Plan&, SweepArgs<T> a, int, hipStream_t) {
+    check_inst(a.one, a.jf, a.ju, "single f/u"); return 0;
+}
+template int launch_sweep<float>(const Plan&, SweepArgs<float>, int, hipStream_t);
+template int launch_sweep<double>(const Plan&, SweepArgs<double>, int, hipStream_t);
+static int g_multi = 0;
+template <typename T>
+int launch_sweep_multi_col(const Plan* plans, int ninst, const SweepInst<T>* insts, const int* tasks, int blocks,
+                           int, int jf, int ju, hipStream_t) {
+    need(insts, ninst * sizeof(SweepInst<T>), "insts");
+    need(tasks, blocks * 4, "tasks");
+    for (int b = 0; b < blocks; ++b) {
+        int t = tasks[b];
+        if (t < 0) continue;
+        int q = t >> 16, r0 = t & 0xffff;
+        if (q >= ninst) { fprintf(stderr, "task instance %d >= %d\n", q, ninst); abort(); }
+        if (r0 >= insts[q].nrhs) { fprintf(stderr, "task rhs\n"); abort(); }
+        if (insts[q].n != plans[q].n || insts[q].np != plans[q].np) { fprintf(stderr, "plan mismatch q=%d\n", q); abort(); }
+        check_inst(insts[q], jf, ju, "multi f/u");
+    }
+    ++g_multi;
+    return 0;
+}
+template int launch_sweep_multi_col<float>(const Plan*, int, const SweepInst<float>*, const int*, int, int, int, int, hipStream_t);
+template int launch_sweep_multi_col<double>(const Plan*, int, const SweepInst<double>*, const int*, int, int, int, int, hipStream_t);
+int krylov_dot_blocks(size_t N) { size_t b = (N + 8191) / 8192; if (b < 1) b = 1; if (b > 256) b = 256; return (int)b; }
+void launch_conj(const c128* x, c128* y, size_t n, hipStream_t) { need(x, n * 16, "conj x"); need(y, n * 16, "conj y"); }
+void launch_multi_dot(const c128* V, int nv, size_t ld, const c128* w, const size_t* off, int S, c128* partial,
+                      c128* out, int nblk, hipStream_t) {
+    need(off, (S + 1) * 8, "off");
+    for (int j = 0; j < nv; ++j) need(V + j * ld, off[S] * 16, "dot V");
+    need(w, off[S] * 16, "dot w"); need(partial, (size_t)nblk * S * nv * 16, "partial"); need(out, nv * S * 16, "dot out");
+    for (int i = 0; i < nv * S; ++i) out[i] = mk<double>(1.0, 0.0);
+}
+void launch_multi_axpy(const c128* V, int nv, size_t ld, const c128* h, c128* w, const size_t* off, int S, size_t,
+                       hipStream_t) {
+    for (int j = 0; j < nv; ++j) need(V + j * ld, off[S] * 16, "axpy V");
+    need(h, nv * S * 16, "axpy h"); need(w, off[S] * 16, "axpy w");
+}
+void launch_scale(const c128* w, const double* sc, c128* out, const size_t* off, int S, size_t, hipStream_t) {
+    need(w, off[S] * 16, "scale w"); need(sc, S * 8, "scale sc"); need(out, off[S] * 16, "scale out");
+}
+void launch_combine(const c128* Z, int nz, size_t ld, const c128* y, c128* x, const size_t* off, int S, size_t,
+                    hipStream_t) {
+    for (int j = 0; j < nz; ++j) need(Z + j * ld, off[S] * 16, "combine Z");
+    need(y, nz * S * 16, "combine y"); need(x, off[S] * 16, "combine x");
+}
+int multi_launches() { return g_multi; }

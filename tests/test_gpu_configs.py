@@ -54,27 +54,69 @@ def test_helm511_64_sources_c64():
 
 
 def test_mixed_batch_of_24_instances():
-    # 8 instances each of n = 127, 255, 511 (media seeds 100..123), c64 sweeps
+    # 8 instances each of n = 127, 255, 511 (media seeds 100..123), c64 sweeps:
+    # one batched factorization and one batched FGMRES over all 24
     _need_gpu()
     from paper_1007_4290_amd.solver import Solver, factor_batch, solve_batch
     wls = W.configs.mixed_batch()
-    by_leaf = {}
-    for wl in wls:
-        by_leaf.setdefault(wl.leaf, []).append(wl)
-    checked = 0
-    for leaf, group in by_leaf.items():
-        solvers = [Solver(wl.velocity(), wl.omega, wl.pml, leaf=leaf, rank=8, rank_tol=1e-6, precision="c64")
-                   for wl in group]
-        factor_batch(solvers)
-        fs = [_t(wl.sources()[0]) for wl in group]
-        us, its, res = solve_batch(solvers, fs, tol=1e-10, maxit=200)
-        assert max(res) <= 1e-10
-        for k, wl in enumerate(group):
-            st = assemble.stencil(wl.velocity(), wl.omega, wl.pml)
-            ue = direct.solve_sparse(st, wl.sources()[0])
-            assert_close(us[k].cpu().numpy(), ue, 1e-5, wl.name)
-            checked += 1
-    assert checked == 24
+    solvers = [Solver(wl.velocity(), wl.omega, wl.pml, leaf=wl.leaf, rank=8, rank_tol=1e-6, precision="c64")
+               for wl in wls]
+    factor_batch(solvers)
+    fs = [_t(wl.sources()[0]) for wl in wls]
+    us, its, res = solve_batch(solvers, fs, tol=1e-10, maxit=200)
+    assert max(res) <= 1e-10
+    for k, wl in enumerate(wls):
+        st = assemble.stencil(wl.velocity(), wl.omega, wl.pml)
+        ue = direct.solve_sparse(st, wl.sources()[0])
+        assert_close(us[k].cpu().numpy(), ue, 1e-5, wl.name)
+    # the batched loop agrees with one solve per context
+    for k in (0, 8, 23):
+        u1, _, r1 = solvers[k].solve(fs[k], tol=1e-10, maxit=200)
+        assert r1 <= 1e-10
+        assert_close(us[k].cpu().numpy(), u1.cpu().numpy(), 1e-8, f"batched vs single {k}")
+
+
+def test_batch_sweep_in_one_launch_equals_single_sweeps():
+    # one leaf size for the whole batch: the sweep of every GMRES step is a
+    # single launch over all instances (levels 3, 4 and 5 in one kernel)
+    _need_gpu()
+    from paper_1007_4290_amd.solver import Solver, factor_batch, solve_batch
+    sizes = [(127, 200), (255, 201), (511, 202), (127, 203)]
+    solvers, fs, refs = [], [], []
+    for n, seed in sizes:
+        c = W.random_field_medium(n, seed)
+        om = 2 * np.pi * (n + 1) / 8
+        solvers.append(Solver(c, om, 16, leaf=16, rank=8, rank_tol=1e-6, precision="c64"))
+        f = W.gaussian_source(n, (0.5, 0.5)).ravel()
+        fs.append(_t(f))
+        refs.append(direct.solve_sparse(assemble.stencil(c, om, 16), f))
+    factor_batch(solvers)
+    us, its, res = solve_batch(solvers, fs, tol=1e-10, maxit=200)
+    for k in range(len(sizes)):
+        assert res[k] <= 1e-10
+        assert_close(us[k].cpu().numpy(), refs[k], 1e-5, f"instance {k}")
+        u1, _, _ = solvers[k].solve(fs[k], tol=1e-10, maxit=200)
+        assert_close(us[k].cpu().numpy(), u1.cpu().numpy(), 1e-8, f"batched vs single {k}")
+
+
+def test_autotuner_choice_solves_to_oracle():
+    # the tuner times leaves 8/16/32 on the trial problem; the chosen leaf solves it
+    _need_gpu()
+    from paper_1007_4290_amd import autotune
+    from paper_1007_4290_amd.solver import Solver
+    n = 127
+    c = W.random_field_medium(n, 300)
+    om = 2 * np.pi * 16
+    f = _t(W.gaussian_source(n, (0.5, 0.5)).reshape(1, -1))
+    leaf, ms = autotune.tune_leaf(c, om, 16, f, leaves=(8, 16, 32), repeats=1, use_cache=False)
+    assert leaf in (8, 16, 32) and leaf in ms and all(v > 0 for v in ms.values())
+    assert ms[leaf] == min(ms.values())
+    choice, timings = autotune.tune_batch_leaves([(c, om, 16, f)], leaves=(16, 32), repeats=1, use_cache=False)
+    assert choice[n] in (16, 32)
+    s = Solver(c, om, 16, leaf=leaf, rank=8, rank_tol=1e-6, precision="c64").factor()
+    u, its, res = s.solve(f, tol=1e-10)
+    ue = direct.solve_sparse(assemble.stencil(c, om, 16), f.cpu().numpy()[0])
+    assert_close(u.cpu().numpy()[0], ue, 1e-5, "tuned leaf")
 
 
 def test_batched_factor_equals_single_factor():

@@ -163,6 +163,39 @@ def test_apply_batch_rows_are_independent():
         assert_close(s.apply(_t(F[k])).cpu().numpy(), U[k], 1e-14, f"rhs {k}")
 
 
+@pytest.mark.parametrize("precision,n,leaf,tol", [
+    ("c64", 127, 16, 2e-5),     # matrix-core products (complex64, 4 right-hand sides per workgroup)
+    ("c128", 127, 16, 1e-14),   # vector products, same summation order as one per workgroup
+    ("c64", 255, 32, 2e-5),
+])
+def test_grouped_sweep_matches_single_rhs_sweep(precision, n, leaf, tol):
+    # rhs_group = 4 loads each layer once for 4 right-hand sides; 6 fields
+    # make one full and one partial group (the last two slots idle)
+    _need_gpu()
+    c, omega, npml = _problem(n, (n + 1) / 8, 12)
+    one = _Solver()(c, omega, npml, leaf=leaf, rank=8, rank_tol=1e-6, precision=precision, rhs_group=1).factor()
+    grp = _Solver()(c, omega, npml, leaf=leaf, rank=8, rank_tol=1e-6, precision=precision, rhs_group=4).factor()
+    rng = np.random.default_rng(n)
+    F = rng.standard_normal((6, n * n)) + 1j * rng.standard_normal((6, n * n))
+    a = one.apply(_t(F)).cpu().numpy()
+    b = grp.apply(_t(F)).cpu().numpy()
+    for k in range(6):
+        assert_close(b[k], a[k], tol, f"rhs {k}")
+
+
+def test_grouped_sweep_solution_matches_oracle():
+    _need_gpu()
+    c, omega, npml = _problem(255, 32, 16)
+    s = _Solver()(c, omega, npml, leaf=16, rank=8, rank_tol=1e-6, precision="c64", rhs_group=4).factor()
+    pos = W.uniform_source_positions(255, 16, 5, seed=12)
+    F = np.stack([W.gaussian_source(255, p).ravel() for p in pos])
+    U, its, res = s.solve(_t(F), tol=1e-10)
+    assert max(res) <= 1e-10
+    Ue = direct.SparseLU(assemble.stencil(c, omega, npml)).solve(F)
+    for k in range(5):
+        assert_close(U[k].cpu().numpy(), Ue[k], 1e-5, f"source {k}")
+
+
 # ----------------------------------------------------------------- gradient
 
 def test_gradient_matches_oracle_adjoint():
