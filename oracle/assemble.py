@@ -26,7 +26,7 @@ from dataclasses import dataclass
 import numpy as np
 import scipy.sparse as sp
 
-from .pml import DEFAULT_C, grid, stretch
+from .pml import DEFAULT_C, grid, stretch_sides
 
 
 @dataclass
@@ -43,26 +43,122 @@ class Stencil:
     c: np.ndarray
 
 
+def pml_widths(pml):
+    """(x1 low, x1 high, x2 low, x2 high) widths in grid points from one width
+    for every side or a 4-tuple."""
+    if np.isscalar(pml):
+        return (int(pml),) * 4
+    w = tuple(int(v) for v in pml)
+    assert len(w) == 4
+    return w
+
+
 def stencil(c, omega, pml, C=DEFAULT_C):
-    """Coefficient fields of eq. helmd for velocity c (shape (n, n))."""
+    """Coefficient fields of eq. helmd for velocity c (shape (n, n)).
+
+    pml: the absorbing-layer width in grid points on every side, or the
+    widths (x1 low, x1 high, x2 low, x2 high); s1 is built from the x1 pair
+    and s2 from the x2 pair."""
     c = np.asarray(c, dtype=np.float64)
     n = c.shape[0]
     assert c.shape == (n, n)
     h, x, xh = grid(n)
-    eta = pml * h
-    s_node = stretch(x, omega, eta, C)
-    s_half = stretch(xh, omega, eta, C)
+    a1, b1, a2, b2 = pml_widths(pml)
+    s1_node = stretch_sides(x, omega, a1 * h, b1 * h, C)
+    s1_half = stretch_sides(xh, omega, a1 * h, b1 * h, C)
+    s2_node = stretch_sides(x, omega, a2 * h, b2 * h, C)
+    s2_half = stretch_sides(xh, omega, a2 * h, b2 * h, C)
     # Horizontal edge between (i, j) and (i+1, j), i = 0..n: (s1/s2)_{i+1/2, j}/h^2.
-    ex = s_half[None, :] / s_node[:, None] / h ** 2           # (n, n+1), [j-1, i]
+    ex = s1_half[None, :] / s2_node[:, None] / h ** 2         # (n, n+1), [j-1, i]
     # Vertical edge between (i, j) and (i, j+1), j = 0..n: (s2/s1)_{i, j+1/2}/h^2.
-    ey = s_half[:, None] / s_node[None, :] / h ** 2           # (n+1, n), [j, i-1]
+    ey = s2_half[:, None] / s1_node[None, :] / h ** 2         # (n+1, n), [j, i-1]
     W = ex[:, :n]
     E = ex[:, 1:]
     S = ey[:n, :]
     N = ey[1:, :]
-    s1s2 = s_node[None, :] * s_node[:, None]
+    s1s2 = s1_node[None, :] * s2_node[:, None]
     D = omega ** 2 / (s1s2 * c ** 2) - (W + E + S + N)
     return Stencil(n=n, omega=omega, h=h, W=W, E=E, S=S, N=N, D=D, s1s2=s1s2, c=c)
+
+
+# The four edges of the unit square, for Dirichlet data u = b on an edge.
+EDGES = ("x1=0", "x1=1", "x2=0", "x2=1")
+
+
+def dirichlet_forcing(st: Stencil, edge, b):
+    """The right-hand side term of Dirichlet data u = b on one edge (Sec. 2.5,
+    depth extrapolation: the boundary values become a forcing on the layer of
+    unknowns next to that edge).  Row p next to the edge has the coefficient
+    of its boundary neighbour in W, E, S or N; moving that term to the right
+    side gives -coefficient * b.  b: n values along the edge (index i-1 or
+    j-1), or (k, n) for k right-hand sides.  Returns (n*n,) or (k, n*n)."""
+    n = st.n
+    b = np.asarray(b, dtype=np.complex128)
+    single = b.ndim == 1
+    B = b.reshape(-1, n)
+    G = np.zeros((B.shape[0], n, n), dtype=np.complex128)
+    if edge == "x2=1":
+        G[:, n - 1, :] = -st.N[n - 1][None, :] * B
+    elif edge == "x2=0":
+        G[:, 0, :] = -st.S[0][None, :] * B
+    elif edge == "x1=0":
+        G[:, :, 0] = -st.W[:, 0][None, :] * B
+    elif edge == "x1=1":
+        G[:, :, n - 1] = -st.E[:, n - 1][None, :] * B
+    else:
+        raise ValueError(edge)
+    G = G.reshape(-1, n * n)
+    return G[0] if single else G
+
+
+# Sweep directions (Sec. 2.4): the layers are rows swept upward (+x2) or
+# downward (-x2), or columns swept rightward (+x1) or leftward (-x1).  A
+# direction is a relabelling of the grid, frame point (i', m') <- natural
+# point (i, j); sweeping the relabelled operator upward is sweeping the
+# original one in that direction.
+DIRECTIONS = ("+x2", "-x2", "+x1", "-x1")
+
+
+def to_frame(field, direction):
+    """A field indexed [j, i] (natural) as [m', i'] (frame of the direction)."""
+    F = np.asarray(field)
+    if direction == "+x2":
+        return F
+    if direction == "-x2":
+        return F[..., ::-1, :]
+    if direction == "+x1":
+        return np.swapaxes(F, -1, -2)
+    if direction == "-x1":
+        return np.swapaxes(F, -1, -2)[..., ::-1, :]
+    raise ValueError(direction)
+
+
+def from_frame(field, direction):
+    F = np.asarray(field)
+    if direction in ("+x2", "+x1"):
+        return to_frame(F, direction)
+    if direction == "-x2":
+        return F[..., ::-1, :]
+    if direction == "-x1":
+        return np.swapaxes(F[..., ::-1, :], -1, -2)
+    raise ValueError(direction)
+
+
+def permuted(st: Stencil, direction):
+    """The stencil of the relabelled grid: the coefficient towards each frame
+    neighbour is the natural coefficient towards the same grid point."""
+    tf = lambda a: np.ascontiguousarray(to_frame(a, direction))  # noqa: E731
+    if direction == "+x2":
+        W, E, S, N = st.W, st.E, st.S, st.N
+    elif direction == "-x2":       # frame layer m'+1 is the natural row below
+        W, E, S, N = tf(st.W), tf(st.E), tf(st.N), tf(st.S)
+    elif direction == "+x1":       # frame rows run along x2, layers are columns
+        W, E, S, N = tf(st.S), tf(st.N), tf(st.W), tf(st.E)
+    elif direction == "-x1":       # columns swept leftward
+        W, E, S, N = tf(st.S), tf(st.N), tf(st.E), tf(st.W)
+    else:
+        raise ValueError(direction)
+    return Stencil(n=st.n, omega=st.omega, h=st.h, W=W, E=E, S=S, N=N, D=tf(st.D), s1s2=tf(st.s1s2), c=tf(st.c))
 
 
 def matrix(st: Stencil):

@@ -72,3 +72,19 @@ def leading_inverse_block(st: assemble.Stencil, m):
     k = m * n
     Ginv = np.linalg.inv(A[:k, :k])
     return Ginv[k - n:, k - n:]
+
+
+def solve_direction(st: assemble.Stencil, f, direction, T=None):
+    """The exact sweep of Algs. 2.1/2.2 in one of the four directions
+    (Sec. 2.4): relabel the grid so that the layers run along the chosen
+    direction, sweep there, and map the result back.  T: the frame's
+    factors if already computed.  Returns (u, T)."""
+    n = st.n
+    sp = assemble.permuted(st, direction)
+    if T is None:
+        T = factor(sp)
+    F = np.asarray(f, dtype=np.complex128).reshape(-1, n, n)
+    Ff = np.ascontiguousarray(assemble.to_frame(F, direction)).reshape(-1, n * n)
+    Uf = solve(sp, T, Ff).reshape(-1, n, n)
+    U = np.ascontiguousarray(assemble.from_frame(Uf, direction)).reshape(-1, n * n)
+    return (U[0] if np.asarray(f).ndim == 1 else U), T

@@ -7,7 +7,7 @@ operator, the free-space Hankel field, or brute-force dense algebra.
 import numpy as np
 import pytest
 
-from oracle import assemble, direct, fastdiag, hankel, pml
+from oracle import assemble, direct, fastdiag, hankel, pml, sweep
 import workloads as W
 
 
@@ -153,3 +153,74 @@ def test_dropped_edge_term_fails_fast_diagonalization_pin():
     bad = direct.solve_sparse(st_bad, f)
     assert np.linalg.norm(ok - u_fd) / np.linalg.norm(u_fd) < 1e-10
     assert np.linalg.norm(bad - u_fd) / np.linalg.norm(u_fd) > 1e-3
+
+
+# ---------------------------------------------------------------- other boundaries and directions
+
+def test_per_side_layers_reduce_to_the_symmetric_layer_and_mirror():
+    n = 31
+    c = W.random_field_medium(n, 17)
+    om = 2 * np.pi * 3
+    a = assemble.stencil(c, om, 5)
+    b = assemble.stencil(c, om, (5, 5, 5, 5))
+    for f in ("W", "E", "S", "N", "D", "s1s2"):
+        np.testing.assert_array_equal(getattr(a, f), getattr(b, f))
+    # reflecting the grid in x2 swaps the two x2 widths (to rounding of the node positions)
+    st = assemble.stencil(c, om, (3, 7, 2, 6))
+    sr = assemble.stencil(c[::-1].copy(), om, (3, 7, 6, 2))
+    np.testing.assert_allclose(sr.D, st.D[::-1], rtol=1e-12)
+    np.testing.assert_allclose(sr.N, st.S[::-1], rtol=1e-12)
+    np.testing.assert_allclose(sr.W, st.W[::-1], rtol=1e-12)
+    # a side of width 0 has no layer: the stretching is 1 there
+    sig = pml.sigma_sides(np.linspace(0, 1, 41), 0.0, 0.25, 9.0)
+    assert np.all(sig[:30] == 0) and sig[-1] == pytest.approx(9.0 / 0.25)
+
+
+def _mode(n, p, omega):
+    # u = sin(p pi x1) exp(i kappa x2) solves the 5-point equation with c = 1 and
+    # no absorbing layer exactly when (2 - 2cos(p pi h) + 2 - 2cos(kappa h)) / h^2 = omega^2
+    h = 1.0 / (n + 1)
+    ck = 1.0 - 0.5 * h * h * (omega ** 2 - (2 - 2 * np.cos(p * np.pi * h)) / h ** 2)
+    kappa = np.arccos(ck) / h
+    x = h * np.arange(0, n + 2)
+    U = np.sin(p * np.pi * x)[None, :] * np.exp(1j * kappa * x)[:, None]   # [j, i] incl. boundary
+    return U, kappa
+
+
+def test_dirichlet_data_reproduce_an_exact_discrete_mode():
+    n, p, om = 31, 2, 2 * np.pi * 2
+    U, kappa = _mode(n, p, om)
+    st = assemble.stencil(W.constant_medium(n), om, 0)
+    g = assemble.dirichlet_forcing(st, "x2=0", U[0, 1:-1]) + assemble.dirichlet_forcing(st, "x2=1", U[-1, 1:-1])
+    u = direct.solve_sparse(st, g)
+    np.testing.assert_allclose(u, U[1:-1, 1:-1].ravel(), rtol=0, atol=1e-10)
+    # the same mode turned by 90 degrees, data on the x1 edges
+    Ut = U.T
+    g = assemble.dirichlet_forcing(st, "x1=0", Ut[1:-1, 0]) + assemble.dirichlet_forcing(st, "x1=1", Ut[1:-1, -1])
+    np.testing.assert_allclose(direct.solve_sparse(st, g), Ut[1:-1, 1:-1].ravel(), rtol=0, atol=1e-10)
+    # planted mistake: dropping the top edge's data is caught
+    g_bad = assemble.dirichlet_forcing(st, "x2=0", U[0, 1:-1])
+    assert np.max(np.abs(direct.solve_sparse(st, g_bad) - U[1:-1, 1:-1].ravel())) > 1e-2
+
+
+@pytest.mark.parametrize("direction", assemble.DIRECTIONS)
+def test_frame_stencil_is_the_relabelled_operator(direction):
+    n = 11
+    st = assemble.stencil(W.random_field_medium(n, 23), 2 * np.pi * 1.5, (1, 2, 3, 2))
+    A = assemble.matrix(st).toarray()
+    idx = np.arange(n * n).reshape(n, n)                    # natural flat index at [j, i]
+    perm = np.ascontiguousarray(assemble.to_frame(idx, direction)).ravel()   # frame position -> natural index
+    Af = assemble.matrix(assemble.permuted(st, direction)).toarray()
+    np.testing.assert_array_equal(Af, A[np.ix_(perm, perm)])
+    back = assemble.from_frame(assemble.to_frame(idx, direction), direction)
+    np.testing.assert_array_equal(back, idx)
+
+
+@pytest.mark.parametrize("direction", assemble.DIRECTIONS)
+def test_exact_sweep_in_every_direction_is_the_inverse(direction):
+    n = 15
+    st = assemble.stencil(W.random_field_medium(n, 29), 2 * np.pi * 2, (2, 3, 1, 4))
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((2, n * n)) + 1j * rng.standard_normal((2, n * n))
+    u, _ = sweep.solve_direction(st, f, direction)
+    np.testing.assert_allclose(u, direct.solve_dense(st, f), rtol=0, atol=1e-10 * np.abs(u).max())
