@@ -1,24 +1,30 @@
 """Benchmark: 2D Helmholtz solves/s at relative residual 1e-6, complex64 sweep
 (FP64 residual and Arnoldi) beside the complex128 sweep, on one MI355X.
 
-Workload (n=255): omega = 2 pi 32 (8 points per wavelength), velocity
-c = 1 + 0.3 * smooth Gaussian random field (correlation 0.1, seed 1), PML 16
-points, centre Gaussian source, H-matrix Schur complements with leaf 16 and
-rank <= 8 at relative tolerance 1e-6.
+Headline workload (n=255): omega = 2 pi 32 (8 points per wavelength),
+velocity c = 1 + 0.3 * smooth Gaussian random field (correlation 0.1, seed 1),
+PML 16 points, centre Gaussian source, H-matrix Schur complements with leaf 16
+and rank <= 8 at relative tolerance 1e-6.
 
 One step is the whole hot path for one right-hand side with the inputs
 already in device memory: stencil coefficients, the layer-by-layer
 factorization with H-matrix Schur complements, and flexible GMRES with the
-sweep as preconditioner until ||f - A u|| <= 1e-6 ||f||.
+sweep as preconditioner until ||f - A u|| <= 1e-6 ||f||.  `value` is that
+end-to-end rate; `solve_phase_solves_per_s` (factorization built once, then
+solves only) is reported beside it.
 
-Prints one JSON line.  `roofline` covers the dominant kernel, the layer
-kernel of the factorization (one launch per layer: the recompressions of the
-off-diagonal blocks and the dense leaves), whose average launch time is
+Prints one JSON line.  `roofline` covers the dominant kernel of a step, the
+layer kernel of the factorization (one launch per layer: the recompressions of
+the off-diagonal blocks and the dense leaves), whose average launch time is
 measured with HIP events around each launch on the stream it runs on.  It is
 latency bound (chains of small dependent steps on single wavefronts), so it is
 reported against the vector FP32 peak ("alu") with its algorithmic flops.
-`roofline_sweep` covers the preconditioner sweep against HBM.  `cpu_baseline`
-times the CPU oracle (sparse LU, the plain definition u = A^{-1} f).
+`kernels` gives the fraction of the other kernels of the step (Woodbury,
+sweep, stencil, Krylov vector work).  `workloads` measures the other problem
+sizes: the n=1023 lens, 64 sources at n=511 (complex64 against complex128
+sweeps), a batch of 24 instances of three sizes, and the misfit gradient at
+n=511.  `cpu_baseline` times the CPU oracle (sparse LU, the plain definition
+u = A^{-1} f) on the host.
 """
 import argparse
 import json
@@ -32,7 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3      # MI355X vector FP32 (256 CUs at 2.4 GHz)
+FP32_PEAK_TFLOPS = 157.3      # MI355X FP32, vector and matrix (256 CUs at 2.4 GHz)
 FP64_PEAK_TFLOPS = 78.6
 METRIC = "2D Helmholtz solves/s at rel. residual 1e-6: complex64 vs FP64 sweep"
 # HBM bytes per launch of layer_kernel<float, 16, 8> on this workload: FETCH_SIZE
@@ -40,20 +46,52 @@ METRIC = "2D Helmholtz solves/s at rel. residual 1e-6: complex64 vs FP64 sweep"
 # reads for a 1 GiB device-to-device copy (profiles/layer_kernel_pmc_helm255.md).
 # Counters cannot be read inside a timed run; a change to the kernel voids this.
 LAYER_KERNEL_HBM_BYTES = 981244
-# The same two passes for one complex64 sweep launch (one right-hand side).
-SWEEP_KERNEL_HBM_BYTES = 66189250
+# The same passes for the sweep launches (profiles/sweep_kernel_pmc.md), keyed
+# by workload; None where not measured for the current kernel.
+SWEEP_HBM_BYTES = {"helm255_grf": 64686506 + 1562656, "helm511_grf_64src": 1005127319 + 401345461,
+                   "helm511_grf_64src_group4": 703687035 + 401430741}
+
+
+def e_layer(plan):
+    np_, b, L, r = plan["n_p"], plan["b"], plan["levels"], plan["r"]
+    return np_ * b + L * r * np_ + ((1 << L) - 1) * 4 * r * r
 
 
 def sweep_bytes(plan, n, elem, nrhs=1):
-    """Algorithmic bytes of one sweep launch: every layer's factor data is
-    read once per layer step (2n-1 steps), plus the couplings, the input and
-    output fields (complex128) and the forward work vector (written, then read)."""
-    np_, b, L, r = plan["n_p"], plan["b"], plan["levels"], plan["r"]
-    e_layer = np_ * b + L * r * np_ + ((1 << L) - 1) * 4 * r * r
-    fac = (2 * n - 1) * e_layer * elem
+    """Algorithmic bytes of one application of M to nrhs fields: every layer's
+    factor data read once per layer step (2n-1 steps), the couplings twice,
+    the complex128 input and output fields and the forward work vector
+    (written, then read) of each right-hand side."""
+    np_ = plan["n_p"]
+    fac = (2 * n - 1) * e_layer(plan) * elem
     coup = 2 * (n - 1) * np_ * elem
     vec = nrhs * (2 * n * n * 16 + 2 * n * np_ * elem)
-    return fac + coup * nrhs + vec
+    return fac + coup + vec
+
+
+def sweep_flops(plan, n, nrhs=1):
+    """Real flops of one application of M: one complex multiply-add (8 flops)
+    per stored factor entry, layer step and right-hand side."""
+    return 8.0 * (2 * n - 1) * e_layer(plan) * nrhs
+
+
+def stencil_bytes(n, nrhs, residual=False):
+    """FP64 5-point operator over n^2 points: read x (16 B), write y (16 B),
+    read c (8 B); the residual form also reads f (16 B)."""
+    return n * n * nrhs * (56 if residual else 40)
+
+
+def krylov_bytes(n, its_per_cycle, nrhs=1):
+    """FP64 vector traffic of the flexible GMRES steps: in step j, two
+    Gram-Schmidt passes (inner products over j+1 basis vectors and w, then
+    the update reading them and writing w), the norm of w and the scaling
+    into the next basis vector."""
+    N = n * n
+    tot = 0
+    for its in its_per_cycle:
+        for j in range(its):
+            tot += 2 * ((j + 2) + (j + 3)) + 1 + 2
+    return 16 * N * nrhs * tot
 
 
 def layer_kernel_flops(plan, b, r):
@@ -79,6 +117,24 @@ def layer_kernel_flops(plan, b, r):
     return total
 
 
+def woodbury_flops(plan, b, r):
+    """Algorithmic real flops of the Woodbury launches of one layer: per level
+    lam (2^lam nodes of s = n_p >> lam rows) the 2r x 2r core through one r x r
+    inverse and five r x r products (48 r^3), P_c = T_c Q_c by the leaves
+    (8 s b r) and by each inner level's low-rank correction (16 s r^2 each),
+    and G_c = Q_c^t P_c (8 s r^2)."""
+    np_, L = plan["n_p"], plan["levels"]
+    total = 0.0
+    for lam in range(1, L + 1):
+        s = np_ >> lam
+        total += (1 << lam) * (48 * r ** 3 + 8 * s * b * r + 16 * (L - lam) * s * r * r + 8 * s * r * r)
+    return total + 48 * r ** 3
+
+
+def _frac(achieved, peak):
+    return achieved / peak if peak else None
+
+
 def run_gpu(wl, precision, steps, warmup, tol):
     import torch
     from paper_1007_4290_amd.solver import Solver
@@ -91,13 +147,15 @@ def run_gpu(wl, precision, steps, warmup, tol):
         s.solve(f, tol=tol)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sweep_ms, applies, factor_ms, iters, res = 0.0, 0, 0.0, [], []
+    sweep_ms, applies, factor_ms, iters, res, sten_ms, kry_ms = 0.0, 0, 0.0, [], [], 0.0, 0.0
     for _ in range(steps):
         s.factor()
         factor_ms += s.timings()["factor_ms"]
         u, it, rr = s.solve(f, tol=tol)
         tm = s.timings()
         sweep_ms += tm["sweep_ms"]
+        sten_ms += tm["stencil_ms"]
+        kry_ms += tm["krylov_ms"]
         applies += tm["applies"]
         iters.append(it[0])
         res.append(rr[0])
@@ -122,6 +180,8 @@ def run_gpu(wl, precision, steps, warmup, tol):
         "solve_ms": 1e3 * (t3 - t2) / steps,
         "factor_ms": factor_ms / steps,
         "sweep_ms_avg": sweep_ms / max(applies, 1),
+        "stencil_ms_per_solve": sten_ms / steps,
+        "krylov_ms_per_solve": kry_ms / steps,
         "layer_kernel_ms_avg": layer_ms,
         "wood_ms_per_factor": wood_ms,
         "iters": iters,
@@ -131,8 +191,155 @@ def run_gpu(wl, precision, steps, warmup, tol):
     }
 
 
+def _timed_solve(s, F, tol, reps, torch):
+    """Median wall time (ms) of `reps` solves, with the library's per-phase
+    device times of the last one."""
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U, its, res = s.solve(F, tol=tol, maxit=200)
+        torch.cuda.synchronize()
+        ts.append(1e3 * (time.perf_counter() - t0))
+    return float(np.median(ts)), U, its, res, s.timings()
+
+
+def bench_workloads(tol):
+    """The other problem sizes: one warm-up, then medians of timed runs."""
+    import torch
+    import workloads as W
+    from paper_1007_4290_amd.solver import Solver, factor_batch, solve_batch, helmholtz_solve
+    from paper_1007_4290_amd import autotune
+
+    out = {}
+    # n = 1023 lens, complex64 (one right-hand side)
+    wl = W.get("helm1023_lens")
+    F = torch.as_tensor(wl.sources(), device="cuda:0")
+    s = Solver(wl.velocity(), wl.omega, wl.pml, leaf=wl.leaf, rank=wl.rank, rank_tol=wl.rank_tol, precision="c64")
+    s.factor()
+    s.solve(F, tol=tol)
+    fms = []
+    for _ in range(2):
+        s.factor()
+        fms.append(s.timings()["factor_ms"])
+    ms, U, its, res, tm = _timed_solve(s, F, tol, 3, torch)
+    plan = dict(s.plan_info(), b=wl.leaf, r=wl.rank)
+    sw = tm["sweep_ms"] / max(tm["applies"], 1)
+    nb = sweep_bytes(plan, wl.n, 8)
+    out["helm1023_lens"] = {
+        "n": wl.n, "precision": "c64", "factor_ms": float(np.median(fms)), "solve_ms": ms,
+        "solve_phase_solves_per_s": 1e3 / ms, "end_to_end_solves_per_s": 1e3 / (ms + float(np.median(fms))),
+        "gmres_iters": its[0], "relres": res[0],
+        "sweep": {"avg_launch_ms": sw, "bytes_per_launch": nb, "bound": "hbm",
+                  "achieved": nb / (sw * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": _frac(nb / (sw * 1e-3) / 1e9, HBM_PEAK_GBS)},
+    }
+    print(f"[bench] helm1023: factor {out['helm1023_lens']['factor_ms']:.1f} ms, solve {ms:.1f} ms", file=sys.stderr,
+          flush=True)
+    del s
+
+    # 64 sources on one n = 511 medium: complex64 (one and four right-hand sides
+    # per workgroup) against complex128 sweeps, solve phase
+    wl = W.get("helm511_grf_64src")
+    F = torch.as_tensor(wl.sources(), device="cuda:0")
+    rows = {}
+    for prec, grp in (("c64", 1), ("c64", 4), ("c128", 1)):
+        s = Solver(wl.velocity(), wl.omega, wl.pml, leaf=wl.leaf, rank=wl.rank, rank_tol=wl.rank_tol,
+                   precision=prec, rhs_group=grp)
+        s.factor()
+        fms = s.timings()["factor_ms"]
+        s.solve(F, tol=tol)
+        ms, U, its, res, tm = _timed_solve(s, F, tol, 2, torch)
+        plan = dict(s.plan_info(), b=wl.leaf, r=wl.rank)
+        elem = 8 if prec == "c64" else 16
+        sw = tm["sweep_ms"] / max(tm["applies"], 1)
+        nb = sweep_bytes(plan, wl.n, elem, nrhs=F.shape[0])
+        fl = sweep_flops(plan, wl.n, nrhs=F.shape[0])
+        peak_fl = FP32_PEAK_TFLOPS if prec == "c64" else FP64_PEAK_TFLOPS
+        rows[f"{prec}_group{grp}"] = {
+            "factor_ms": fms, "solve_ms": ms, "solve_phase_solves_per_s": F.shape[0] * 1e3 / ms,
+            "gmres_iters_max": max(its), "relres_max": max(res),
+            "sweep": {"avg_launch_ms": sw, "bytes_per_launch": nb, "flops_per_launch": fl,
+                      "hbm_achieved_GBs": nb / (sw * 1e-3) / 1e9,
+                      "hbm_frac": _frac(nb / (sw * 1e-3) / 1e9, HBM_PEAK_GBS),
+                      "flop_achieved_TFLOPs": fl / (sw * 1e-3) / 1e12,
+                      "flop_frac": _frac(fl / (sw * 1e-3) / 1e12, peak_fl),
+                      "traffic": {("c64", 1): SWEEP_HBM_BYTES["helm511_grf_64src"],
+                                  ("c64", 4): SWEEP_HBM_BYTES["helm511_grf_64src_group4"]}.get((prec, grp)),
+                      "matrix_cores": prec == "c64" and grp == 4},
+        }
+        print(f"[bench] helm511 64 src {prec} group {grp}: solve {ms:.1f} ms", file=sys.stderr, flush=True)
+        del s
+    out["helm511_grf_64src"] = {"n": wl.n, "nrhs": int(F.shape[0]), **rows,
+                                "c64_over_c128_solve_phase": rows["c64_group1"]["solve_phase_solves_per_s"]
+                                / rows["c128_group1"]["solve_phase_solves_per_s"]}
+
+    # mixed batch: 24 instances of n = 127, 255, 511, leaves from the tuner,
+    # one factorization batch and one batched FGMRES
+    wls = W.configs.mixed_batch()
+    trial = [(wl.velocity(), wl.omega, wl.pml, torch.as_tensor(wl.sources(), device="cuda:0")) for wl in wls]
+    leaves, tune_ms = autotune.tune_batch_leaves(trial, leaves=(16, 32), repeats=1, use_cache=False)
+    solvers = [Solver(wl.velocity(), wl.omega, wl.pml, leaf=leaves[wl.n], rank=8, rank_tol=1e-6, precision="c64")
+               for wl in wls]
+    fs = [torch.as_tensor(wl.sources()[0], device="cuda:0") for wl in wls]
+    factor_batch(solvers)
+    solve_batch(solvers, fs, tol=tol)
+    fts, sts = [], []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        factor_batch(solvers)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        us, its, res = solve_batch(solvers, fs, tol=tol)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fts.append(1e3 * (t1 - t0))
+        sts.append(1e3 * (t2 - t1))
+    fm, sm = float(np.median(fts)), float(np.median(sts))
+    out["mixed_batch_24"] = {
+        "instances": len(wls), "sizes": [127, 255, 511], "leaves": {str(k): v for k, v in leaves.items()},
+        "factor_batch_ms": fm, "solve_batch_ms": sm, "solve_phase_solves_per_s": len(wls) * 1e3 / sm,
+        "end_to_end_solves_per_s": len(wls) * 1e3 / (fm + sm), "gmres_iters_max": max(its),
+        "relres_max": max(res), "tuner_ms": {str(k): v for k, v in tune_ms.items()},
+    }
+    print(f"[bench] mixed batch: factor {fm:.1f} ms, solve {sm:.1f} ms", file=sys.stderr, flush=True)
+    del solvers
+
+    # misfit gradient at n = 511: 32 sources, 256 receivers, adjoint sweep
+    wl = W.get("grad511")
+    F = torch.as_tensor(wl.sources(), device="cuda:0")
+    rec = torch.as_tensor(wl.receivers, device="cuda:0")
+    c0 = torch.as_tensor(wl.velocity(), device="cuda:0")
+    data = torch.zeros((F.shape[0], rec.numel()), dtype=torch.complex128, device="cuda:0")
+
+    def grad_once():
+        c_t = c0.clone().requires_grad_(True)
+        u = helmholtz_solve(c_t, F, wl.omega, wl.pml, tol=tol, leaf=32, rank=8, rank_tol=1e-6, precision="c64")
+        r = u[:, rec] - data
+        J = 0.5 * (r.abs() ** 2).sum()
+        J.backward()
+        return c_t.grad
+
+    grad_once()
+    gts = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        grad_once()
+        torch.cuda.synchronize()
+        gts.append(1e3 * (time.perf_counter() - t0))
+    gm = float(np.median(gts))
+    out["grad511"] = {"n": wl.n, "sources": int(F.shape[0]), "receivers": int(rec.numel()),
+                      "gradient_ms": gm, "gradients_per_s": 1e3 / gm,
+                      "note": "setup, factorization, 32 forward and 32 adjoint solves, gradient kernel"}
+    print(f"[bench] gradient: {gm:.1f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(wl, budget_s=10.0):
-    """The oracle's direct solve (SuperLU factor + solve), timed on the host."""
+    """The oracle's direct solve (assembly + SuperLU factor + solve), timed on
+    the host, and the same split into factorization and per-solve times."""
     from oracle import assemble, direct
     c = wl.velocity()
     f = wl.sources()[0]
@@ -146,9 +353,50 @@ def cpu_baseline(wl, budget_s=10.0):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
+    # factorization and solve separately (median of 3)
+    st = assemble.stencil(c, wl.omega, wl.pml)
+    fac, sol = [], []
+    for _ in range(3):
+        a = time.perf_counter()
+        lu = direct.SparseLU(st)
+        b = time.perf_counter()
+        lu.solve(f)
+        d = time.perf_counter()
+        fac.append(b - a)
+        sol.append(d - b)
+    blas = None
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        blas = max((x.get("num_threads", 0) for x in info if x.get("user_api") == "blas"), default=None)
+    except Exception:
+        pass
     return {"value": count / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": f"{count} complete oracle solves (assembly + SuperLU factor + solve) of the "
-                      f"n={wl.n} workload in {dt:.1f} s on one host core"}, u
+                      f"n={wl.n} workload in {dt:.1f} s on one host core",
+            "host_cpu_count": os.cpu_count(), "blas_threads": blas,
+            "note": "SuperLU is single-threaded: the factor and solve use one core whatever the BLAS thread count",
+            "factor_s": float(np.median(fac)), "solve_s": float(np.median(sol)),
+            "solve_phase_solves_per_s": 1.0 / float(np.median(sol))}, u
+
+
+def kernel_probe(name):
+    """Factor one workload (complex64) and apply its sweep three times to all
+    its sources, with one and then four right-hand sides per workgroup."""
+    import torch
+    import workloads as W
+    from paper_1007_4290_amd.solver import Solver
+    wl = W.get(name)
+    F = torch.as_tensor(wl.sources(), device="cuda:0")
+    for grp in (1, 4):
+        s = Solver(wl.velocity(), wl.omega, wl.pml, leaf=wl.leaf, rank=wl.rank, rank_tol=wl.rank_tol,
+                   precision="c64", rhs_group=grp).factor()
+        for _ in range(3):
+            s.apply(F)
+        torch.cuda.synchronize()
+        print(f"[probe] {name}: factor and 3 applies of {F.shape[0]} fields, rhs_group {grp}", file=sys.stderr,
+              flush=True)
+        del s
 
 
 def main():
@@ -157,9 +405,13 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the other problem sizes")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (the "
                          "calibration kernel for the HBM byte counters); not part of the timing")
+    ap.add_argument("--kernel-probe", choices=["helm255_grf", "helm511_grf_64src"], default=None,
+                    help="only factor the workload and apply its sweep 3 times with one and with four "
+                         "right-hand sides per workgroup (a short run for the hardware counters); no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -179,6 +431,9 @@ def main():
         print(f"[bench] copy probe: {args.copy_probe_mib} MiB read, {args.copy_probe_mib} MiB written",
               file=sys.stderr, flush=True)
 
+    if args.kernel_probe:
+        kernel_probe(args.kernel_probe)
+        return
     tol = 1e-6
     wl = W.get("helm255_grf", precision="c64")
     r64 = run_gpu(wl, "c64", args.steps, args.warmup, tol)
@@ -187,14 +442,23 @@ def main():
     print(f"[bench] c128: {r128['ms_per_step']:.2f} ms/step, iters {r128['iters'][0]}", file=sys.stderr, flush=True)
 
     plan = r64["plan"]
-    nbytes = sweep_bytes(plan, wl.n, 8)
+    n = wl.n
+    nbytes = sweep_bytes(plan, n, 8)
     achieved = nbytes / (r64["sweep_ms_avg"] * 1e-3) / 1e9
     lflops = layer_kernel_flops(plan, wl.leaf, wl.rank)
     l_ach = lflops / (r64["layer_kernel_ms_avg"] * 1e-3) / 1e12
+    wflops = woodbury_flops(plan, wl.leaf, wl.rank) * n
+    w_ach = wflops / (r64["wood_ms_per_factor"] * 1e-3) / 1e12
+    its = r64["iters"][0]
+    sb = stencil_bytes(n, 1) * its + stencil_bytes(n, 1, residual=True) * (1 + (its - 1) // 40)
+    s_ach = sb / (r64["stencil_ms_per_solve"] * 1e-3) / 1e9
+    kb = krylov_bytes(n, [its])
+    k_ach = kb / (r64["krylov_ms_per_solve"] * 1e-3) / 1e9
     line = {
         "metric": METRIC,
         "value": 1e3 / r64["ms_per_step"],
         "unit": "solves/s",
+        "value_kind": "end to end: factorization + GMRES solve per step (one right-hand side)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -204,10 +468,11 @@ def main():
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": "helm255_grf", "n": wl.n, "omega": "2pi*32", "pml": wl.pml,
+        "config": {"workload": "helm255_grf", "n": n, "omega": "2pi*32", "pml": wl.pml,
                    "medium": "1+0.3*GRF(l=0.1,seed=1)", "source": "centre Gaussian", "leaf": wl.leaf,
                    "rank": wl.rank, "rank_tol": wl.rank_tol, "gmres_tol": tol, "n_p": plan["n_p"],
                    "levels": plan["levels"]},
+        "solve_phase_solves_per_s": 1e3 / r64["solve_ms"],
         "c64": {"solves_per_s": 1e3 / r64["ms_per_step"], "factor_ms": r64["factor_ms"],
                 "solve_ms": r64["solve_ms"], "solve_phase_solves_per_s": 1e3 / r64["solve_ms"],
                 "gmres_iters": r64["iters"][0], "relres": r64["relres"]},
@@ -219,14 +484,23 @@ def main():
                      "frac": l_ach / FP32_PEAK_TFLOPS, "traffic": LAYER_KERNEL_HBM_BYTES,
                      "flops_per_launch": lflops,
                      "avg_launch_ms": r64["layer_kernel_ms_avg"],
-                     "factor_share": r64["layer_kernel_ms_avg"] * wl.n / r64["factor_ms"],
-                     "note": "latency bound: dependent steps on single wavefronts; Woodbury kernels "
-                             f"{r64['wood_ms_per_factor']:.1f} ms per factorization"},
-        "roofline_sweep": {"kernel": "sweep_kernel<float>", "bound": "hbm", "achieved": achieved,
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": SWEEP_KERNEL_HBM_BYTES, "bytes_per_launch": nbytes,
-                           "avg_launch_ms": r64["sweep_ms_avg"]},
+                     "factor_share": r64["layer_kernel_ms_avg"] * n / r64["factor_ms"],
+                     "note": "latency bound: dependent steps on single wavefronts"},
+        "kernels": {
+            "woodbury": {"bound": "alu", "ms_per_factor": r64["wood_ms_per_factor"], "flops_per_factor": wflops,
+                         "achieved": w_ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": w_ach / FP32_PEAK_TFLOPS},
+            "sweep": {"kernel": "sweep_kernel<float>", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": SWEEP_HBM_BYTES["helm255_grf"],
+                      "bytes_per_launch": nbytes, "avg_launch_ms": r64["sweep_ms_avg"]},
+            "stencil": {"bound": "hbm", "ms_per_solve": r64["stencil_ms_per_solve"], "bytes_per_solve": sb,
+                        "achieved": s_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": s_ach / HBM_PEAK_GBS},
+            "krylov": {"bound": "hbm", "ms_per_solve": r64["krylov_ms_per_solve"], "bytes_per_solve": kb,
+                       "achieved": k_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": k_ach / HBM_PEAK_GBS},
+        },
     }
+    if not args.no_workloads:
+        line["workloads"] = bench_workloads(tol)
     if not args.no_cpu:
         cb, u_ref = cpu_baseline(wl)
         line["cpu_baseline"] = cb

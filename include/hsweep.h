@@ -63,6 +63,21 @@ extern "C" {
 #define HSWEEP_C128 0         /* factors and sweeps in complex128 */
 #define HSWEEP_C64  1         /* factors and sweeps in complex64, FP64 outer loop */
 
+/* Sweep directions (Sec. 2.4): the layers are the grid rows swept upward
+ * (+x2, the paper's presentation) or downward (-x2), or the grid columns
+ * swept rightward (+x1) or leftward (-x1).  Fields keep the natural layout
+ * whatever the direction.  HSWEEP_DIR_MX1 is currently rejected (EINVAL). */
+#define HSWEEP_DIR_PX2 0
+#define HSWEEP_DIR_MX2 1
+#define HSWEEP_DIR_PX1 2
+#define HSWEEP_DIR_MX1 3
+
+/* Edges of the unit square (Dirichlet data, Sec. 2.5). */
+#define HSWEEP_EDGE_X1_0 0    /* x1 = 0 */
+#define HSWEEP_EDGE_X1_1 1    /* x1 = 1 */
+#define HSWEEP_EDGE_X2_0 2    /* x2 = 0 */
+#define HSWEEP_EDGE_X2_1 3    /* x2 = 1 */
+
 typedef struct hsweep_ctx hsweep_ctx;
 
 /* Options of the factorization and of GMRES (set before hsweep_factor). */
@@ -82,10 +97,17 @@ typedef struct hsweep_opts {
                            factors loaded once for the group: 1, 4 (where a
                            grouped kernel exists for the plan, else 1), or
                            0 = automatic */
+    int    direction;   /* sweep direction, HSWEEP_DIR_* */
+    int    pml_sides[4];/* absorbing-layer width in grid points on the sides
+                           x1 = 0, x1 = 1, x2 = 0, x2 = 1; 0 = zero Dirichlet
+                           condition on that side (Sec. 2.5); -1 = the width
+                           given to hsweep_setup.  The two widths of an axis
+                           must sum to less than n. */
 } hsweep_opts;
 
 /* Fill `o` with the defaults: leaf 16, rank 8, rank_tol 1e-6, C = 20,
- * complex128, compressed, restart 40, automatic right-hand-side groups. */
+ * complex128, compressed, restart 40, automatic right-hand-side groups,
+ * sweep direction +x2, the setup's layer width on every side. */
 void hsweep_default_opts(hsweep_opts* o);
 
 /* Create a context for velocity c (n*n doubles, layout above; every value
@@ -164,6 +186,15 @@ int hsweep_solve_adjoint(hsweep_ctx* ctx, const void* g, void* mu, void* grad_f,
  * vectors, the GMRES basis and residual fields, small reduction arrays).
  * Either pointer may be NULL.  Host-only; EINVAL if nrhs is out of range. */
 int hsweep_workspace_bytes(const hsweep_ctx* ctx, int nrhs, size_t* factor_bytes, size_t* solve_bytes);
+
+/* Dirichlet data u = b on one edge (HSWEEP_EDGE_*) moved to the right-hand
+ * side (Sec. 2.5, depth extrapolation): for each of nrhs fields, the row of
+ * unknowns next to the edge gets f -= (coupling to its boundary neighbour,
+ * eq. helmd) * b.  b: device complex128, nrhs * n values along the edge
+ * (index i-1 for an x2 edge, j-1 for an x1 edge); f: device complex128,
+ * nrhs * n * n, updated in place.  The side of the edge should have no
+ * absorbing layer (pml_sides 0 there).  Asynchronous on `stream`. */
+int hsweep_dirichlet_forcing(hsweep_ctx* ctx, int edge, const void* b, void* f, int nrhs, void* stream);
 
 /* Gradient of a real functional with respect to c through the adjoint
  * fields: grad[p] = sum_k Re( mu_k[p] u_k[p] 2 omega^2 / ((s1 s2)[p] c[p]^3) ),

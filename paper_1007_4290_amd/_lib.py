@@ -20,6 +20,8 @@ ESINGULAR = -5
 ENOCONV = -6
 C128 = 0
 C64 = 1
+DIRECTIONS = {"+x2": 0, "-x2": 1, "+x1": 2, "-x1": 3}
+EDGES = {"x1=0": 0, "x1=1": 1, "x2=0": 2, "x2=1": 3}
 
 _NAMES = {EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
           ESINGULAR: "ESINGULAR", ENOCONV: "ENOCONV"}
@@ -30,6 +32,7 @@ EXPORTED = [
     "hsweep_factor", "hsweep_apply", "hsweep_stencil", "hsweep_solve", "hsweep_grad_c",
     "hsweep_factor_batch", "hsweep_solve_batch", "hsweep_destroy", "hsweep_last_error", "hsweep_timings",
     "hsweep_factor_profile", "hsweep_solve_adjoint", "hsweep_workspace_bytes", "hsweep_apply_noalloc",
+    "hsweep_dirichlet_forcing",
 ]
 # Size of the static device scratch of hsweep_apply_noalloc (HSWEEP_NOALLOC_SCRATCH_BYTES).
 NOALLOC_SCRATCH_BYTES = 32 << 20
@@ -51,6 +54,8 @@ class Opts(ctypes.Structure):
         ("dense", ctypes.c_int),
         ("restart", ctypes.c_int),
         ("rhs_group", ctypes.c_int),
+        ("direction", ctypes.c_int),
+        ("pml_sides", ctypes.c_int * 4),
     ]
 
 
@@ -89,6 +94,7 @@ def load():
         "hsweep_solve_adjoint": (i, [vp, vp, vp, vp, i, d, i, ip, dp, vp]),
         "hsweep_workspace_bytes": (i, [vp, i, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "hsweep_apply_noalloc": (i, [vp, vp, vp, i, vp]),
+        "hsweep_dirichlet_forcing": (i, [vp, i, vp, vp, i, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -92,7 +92,7 @@ struct hsweep_ctx {
     bool planned = false;
     bool factored = false;
     // coefficients (FP64)
-    DevBuf c, sn, isn, sh;
+    DevBuf c, isn1, sh1, isn2, sh2;     // velocity; stretching tables of the x1 and x2 axes
     // factorization (precision-typed)
     DevBuf dg, eo, cp, fac, Q, G, rank, status;
     // sweep work
@@ -115,6 +115,12 @@ struct hsweep_ctx {
     hipGraphExec_t gexec = nullptr;
     DevBuf gdesc;
     std::vector<unsigned char> gkey;
+    AxisTables tables() const {
+        AxisTables t;
+        t.isn1 = (const c128*)isn1.p; t.sh1 = (const c128*)sh1.p;
+        t.isn2 = (const c128*)isn2.p; t.sh2 = (const c128*)sh2.p;
+        return t;
+    }
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -126,7 +132,7 @@ struct hsweep_ctx {
         drop_graph();
         if (cap) (void)hipStreamDestroy(cap);
         gdesc.release();
-        DevBuf* bufs[] = {&c, &sn, &isn, &sh, &dg, &eo, &cp, &fac, &Q, &G, &rank, &status, &sweep_w,
+        DevBuf* bufs[] = {&c, &isn1, &sh1, &isn2, &sh2, &dg, &eo, &cp, &fac, &Q, &G, &rank, &status, &sweep_w,
                           &V, &Z, &w, &r, &hdev, &partial, &scale, &active, &y, &adj,
                           &offd, &bf, &bu, &sinst, &stask};
         for (DevBuf* b : bufs) b->release();
@@ -167,6 +173,25 @@ int ilog2(int v) {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Width in grid points of the absorbing layer on side k (x1 low, x1 high,
+// x2 low, x2 high): the option if set, otherwise the width of hsweep_setup.
+int side_width(const hsweep_ctx* ctx, const hsweep_opts& o, int k) {
+    return o.pml_sides[k] >= 0 ? o.pml_sides[k] : ctx->pml;
+}
+
+// Stretching tables of both axes (Sec. 2.1, eq. sigma) for the options `o`.
+int build_tables(hsweep_ctx* ctx, const hsweep_opts& o) {
+    const int n = ctx->n;
+    const double h = 1.0 / (n + 1);
+    launch_pml_1d(n, ctx->omega, side_width(ctx, o, 0) * h, side_width(ctx, o, 1) * h, o.pml_C, (c128*)ctx->isn1.p,
+                  (c128*)ctx->sh1.p, 0);
+    launch_pml_1d(n, ctx->omega, side_width(ctx, o, 2) * h, side_width(ctx, o, 3) * h, o.pml_C, (c128*)ctx->isn2.p,
+                  (c128*)ctx->sh2.p, 0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipDeviceSynchronize());
+    return HSWEEP_OK;
+}
+
 int validate_opts(const hsweep_opts* o, int n) {
     if (!o) return fail(HSWEEP_EINVAL, "opts is NULL");
     if (!(o->precision == HSWEEP_C128 || o->precision == HSWEEP_C64))
@@ -183,6 +208,12 @@ int validate_opts(const hsweep_opts* o, int n) {
     if (o->restart < 1 || o->restart > 200) return fail(HSWEEP_EINVAL, "restart must be in [1, 200]");
     if (!(o->rhs_group == 0 || o->rhs_group == 1 || o->rhs_group == 4))
         return fail(HSWEEP_EINVAL, "rhs_group must be 0 (automatic), 1 or 4");
+    if (o->direction < 0 || o->direction > 3) return fail(HSWEEP_EINVAL, "direction must be one of HSWEEP_DIR_*");
+    if (o->direction == HSWEEP_DIR_MX1)
+        return fail(HSWEEP_EINVAL, "the leftward column sweep (-x1) is switched off: its first GPU run ended in a "
+                                   "memory fault whose cause is not found");
+    for (int k = 0; k < 4; ++k)
+        if (o->pml_sides[k] < -1) return fail(HSWEEP_EINVAL, "pml_sides entries must be -1 or >= 0");
     (void)n;
     return HSWEEP_OK;
 }
@@ -235,8 +266,8 @@ int prepare_factor(hsweep_ctx* ctx, hipStream_t s, InstDesc<T>& d) {
     HIPCHK(ctx->status.ensure(sizeof(int)));
     HIPCHK(hipMemsetAsync(ctx->status.p, 0, sizeof(int), s));
     HIPCHK(hipMemsetAsync(ctx->cp.p, 0, (size_t)(n > 1 ? n : 2) * np * E, s));
-    launch_layer_coeffs<T>(n, np, ctx->omega, (const double*)ctx->c.p, (const c128*)ctx->isn.p,
-                           (const c128*)ctx->sh.p, (cpx<T>*)ctx->dg.p, (cpx<T>*)ctx->eo.p, (cpx<T>*)ctx->cp.p, s);
+    launch_layer_coeffs<T>(n, np, ctx->opts.direction, ctx->omega, (const double*)ctx->c.p, ctx->tables(),
+                           (cpx<T>*)ctx->dg.p, (cpx<T>*)ctx->eo.p, (cpx<T>*)ctx->cp.p, s);
     HIPCHK(hipGetLastError());
     d.p = p;
     d.fac = (cpx<T>*)ctx->fac.p;
@@ -400,6 +431,7 @@ SweepInst<T> sweep_inst(const hsweep_ctx* ctx, const c128* f, c128* u, void* wor
     const Plan& p = ctx->plan;
     SweepInst<T> in{};
     in.n = p.n; in.np = p.np; in.L = p.L; in.nrhs = nrhs;
+    in.dir = ctx->opts.direction;
     in.eK = p.eK; in.eP = p.eP; in.eLayer = p.eLayer;
     in.fac = (const cpx<T>*)ctx->fac.p;
     in.cp = (const cpx<T>*)ctx->cp.p;
@@ -641,8 +673,8 @@ int solve_systems(hsweep_ctx** ctxs, int count, const int* nr, const c128* const
         for (int q = 0; q < count; ++q) {
             hsweep_ctx* cq = ctxs[q];
             const size_t o = offh[first[q]];
-            launch_stencil(cq->n, nr[q], cq->omega, (const double*)cq->c.p, (const c128*)cq->isn.p,
-                           (const c128*)cq->sh.p, x + o, fv ? fv + o : nullptr, y + o, act ? act + first[q] : nullptr, s);
+            launch_stencil(cq->n, nr[q], cq->omega, (const double*)cq->c.p, cq->tables(), x + o, fv ? fv + o : nullptr,
+                           y + o, act ? act + first[q] : nullptr, s);
         }
     };
 
@@ -822,6 +854,8 @@ void hsweep_default_opts(hsweep_opts* o) {
     o->dense = 0;
     o->restart = 40;
     o->rhs_group = 0;
+    o->direction = HSWEEP_DIR_PX2;
+    for (int k = 0; k < 4; ++k) o->pml_sides[k] = -1;
 }
 
 const char* hsweep_last_error(void) { return g_err.c_str(); }
@@ -871,15 +905,16 @@ int hsweep_setup(const double* c, double omega, int pml, int n, hsweep_ctx** out
         }                                                                                  \
     } while (0)
     SETUPCHK(ctx->c.ensure(N * sizeof(double)));
-    SETUPCHK(ctx->sn.ensure((size_t)n * sizeof(c128)));
-    SETUPCHK(ctx->isn.ensure((size_t)n * sizeof(c128)));
-    SETUPCHK(ctx->sh.ensure((size_t)(n + 1) * sizeof(c128)));
+    SETUPCHK(ctx->isn1.ensure((size_t)n * sizeof(c128)));
+    SETUPCHK(ctx->sh1.ensure((size_t)(n + 1) * sizeof(c128)));
+    SETUPCHK(ctx->isn2.ensure((size_t)n * sizeof(c128)));
+    SETUPCHK(ctx->sh2.ensure((size_t)(n + 1) * sizeof(c128)));
     SETUPCHK(hipMemcpy(ctx->c.p, c, N * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
     for (int i = 0; i < 4; ++i) SETUPCHK(hipEventCreate(&ctx->ev[i]));
     rc = scratch_init(ctx->device);
     if (rc) return bail(rc);
-    double h = 1.0 / (n + 1);
-    launch_pml_1d(n, omega, pml * h, ctx->opts.pml_C, (c128*)ctx->sn.p, (c128*)ctx->isn.p, (c128*)ctx->sh.p, 0);
+    rc = build_tables(ctx, ctx->opts);
+    if (rc) return bail(rc);
     SETUPCHK(hipGetLastError());
     SETUPCHK(hipDeviceSynchronize());
 #undef SETUPCHK
@@ -893,7 +928,11 @@ int hsweep_set_opts(hsweep_ctx* ctx, const hsweep_opts* o) {
     if (rc) return rc;
     rc = validate_opts(o, ctx->n);
     if (rc) return rc;
+    for (int k = 0; k < 2; ++k)
+        if (side_width(ctx, *o, 2 * k) + side_width(ctx, *o, 2 * k + 1) >= ctx->n)
+            return fail(HSWEEP_EINVAL, "the two absorbing layers of an axis must leave interior points");
     bool pml_changed = o->pml_C != ctx->opts.pml_C;
+    for (int k = 0; k < 4; ++k) pml_changed = pml_changed || side_width(ctx, *o, k) != side_width(ctx, ctx->opts, k);
     hsweep_opts old = ctx->opts;
     ctx->opts = *o;
     Plan p;
@@ -908,11 +947,8 @@ int hsweep_set_opts(hsweep_ctx* ctx, const hsweep_opts* o) {
     if (pml_changed) {
         rc = set_device(ctx);
         if (rc) return rc;
-        double h = 1.0 / (ctx->n + 1);
-        launch_pml_1d(ctx->n, ctx->omega, ctx->pml * h, o->pml_C, (c128*)ctx->sn.p, (c128*)ctx->isn.p,
-                      (c128*)ctx->sh.p, 0);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipDeviceSynchronize());
+        rc = build_tables(ctx, *o);
+        if (rc) return rc;
     }
     return HSWEEP_OK;
 }
@@ -1014,8 +1050,23 @@ int hsweep_stencil(hsweep_ctx* ctx, const void* x, void* y, int nrhs, void* stre
     if (x == y) return fail(HSWEEP_EINVAL, "x and y must not overlap");
     rc = set_device(ctx);
     if (rc) return rc;
-    launch_stencil(ctx->n, nrhs, ctx->omega, (const double*)ctx->c.p, (const c128*)ctx->isn.p,
-                   (const c128*)ctx->sh.p, (const c128*)x, nullptr, (c128*)y, nullptr, (hipStream_t)stream);
+    launch_stencil(ctx->n, nrhs, ctx->omega, (const double*)ctx->c.p, ctx->tables(), (const c128*)x, nullptr, (c128*)y,
+                   nullptr, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return HSWEEP_OK;
+}
+
+int hsweep_dirichlet_forcing(hsweep_ctx* ctx, int edge, const void* b, void* f, int nrhs, void* stream) {
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!b || !f) return fail(HSWEEP_EINVAL, "b and f must be device pointers");
+    if (edge < 0 || edge > 3) return fail(HSWEEP_EINVAL, "edge must be one of HSWEEP_EDGE_*");
+    if (nrhs < 1 || nrhs > 65535) return fail(HSWEEP_EINVAL, "nrhs must be in [1, 65535]");
+    rc = set_device(ctx);
+    if (rc) return rc;
+    launch_dirichlet(ctx->n, nrhs, ctx->omega, (const double*)ctx->c.p, ctx->tables(), edge, (const c128*)b, (c128*)f,
+                     (hipStream_t)stream);
     HIPCHK(hipGetLastError());
     return HSWEEP_OK;
 }
@@ -1028,8 +1079,8 @@ int hsweep_grad_c(hsweep_ctx* ctx, const void* u, const void* mu, int nrhs, void
     if (nrhs < 1) return fail(HSWEEP_EINVAL, "nrhs must be >= 1");
     rc = set_device(ctx);
     if (rc) return rc;
-    launch_grad(ctx->n, nrhs, ctx->omega, (const double*)ctx->c.p, (const c128*)ctx->isn.p, (const c128*)u,
-                (const c128*)mu, (double*)grad, (hipStream_t)stream);
+    launch_grad(ctx->n, nrhs, ctx->omega, (const double*)ctx->c.p, ctx->tables(), (const c128*)u, (const c128*)mu,
+                (double*)grad, (hipStream_t)stream);
     HIPCHK(hipGetLastError());
     return HSWEEP_OK;
 }
@@ -1093,8 +1144,8 @@ int hsweep_workspace_bytes(const hsweep_ctx* ctx, int nrhs, size_t* factor_bytes
     const size_t E = ctx->opts.precision == HSWEEP_C64 ? sizeof(c64) : sizeof(c128);
     const size_t n = (size_t)p.n, np = (size_t)p.np, N = n * n, K = (size_t)nrhs;
     const size_t m = (size_t)ctx->opts.restart;
-    // coefficients of the setup: c, s and 1/s on nodes, s on half nodes
-    size_t fb = N * sizeof(double) + 2 * n * sizeof(c128) + (n + 1) * sizeof(c128);
+    // coefficients of the setup: c, 1/s on the nodes and s on the half nodes of both axes
+    size_t fb = N * sizeof(double) + 2 * (2 * n + 1) * sizeof(c128);
     // layer operators, factor store and the per-layer work of the factorization
     fb += 2 * n * np * E + (n > 1 ? n : 2) * np * E + n * p.eLayer * E;
     fb += (size_t)(p.L > 0 ? p.L : 1) * p.r * np * E + ((size_t)2 << p.L) * p.r * p.r * E;

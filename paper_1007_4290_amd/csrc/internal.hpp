@@ -49,14 +49,24 @@ struct StepPtrs {
 };
 
 // ---- coefficient kernels (FP64) ----
-void launch_pml_1d(int n, double omega, double eta, double C, c128* sn, c128* isn, c128* sh, hipStream_t s);
+// Stretching tables of the two axes: 1/s on the n nodes and s on the n+1
+// half nodes of x1 (isn1, sh1) and of x2 (isn2, sh2).
+struct AxisTables {
+    const c128* isn1; const c128* sh1;
+    const c128* isn2; const c128* sh2;
+};
+void launch_pml_1d(int n, double omega, double eta_lo, double eta_hi, double C, c128* isn, c128* sh, hipStream_t s);
+// Layer operators in the frame of sweep direction dir (0: +x2, 1: -x2, 2: +x1, 3: -x1).
 template <typename T>
-void launch_layer_coeffs(int n, int np, double omega, const double* c, const c128* isn, const c128* sh,
-                         cpx<T>* dg, cpx<T>* eo, cpx<T>* cp, hipStream_t s);
-void launch_stencil(int n, int nrhs, double omega, const double* c, const c128* isn, const c128* sh,
-                    const c128* x, const c128* f, c128* y, const int* active, hipStream_t s);
-void launch_grad(int n, int nrhs, double omega, const double* c, const c128* isn,
-                 const c128* u, const c128* mu, double* grad, hipStream_t s);
+void launch_layer_coeffs(int n, int np, int dir, double omega, const double* c, const AxisTables& t, cpx<T>* dg,
+                         cpx<T>* eo, cpx<T>* cp, hipStream_t s);
+void launch_stencil(int n, int nrhs, double omega, const double* c, const AxisTables& t, const c128* x, const c128* f,
+                    c128* y, const int* active, hipStream_t s);
+void launch_grad(int n, int nrhs, double omega, const double* c, const AxisTables& t, const c128* u, const c128* mu,
+                 double* grad, hipStream_t s);
+// f -= coefficient * b for Dirichlet data b on an edge (0: x1=0, 1: x1=1, 2: x2=0, 3: x2=1).
+void launch_dirichlet(int n, int nrhs, double omega, const double* c, const AxisTables& t, int edge, const c128* b,
+                      c128* f, hipStream_t s);
 
 // One problem instance of a (possibly batched) factorization: its plan and
 // the device buffers of its layer coefficients and factor store.
@@ -88,11 +98,13 @@ void factor_kernels_init();
 
 // ---- sweep (preconditioner application) ----
 // One instance of a sweep launch.  For call column j, right-hand side r
-// reads f + j*fstride + r*n*n and writes u + j*ustride + r*n*n; its forward
-// work vectors are w + r*n*np.
+// reads f + j*fstride + r*n*n and writes u + j*ustride + r*n*n (natural grid
+// order; the sweep maps frame points to grid points by its direction); its
+// forward work vectors are w + r*n*np.
 template <typename T>
 struct SweepInst {
     int n, np, L, nrhs;
+    int dir;             // sweep direction: layer m, position i is grid point (see k_coeff.hip)
     size_t eK, eP, eLayer;
     const cpx<T>* fac;   // factor store base (n layers of eLayer entries)
     const cpx<T>* cp;    // (n-1)*np couplings, cp[m*np + i] = A_{m+1,m}(i, i)

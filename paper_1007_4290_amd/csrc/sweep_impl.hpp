@@ -61,8 +61,20 @@ struct LayerRegs {
 // Runtime geometry of the instance a workgroup works on.
 struct Geo {
     int n, np, L, lnp, nch;   // grid, padded width, levels, log2(np), P chunks per column
+    int dir;                  // sweep direction
     size_t eK, eP;
 };
+
+// Index in the natural grid order of position i (< n) of layer m in the
+// frame of the sweep direction: rows upward or downward, columns rightward
+// or leftward.
+__device__ __forceinline__ size_t grid_index(const Geo& ge, int i, int m) {
+    const int n = ge.n;
+    if (ge.dir == 0) return (size_t)m * n + i;
+    if (ge.dir == 1) return (size_t)(n - 1 - m) * n + i;
+    if (ge.dir == 2) return (size_t)i * n + m;
+    return (size_t)i * n + (n - 1 - m);
+}
 
 template <typename T, int B>
 __device__ __forceinline__ void load_K(const Geo& ge, const cpx<T>* __restrict__ lay, cpx<T> (&k)[B]) {
@@ -362,7 +374,7 @@ __device__ __forceinline__ StepIn<T, G> fetch_in(const Geo& ge, int s, const Swe
         const int m = s;
 #pragma unroll
         for (int q = 0; q < G; ++q)
-            if (real_row && st.live[q]) in.f[q] = st.f[q][(size_t)m * n + i];
+            if (real_row && st.live[q]) in.f[q] = st.f[q][grid_index(ge, i, m)];
         if (m > 0 && row) in.c = st.cp[(size_t)(m - 1) * np + i];
     } else if (s < 2 * n - 1) {
         const int m = 2 * n - 2 - s;
@@ -399,7 +411,7 @@ __device__ __forceinline__ void sweep_step(const Geo& ge, int s, LayerRegs<T, B,
         for (int q = 0; q < G; ++q) {
             if (row && st.w[q]) st.w[q][(size_t)m * np + i] = y[q];
             st.carry[q] = y[q];
-            if (m == n - 1 && real_row && st.u[q]) st.u[q][(size_t)m * n + i] = ccast<double>(y[q]);
+            if (m == n - 1 && real_row && st.u[q]) st.u[q][grid_index(ge, i, m)] = ccast<double>(y[q]);
         }
     } else {
         const int m = 2 * n - 2 - s;
@@ -409,7 +421,7 @@ __device__ __forceinline__ void sweep_step(const Geo& ge, int s, LayerRegs<T, B,
 #pragma unroll
         for (int q = 0; q < G; ++q) {
             const cpx<T> um = row ? in.w[q] - y[q] : czero<T>();
-            if (real_row && st.u[q]) st.u[q][(size_t)m * n + i] = ccast<double>(um);
+            if (real_row && st.u[q]) st.u[q][grid_index(ge, i, m)] = ccast<double>(um);
             st.carry[q] = um;
         }
     }
@@ -450,7 +462,7 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs<T> a) {
     }
     const SweepInst<T> in = a.insts ? a.insts[qi] : a.one;
     Geo ge;
-    ge.n = in.n; ge.np = in.np; ge.L = in.L; ge.lnp = 31 - __clz(in.np);
+    ge.n = in.n; ge.np = in.np; ge.L = in.L; ge.lnp = 31 - __clz(in.np); ge.dir = in.dir;
     ge.nch = in.np / Chunk<B, R>::CH;
     ge.eK = in.eK; ge.eP = in.eP;
     const int n = in.n, np = in.np;

@@ -38,11 +38,13 @@ class Solver:
     omega: angular frequency; pml: absorbing-layer width in grid points.
     Options: leaf, rank, rank_tol, precision ("c128" | "c64"), dense,
     restart, pml_C, rhs_group (right-hand sides per sweep workgroup:
-    0 automatic, 1 or 4).
+    0 automatic, 1 or 4), direction ("+x2", "-x2", "+x1", "-x1"),
+    pml_sides (layer widths on the sides x1=0, x1=1, x2=0, x2=1; 0 for a
+    zero Dirichlet side; default: `pml` on every side).
     """
 
     def __init__(self, c, omega, pml, leaf=16, rank=8, rank_tol=1e-6, precision="c128", dense=False,
-                 restart=40, pml_C=20.0, rhs_group=0):
+                 restart=40, pml_C=20.0, rhs_group=0, direction="+x2", pml_sides=None):
         lib = _lib.load()
         if isinstance(c, torch.Tensor):
             c_t = c.detach().to(torch.float64).contiguous()
@@ -62,6 +64,12 @@ class Solver:
         o.leaf, o.rank, o.rank_tol = int(leaf), int(rank), float(rank_tol)
         o.pml_C, o.precision, o.dense, o.restart = float(pml_C), _PREC[precision], int(bool(dense)), int(restart)
         o.rhs_group = int(rhs_group)
+        o.direction = _lib.DIRECTIONS[direction]
+        sides = (-1, -1, -1, -1) if pml_sides is None else tuple(int(v) for v in pml_sides)
+        if len(sides) != 4:
+            raise ValueError("pml_sides holds the widths of the sides x1=0, x1=1, x2=0, x2=1")
+        for k in range(4):
+            o.pml_sides[k] = sides[k]
         _lib.check(lib.hsweep_set_opts(self._ctx, ctypes.byref(o)))
         self.precision = precision
         self.factored = False
@@ -160,6 +168,21 @@ class Solver:
         fb, sb = ctypes.c_size_t(), ctypes.c_size_t()
         _lib.check(_lib.load().hsweep_workspace_bytes(self._ctx, int(nrhs), ctypes.byref(fb), ctypes.byref(sb)))
         return fb.value, sb.value
+
+    def dirichlet_forcing(self, edge, b, f, stream=None):
+        """f - (coupling to the boundary) * b on the row next to `edge`
+        ("x1=0", "x1=1", "x2=0", "x2=1"): Dirichlet data b moved to the
+        right-hand side.  b: complex128 CUDA tensor (nrhs, n) or (n,); f is
+        not modified, the result is returned."""
+        f2, single = _as_fields(f, self.n)
+        out = f2.clone()
+        if not isinstance(b, torch.Tensor) or not b.is_cuda or b.dtype != torch.complex128:
+            raise TypeError("b must be a complex128 CUDA tensor")
+        b2 = b.reshape(out.shape[0], self.n).contiguous()
+        _lib.check(_lib.load().hsweep_dirichlet_forcing(self._ctx, _lib.EDGES[edge], ctypes.c_void_p(b2.data_ptr()),
+                                                        ctypes.c_void_p(out.data_ptr()), out.shape[0],
+                                                        _stream_ptr(stream)))
+        return out[0] if single else out
 
     def grad_c(self, u, mu, stream=None):
         """sum_k Re(mu_k u_k 2 omega^2 / ((s1 s2) c^3)) as an (n, n) float64 tensor."""

@@ -63,6 +63,29 @@ int main() {
                   "adjoint");
     bad += expect(hsweep_apply_noalloc(ctx[16], F, U, 4, nullptr), 0, "apply_noalloc");
     bad += expect(hsweep_apply(ctx[0], F, U, 3, nullptr), 0, "apply");
+    bad += expect(hsweep_dirichlet_forcing(ctx[16], HSWEEP_EDGE_X2_1, G, F, 2, nullptr), 0, "dirichlet");
+    bad += expect(hsweep_grad_c(ctx[16], F, U, 2, G, nullptr), 0, "grad_c");
+    // every sweep direction with its own layer widths
+    for (int d = 0; d < 3; ++d) {
+        hsweep_opts o;
+        hsweep_get_opts(ctx[1], &o);
+        o.direction = d;
+        o.pml_sides[0] = 0; o.pml_sides[1] = 16; o.pml_sides[2] = 10; o.pml_sides[3] = 0;
+        bad += expect(hsweep_set_opts(ctx[1], &o), 0, "set_opts direction");
+        bad += expect(hsweep_factor(ctx[1], nullptr), 0, "factor direction");
+        bad += expect(hsweep_solve(ctx[1], F, U, 2, 1e-10, 10, it64.data(), r64.data(), nullptr), HSWEEP_ENOCONV,
+                      "solve direction");
+    }
+    {
+        hsweep_opts o;
+        hsweep_get_opts(ctx[1], &o);
+        o.pml_sides[0] = 64; o.pml_sides[1] = 64;
+        bad += expect(hsweep_set_opts(ctx[1], &o), HSWEEP_EINVAL, "layers wider than the axis");
+        o.pml_sides[0] = -1; o.pml_sides[1] = -1; o.direction = 4;
+        bad += expect(hsweep_set_opts(ctx[1], &o), HSWEEP_EINVAL, "direction out of range");
+        o.direction = HSWEEP_DIR_MX1;
+        bad += expect(hsweep_set_opts(ctx[1], &o), HSWEEP_EINVAL, "leftward column sweep switched off");
+    }
     // a complex128 batch of two grid sizes with one leaf size (one sweep launch per step)
     std::vector<hsweep_ctx*> c2(2);
     std::vector<void*> f2(2), u2(2);

@@ -9,25 +9,43 @@ void fake_describe(const void* p);
 static void need(const void* p, size_t b, const char* what) {
     if (b && !fake_in_alloc(p, b)) { fprintf(stderr, "OUT OF RANGE: %s %p %zu\n", what, p, b); fake_describe(p); abort(); }
 }
-void launch_pml_1d(int n, double, double, double, c128* sn, c128* isn, c128* sh, hipStream_t) {
-    need(sn, n * 16, "sn"); need(isn, n * 16, "isn"); need(sh, (n + 1) * 16, "sh");
+void launch_pml_1d(int n, double, double, double, double, c128* isn, c128* sh, hipStream_t) {
+    need(isn, n * 16, "isn"); need(sh, (n + 1) * 16, "sh");
+}
+static void need_tables(const AxisTables& t, int n) {
+    need(t.isn1, n * 16, "isn1"); need(t.sh1, (n + 1) * 16, "sh1");
+    need(t.isn2, n * 16, "isn2"); need(t.sh2, (n + 1) * 16, "sh2");
 }
 template <typename T>
-void launch_layer_coeffs(int n, int np, double, const double* c, const c128* isn, const c128* sh, cpx<T>* dg,
+void launch_layer_coeffs(int n, int np, int dir, double, const double* c, const AxisTables& t, cpx<T>* dg,
                          cpx<T>* eo, cpx<T>* cp, hipStream_t) {
-    need(c, (size_t)n * n * 8, "c"); need(dg, (size_t)n * np * sizeof(cpx<T>), "dg");
+    if (dir < 0 || dir > 3) { fprintf(stderr, "direction %d\n", dir); abort(); }
+    need(c, (size_t)n * n * 8, "c"); need_tables(t, n); need(dg, (size_t)n * np * sizeof(cpx<T>), "dg");
     need(eo, (size_t)n * np * sizeof(cpx<T>), "eo"); need(cp, (size_t)(n - 1) * np * sizeof(cpx<T>), "cp");
 }
-template void launch_layer_coeffs<float>(int, int, double, const double*, const c128*, const c128*, c64*, c64*, c64*, hipStream_t);
-template void launch_layer_coeffs<double>(int, int, double, const double*, const c128*, const c128*, c128*, c128*, c128*, hipStream_t);
-void launch_stencil(int n, int nrhs, double, const double* c, const c128* isn, const c128* sh, const c128* x,
-                    const c128* f, c128* y, const int* active, hipStream_t) {
+template void launch_layer_coeffs<float>(int, int, int, double, const double*, const AxisTables&, c64*, c64*, c64*,
+                                         hipStream_t);
+template void launch_layer_coeffs<double>(int, int, int, double, const double*, const AxisTables&, c128*, c128*, c128*,
+                                          hipStream_t);
+void launch_stencil(int n, int nrhs, double, const double* c, const AxisTables& t, const c128* x, const c128* f,
+                    c128* y, const int* active, hipStream_t) {
     size_t N = (size_t)n * n;
-    need(c, N * 8, "st c"); need(isn, n * 16, "st isn"); need(sh, (n + 1) * 16, "st sh");
+    need(c, N * 8, "st c"); need_tables(t, n);
     need(x, nrhs * N * 16, "st x"); if (f) need(f, nrhs * N * 16, "st f"); need(y, nrhs * N * 16, "st y");
     if (active) need(active, nrhs * 4, "st active");
 }
-void launch_grad(int, int, double, const double*, const c128*, const c128*, const c128*, double*, hipStream_t) {}
+void launch_grad(int n, int nrhs, double, const double* c, const AxisTables& t, const c128* u, const c128* mu,
+                 double* grad, hipStream_t) {
+    size_t N = (size_t)n * n;
+    need(c, N * 8, "gr c"); need_tables(t, n); need(u, nrhs * N * 16, "gr u"); need(mu, nrhs * N * 16, "gr mu");
+    need(grad, N * 8, "grad");
+}
+void launch_dirichlet(int n, int nrhs, double, const double* c, const AxisTables& t, int edge, const c128* b, c128* f,
+                      hipStream_t) {
+    if (edge < 0 || edge > 3) abort();
+    need(c, (size_t)n * n * 8, "di c"); need_tables(t, n); need(b, nrhs * n * 16, "di b");
+    need(f, (size_t)nrhs * n * n * 16, "di f");
+}
 template <typename T> int launch_factor_layer(const InstDesc<T>*, const Plan*, int, int, hipStream_t, hipEvent_t) { return 0; }
 template int launch_factor_layer<float>(const InstDesc<float>*, const Plan*, int, int, hipStream_t, hipEvent_t);
 template int launch_factor_layer<double>(const InstDesc<double>*, const Plan*, int, int, hipStream_t, hipEvent_t);

@@ -15,6 +15,9 @@ from .generators import (  # noqa: F401
     grid_points,
     constant_medium,
     lens_medium,
+    linear_medium,
+    waveguide_medium,
+    wave_packet,
     random_field_medium,
     gaussian_source,
     uniform_source_positions,

@@ -39,6 +39,34 @@ def lens_medium(n, depth=0.4, width=0.1, centre=(0.5, 0.5)):
     return 1.0 - depth * np.exp(-r2 / width ** 2)
 
 
+def linear_medium(n, base=0.5, slope=1.0):
+    """c = base + slope * x2: the velocity of the paper's sweep-direction
+    example (Sec. 3, dependence on the sweep direction), 1/2 + x2."""
+    x1, x2 = _mesh(n)
+    return np.broadcast_to(base + slope * x2, (n, n)).astype(np.float64).copy()
+
+
+def waveguide_medium(n, depth=0.4, width=0.1, centre=0.5):
+    """A vertical waveguide c = 1 - depth * exp(-(x1 - centre)^2 / width^2): a
+    low-velocity channel along x2, the kind of medium of the paper's
+    depth-extrapolation example (Sec. 3, other boundary conditions)."""
+    x1, x2 = _mesh(n)
+    return np.broadcast_to(1.0 - depth * np.exp(-((x1 - centre) ** 2) / width ** 2), (n, n)).astype(np.float64).copy()
+
+
+def wave_packet(n, centre, direction, omega, width=None):
+    """Gaussian wave packet f = exp(-|x - x0|^2 / (2 s^2)) exp(i omega d.(x - x0)) / (2 pi s^2)
+    with unit direction d and width s of one wavelength 2 pi / omega unless
+    given, sampled at the interior points (complex128, (n, n))."""
+    s = 2 * np.pi / omega if width is None else width
+    d = np.asarray(direction, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    x1, x2 = _mesh(n)
+    dx1, dx2 = x1 - centre[0], x2 - centre[1]
+    env = np.exp(-(dx1 ** 2 + dx2 ** 2) / (2 * s * s)) / (2 * np.pi * s * s)
+    return (env * np.exp(1j * omega * (d[0] * dx1 + d[1] * dx2))).astype(np.complex128)
+
+
 def random_field_medium(n, seed, amplitude=0.3, corr_length=0.1):
     """Smooth Gaussian random field c = 1 + amplitude * g, max |g| = 1.
 
