@@ -16,9 +16,12 @@ representation" (2010):
 * sweep      -- exact sweeping factorization and solve     (Sec. 2.1, Algs. 2.1-2.2)
 * hmatrix    -- weakly admissible H-matrix algebra, the approximate
                 factorization and sweep                   (Sec. 2.3-2.4, Algs. 2.3-2.4)
+* strong     -- strongly admissible H-matrices with randomized SVD for
+                F = H . H, the factorization and sweep in that format
+                                                          (Sec. 2.3 strongly admissible case, Algs. 2.3-2.4)
 * gmres      -- (flexible) GMRES in FP64                   (Sec. 2.4, preconditioned solve)
 * fastdiag   -- separable closed form for constant c       (textbook fast diagonalization)
 * hankel     -- free-space Green's function reference      (Sec. 2.2, Hankel kernel)
 * gradient   -- receiver misfit, adjoint gradient, finite differences
 """
-from . import pml, assemble, direct, sweep, gmres, fastdiag, hankel, gradient, hmatrix  # noqa: F401
+from . import pml, assemble, direct, sweep, gmres, fastdiag, hankel, gradient, hmatrix, strong  # noqa: F401
