@@ -54,6 +54,17 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double fast_rsq(double x) { return 1.0 / sqrt(x); }
+// square root without the correctly rounded fix-up (about 1 ulp), for values
+// that only set up a rotation
+__device__ __forceinline__ float raw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double raw_sqrt(double x) { return sqrt(x); }
+// 1/sqrt(x) in FP64: the hardware estimate and one Newton step (relative
+// error near 1e-14, far below what the pivoted Cholesky of a single-precision
+// Gram matrix needs), in place of a correctly rounded sqrt and divide
+__device__ __forceinline__ double rsq_nr(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    return y * (1.5 - 0.5 * x * y * y);
+}
 // 1 / a through one reciprocal of |a|^2 (pivots here are far from the
 // overflow and underflow limits of |a|^2)
 template <typename T> __device__ __forceinline__ cpx<T> cinv_fast(cpx<T> a) {
@@ -738,7 +749,9 @@ __device__ __forceinline__ void wave_apply_q(const cpx<T>* A, int lda, int s, in
 // identity.  A pair is rotated when |a^H b| > thr |a| |b|, |a^H b| > gabs and
 // both columns are above the negligible level tiny (squared norm).  Sweeps
 // stop after one in which no pair was rotated by more than cos = sqrt(thr)
-// (the next sweep, converging quadratically, would rotate none).  J
+// (the next sweep, converging quadratically, would rotate none), or -- for up
+// to JACOBI_CHECK_PMAX columns with a compile-time group size -- as soon as
+// a test of all pairs finds none that a further sweep would rotate.  J
 // (column-major, leading dimension NR * G) starts as the identity and
 // accumulates the rotations, so that N_in J = N_out with nearly orthogonal
 // columns; nrm2[c] is the squared norm of column c.  Since J is unitary,
@@ -747,6 +760,58 @@ __device__ __forceinline__ void wave_apply_q(const cpx<T>* A, int lda, int s, in
 // GT: the lane-group size when known at compile time (then the butterflies
 // and the lane geometry are constants), 0 to take it from P at run time.
 // NRJ: rows of J per lane (J has only P rows), at most NR.
+// Largest column count for which a sweep's end is tested on all pairs at once
+// (at most two of the P (P + 1) / 2 inner products per lane).
+constexpr int JACOBI_CHECK_PMAX = 15;
+
+// All inner products of the P columns of N (rows [0, rows), column-major,
+// leading dimension ld) by one wavefront, after a sweep: writes every squared
+// column norm to nrm2 and returns whether any pair still meets the rotation
+// test of the sweeps.  When none does, a further sweep would rotate nothing,
+// so this replaces that sweep.  P <= JACOBI_CHECK_PMAX.
+template <typename CT, int ROWS>
+__device__ __forceinline__ bool jacobi_pairs_left(const lds<cpx<CT>>* N, int P, int ld, lds<CT>* nrm2, CT thr,
+                                                  CT gabs, CT tiny) {
+    const int lane = threadIdx.x & 63;
+    const int ne = P * (P + 1) / 2;
+    int pa[2] = {0, 0}, pb[2] = {0, 0};
+    cpx<CT> dot[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = lane + 64 * h;
+        dot[h] = czero<CT>();
+        if (e < ne) {
+            int a = 0, rem = e;                  // (a, b), a <= b, upper triangle by rows
+            while (rem >= P - a) { rem -= P - a; ++a; }
+            pa[h] = a;
+            pb[h] = a + rem;
+            const lds<cpx<CT>>* ca = N + (size_t)pa[h] * ld;
+            const lds<cpx<CT>>* cb = N + (size_t)pb[h] * ld;
+            cpx<CT> d0 = czero<CT>(), d1 = d0;
+#pragma unroll
+            for (int r = 0; r + 1 < ROWS; r += 2) {
+                cfma_conj(d0, ldc(ca + r), ldc(cb + r));
+                cfma_conj(d1, ldc(ca + r + 1), ldc(cb + r + 1));
+            }
+            if constexpr (ROWS & 1) cfma_conj(d0, ldc(ca + ROWS - 1), ldc(cb + ROWS - 1));
+            dot[h] = d0 + d1;
+            if (pa[h] == pb[h]) nrm2[pa[h]] = dot[h].re;
+        }
+    }
+    wave_sync();
+    bool more = false;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = lane + 64 * h;
+        if (e < ne && pa[h] != pb[h]) {
+            const CT al = nrm2[pa[h]], be = nrm2[pb[h]];
+            const CT ag2 = abs2(dot[h]);
+            more = more || (al > tiny && be > tiny && ag2 > thr * thr * (al * be) && ag2 > gabs * gabs);
+        }
+    }
+    return __ballot(more) != 0;
+}
+
 template <typename CT, int NR, int GT, int NRJ = NR>
 __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, CT* nrm2g, CT thr, CT gabs, CT tiny,
                                               int max_sweeps) {
@@ -773,6 +838,7 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
     for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
         const bool last = sweep == max_sweeps;
         CT mxc = CT(0);                       // largest squared cosine rotated in this sweep
+        int nrot = 0;                         // pairs rotated in this sweep (wave-uniform)
         for (int rd = 0; rd < P1; ++rd) {
             // round-robin pairs: (rd, P-1) and ((rd + q) mod (P-1), (rd - q) mod (P-1))
             int a = rd + q, b = rd - q + P1;
@@ -816,7 +882,7 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
             // rotation (identity when the pair is left alone)
             const CT iag = doit ? fast_rsq(ag2) : CT(0);              // 1 / |gamma|
             const CT zeta = CT(0.5) * (be - al) * iag;
-            const CT tm = fast_rcp(fabs(zeta) + sqrt(CT(1) + zeta * zeta));
+            const CT tm = fast_rcp(fabs(zeta) + raw_sqrt(CT(1) + zeta * zeta));
             const CT t = doit ? (zeta >= CT(0) ? tm : -tm) : CT(0);
             const CT cs = fast_rsq(CT(1) + t * t);
             const CT sn = cs * t;
@@ -854,13 +920,25 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
                 nrm2[a] = al;
                 nrm2[b] = be;
             }
-            if (doit) mxc = fmax(mxc, ag2 / ab);
+            if (doit) mxc = fmax(mxc, ag2 * fast_rcp(ab));
+            nrot += __popcll(__ballot(doit && g == 0));
             wave_sync();
             if (last) break;
         }
         if (last) break;
         int unused = 0;
         wops::argmax(mxc, unused);
+        if constexpr (GT >= 8) {                      // G = 8 or 16: P <= 16
+            if (P <= JACOBI_CHECK_PMAX && nrot <= P) {
+                // after a sweep with few rotations (the last one before
+                // convergence typically turns one or two pairs), one pass
+                // over all pairs instead of a sweep that would find nothing
+                // left to rotate; it also gives the norms
+                const bool more = jacobi_pairs_left<CT, NR * GT>(N, P, ld, nrm2, thr, gabs, tiny);
+                if (!more || !(mxc > thr) || sweep + 1 == max_sweeps) break;
+                continue;
+            }
+        }
         if (!(mxc > thr)) sweep = max_sweeps - 1;   // converged: one more pass for the norms
     }
     wave_sync();
@@ -928,10 +1006,13 @@ __device__ __forceinline__ void gram_pair(const cpx<T>* A, const cpx<T>* B, int 
     const int nt = k * (k + 1) / 2;
     for (int e = threadIdx.x; e < 2 * nt; e += NT) {
         const bool second = e >= nt;
-        int q = second ? e - nt : e;
-        int b = 0;                                   // column b, row a <= b
-        while (q > b) { q -= b + 1; ++b; }
-        const int a = q;
+        const int q = second ? e - nt : e;
+        // column b, row a <= b of entry q = b (b + 1) / 2 + a: b from the
+        // float root, corrected by one step either way (exact for k <= 64)
+        int b = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+        b += (b + 1) * (b + 2) / 2 <= q ? 1 : 0;
+        b -= b * (b + 1) / 2 > q ? 1 : 0;
+        const int a = q - b * (b + 1) / 2;
         const lds<cpx<T>>* X = to_lds(second ? B : A);
         const lds<cpx<T>>* xa = X + (size_t)a * lda;
         const lds<cpx<T>>* xb = X + (size_t)b * lda;
@@ -987,7 +1068,8 @@ __device__ __forceinline__ int wave_pchol(const c128* Gg, int k, int kmax, c128*
         const int p = wops::argmax_nonneg((float)d, c, !chosen && h == 0);
         const double key = p >= 0 ? readlane_f(d, p * hs) : -1.0;   // exact Schur diagonal of the pivot
         if (!(key > stop)) { kr = j; break; }
-        const double rpp = sqrt(key);
+        const double ir = rsq_nr(key);
+        const double rpp = key * ir;
         c128 val = ldc(G + (size_t)cc * k + p);          // G[p][c]
         // this lane's share of the dot over the rows so far (rows h, h + hs,
         // ...) in chunks of 4, one accumulator per chunk position; all 8 loads
@@ -1014,7 +1096,6 @@ __device__ __forceinline__ int wave_pchol(const c128* Gg, int k, int kmax, c128*
             sd.im += wops::dpp<wops::QP_XOR1>(sd.im, 0.0);
         }
         val -= sd;
-        const double ir = 1.0 / rpp;
         c128 r = chosen ? czero<double>() : (c == p ? mk(rpp, 0.0) : ir * val);
         if (!chosen && c != p) d -= abs2(r);
         if (col && h == 0) stc(Rr + (size_t)j * k + c, r);
