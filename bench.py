@@ -43,13 +43,13 @@ FP64_PEAK_TFLOPS = 78.6
 METRIC = "2D Helmholtz solves/s at rel. residual 1e-6: complex64 vs FP64 sweep"
 # HBM bytes per launch of layer_kernel<float, 16, 8> on this workload: FETCH_SIZE
 # + WRITE_SIZE from two rocprofv3 counter passes, each scaled by what the counter
-# reads for a 1 GiB device-to-device copy (profiles/layer_kernel_pmc_helm255.md).
+# reads for a 1 GiB device-to-device copy (profiles/factor_kernels_pmc_helm255.md).
 # Counters cannot be read inside a timed run; a change to the kernel voids this.
-LAYER_KERNEL_HBM_BYTES = 981244
+LAYER_KERNEL_HBM_BYTES = 926208 + 98784
 # The same passes for the sweep launches (profiles/sweep_kernel_pmc.md), keyed
 # by workload; None where not measured for the current kernel.
-SWEEP_HBM_BYTES = {"helm255_grf": 64686506 + 1562656, "helm511_grf_64src": 1005127319 + 401345461,
-                   "helm511_grf_64src_group4": 703687035 + 401430741}
+SWEEP_HBM_BYTES = {"helm255_grf": 64636567 + 1562656, "helm511_grf_64src": 1005106822 + 401345205,
+                   "helm511_grf_64src_group4": 703677099 + 401409867}
 
 
 def e_layer(plan):
