@@ -53,12 +53,14 @@ def pml_widths(pml):
     return w
 
 
-def stencil(c, omega, pml, C=DEFAULT_C):
+def stencil(c, omega, pml, C=DEFAULT_C, abc=()):
     """Coefficient fields of eq. helmd for velocity c (shape (n, n)).
 
     pml: the absorbing-layer width in grid points on every side, or the
     widths (x1 low, x1 high, x2 low, x2 high); s1 is built from the x1 pair
-    and s2 from the x2 pair."""
+    and s2 from the x2 pair.  abc: edges (names from EDGES) that carry the
+    second-order absorbing boundary condition instead of u = 0; their layer
+    width must be 0 (see `absorbing_closure`)."""
     c = np.asarray(c, dtype=np.float64)
     n = c.shape[0]
     assert c.shape == (n, n)
@@ -78,7 +80,78 @@ def stencil(c, omega, pml, C=DEFAULT_C):
     N = ey[1:, :]
     s1s2 = s1_node[None, :] * s2_node[:, None]
     D = omega ** 2 / (s1s2 * c ** 2) - (W + E + S + N)
-    return Stencil(n=n, omega=omega, h=h, W=W, E=E, S=S, N=N, D=D, s1s2=s1s2, c=c)
+    st = Stencil(n=n, omega=omega, h=h, W=W.copy(), E=E.copy(), S=S.copy(), N=N.copy(), D=D, s1s2=s1s2, c=c)
+    if abc:
+        widths = dict(zip(EDGES, (a1, b1, a2, b2)))
+        for e in abc:
+            assert e in EDGES and widths[e] == 0, "an absorbing-condition edge has no layer"
+        absorbing_closure(st, tuple(abc))
+    return st
+
+
+def abc_a(k, h):
+    """u_b = a u_0 + g D_tt u_0: the weight of u_0 (see absorbing_closure)."""
+    return (2 + 1j * k * h) / (2 - 1j * k * h)
+
+
+def abc_g(k, h):
+    """The weight of the tangential second difference (see absorbing_closure)."""
+    return 1j * h / (k * (2 - 1j * k * h))
+
+
+def absorbing_closure(st: Stencil, abc):
+    """Second-order absorbing boundary condition (Sec. 3, other boundary
+    conditions; Engquist and Majda) on the edges in `abc`, in place.
+
+    On an edge with outward normal n and tangent t the condition is
+        du/dn = i k u + (i / (2k)) d2u/dt2,   k = omega / c,
+    which a plane wave leaving the domain at angle theta meets up to
+    O(theta^4).  It is imposed at the half point between the boundary node
+    u_b and the first interior node u_0 of each line normal to the edge:
+        (u_b - u_0)/h = i k (u_b + u_0)/2 + (i/(2k)) D_tt u_0,
+    D_tt the second difference along the edge, so that
+        u_b = a u_0 + g D_tt u_0,  a = (2 + i k h)/(2 - i k h),  g = i h / (k (2 - i k h)),
+    and u_b is eliminated from the row of u_0: its coefficient e_b (the
+    edge coupling to the boundary node) moves e_b a onto the diagonal and
+    e_b g D_tt u_0 into couplings along the edge.  Those are written in flux
+    form with one weight per edge, tau = (w_p + w_q)/2 with w = e_b g / h^2
+    at each of its two points, so the operator stays symmetric.  At an end
+    of the edge the flux goes to the corner value: zero where the adjacent
+    side is not absorbing (its boundary value is zero), none where it is.
+    The edge couplings to the boundary nodes themselves stay in W/E/S/N."""
+    n, h, om = st.n, st.h, st.omega
+    k_of = lambda cv: om / cv                     # noqa: E731
+    for e in abc:
+        if e in ("x1=0", "x1=1"):
+            col = 0 if e == "x1=0" else n - 1
+            eb = (st.W[:, 0] if e == "x1=0" else st.E[:, n - 1]).copy()
+            k = k_of(st.c[:, col])
+            st.D[:, col] += eb * abc_a(k, h)
+            w = eb * abc_g(k, h) / h ** 2
+            tau = 0.5 * (w[:-1] + w[1:])                 # edge between rows j and j+1
+            st.N[:-1, col] += tau
+            st.S[1:, col] += tau
+            st.D[:-1, col] -= tau
+            st.D[1:, col] -= tau
+            if "x2=0" not in abc:
+                st.D[0, col] -= w[0]
+            if "x2=1" not in abc:
+                st.D[n - 1, col] -= w[n - 1]
+        else:
+            row = 0 if e == "x2=0" else n - 1
+            eb = (st.S[0, :] if e == "x2=0" else st.N[n - 1, :]).copy()
+            k = k_of(st.c[row, :])
+            st.D[row, :] += eb * abc_a(k, h)
+            w = eb * abc_g(k, h) / h ** 2
+            tau = 0.5 * (w[:-1] + w[1:])                 # edge between columns i and i+1
+            st.E[row, :-1] += tau
+            st.W[row, 1:] += tau
+            st.D[row, :-1] -= tau
+            st.D[row, 1:] -= tau
+            if "x1=0" not in abc:
+                st.D[row, 0] -= w[0]
+            if "x1=1" not in abc:
+                st.D[row, n - 1] -= w[n - 1]
 
 
 # The four edges of the unit square, for Dirichlet data u = b on an edge.

@@ -224,3 +224,91 @@ def test_exact_sweep_in_every_direction_is_the_inverse(direction):
     f = rng.standard_normal((2, n * n)) + 1j * rng.standard_normal((2, n * n))
     u, _ = sweep.solve_direction(st, f, direction)
     np.testing.assert_allclose(u, direct.solve_dense(st, f), rtol=0, atol=1e-10 * np.abs(u).max())
+
+
+# ---------------------------------------------------------------- absorbing boundary condition
+
+def _reflection(n, p, om, monkey=None):
+    """Solve with u = sin(p pi x1) on x2 = 0, zero on the x1 sides and the
+    absorbing condition on x2 = 1 (c = 1, no layers).  The solution is a
+    combination of the two exact discrete modes sin(p pi x1) e^{+-i kappa x2};
+    returns their ratio at x2 = 1 (the reflection coefficient) and the misfit
+    of that two-mode form."""
+    h = 1.0 / (n + 1)
+    x = h * np.arange(1, n + 1)
+    st = assemble.stencil(W.constant_medium(n), om, 0, abc=("x2=1",))
+    b = np.sin(p * np.pi * x)
+    u = direct.solve_sparse(st, assemble.dirichlet_forcing(st, "x2=0", b)).reshape(n, n)
+    U = u @ b / (b @ b)
+    lam = (2 - 2 * np.cos(p * np.pi * h)) / h ** 2
+    kap = np.arccos(1 - 0.5 * h * h * (om ** 2 - lam)) / h
+    M = np.stack([np.exp(1j * kap * x), np.exp(-1j * kap * x)], 1)
+    (A, B), *_ = np.linalg.lstsq(M, U, rcond=None)
+    fit = np.abs(M @ np.array([A, B]) - U).max() / np.abs(U).max()
+    return B * np.exp(-1j * kap) / (A * np.exp(1j * kap)), fit
+
+
+def _engquist_majda(p, om, first_order=False):
+    # plane wave e^{i(kx x1 + ky x2)} against du/dn = i k u + (i/(2k)) u_tt:
+    # r = (cos t - 1 + sin^2 t / 2) / (cos t + 1 - sin^2 t / 2)
+    s2 = (p * np.pi / om) ** 2
+    ct = np.sqrt(1 - s2)
+    q = 1.0 if first_order else 1 - s2 / 2
+    return (ct - q) / (ct + q)
+
+
+@pytest.mark.parametrize("p", [3, 6])
+def test_absorbing_condition_reflection_converges_to_the_continuous_one(p):
+    om = 2 * np.pi * 4
+    R2 = _engquist_majda(p, om)
+    errs = []
+    for n in (63, 127, 255):
+        r, fit = _reflection(n, p, om)
+        assert fit <= 1e-10                       # exact separable solution: corners close on zero values
+        errs.append(abs(r - R2))
+    assert errs[0] / errs[1] >= 1.8 and errs[1] / errs[2] >= 1.8
+    assert errs[-1] <= 5e-3
+    if p == 6:                                    # 49 degrees: far from the first-order condition
+        assert abs(r - _engquist_majda(p, om, first_order=True)) > 0.1
+
+
+def test_absorbing_condition_near_normal_incidence_converges_at_second_order():
+    om = 2 * np.pi * 4                       # p = 1: 7 degrees, where the tangential term is negligible
+    e = [abs(_reflection(n, 1, om)[0] - _engquist_majda(1, om)) for n in (63, 127, 255)]
+    assert e[0] / e[1] >= 3.5 and e[1] / e[2] >= 3.5
+
+
+def test_flipped_tangential_term_is_caught(monkeypatch):
+    # Planted mistake: the tangential term with the wrong sign.
+    good = assemble.abc_g
+    monkeypatch.setattr(assemble, "abc_g", lambda k, h: -good(k, h))
+    om = 2 * np.pi * 4
+    r, _ = _reflection(255, 6, om)
+    assert abs(r - _engquist_majda(6, om)) > 0.1
+
+
+def test_absorbing_condition_keeps_symmetry_and_absorbs_a_point_source():
+    import scipy.special as sps
+    n = 255
+    om = 2 * np.pi * 8
+    h = 1.0 / (n + 1)
+    x = h * np.arange(1, n + 1)
+    X, Y = np.meshgrid(x, x)
+    f = W.gaussian_source(n, (0.5, 0.5)).ravel()
+    r = np.hypot(X - 0.5, Y - 0.5)
+    ref = -(1j / 4) * np.exp(-(om * 1.5 * h) ** 2 / 2) * sps.hankel1(0, om * np.maximum(r, 1e-9))
+    ann = (r >= 0.1) & (r <= 0.3)
+    err = {}
+    for abc in (assemble.EDGES, ()):
+        st = assemble.stencil(W.constant_medium(n), om, 0, abc=abc)
+        A = assemble.matrix(st)
+        assert abs(A - A.T).max() == 0
+        u = direct.solve_sparse(st, f).reshape(n, n)
+        err[abc] = np.linalg.norm(u[ann] - ref[ann]) / np.linalg.norm(ref[ann])
+    assert err[assemble.EDGES] <= 0.06 and err[()] >= 0.5
+    # mixed sides: absorbing condition beside layers and zero Dirichlet sides
+    st = assemble.stencil(W.random_field_medium(31, 3), 2 * np.pi * 3, (0, 4, 0, 0), abc=("x1=0", "x2=1"))
+    A = assemble.matrix(st)
+    assert abs(A - A.T).max() == 0
+    U = np.random.default_rng(2).standard_normal((3, 31 * 31)) + 0j
+    np.testing.assert_allclose(assemble.apply(st, U), (A @ U.T).T, rtol=0, atol=1e-10 * np.abs(A).max())
