@@ -78,6 +78,19 @@ extern "C" {
 #define HSWEEP_EDGE_X2_0 2    /* x2 = 0 */
 #define HSWEEP_EDGE_X2_1 3    /* x2 = 1 */
 
+/* pml_sides entry for a side that carries the second-order absorbing
+ * boundary condition of Engquist and Majda (Sec. 3, other boundary
+ * conditions) instead of a layer: du/dn = i k u + (i/(2k)) d2u/dt2,
+ * k = omega/c, imposed at the half point between the boundary node and the
+ * first row of unknowns, which eliminates the boundary value
+ * u_b = a u_0 + g D_tt u_0 (a = (2 + ikh)/(2 - ikh), g = ih/(k(2 - ikh)),
+ * D_tt the second difference along the side).  That row's diagonal and its
+ * couplings along the side change (flux form with one weight per edge, the
+ * mean of its two end points, so A = A^t still holds); at an end of the side
+ * the flux goes to the corner value, zero next to a side without the
+ * condition and dropped next to one with it. */
+#define HSWEEP_SIDE_ABC (-2)
+
 typedef struct hsweep_ctx hsweep_ctx;
 
 /* Options of the factorization and of GMRES (set before hsweep_factor). */
@@ -101,8 +114,9 @@ typedef struct hsweep_opts {
     int    pml_sides[4];/* absorbing-layer width in grid points on the sides
                            x1 = 0, x1 = 1, x2 = 0, x2 = 1; 0 = zero Dirichlet
                            condition on that side (Sec. 2.5); -1 = the width
-                           given to hsweep_setup.  The two widths of an axis
-                           must sum to less than n. */
+                           given to hsweep_setup; HSWEEP_SIDE_ABC = no layer
+                           and the absorbing boundary condition.  The two
+                           widths of an axis must sum to less than n. */
 } hsweep_opts;
 
 /* Fill `o` with the defaults: leaf 16, rank 8, rank_tol 1e-6, C = 20,
@@ -193,14 +207,17 @@ int hsweep_workspace_bytes(const hsweep_ctx* ctx, int nrhs, size_t* factor_bytes
  * eq. helmd) * b.  b: device complex128, nrhs * n values along the edge
  * (index i-1 for an x2 edge, j-1 for an x1 edge); f: device complex128,
  * nrhs * n * n, updated in place.  The side of the edge should have no
- * absorbing layer (pml_sides 0 there).  Asynchronous on `stream`. */
+ * absorbing layer (pml_sides 0 there); EINVAL if it carries the absorbing
+ * boundary condition.  Asynchronous on `stream`. */
 int hsweep_dirichlet_forcing(hsweep_ctx* ctx, int edge, const void* b, void* f, int nrhs, void* stream);
 
 /* Gradient of a real functional with respect to c through the adjoint
  * fields: grad[p] = sum_k Re( mu_k[p] u_k[p] 2 omega^2 / ((s1 s2)[p] c[p]^3) ),
  * the c-derivative of the diagonal of A (eq. helmd) contracted with the
  * adjoint mu_k = A^{-1} conj(g_k) (A = A^t).  u, mu: device complex128,
- * nrhs*n*n; grad: device double, n*n (overwritten).  Asynchronous. */
+ * nrhs*n*n; grad: device double, n*n (overwritten).  Asynchronous.  EINVAL
+ * when a side carries the absorbing boundary condition (its rows depend on c
+ * through k as well, which this formula leaves out). */
 int hsweep_grad_c(hsweep_ctx* ctx, const void* u, const void* mu, int nrhs,
                   void* grad, void* stream);
 

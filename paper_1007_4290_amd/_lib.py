@@ -22,6 +22,7 @@ C128 = 0
 C64 = 1
 DIRECTIONS = {"+x2": 0, "-x2": 1, "+x1": 2, "-x1": 3}
 EDGES = {"x1=0": 0, "x1=1": 1, "x2=0": 2, "x2=1": 3}
+SIDE_ABC = -2          # pml_sides entry: the absorbing boundary condition on that side
 
 _NAMES = {EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
           ESINGULAR: "ESINGULAR", ENOCONV: "ENOCONV"}

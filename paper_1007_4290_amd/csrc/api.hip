@@ -119,6 +119,9 @@ struct hsweep_ctx {
         AxisTables t;
         t.isn1 = (const c128*)isn1.p; t.sh1 = (const c128*)sh1.p;
         t.isn2 = (const c128*)isn2.p; t.sh2 = (const c128*)sh2.p;
+        t.abc = 0;
+        for (int k = 0; k < 4; ++k)
+            if (opts.pml_sides[k] == HSWEEP_SIDE_ABC) t.abc |= 1 << k;
         return t;
     }
     void drop_graph() {
@@ -176,6 +179,7 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 // Width in grid points of the absorbing layer on side k (x1 low, x1 high,
 // x2 low, x2 high): the option if set, otherwise the width of hsweep_setup.
 int side_width(const hsweep_ctx* ctx, const hsweep_opts& o, int k) {
+    if (o.pml_sides[k] == HSWEEP_SIDE_ABC) return 0;
     return o.pml_sides[k] >= 0 ? o.pml_sides[k] : ctx->pml;
 }
 
@@ -213,7 +217,8 @@ int validate_opts(const hsweep_opts* o, int n) {
         return fail(HSWEEP_EINVAL, "the leftward column sweep (-x1) is switched off: its first GPU run ended in a "
                                    "memory fault whose cause is not found");
     for (int k = 0; k < 4; ++k)
-        if (o->pml_sides[k] < -1) return fail(HSWEEP_EINVAL, "pml_sides entries must be -1 or >= 0");
+        if (o->pml_sides[k] < -1 && o->pml_sides[k] != HSWEEP_SIDE_ABC)
+            return fail(HSWEEP_EINVAL, "pml_sides entries must be -1, HSWEEP_SIDE_ABC or >= 0");
     (void)n;
     return HSWEEP_OK;
 }
@@ -1063,6 +1068,8 @@ int hsweep_dirichlet_forcing(hsweep_ctx* ctx, int edge, const void* b, void* f, 
     if (!b || !f) return fail(HSWEEP_EINVAL, "b and f must be device pointers");
     if (edge < 0 || edge > 3) return fail(HSWEEP_EINVAL, "edge must be one of HSWEEP_EDGE_*");
     if (nrhs < 1 || nrhs > 65535) return fail(HSWEEP_EINVAL, "nrhs must be in [1, 65535]");
+    if ((ctx->tables().abc >> edge) & 1)
+        return fail(HSWEEP_EINVAL, "Dirichlet data on an edge with the absorbing boundary condition");
     rc = set_device(ctx);
     if (rc) return rc;
     launch_dirichlet(ctx->n, nrhs, ctx->omega, (const double*)ctx->c.p, ctx->tables(), edge, (const c128*)b, (c128*)f,
@@ -1077,6 +1084,8 @@ int hsweep_grad_c(hsweep_ctx* ctx, const void* u, const void* mu, int nrhs, void
     if (rc) return rc;
     if (!u || !mu || !grad) return fail(HSWEEP_EINVAL, "u, mu and grad must be device pointers");
     if (nrhs < 1) return fail(HSWEEP_EINVAL, "nrhs must be >= 1");
+    if (ctx->tables().abc)
+        return fail(HSWEEP_EINVAL, "the velocity gradient is not available with the absorbing boundary condition");
     rc = set_device(ctx);
     if (rc) return rc;
     launch_grad(ctx->n, nrhs, ctx->omega, (const double*)ctx->c.p, ctx->tables(), (const c128*)u, (const c128*)mu,

@@ -54,6 +54,7 @@ struct StepPtrs {
 struct AxisTables {
     const c128* isn1; const c128* sh1;
     const c128* isn2; const c128* sh2;
+    int abc;        // bit k set: side k (HSWEEP_EDGE_* order) has the absorbing boundary condition
 };
 void launch_pml_1d(int n, double omega, double eta_lo, double eta_hi, double C, c128* isn, c128* sh, hipStream_t s);
 // Layer operators in the frame of sweep direction dir (0: +x2, 1: -x2, 2: +x1, 3: -x1).

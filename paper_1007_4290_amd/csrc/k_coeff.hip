@@ -13,6 +13,19 @@
 // operator is exactly symmetric.  1/s(x) = 1 + i sigma(x)/omega is stored
 // directly to avoid a complex division.
 //
+// A side with the second-order absorbing boundary condition (Sec. 3, other
+// boundary conditions) has no layer; its boundary value is eliminated,
+// u_b = a u_0 + g D_tt u_0 with a = (2 + ikh)/(2 - ikh), g = ih/(k(2 - ikh)),
+// k = omega/c at the first interior point: the row of u_0 gets e_b a on its
+// diagonal (e_b its coupling to the boundary node) and e_b g D_tt u_0 as
+// couplings along the side, in flux form with one weight per edge (the mean
+// of w = e_b g / h^2 at its two points, symmetric again); at an end of the
+// side the flux goes to the corner value, zero next to a side without the
+// condition and dropped next to one with it.  Coef::exg, eyg and diagg are
+// the couplings and diagonal with these closures; ex and ey stay the plain
+// edge couplings (the ones to boundary nodes are what Dirichlet data and the
+// closures multiply).
+//
 // The factorization works in the frame of its sweep direction (Sec. 2.4):
 // frame point (i', m') (position i' along layer m') is the grid point
 //   +x2: (i', m')   -x2: (i', n-1-m')   +x1: (m', i')   -x1: (n-1-m', i'),
@@ -41,7 +54,7 @@ __global__ void pml_1d_kernel(int n, double omega, double eta_lo, double eta_hi,
 }
 
 struct Coef {
-    const double* c; AxisTables t; int n; double ih2; double w2;
+    const double* c; AxisTables t; int n; double h; double ih2; double w; double w2;
     // edge between (i, j) and (i+1, j) for half index ih = i + 1 in 0..n (0-based nodes i)
     __device__ __forceinline__ c128 ex(int ih, int j) const { return ih2 * (t.sh1[ih] * t.isn2[j]); }
     // edge between (i, j) and (i, j+1) for half index jh = j + 1 in 0..n
@@ -50,6 +63,58 @@ struct Coef {
         double cc = c[(size_t)j * n + i];
         c128 d = (w2 / (cc * cc)) * (t.isn1[i] * t.isn2[j]);
         return d - (ex(i, j) + ex(i + 1, j) + ey(i, j) + ey(i, j + 1));
+    }
+    // ---- absorbing boundary condition on the sides of t.abc (HSWEEP_EDGE_* bits)
+    __device__ __forceinline__ bool abc(int sd) const { return (t.abc >> sd) & 1; }
+    __device__ __forceinline__ double kw(int i, int j) const { return w / c[(size_t)j * n + i]; }
+    __device__ __forceinline__ c128 abc_a(double k) const { return mk(2.0, k * h) * cinv(mk(2.0, -k * h)); }
+    __device__ __forceinline__ c128 abc_g(double k) const { return mk(0.0, h) * cinv(mk(2.0 * k, -k * k * h)); }
+    // coupling of the point next to side sd to its boundary node
+    __device__ __forceinline__ c128 eb(int sd, int i, int j) const {
+        return sd == 0 ? ex(0, j) : sd == 1 ? ex(n, j) : sd == 2 ? ey(i, 0) : ey(i, n);
+    }
+    // tangential weight w = e_b g / h^2 of that point
+    __device__ __forceinline__ c128 abc_w(int sd, int i, int j) const {
+        return ih2 * (eb(sd, i, j) * abc_g(kw(i, j)));
+    }
+    // couplings between two grid points (1 <= ih, jh <= n - 1)
+    __device__ __forceinline__ c128 exg(int ih, int j) const {
+        c128 e = ex(ih, j);
+        if (t.abc) {
+            if (j == 0 && abc(2)) e += 0.5 * (abc_w(2, ih - 1, 0) + abc_w(2, ih, 0));
+            if (j == n - 1 && abc(3)) e += 0.5 * (abc_w(3, ih - 1, n - 1) + abc_w(3, ih, n - 1));
+        }
+        return e;
+    }
+    __device__ __forceinline__ c128 eyg(int i, int jh) const {
+        c128 e = ey(i, jh);
+        if (t.abc) {
+            if (i == 0 && abc(0)) e += 0.5 * (abc_w(0, 0, jh - 1) + abc_w(0, 0, jh));
+            if (i == n - 1 && abc(1)) e += 0.5 * (abc_w(1, n - 1, jh - 1) + abc_w(1, n - 1, jh));
+        }
+        return e;
+    }
+    // closure of side sd at a point next to it: position q along the side,
+    // ends shared with sides lo and hi
+    __device__ __forceinline__ c128 closure(int sd, int i, int j, int q, int lo, int hi) const {
+        const bool along_x2 = sd < 2;                 // x1 sides run along x2
+        c128 d = eb(sd, i, j) * abc_a(kw(i, j));
+        const c128 wq = abc_w(sd, i, j);
+        if (q > 0) d -= 0.5 * (wq + (along_x2 ? abc_w(sd, i, j - 1) : abc_w(sd, i - 1, j)));
+        else if (!abc(lo)) d -= wq;
+        if (q < n - 1) d -= 0.5 * (wq + (along_x2 ? abc_w(sd, i, j + 1) : abc_w(sd, i + 1, j)));
+        else if (!abc(hi)) d -= wq;
+        return d;
+    }
+    __device__ __forceinline__ c128 diagg(int i, int j) const {
+        c128 d = diag(i, j);
+        if (t.abc) {
+            if (i == 0 && abc(0)) d += closure(0, i, j, j, 2, 3);
+            if (i == n - 1 && abc(1)) d += closure(1, i, j, j, 2, 3);
+            if (j == 0 && abc(2)) d += closure(2, i, j, i, 0, 1);
+            if (j == n - 1 && abc(3)) d += closure(3, i, j, i, 0, 1);
+        }
+        return d;
     }
 };
 
@@ -70,13 +135,13 @@ __global__ void layer_coeffs_kernel(Coef cf, int np, int dir, cpx<T>* dg, cpx<T>
     else if (dir == 1) { i = a; j = n - 1 - m; }
     else if (dir == 2) { i = m; j = a; }
     else { i = n - 1 - m; j = a; }
-    dg[o] = real ? ccast<T>(cf.diag(i, j)) : mk<T>(T(1), T(0));
+    dg[o] = real ? ccast<T>(cf.diagg(i, j)) : mk<T>(T(1), T(0));
     // along the layer: the next frame point is (i+1, j) for rows, (i, j+1) for columns
-    c128 e = dir < 2 ? cf.ex(i + 1, j) : cf.ey(i, j + 1);
+    c128 e = ip < n - 1 ? (dir < 2 ? cf.exg(i + 1, j) : cf.eyg(i, j + 1)) : czero<double>();
     eo[o] = ip < n - 1 ? ccast<T>(e) : czero<T>();
     if (m < n - 1) {
         // across layers: frame layer m+1 is row j+1, row j-1, column i+1 or column i-1
-        c128 q = dir == 0 ? cf.ey(i, j + 1) : dir == 1 ? cf.ey(i, j) : dir == 2 ? cf.ex(i + 1, j) : cf.ex(i, j);
+        c128 q = dir == 0 ? cf.eyg(i, j + 1) : dir == 1 ? cf.eyg(i, j) : dir == 2 ? cf.exg(i + 1, j) : cf.exg(i, j);
         cp[o] = real ? ccast<T>(q) : czero<T>();
     }
 }
@@ -93,11 +158,11 @@ __global__ void stencil_kernel(Coef cf, const c128* __restrict__ x, const c128* 
     size_t o = k * N + (size_t)j * n + i;
     if (active && !active[k]) { y[o] = czero<double>(); return; }
     const c128* xk = x + k * N;
-    c128 acc = cf.diag(i, j) * xk[(size_t)j * n + i];
-    if (i > 0) acc += cf.ex(i, j) * xk[(size_t)j * n + i - 1];
-    if (i < n - 1) acc += cf.ex(i + 1, j) * xk[(size_t)j * n + i + 1];
-    if (j > 0) acc += cf.ey(i, j) * xk[(size_t)(j - 1) * n + i];
-    if (j < n - 1) acc += cf.ey(i, j + 1) * xk[(size_t)(j + 1) * n + i];
+    c128 acc = cf.diagg(i, j) * xk[(size_t)j * n + i];
+    if (i > 0) acc += cf.exg(i, j) * xk[(size_t)j * n + i - 1];
+    if (i < n - 1) acc += cf.exg(i + 1, j) * xk[(size_t)j * n + i + 1];
+    if (j > 0) acc += cf.eyg(i, j) * xk[(size_t)(j - 1) * n + i];
+    if (j < n - 1) acc += cf.eyg(i, j + 1) * xk[(size_t)(j + 1) * n + i];
     y[o] = f ? f[o] - acc : acc;
 }
 
@@ -141,7 +206,9 @@ Coef make_coef(int n, double omega, const double* c, const AxisTables& t) {
     Coef cf;
     cf.c = c; cf.t = t; cf.n = n;
     double h = 1.0 / (n + 1);
+    cf.h = h;
     cf.ih2 = 1.0 / (h * h);
+    cf.w = omega;
     cf.w2 = omega * omega;
     return cf;
 }

@@ -40,7 +40,8 @@ class Solver:
     restart, pml_C, rhs_group (right-hand sides per sweep workgroup:
     0 automatic, 1 or 4), direction ("+x2", "-x2", "+x1", "-x1"),
     pml_sides (layer widths on the sides x1=0, x1=1, x2=0, x2=1; 0 for a
-    zero Dirichlet side; default: `pml` on every side).
+    zero Dirichlet side, "abc" for the second-order absorbing boundary
+    condition; default: `pml` on every side).
     """
 
     def __init__(self, c, omega, pml, leaf=16, rank=8, rank_tol=1e-6, precision="c128", dense=False,
@@ -65,7 +66,8 @@ class Solver:
         o.pml_C, o.precision, o.dense, o.restart = float(pml_C), _PREC[precision], int(bool(dense)), int(restart)
         o.rhs_group = int(rhs_group)
         o.direction = _lib.DIRECTIONS[direction]
-        sides = (-1, -1, -1, -1) if pml_sides is None else tuple(int(v) for v in pml_sides)
+        sides = (-1, -1, -1, -1) if pml_sides is None else \
+            tuple(_lib.SIDE_ABC if (isinstance(v, str) and v == "abc") else int(v) for v in pml_sides)
         if len(sides) != 4:
             raise ValueError("pml_sides holds the widths of the sides x1=0, x1=1, x2=0, x2=1")
         for k in range(4):

@@ -12,6 +12,11 @@ the GPU against the FP64 oracle.
 * The medium c = 1/2 + x2 with a source at (0.125, 0.5), swept upward and
   downward: both converge to the oracle's solution; the iteration counts are
   recorded.
+* The second-order absorbing boundary condition on some or all sides: the
+  FP64 operator equals the oracle's, exact factors invert it, and the
+  paper's two absorbing-condition problems (c = 1, a point source at
+  (0.5, 0.25) and a wave packet at (0.25, 0.25) towards (1, 1)) solved with
+  compressed complex64 factors give the oracle's solutions to 1e-5.
 """
 import numpy as np
 import pytest
@@ -158,3 +163,68 @@ def test_sweep_direction_experiment_linear_medium():
             u6, it6, _ = s.solve(_t(f), tol=1e-6, maxit=300)
             its[(direction, rank)] = it6[0]
     print("GMRES iterations at tolerance 1e-6:", its)
+
+
+ABC_LAYOUTS = [("abc", "abc", "abc", "abc"), ("abc", 4, 0, "abc"), (0, 0, 3, "abc")]
+
+
+def _oracle_sides(sides):
+    widths = tuple(0 if v == "abc" else v for v in sides)
+    abc = tuple(e for e, v in zip(assemble.EDGES, sides) if v == "abc")
+    return widths, abc
+
+
+@pytest.mark.parametrize("sides", ABC_LAYOUTS)
+def test_absorbing_condition_operator_and_exact_factors(sides):
+    _need_gpu()
+    n = 31
+    c = W.random_field_medium(n, 53)
+    om = 2 * np.pi * 4
+    widths, abc = _oracle_sides(sides)
+    st = assemble.stencil(c, om, widths, abc=abc)
+    rng = np.random.default_rng(11)
+    F = rng.standard_normal((2, n * n)) + 1j * rng.standard_normal((2, n * n))
+    Ue = direct.solve_sparse(st, F)
+    for direction in DIRS:
+        for kw in (dict(dense=True), dict(leaf=4, rank=16, rank_tol=0.0)):
+            s = _Solver()(c, om, 4, precision="c128", direction=direction, pml_sides=sides, **kw)
+            assert_close(s.stencil(_t(F)).cpu().numpy(), assemble.apply(st, F), 1e-13, f"stencil {sides}")
+            U = s.factor().apply(_t(F)).cpu().numpy()
+            for k in range(2):
+                assert_close(U[k], Ue[k], 1e-10, f"{sides} {direction} {kw} rhs {k}")
+
+
+@pytest.mark.parametrize("source", ["point", "packet"])
+def test_absorbing_condition_problems_of_the_paper(source):
+    _need_gpu()
+    n = 255
+    om = 2 * np.pi * 32
+    c = W.constant_medium(n)
+    if source == "point":
+        f = W.gaussian_source(n, (0.5, 0.25)).reshape(1, -1)
+    else:
+        f = W.wave_packet(n, (0.25, 0.25), (1.0, 1.0), om).reshape(1, -1)
+    sides = ("abc",) * 4
+    widths, abc = _oracle_sides(sides)
+    ue = direct.solve_sparse(assemble.stencil(c, om, widths, abc=abc), f[0])
+    s = _Solver()(c, om, 0, leaf=16, rank=8, rank_tol=1e-6, precision="c64", pml_sides=sides).factor()
+    u, its, res = s.solve(_t(f), tol=1e-10, maxit=300)
+    assert res[0] <= 1e-10
+    assert_close(u.cpu().numpy()[0], ue, 1e-5, source)
+    _, its6, _ = s.solve(_t(f), tol=1e-6, maxit=300)
+    print(f"absorbing condition, {source}: GMRES iterations {its6[0]} at 1e-6, {its[0]} at 1e-10")
+
+
+def test_absorbing_condition_rejects_gradient_and_edge_data():
+    _need_gpu()
+    from paper_1007_4290_amd import _lib
+    n = 31
+    s = _Solver()(W.constant_medium(n), 2 * np.pi * 4, 4, pml_sides=("abc", 4, 4, 4)).factor()
+    z = _t(np.zeros((1, n * n), complex))
+    with pytest.raises(_lib.HsweepError) as e:
+        s.dirichlet_forcing("x1=0", _t(np.zeros((1, n), complex)), z)
+    assert e.value.code == _lib.EINVAL
+    s.dirichlet_forcing("x1=1", _t(np.zeros((1, n), complex)), z)       # a layered side is fine
+    with pytest.raises(_lib.HsweepError) as e:
+        s.grad_c(z, z)
+    assert e.value.code == _lib.EINVAL
