@@ -7,6 +7,7 @@ Usage: python -m paper_1007_4290_amd.build
 """
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -31,6 +32,36 @@ FLAGS = ARCH + [
 ]
 
 
+# Register spills allowed per sweep kernel (VGPRs spilled to scratch, from the
+# compiler's resource-usage remarks), keyed by (element, leaf, rank, levels,
+# right-hand sides per workgroup, threads).  Every sweep kernel not listed must
+# not spill; the build fails on a kernel above its budget.  The listed ones are
+# wide layers whose phased register mode still exceeds the budget of 128 VGPRs
+# at 1024 threads (or 256 at 512), mostly in complex128.
+SWEEP_SPILL_BUDGET = {
+    ("f", 32, 8, 5, 1, 1024): 12, ("f", 64, 8, 4, 1, 1024): 125, ("f", 32, 8, 5, 4, 1024): 93,
+    ("d", 4, 8, 2, 1, 64): 4, ("d", 4, 16, 2, 1, 128): 7, ("d", 8, 16, 2, 1, 128): 5,
+    ("d", 16, 8, 6, 1, 1024): 35, ("d", 64, 8, 3, 1, 512): 146, ("d", 64, 8, 4, 1, 1024): 664,
+    ("d", 32, 8, 5, 1, 1024): 163, ("d", 32, 8, 4, 4, 512): 46, ("d", 32, 8, 5, 4, 1024): 339,
+}
+_SWEEP_NAME = re.compile(r"sweep_kernelI([fd])Li(\d+)ELi(\d+)ELi(\d+)ELi(\d+)ELi(\d+)E")
+
+
+def sweep_spills(remarks):
+    """{kernel key: VGPRs spilled} from -Rpass-analysis=kernel-resource-usage output."""
+    out, cur = {}, None
+    for line in remarks.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            t = _SWEEP_NAME.search(m.group(1))
+            cur = (t.group(1),) + tuple(int(v) for v in t.groups()[1:]) if t else None
+            continue
+        m = re.search(r"remark:\s+VGPRs Spill: (\d+)", line)
+        if m and cur is not None:
+            out[cur] = int(m.group(1))
+    return out
+
+
 def hipcc():
     env = os.environ.get("HIPCC")
     if env:
@@ -42,7 +73,8 @@ def hipcc():
 
 def _compile(src, verbose):
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + FLAGS + ["-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-Rpass-analysis=kernel-resource-usage"] if src.startswith("k_sweep") else []
+    cmd = [hipcc()] + FLAGS + extra + ["-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -58,6 +90,9 @@ def build(verbose=False, jobs=None):
             if res.returncode != 0:
                 sys.stderr.write(res.stdout + res.stderr)
                 raise RuntimeError(f"hipcc failed on {src}")
+            over = {k: v for k, v in sweep_spills(res.stderr).items() if v > SWEEP_SPILL_BUDGET.get(k, 0)}
+            if over:
+                raise RuntimeError(f"sweep kernels in {src} spill past their budget (VGPRs): {over}")
             objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [hipcc()] + ARCH + ["-shared", "-fPIC"] + objs + ["-o", tmp]

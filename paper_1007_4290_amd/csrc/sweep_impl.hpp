@@ -112,6 +112,26 @@ __device__ __forceinline__ void load_pc(const Geo& ge, const cpx<T>* __restrict_
     }
 }
 
+// One level's chunk tile of load_pc (zero past the layer's levels or rows).
+template <typename T, int B, int R>
+__device__ __forceinline__ void load_pc_level(const Geo& ge, const cpx<T>* __restrict__ lay, int l, cpx<T> (&pc)[R]) {
+    const int i = threadIdx.x, np = ge.np;
+    constexpr int CH = Chunk<B, R>::CH, NTQ = Chunk<B, R>::NTQ;
+#pragma unroll
+    for (int j = 0; j < R; ++j) pc[j] = czero<T>();
+    if (l < ge.L && i < np) {
+        const cpx<T>* Pl = lay + ge.eK + (size_t)l * R * np;
+#pragma unroll
+        for (int tq = 0; tq < NTQ; ++tq) {
+            const int e = i + tq * np;
+            const int kc = e / ge.nch, ch = e % ge.nch;
+            const cpx<T>* Pc = Pl + (size_t)kc * np + ch * CH;
+#pragma unroll
+            for (int j = 0; j < CH; ++j) pc[tq * CH + j] = Pc[j];
+        }
+    }
+}
+
 template <typename T, int B, int R, int LM>
 __device__ __forceinline__ void load_pr(const Geo& ge, const cpx<T>* __restrict__ lay, cpx<T> (&pr)[LM > 0 ? LM : 1][R]) {
     const int i = threadIdx.x, np = ge.np;
@@ -125,6 +145,19 @@ __device__ __forceinline__ void load_pr(const Geo& ge, const cpx<T>* __restrict_
 #pragma unroll
             for (int k = 0; k < R; ++k) pr[l][k] = Pl[(size_t)k * np + i];
         }
+    }
+}
+
+// One level's P row of load_pr.
+template <typename T, int R>
+__device__ __forceinline__ void load_pr_level(const Geo& ge, const cpx<T>* __restrict__ lay, int l, cpx<T> (&pr)[R]) {
+    const int i = threadIdx.x, np = ge.np;
+#pragma unroll
+    for (int k = 0; k < R; ++k) pr[k] = czero<T>();
+    if (l < ge.L && i < np) {
+        const cpx<T>* Pl = lay + ge.eK + (size_t)l * R * np;
+#pragma unroll
+        for (int k = 0; k < R; ++k) pr[k] = Pl[(size_t)k * np + i];
     }
 }
 
@@ -221,14 +254,21 @@ __device__ __forceinline__ void apply_T(const Geo& ge, LayerRegs<T, B, R, LM>& g
         }
     }
     if (L == 0) return;
-    // ---- node reductions g_c = P_c^t x[c]
-    if (PHASED) load_pc<T, B, R, LM>(ge, lay, g.pc);
+    // ---- node reductions g_c = P_c^t x[c].  In the phased mode the chunk
+    // tiles are streamed level by level, the next level's loads issued
+    // before the current level's sums (two levels live instead of all).
     {
         constexpr int CH = Chunk<B, R>::CH, NTQ = Chunk<B, R>::NTQ;
         const int nch = ge.nch;
+        cpx<T> pcb[2][PHASED ? R : 1];
+        if constexpr (PHASED) load_pc_level<T, B, R>(ge, lay, 0, pcb[0]);
 #pragma unroll
         for (int l = 0; l < LM; ++l) {
             if (l < L) {
+                if constexpr (PHASED) {
+                    if (l + 1 < LM) load_pc_level<T, B, R>(ge, lay, l + 1, pcb[(l + 1) & 1]);
+                }
+                const cpx<T>* tile = PHASED ? pcb[l & 1] : g.pc[l];
                 const int lvl = l + 1;
                 const int cpn = nch >> lvl;              // chunks per node of this level (<= 64)
 #pragma unroll
@@ -242,7 +282,7 @@ __device__ __forceinline__ void apply_T(const Geo& ge, LayerRegs<T, B, R, LM>& g
 #pragma unroll
                         for (int j = 0; j < CH; ++j) {
 #pragma unroll
-                            for (int q = 0; q < G; ++q) cfma(acc[q], g.pc[l][tq * CH + j], xc[(size_t)j * G + q]);
+                            for (int q = 0; q < G; ++q) cfma(acc[q], tile[tq * CH + j], xc[(size_t)j * G + q]);
                         }
                     }
 #pragma unroll
@@ -257,8 +297,8 @@ __device__ __forceinline__ void apply_T(const Geo& ge, LayerRegs<T, B, R, LM>& g
             }
         }
     }
-    if (PHASED) load_x<T, R>(ge, lay, g.x);
     __syncthreads();
+    if (PHASED) load_x<T, R>(ge, lay, g.x);
     // ---- cores z_q = X_q [g_left; g_right]
     {
         const int npar = (1 << L) - 1;
@@ -293,7 +333,10 @@ __device__ __forceinline__ void apply_T(const Geo& ge, LayerRegs<T, B, R, LM>& g
             for (int q2 = 0; q2 < G; ++q2) sh.zs[(size_t)i * G + q2] = acc[q2];
         }
     }
-    if (PHASED) load_pr<T, B, R, LM>(ge, lay, g.pr);   // the core rows are dead here
+    // phased: the P rows are streamed level by level like the chunk tiles,
+    // the first level loaded here (the core rows are dead)
+    cpx<T> prb[2][PHASED ? R : 1];
+    if constexpr (PHASED) load_pr_level<T, R>(ge, lay, 0, prb[0]);
     __syncthreads();
     // ---- broadcast y[c] -= P_c z_q(side of c)
     if constexpr (use_mfma<T, G>()) {
@@ -301,12 +344,16 @@ __device__ __forceinline__ void apply_T(const Geo& ge, LayerRegs<T, B, R, LM>& g
 #pragma unroll
         for (int l = 0; l < LM; ++l) {
             if (l < L) {
+                if constexpr (PHASED) {
+                    if (l + 1 < LM) load_pr_level<T, R>(ge, lay, l + 1, prb[(l + 1) & 1]);
+                }
+                const cpx<T>* prl = PHASED ? prb[l & 1] : g.pr[l];
                 const int lvl = l + 1;
                 const int c = row ? i >> (ge.lnp - lvl) : 0;   // node index at lvl
                 const int q = (1 << (lvl - 1)) - 1 + (c >> 1);
                 const float* zf = (const float*)(sh.zs + ((size_t)q * 2 * R + (c & 1) * R) * G);
 #pragma unroll
-                for (int k = 0; k < R; ++k) mfma_row4(acc, zf + (size_t)k * 2 * G, m4, row ? g.pr[l][k] : czero<T>());
+                for (int k = 0; k < R; ++k) mfma_row4(acc, zf + (size_t)k * 2 * G, m4, row ? prl[k] : czero<T>());
             }
         }
         cpx<T> d[4];
@@ -317,6 +364,10 @@ __device__ __forceinline__ void apply_T(const Geo& ge, LayerRegs<T, B, R, LM>& g
 #pragma unroll
         for (int l = 0; l < LM; ++l) {
             if (l < L) {
+                if constexpr (PHASED) {
+                    if (l + 1 < LM) load_pr_level<T, R>(ge, lay, l + 1, prb[(l + 1) & 1]);
+                }
+                const cpx<T>* prl = PHASED ? prb[l & 1] : g.pr[l];
                 const int lvl = l + 1;
                 const int c = i >> (ge.lnp - lvl);   // node index at lvl
                 const int q = (1 << (lvl - 1)) - 1 + (c >> 1);
@@ -327,7 +378,7 @@ __device__ __forceinline__ void apply_T(const Geo& ge, LayerRegs<T, B, R, LM>& g
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
 #pragma unroll
-                    for (int q2 = 0; q2 < G; ++q2) cfma(acc[q2], g.pr[l][k], z[(size_t)k * G + q2]);
+                    for (int q2 = 0; q2 < G; ++q2) cfma(acc[q2], prl[k], z[(size_t)k * G + q2]);
                 }
 #pragma unroll
                 for (int q2 = 0; q2 < G; ++q2) y[q2] -= acc[q2];
