@@ -399,6 +399,38 @@ def kernel_probe(name):
         del s
 
 
+def iteration_tables():
+    """GMRES iterations at a fixed 8 points per wavelength as omega grows (the
+    shape of the paper's 2D PML tables, Sec. 3): lens, waveguide and random
+    media at n = 127, 255, 511, 1023 (omega = 2 pi (n+1)/8, layers of 16
+    points), a point source at (0.5, 0.125) and a wave packet at
+    (0.125, 0.125) towards (1, 1), complex64 factors (leaf 16 up to n = 255,
+    32 above, rank 8, tolerance 1e-6), GMRES to 1e-3 (the paper's tolerance)
+    and to 1e-6.  Prints one JSON line; not part of the default run."""
+    import torch
+    import workloads as W
+    from paper_1007_4290_amd.solver import Solver
+    media = {"lens": W.lens_medium, "waveguide": W.waveguide_medium,
+             "random": lambda n: W.random_field_medium(n, seed=1, amplitude=0.3)}
+    out = {}
+    for name, med in media.items():
+        for n in (127, 255, 511, 1023):
+            om = 2 * np.pi * (n + 1) / 8
+            c = med(n)
+            F = np.stack([W.gaussian_source(n, (0.5, 0.125)).ravel(),
+                          W.wave_packet(n, (0.125, 0.125), (1.0, 1.0), om).ravel()])
+            s = Solver(c, om, 16, leaf=16 if n <= 255 else 32, rank=8, rank_tol=1e-6, precision="c64").factor()
+            f = torch.as_tensor(F, device="cuda:0")
+            _, it3, _ = s.solve(f, tol=1e-3, maxit=300)
+            _, it6, r6 = s.solve(f, tol=1e-6, maxit=300)
+            out[f"{name}_{n}"] = {"omega_over_2pi": (n + 1) / 8, "iters_tol1e-3": list(it3), "iters_tol1e-6": list(it6),
+                                  "relres_tol1e-6": [float(x) for x in r6]}
+            print(f"[tables] {name} n={n}: iterations {list(it3)} at 1e-3, {list(it6)} at 1e-6",
+                  file=sys.stderr, flush=True)
+            del s
+    print(json.dumps({"iteration_tables": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -412,6 +444,9 @@ def main():
     ap.add_argument("--kernel-probe", choices=["helm255_grf", "helm511_grf_64src"], default=None,
                     help="only factor the workload and apply its sweep 3 times with one and with four "
                          "right-hand sides per workgroup (a short run for the hardware counters); no JSON line")
+    ap.add_argument("--iteration-tables", action="store_true",
+                    help="only the GMRES iteration counts of three media at 8 points per wavelength, "
+                         "n = 127..1023 (one JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -433,6 +468,9 @@ def main():
 
     if args.kernel_probe:
         kernel_probe(args.kernel_probe)
+        return
+    if args.iteration_tables:
+        iteration_tables()
         return
     tol = 1e-6
     wl = W.get("helm255_grf", precision="c64")
