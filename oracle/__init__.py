@@ -19,9 +19,12 @@ representation" (2010):
 * strong     -- strongly admissible H-matrices with randomized SVD for
                 F = H . H, the factorization and sweep in that format
                                                           (Sec. 2.3 strongly admissible case, Algs. 2.3-2.4)
+* threed     -- the 3D method: 7-point PML operator, separable closed form,
+                exact face-by-face sweep, strongly admissible face
+                H-matrices on a quadtree                  (Sec. 4)
 * gmres      -- (flexible) GMRES in FP64                   (Sec. 2.4, preconditioned solve)
 * fastdiag   -- separable closed form for constant c       (textbook fast diagonalization)
 * hankel     -- free-space Green's function reference      (Sec. 2.2, Hankel kernel)
 * gradient   -- receiver misfit, adjoint gradient, finite differences
 """
-from . import pml, assemble, direct, sweep, gmres, fastdiag, hankel, gradient, hmatrix, strong  # noqa: F401
+from . import pml, assemble, direct, sweep, gmres, fastdiag, hankel, gradient, hmatrix, strong, threed  # noqa: F401

@@ -114,25 +114,51 @@ class SB:
         return slice(child.s[0] - self.s[0], child.s[1] - self.s[0])
 
 
-def structure(t, s, level, L):
+class Line:
+    """Cluster geometry of a layer of a 2D grid: the indices 0..n-1 on a line,
+    bisected; clusters are index ranges (lo, hi)."""
+
+    def __init__(self, n, leaf):
+        self.n = n
+        self.L = depth(n, leaf)
+
+    def root(self):
+        return (0, self.n)
+
+    def split(self, c):
+        return _split(c)
+
+    @staticmethod
+    def rng(c):
+        return c
+
+    @staticmethod
+    def admissible(t, s, level):
+        return well_separated(t, s)
+
+
+def structure(t, s, level, geo):
     """Zero block of the strong format on clusters t, s of one level."""
-    if well_separated(t, s):
-        b = SB(t, s, level, "F")
+    tr, sr = geo.rng(t), geo.rng(s)
+    if geo.admissible(t, s, level):
+        b = SB(tr, sr, level, "F")
         b.u = np.zeros((b.m, 0), complex)
         b.v = np.zeros((b.q, 0), complex)
-    elif level == L:
-        b = SB(t, s, level, "D")
+    elif level == geo.L:
+        b = SB(tr, sr, level, "D")
         b.d = np.zeros((b.m, b.q), complex)
     else:
-        b = SB(t, s, level, "H")
-        tc, sc = _split(t), _split(s)
-        b.ch = [[structure(tc[a], sc[c], level + 1, L) for c in range(2)] for a in range(2)]
+        b = SB(tr, sr, level, "H")
+        tc, sc = geo.split(t), geo.split(s)
+        b.ch = [[structure(tc[a], sc[c], level + 1, geo) for c in range(2)] for a in range(2)]
     return b
 
 
-def zeros(n, leaf):
-    """The zero n x n matrix in the strong format."""
-    return structure((0, n), (0, n), 0, depth(n, leaf))
+def zeros(n, leaf, geo=None):
+    """The zero n x n matrix in the strong format (cluster geometry `geo`,
+    by default the bisected line of n indices)."""
+    geo = geo if geo is not None else Line(n, leaf)
+    return structure(geo.root(), geo.root(), 0, geo)
 
 
 def zeros_like(B):
