@@ -1073,21 +1073,23 @@ __device__ __forceinline__ int wave_pchol(const c128* Gg, int k, int kmax, c128*
         c128 val = ldc(G + (size_t)cc * k + p);          // G[p][c]
         // this lane's share of the dot over the rows so far (rows h, h + hs,
         // ...) in chunks of 4, one accumulator per chunk position; all 8 loads
-        // are in flight before the first use (rows past j - 1 are zeroed)
+        // are in flight before the first use.  Rows j and beyond are still
+        // zero (cleared before the factorization, PCHOL_PAD rows of padding
+        // past kmax), so a chunk that runs past row j - 1 adds nothing.
         c128 s0 = czero<double>(), s1 = s0, s2 = s0, s3 = s0;
         for (int t0 = h; t0 < j; t0 += 4 * hs) {
             c128 ap[4], ac[4];
+            const lds<c128>* rt = Rr + (size_t)t0 * k;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int t = min(t0 + u * hs, j - 1);
-                ap[u] = ldc(Rr + (size_t)t * k + p);
-                ac[u] = ldc(Rr + (size_t)t * k + cc);
+                ap[u] = ldc(rt + (size_t)u * hs * k + p);
+                ac[u] = ldc(rt + (size_t)u * hs * k + cc);
             }
             __builtin_amdgcn_sched_barrier(0);
             cfma_conj(s0, ap[0], ac[0]);
-            cfma_conj(s1, t0 + hs < j ? ap[1] : czero<double>(), ac[1]);
-            cfma_conj(s2, t0 + 2 * hs < j ? ap[2] : czero<double>(), ac[2]);
-            cfma_conj(s3, t0 + 3 * hs < j ? ap[3] : czero<double>(), ac[3]);
+            cfma_conj(s1, ap[1], ac[1]);
+            cfma_conj(s2, ap[2], ac[2]);
+            cfma_conj(s3, ap[3], ac[3]);
         }
         c128 sd = (s0 + s1) + (s2 + s3);
         if (two) {
@@ -1130,6 +1132,9 @@ constexpr size_t TINV_LDS_MAX = 150 * 1024;
 // the Householder QR of the stacked factors by a pivoted Cholesky of their
 // FP64 Gram matrices.
 constexpr int GRAM_KMAX = 40;
+// zero rows after the kmax Cholesky rows: the row loop reads up to 3 row
+// strides (of at most 2 rows) past its last live row
+constexpr int PCHOL_PAD = 8;
 __host__ __device__ inline bool gram_path(size_t elem, double tol, int k) {
     return elem == sizeof(c64) && tol > 0.0 && k <= GRAM_KMAX;
 }
@@ -1182,8 +1187,10 @@ __host__ __device__ inline RecompLayout recomp_layout(int s, int k, int r, int X
         const size_t over = g0 + 2 * (size_t)k * k;
         g = over > g ? over : g;
     }
-    l.gRu = g; if (gram) g += (size_t)l.kk * k;
-    l.gRv = g; if (gram) g += (size_t)l.kk * k;
+    // Cholesky rows, with PCHOL_PAD zero rows past the last so that the
+    // row loop of wave_pchol reads in blocks without bounds tests
+    l.gRu = g; if (gram) g += (size_t)(l.kk + PCHOL_PAD) * k;
+    l.gRv = g; if (gram) g += (size_t)(l.kk + PCHOL_PAD) * k;
     l.gYu = g; if (gram) g += (size_t)l.kk * r;
     l.gYv = g; if (gram) g += (size_t)l.kk * r;
     l.tinv = gram && (g + 2 * (size_t)l.kk * l.kk) * sizeof(c128) <= TINV_LDS_MAX;
@@ -1288,6 +1295,11 @@ __device__ __forceinline__ void recompress_job(const Plan& p, const StepPtrs<T>&
     if (gram) {
         // Gram path: FP64 Gram matrices, then pivoted Cholesky (waves 0 and 1)
         gram_pair(Ut, Vt, s, lda, k, GU, GV);
+        {
+            // rows of R not yet formed read as zero in wave_pchol's dot products
+            const int nz = (ly.kk + PCHOL_PAD) * k;
+            for (int e = tid; e < 2 * nz; e += NT) (e < nz ? RU : RV)[e < nz ? e : e - nz] = czero<double>();
+        }
         __syncthreads();
         if (wv < 2) {
             const bool w1 = wv == 1;
