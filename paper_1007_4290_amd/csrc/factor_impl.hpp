@@ -761,10 +761,10 @@ __device__ __forceinline__ void wave_apply_q(const cpx<T>* A, int lda, int s, in
 // and the lane geometry are constants), 0 to take it from P at run time.
 // NRJ: rows of J per lane (J has only P rows), at most NR.
 // Largest column count for which a sweep's end is tested on all pairs at once
-// (at most two of the P (P + 1) / 2 inner products per lane).
-constexpr int JACOBI_CHECK_PMAX = 15;
+// (up to P (P - 1) / 2 <= 496 inner products, at most 8 per lane).
+constexpr int JACOBI_CHECK_PMAX = 32;
 
-// All inner products of the P columns of N (rows [0, rows), column-major,
+// All inner products of the P columns of N (rows [0, ROWS), column-major,
 // leading dimension ld) by one wavefront, after a sweep: writes every squared
 // column norm to nrm2 and returns whether any pair still meets the rotation
 // test of the sweeps.  When none does, a further sweep would rotate nothing,
@@ -773,41 +773,34 @@ template <typename CT, int ROWS>
 __device__ __forceinline__ bool jacobi_pairs_left(const lds<cpx<CT>>* N, int P, int ld, lds<CT>* nrm2, CT thr,
                                                   CT gabs, CT tiny) {
     const int lane = threadIdx.x & 63;
-    const int ne = P * (P + 1) / 2;
-    int pa[2] = {0, 0}, pb[2] = {0, 0};
-    cpx<CT> dot[2];
+    auto dot = [&](int a, int b) {
+        const lds<cpx<CT>>* ca = N + (size_t)a * ld;
+        const lds<cpx<CT>>* cb = N + (size_t)b * ld;
+        cpx<CT> d0 = czero<CT>(), d1 = d0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int e = lane + 64 * h;
-        dot[h] = czero<CT>();
-        if (e < ne) {
-            int a = 0, rem = e;                  // (a, b), a <= b, upper triangle by rows
-            while (rem >= P - a) { rem -= P - a; ++a; }
-            pa[h] = a;
-            pb[h] = a + rem;
-            const lds<cpx<CT>>* ca = N + (size_t)pa[h] * ld;
-            const lds<cpx<CT>>* cb = N + (size_t)pb[h] * ld;
-            cpx<CT> d0 = czero<CT>(), d1 = d0;
-#pragma unroll
-            for (int r = 0; r + 1 < ROWS; r += 2) {
-                cfma_conj(d0, ldc(ca + r), ldc(cb + r));
-                cfma_conj(d1, ldc(ca + r + 1), ldc(cb + r + 1));
-            }
-            if constexpr (ROWS & 1) cfma_conj(d0, ldc(ca + ROWS - 1), ldc(cb + ROWS - 1));
-            dot[h] = d0 + d1;
-            if (pa[h] == pb[h]) nrm2[pa[h]] = dot[h].re;
+        for (int r = 0; r + 1 < ROWS; r += 2) {
+            cfma_conj(d0, ldc(ca + r), ldc(cb + r));
+            cfma_conj(d1, ldc(ca + r + 1), ldc(cb + r + 1));
         }
-    }
+        if constexpr (ROWS & 1) cfma_conj(d0, ldc(ca + ROWS - 1), ldc(cb + ROWS - 1));
+        return d0 + d1;
+    };
+    if (lane < P) nrm2[lane] = dot(lane, lane).re;
     wave_sync();
+    // pairs a < b, row-major: index e = a (2P - a - 1) / 2 + (b - a - 1); a
+    // from the float root of the quadratic, corrected by one step either way
     bool more = false;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int e = lane + 64 * h;
-        if (e < ne && pa[h] != pb[h]) {
-            const CT al = nrm2[pa[h]], be = nrm2[pb[h]];
-            const CT ag2 = abs2(dot[h]);
-            more = more || (al > tiny && be > tiny && ag2 > thr * thr * (al * be) && ag2 > gabs * gabs);
-        }
+    const int ne = P * (P - 1) / 2;
+    const float tp = (float)(2 * P - 1);
+    for (int e = lane; e < ne; e += 64) {
+        int a = (int)((tp - __builtin_amdgcn_sqrtf(tp * tp - 8.0f * (float)e)) * 0.5f);
+        a = a < 0 ? 0 : (a > P - 2 ? P - 2 : a);
+        if (a * (2 * P - a - 1) / 2 > e) --a;
+        else if ((a + 1) * (2 * P - a - 2) / 2 <= e) ++a;
+        const int b = e - a * (2 * P - a - 1) / 2 + a + 1;
+        const CT al = nrm2[a], be = nrm2[b];
+        const CT ag2 = abs2(dot(a, b));
+        more = more || (al > tiny && be > tiny && ag2 > thr * thr * (al * be) && ag2 > gabs * gabs);
     }
     return __ballot(more) != 0;
 }
@@ -928,7 +921,7 @@ __device__ __forceinline__ void wave_jacobi_n(cpx<CT>* Ng, int P, cpx<CT>* Jg, C
         if (last) break;
         int unused = 0;
         wops::argmax(mxc, unused);
-        if constexpr (GT >= 8) {                      // G = 8 or 16: P <= 16
+        if constexpr (GT > 0) {                       // compile-time group size
             if (P <= JACOBI_CHECK_PMAX && nrot <= P) {
                 // after a sweep with few rotations (the last one before
                 // convergence typically turns one or two pairs), one pass
