@@ -45,11 +45,11 @@ METRIC = "2D Helmholtz solves/s at rel. residual 1e-6: complex64 vs FP64 sweep"
 # + WRITE_SIZE from two rocprofv3 counter passes, each scaled by what the counter
 # reads for a 1 GiB device-to-device copy (profiles/factor_kernels_pmc_helm255.md).
 # Counters cannot be read inside a timed run; a change to the kernel voids this.
-LAYER_KERNEL_HBM_BYTES = 926208 + 98784
+LAYER_KERNEL_HBM_BYTES = 913175 + 98784
 # The same passes for the sweep launches (profiles/sweep_kernel_pmc.md), keyed
 # by workload; None where not measured for the current kernel.
-SWEEP_HBM_BYTES = {"helm255_grf": 64636567 + 1562656, "helm511_grf_64src": 1005106822 + 401345205,
-                   "helm511_grf_64src_group4": 703677099 + 401409867}
+SWEEP_HBM_BYTES = {"helm255_grf": 64644540 + 1562656, "helm511_grf_64src": 1005177426 + 401348213,
+                   "helm511_grf_64src_group4": 703650680 + 401475733}
 
 
 def e_layer(plan):
