@@ -86,6 +86,45 @@ int main() {
         o.direction = HSWEEP_DIR_MX1;
         bad += expect(hsweep_set_opts(ctx[1], &o), HSWEEP_EINVAL, "leftward column sweep switched off");
     }
+    // absorbing boundary condition on two sides: factor and solve in every
+    // direction; Dirichlet data on an absorbing edge and the gradient are refused
+    for (int d = 0; d < 3; ++d) {
+        hsweep_opts o;
+        hsweep_get_opts(ctx[1], &o);
+        o.direction = d;
+        o.pml_sides[0] = HSWEEP_SIDE_ABC; o.pml_sides[1] = 4; o.pml_sides[2] = 0; o.pml_sides[3] = HSWEEP_SIDE_ABC;
+        bad += expect(hsweep_set_opts(ctx[1], &o), 0, "set_opts abc");
+        bad += expect(hsweep_factor(ctx[1], nullptr), 0, "factor abc");
+        bad += expect(hsweep_solve(ctx[1], F, U, 2, 1e-10, 10, it64.data(), r64.data(), nullptr), HSWEEP_ENOCONV,
+                      "solve abc");
+    }
+    bad += expect(hsweep_dirichlet_forcing(ctx[1], HSWEEP_EDGE_X1_0, G, F, 1, nullptr), HSWEEP_EINVAL,
+                  "dirichlet on an absorbing edge");
+    bad += expect(hsweep_dirichlet_forcing(ctx[1], HSWEEP_EDGE_X1_1, G, F, 1, nullptr), 0, "dirichlet on a layered edge");
+    bad += expect(hsweep_grad_c(ctx[1], F, U, 1, G, nullptr), HSWEEP_EINVAL, "gradient with absorbing sides");
+    // the remaining entry points and argument errors
+    {
+        int np = 0, lv = 0;
+        size_t fb = 0, sb = 0;
+        bad += expect(hsweep_plan_info(ctx[16], &np, &lv, &fb), 0, "plan_info");
+        if (np != 512 || lv != 4 || fb == 0) { printf("plan_info: n_p %d levels %d bytes %zu\n", np, lv, fb); ++bad; }
+        bad += expect(hsweep_workspace_bytes(ctx[16], 64, &fb, &sb), 0, "workspace_bytes");
+        if (fb == 0 || sb == 0) { printf("workspace_bytes: %zu %zu\n", fb, sb); ++bad; }
+        bad += expect(hsweep_stencil(ctx[16], F, U, 64, nullptr), 0, "stencil 64");
+        std::vector<double> prof(4 * 511 + 8);
+        int got = hsweep_factor_profile(ctx[16], nullptr, prof.data(), (int)prof.size());
+        if (got < 0) { printf("factor_profile: %d (%s)\n", got, hsweep_last_error()); ++bad; }
+        double tm[8];
+        if (hsweep_timings(ctx[16], tm, 8) < 0) { printf("timings: %s\n", hsweep_last_error()); ++bad; }
+        bad += expect(hsweep_apply(ctx[16], F, F, 1, nullptr), HSWEEP_EINVAL, "apply in place");
+        bad += expect(hsweep_apply(ctx[16], F, U, 0, nullptr), HSWEEP_EINVAL, "apply nrhs 0");
+        bad += expect(hsweep_solve(ctx[16], F, U, 1, 0.0, 10, it64.data(), r64.data(), nullptr), HSWEEP_EINVAL,
+                      "solve tol 0");
+        bad += expect(hsweep_dirichlet_forcing(ctx[16], 4, G, F, 1, nullptr), HSWEEP_EINVAL, "edge out of range");
+        bad += expect(hsweep_apply(nullptr, F, U, 1, nullptr), HSWEEP_EINVAL, "null context");
+        std::vector<hsweep_ctx*> two = {ctx[0], ctx[16]};      // leaf 16 and leaf 32 in one factor batch
+        bad += expect(hsweep_factor_batch(two.data(), 2, nullptr), 0, "factor_batch of two leaf sizes");
+    }
     // a complex128 batch of two grid sizes with one leaf size (one sweep launch per step)
     std::vector<hsweep_ctx*> c2(2);
     std::vector<void*> f2(2), u2(2);

@@ -46,7 +46,36 @@ void launch_dirichlet(int n, int nrhs, double, const double* c, const AxisTables
     need(c, (size_t)n * n * 8, "di c"); need_tables(t, n); need(b, nrhs * n * 16, "di b");
     need(f, (size_t)nrhs * n * n * 16, "di f");
 }
-template <typename T> int launch_factor_layer(const InstDesc<T>*, const Plan*, int, int, hipStream_t, hipEvent_t) { return 0; }
+// Layer step m of each instance reads layer m-1 of its factor store and its
+// couplings, writes layer m, and uses the shared Q, G, rank and status buffers.
+template <typename T>
+int launch_factor_layer(const InstDesc<T>* descs, const Plan* plans, int ninst, int m, hipStream_t, hipEvent_t) {
+    need(descs, ninst * sizeof(InstDesc<T>), "descs");
+    for (int q = 0; q < ninst; ++q) {
+        const InstDesc<T>& d = descs[q];
+        const Plan& p = plans[q];
+        if (d.p.n != p.n || d.p.np != p.np || d.p.L != p.L || d.p.eLayer != p.eLayer) {
+            fprintf(stderr, "descriptor %d does not match its plan\n", q); abort();
+        }
+        if (p.b != plans[0].b || (p.L > 0 && plans[0].L > 0 && p.r != plans[0].r)) return -1;
+        if (m >= p.n) continue;
+        const size_t e = sizeof(cpx<T>);
+        need(d.fac + (size_t)m * p.eLayer, p.eLayer * e, "fac layer m");
+        if (m > 0) {
+            need(d.fac + (size_t)(m - 1) * p.eLayer, p.eLayer * e, "fac layer m-1");
+            need(d.cp + (size_t)(m - 1) * p.np, p.np * e, "factor cp");
+        }
+        need(d.dg + (size_t)m * p.np, p.np * e, "factor dg");
+        need(d.eo + (size_t)m * p.np, p.np * e, "factor eo");
+        if (p.L > 0) {
+            need(d.Q, (size_t)p.L * p.r * p.np * e, "Q");
+            need(d.G, ((size_t)2 << p.L) * p.r * p.r * e, "G");
+        }
+        need(d.rank + (size_t)m * (1 << p.L), (size_t)(1 << p.L) * 4, "rank");
+        need(d.status, 4, "status");
+    }
+    return 0;
+}
 template int launch_factor_layer<float>(const InstDesc<float>*, const Plan*, int, int, hipStream_t, hipEvent_t);
 template int launch_factor_layer<double>(const InstDesc<double>*, const Plan*, int, int, hipStream_t, hipEvent_t);
 template <typename T> void factor_kernels_init() {}
