@@ -3,8 +3,9 @@
 // every kernel launcher is replaced by a check that the device ranges the
 // kernel would touch lie inside live allocations (stubs.cpp).  Covers the
 // batched factorization and FGMRES over mixed grid sizes and leaf sizes, a
-// multi-right-hand-side solve, the adjoint solve and the allocation-free
-// apply.  The stand-in dot products return 1, so GMRES runs to maxit: the
+// multi-right-hand-side solve, the adjoint solve, the allocation-free apply,
+// every sweep direction, absorbing-condition sides, the query entry points
+// and argument errors.  The stand-in dot products return 1, so GMRES runs to maxit: the
 // point is the ranges, not the numbers.
 #include <math.h>
 #include <stdio.h>

@@ -1,8 +1,9 @@
 """Host logic of the C-ABI checked on the CPU: the library's host code is
 compiled with g++ against a host-memory stand-in of the HIP runtime, and
 every kernel launch is replaced by a check that the device ranges it would
-touch lie inside live allocations (tests/hostcheck).  This caught a work
-buffer sized with sizeof of a shadowing bool instead of the element type.
+touch lie inside live allocations (tests/hostcheck).  The build uses the
+address and undefined-behaviour sanitizers.  This caught a work buffer sized
+with sizeof of a shadowing bool instead of the element type.
 """
 import os
 import shutil
