@@ -43,7 +43,7 @@ FP64_PEAK_TFLOPS = 78.6
 METRIC = "2D Helmholtz solves/s at rel. residual 1e-6: complex64 vs FP64 sweep"
 # HBM bytes per launch of layer_kernel<float, 16, 8> on this workload: FETCH_SIZE
 # + WRITE_SIZE from two rocprofv3 counter passes, each scaled by what the counter
-# reads for a 1 GiB device-to-device copy (profiles/factor_kernels_pmc_helm255.md).
+# reads for a 1 GiB device-to-device copy (profiles/factor_kernels_pmc.md).
 # Counters cannot be read inside a timed run; a change to the kernel voids this.
 LAYER_KERNEL_HBM_BYTES = 913175 + 98784
 # The same passes for the sweep launches (profiles/sweep_kernel_pmc.md), keyed
