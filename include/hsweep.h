@@ -91,6 +91,20 @@ extern "C" {
  * condition and dropped next to one with it. */
 #define HSWEEP_SIDE_ABC (-2)
 
+/* Admissibility of the layer H-matrices (Sec. 2.3).  WEAK: every
+ * off-diagonal block of the bisection is low rank (rank <= `rank`), the
+ * inverse kept in a Woodbury form; all precisions and batching.  STRONG:
+ * only blocks of well-separated clusters (at least one cluster of the same
+ * level between them) are low rank, rank <= `rank` at relative tolerance
+ * rank_tol; the near field stays dense down to the leaves, products of two
+ * non-low-rank blocks that land on a low-rank block are built by randomized
+ * SVD (oversampling 8) and the inverse by recursive 2 x 2 block inversion in
+ * that format.  STRONG runs in complex128 only (EINVAL otherwise), one
+ * context at a time (EINVAL in the batch calls, hsweep_apply_noalloc and
+ * hsweep_factor_profile); n_p = n (no padding). */
+#define HSWEEP_ADM_WEAK   0
+#define HSWEEP_ADM_STRONG 1
+
 typedef struct hsweep_ctx hsweep_ctx;
 
 /* Options of the factorization and of GMRES (set before hsweep_factor). */
@@ -117,11 +131,13 @@ typedef struct hsweep_opts {
                            given to hsweep_setup; HSWEEP_SIDE_ABC = no layer
                            and the absorbing boundary condition.  The two
                            widths of an axis must sum to less than n. */
+    int    admissibility; /* HSWEEP_ADM_WEAK (default) or HSWEEP_ADM_STRONG */
 } hsweep_opts;
 
 /* Fill `o` with the defaults: leaf 16, rank 8, rank_tol 1e-6, C = 20,
  * complex128, compressed, restart 40, automatic right-hand-side groups,
- * sweep direction +x2, the setup's layer width on every side. */
+ * sweep direction +x2, the setup's layer width on every side, weak
+ * admissibility. */
 void hsweep_default_opts(hsweep_opts* o);
 
 /* Create a context for velocity c (n*n doubles, layout above; every value
@@ -198,7 +214,9 @@ int hsweep_solve_adjoint(hsweep_ctx* ctx, const void* g, void* mu, void* grad_f,
  * operators, factor store and the factorization's per-layer work) and
  * *solve_bytes for an hsweep_solve of nrhs right-hand sides (sweep work
  * vectors, the GMRES basis and residual fields, small reduction arrays).
- * Either pointer may be NULL.  Host-only; EINVAL if nrhs is out of range. */
+ * Either pointer may be NULL.  Host-only; EINVAL if nrhs is out of range.
+ * With HSWEEP_ADM_STRONG the factor store is known only after
+ * hsweep_factor (0 before) and the factorization's scratch is not counted. */
 int hsweep_workspace_bytes(const hsweep_ctx* ctx, int nrhs, size_t* factor_bytes, size_t* solve_bytes);
 
 /* Dirichlet data u = b on one edge (HSWEEP_EDGE_*) moved to the right-hand

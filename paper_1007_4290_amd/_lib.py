@@ -23,6 +23,7 @@ C64 = 1
 DIRECTIONS = {"+x2": 0, "-x2": 1, "+x1": 2, "-x1": 3}
 EDGES = {"x1=0": 0, "x1=1": 1, "x2=0": 2, "x2=1": 3}
 SIDE_ABC = -2          # pml_sides entry: the absorbing boundary condition on that side
+ADMISSIBILITY = {"weak": 0, "strong": 1}
 
 _NAMES = {EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
           ESINGULAR: "ESINGULAR", ENOCONV: "ENOCONV"}
@@ -57,6 +58,7 @@ class Opts(ctypes.Structure):
         ("rhs_group", ctypes.c_int),
         ("direction", ctypes.c_int),
         ("pml_sides", ctypes.c_int * 4),
+        ("admissibility", ctypes.c_int),
     ]
 
 

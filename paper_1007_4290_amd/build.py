@@ -19,7 +19,7 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhsweep.so")
 
 SOURCES = ["api.hip", "k_coeff.hip", "k_factor.hip", "k_factor_f64.hip", "k_sweep.hip", "k_sweep_a.hip",
-           "k_sweep_b.hip", "k_sweep_c.hip", "k_sweep_g4.hip", "k_krylov.hip"]
+           "k_sweep_b.hip", "k_sweep_c.hip", "k_sweep_g4.hip", "k_krylov.hip", "strong.hip"]
 
 ARCH = ["--offload-arch=gfx950"]
 FLAGS = ARCH + [
@@ -95,7 +95,8 @@ def build(verbose=False, jobs=None):
                 raise RuntimeError(f"sweep kernels in {src} spill past their budget (VGPRs): {over}")
             objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + ARCH + ["-shared", "-fPIC"] + objs + ["-o", tmp]
+    # -z defs: a symbol missing from every object fails the link, not the first call
+    cmd = [hipcc()] + ARCH + ["-shared", "-fPIC", "-Wl,-z,defs"] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -115,6 +115,8 @@ struct hsweep_ctx {
     hipGraphExec_t gexec = nullptr;
     DevBuf gdesc;
     std::vector<unsigned char> gkey;
+    // strongly admissible factors (admissibility HSWEEP_ADM_STRONG)
+    StrongFactors* strong = nullptr;
     AxisTables tables() const {
         AxisTables t;
         t.isn1 = (const c128*)isn1.p; t.sh1 = (const c128*)sh1.p;
@@ -132,6 +134,7 @@ struct hsweep_ctx {
         gkey.clear();
     }
     ~hsweep_ctx() {
+        strong_free(strong);
         drop_graph();
         if (cap) (void)hipStreamDestroy(cap);
         gdesc.release();
@@ -219,6 +222,10 @@ int validate_opts(const hsweep_opts* o, int n) {
     for (int k = 0; k < 4; ++k)
         if (o->pml_sides[k] < -1 && o->pml_sides[k] != HSWEEP_SIDE_ABC)
             return fail(HSWEEP_EINVAL, "pml_sides entries must be -1, HSWEEP_SIDE_ABC or >= 0");
+    if (o->admissibility != HSWEEP_ADM_WEAK && o->admissibility != HSWEEP_ADM_STRONG)
+        return fail(HSWEEP_EINVAL, "admissibility must be HSWEEP_ADM_WEAK or HSWEEP_ADM_STRONG");
+    if (o->admissibility == HSWEEP_ADM_STRONG && (o->precision != HSWEEP_C128 || o->dense))
+        return fail(HSWEEP_EINVAL, "the strongly admissible format runs in complex128 with compressed factors");
     (void)n;
     return HSWEEP_OK;
 }
@@ -227,6 +234,12 @@ int validate_opts(const hsweep_opts* o, int n) {
 int make_plan(hsweep_ctx* ctx, Plan& p) {
     const hsweep_opts& o = ctx->opts;
     p.n = ctx->n;
+    if (o.admissibility == HSWEEP_ADM_STRONG) {
+        // no padding and none of the weak format's kernel limits
+        p.np = ctx->n; p.b = o.leaf; p.L = (int)strong_layer_depth(ctx->n, o.leaf); p.r = o.rank; p.tol = o.rank_tol;
+        plan_sizes(p);
+        return HSWEEP_OK;
+    }
     if (o.dense) {
         int np = 1 << ilog2(ctx->n);
         if (np < 4) np = 4;
@@ -420,6 +433,31 @@ int do_factor_profile(hsweep_ctx* ctx, hipStream_t s, double* layer_ms, double* 
     return HSWEEP_OK;
 }
 
+// Strongly admissible factors (complex128): the frame coefficients of every
+// layer, then the layer loop of Alg. 2.3 in the strong format.
+constexpr uint64_t kStrongSeed = 0x2545F4914F6CDD1Dull;
+
+int do_factor_strong(hsweep_ctx* ctx, hipStream_t s) {
+    const int n = ctx->n;
+    const size_t E = sizeof(c128);
+    strong_free(ctx->strong);
+    ctx->strong = nullptr;
+    HIPCHK(ctx->dg.ensure((size_t)n * n * E));
+    HIPCHK(ctx->eo.ensure((size_t)n * n * E));
+    HIPCHK(ctx->cp.ensure((size_t)(n > 1 ? n : 2) * n * E));
+    HIPCHK(hipMemsetAsync(ctx->cp.p, 0, (size_t)(n > 1 ? n : 2) * n * E, s));
+    launch_layer_coeffs<double>(n, n, ctx->opts.direction, ctx->omega, (const double*)ctx->c.p, ctx->tables(),
+                                (c128*)ctx->dg.p, (c128*)ctx->eo.p, (c128*)ctx->cp.p, s);
+    HIPCHK(hipGetLastError());
+    std::string msg;
+    const int rc = strong_factor(&ctx->strong, n, ctx->opts.leaf, ctx->opts.rank, ctx->opts.rank_tol, kStrongSeed,
+                                 (const c128*)ctx->dg.p, (const c128*)ctx->eo.p, (const c128*)ctx->cp.p, s, &msg);
+    if (rc) return fail(rc, msg);
+    return HSWEEP_OK;
+}
+
+bool is_strong(const hsweep_ctx* ctx) { return ctx->opts.admissibility == HSWEEP_ADM_STRONG; }
+
 // Right-hand sides per sweep workgroup: the option if set (4 only where a
 // grouped kernel exists for the plan), otherwise 4 for many right-hand sides.
 int sweep_group(const hsweep_ctx* ctx, int nrhs) {
@@ -465,6 +503,12 @@ int do_apply(hsweep_ctx* ctx, const c128* f, c128* u, int nrhs, const int* activ
 }
 
 int apply_dispatch(hsweep_ctx* ctx, const c128* f, c128* u, int nrhs, const int* active, hipStream_t s) {
+    if (is_strong(ctx)) {
+        if (!ctx->strong) return fail(HSWEEP_ESTATE, "no strongly admissible factors");
+        std::string msg;
+        const int rc = strong_apply(ctx->strong, ctx->opts.direction, f, u, nrhs, active, s, &msg);
+        return rc ? fail(rc, msg) : HSWEEP_OK;
+    }
     if (ctx->opts.precision == HSWEEP_C64) return do_apply<float>(ctx, f, u, nrhs, active, s);
     return do_apply<double>(ctx, f, u, nrhs, active, s);
 }
@@ -861,6 +905,7 @@ void hsweep_default_opts(hsweep_opts* o) {
     o->rhs_group = 0;
     o->direction = HSWEEP_DIR_PX2;
     for (int k = 0; k < 4; ++k) o->pml_sides[k] = -1;
+    o->admissibility = HSWEEP_ADM_WEAK;
 }
 
 const char* hsweep_last_error(void) { return g_err.c_str(); }
@@ -977,7 +1022,8 @@ int hsweep_plan_info(const hsweep_ctx* ctx, int* n_p, int* levels, size_t* facto
     if (n_p) *n_p = p.np;
     if (levels) *levels = p.L;
     size_t elem = ctx->opts.precision == HSWEEP_C64 ? sizeof(c64) : sizeof(c128);
-    if (factor_bytes) *factor_bytes = ctx->factored ? (size_t)p.n * p.eLayer * elem : 0;
+    if (factor_bytes)
+        *factor_bytes = !ctx->factored ? 0 : is_strong(ctx) ? strong_bytes(ctx->strong) : (size_t)p.n * p.eLayer * elem;
     return HSWEEP_OK;
 }
 
@@ -997,9 +1043,13 @@ int hsweep_factor(hsweep_ctx* ctx, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     ctx->factored = false;
     HIPCHK(hipEventRecord(ctx->ev[0], s));
-    hsweep_ctx* one[1] = {ctx};
-    (void)one;
-    rc = ctx->opts.precision == HSWEEP_C64 ? do_factor_one<float>(ctx, s) : do_factor_one<double>(ctx, s);
+    if (is_strong(ctx)) {
+        rc = do_factor_strong(ctx, s);
+    } else {
+        strong_free(ctx->strong);
+        ctx->strong = nullptr;
+        rc = ctx->opts.precision == HSWEEP_C64 ? do_factor_one<float>(ctx, s) : do_factor_one<double>(ctx, s);
+    }
     if (rc) return rc;
     HIPCHK(hipEventRecord(ctx->ev[1], s));
     HIPCHK(hipEventSynchronize(ctx->ev[1]));
@@ -1029,6 +1079,7 @@ int hsweep_apply_noalloc(hsweep_ctx* ctx, const void* f, void* u, int nrhs, void
     if (!f || !u) return fail(HSWEEP_EINVAL, "f and u must be device pointers");
     if (nrhs < 1 || nrhs > 65535) return fail(HSWEEP_EINVAL, "nrhs must be in [1, 65535]");
     if (f == u) return fail(HSWEEP_EINVAL, "f and u must not overlap");
+    if (is_strong(ctx)) return fail(HSWEEP_EINVAL, "hsweep_apply_noalloc serves the weak format only");
     if (!ctx->factored) return fail(HSWEEP_ESTATE, "hsweep_apply_noalloc before hsweep_factor");
     const Plan& p = ctx->plan;
     const size_t elem = ctx->opts.precision == HSWEEP_C64 ? sizeof(c64) : sizeof(c128);
@@ -1155,13 +1206,23 @@ int hsweep_workspace_bytes(const hsweep_ctx* ctx, int nrhs, size_t* factor_bytes
     const size_t m = (size_t)ctx->opts.restart;
     // coefficients of the setup: c, 1/s on the nodes and s on the half nodes of both axes
     size_t fb = N * sizeof(double) + 2 * (2 * n + 1) * sizeof(c128);
-    // layer operators, factor store and the per-layer work of the factorization
-    fb += 2 * n * np * E + (n > 1 ? n : 2) * np * E + n * p.eLayer * E;
-    fb += (size_t)(p.L > 0 ? p.L : 1) * p.r * np * E + ((size_t)2 << p.L) * p.r * p.r * E;
-    fb += n * ((size_t)1 << p.L) * sizeof(int) + sizeof(int);
-    // sweep work vectors and the flexible-GMRES basis, residuals and small arrays
+    size_t sb = 0;
+    if (is_strong(ctx)) {
+        // layer operators and the stored strong factors (known after hsweep_factor;
+        // the factorization's own scratch is not counted); the sweep keeps w_m of
+        // every layer and two layer vectors per right-hand side
+        fb += 2 * n * n * sizeof(c128) + (n > 1 ? n : 2) * n * sizeof(c128);
+        fb += ctx->factored ? strong_bytes(ctx->strong) : 0;
+        sb = (n + 2) * n * K * sizeof(c128);
+    } else {
+        // layer operators, factor store and the per-layer work of the factorization
+        fb += 2 * n * np * E + (n > 1 ? n : 2) * np * E + n * p.eLayer * E;
+        fb += (size_t)(p.L > 0 ? p.L : 1) * p.r * np * E + ((size_t)2 << p.L) * p.r * p.r * E;
+        fb += n * ((size_t)1 << p.L) * sizeof(int) + sizeof(int);
+        sb = K * n * np * E;                    // sweep work vectors
+    }
+    // the flexible-GMRES basis, residuals and small arrays
     const size_t nblk = (size_t)krylov_dot_blocks(N);
-    size_t sb = K * n * np * E;
     sb += (2 * m + 1) * K * N * sizeof(c128) + 2 * K * N * sizeof(c128);
     sb += 3 * (m + 1) * K * sizeof(c128) + nblk * K * (m + 1) * sizeof(c128);
     sb += K * (sizeof(double) + sizeof(int)) + m * K * sizeof(c128) + (K + 1) * sizeof(size_t);
@@ -1185,6 +1246,7 @@ int hsweep_factor_batch(hsweep_ctx** ctxs, int count, void* stream) {
         }
         if (ctxs[q]->opts.precision != ctxs[0]->opts.precision || ctxs[q]->device != ctxs[0]->device)
             return fail(HSWEEP_EINVAL, "contexts of one batch need the same precision and device");
+        if (is_strong(ctxs[q])) return fail(HSWEEP_EINVAL, "batched factorization serves the weak format only");
     }
     int rc = set_device(ctxs[0]);
     if (rc) return rc;
@@ -1230,6 +1292,7 @@ int hsweep_solve_batch(hsweep_ctx** ctxs, int count, const void* const* f, void*
         int rc = check_ctx(ctxs[q]);
         if (rc) return rc;
         if (!f[q] || !u[q] || f[q] == u[q]) return fail(HSWEEP_EINVAL, "f[k] and u[k] must be distinct device pointers");
+        if (is_strong(ctxs[q])) return fail(HSWEEP_EINVAL, "batched solves serve the weak format only");
         if (!ctxs[q]->factored) return fail(HSWEEP_ESTATE, "hsweep_solve_batch before the contexts are factored");
         if (ctxs[q]->opts.precision != ctxs[0]->opts.precision || ctxs[q]->device != ctxs[0]->device)
             return fail(HSWEEP_EINVAL, "contexts of one batch need the same precision and device");
@@ -1255,6 +1318,7 @@ int hsweep_factor_profile(hsweep_ctx* ctx, void* stream, double* out, int count)
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!out || count < 3) return fail(HSWEEP_EINVAL, "out must hold count >= 3 doubles");
+    if (is_strong(ctx)) return fail(HSWEEP_EINVAL, "hsweep_factor_profile times the weak format's kernels only");
     if (!ctx->planned) {
         Plan p;
         rc = make_plan(ctx, p);

@@ -2,6 +2,7 @@
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
+#include <string>
 #include <vector>
 #include "cplx.hpp"
 
@@ -156,3 +157,22 @@ void launch_combine(const c128* Z, int nz, size_t ld, const c128* y, c128* x, co
 int krylov_dot_blocks(size_t N);
 // y = conj(x), n complex entries
 void launch_conj(const c128* x, c128* y, size_t n, hipStream_t s);
+
+// ---- strongly admissible layer factors (complex128, strong.hip) ----
+// Factors of the n layers in the strong format from the frame coefficients
+// of layer_coeffs (dg, eo: n x n; cp: (n-1) x n, all with row stride n):
+// leaf size `leaf`, rank cap rmax, relative truncation tol, randomized SVD
+// test vectors drawn from `seed`.  On success *out owns the factors; on
+// failure an HSWEEP_* code is returned and *msg says why.
+struct StrongFactors;
+int strong_factor(StrongFactors** out, int n, int leaf, int rmax, double tol, uint64_t seed, const c128* dg,
+                  const c128* eo, const c128* cp, hipStream_t s, std::string* msg);
+// The sweep with these factors for nrhs fields f -> u (natural grid order,
+// frame of sweep direction dir); fields with active[r] == 0 get u = 0.
+int strong_apply(StrongFactors* sf, int dir, const c128* f, c128* u, int nrhs, const int* active, hipStream_t s,
+                 std::string* msg);
+void strong_free(StrongFactors* sf);
+size_t strong_bytes(const StrongFactors* sf);     // stored factor bytes
+int strong_levels(const StrongFactors* sf);
+int strong_max_rank(const StrongFactors* sf);
+size_t strong_layer_depth(int n, int leaf);

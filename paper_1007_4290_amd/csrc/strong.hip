@@ -1,0 +1,1014 @@
+// Strongly admissible H-matrix factors of the layer Schur complements and
+// their sweep, in complex128 (Sec. 2.3, strongly admissible case; Alg. 2.3
+// and Alg. 2.4 in that format).
+//
+// Format.  The n positions of a layer are bisected (lo, mid = lo + (hi-lo)/2,
+// hi) to the depth L at which every cluster holds at most `leaf` positions,
+// so every leaf is on level L.  Two clusters of one level are well
+// separated when their distance (the smallest index difference) is at least
+// their width (the larger size); for clusters of one level that means at
+// least one cluster lies between them.  A block (t, s) of two clusters of
+// one level is factorized, U V^t, when they are well separated (then their
+// parents were not); dense when they are not and both are leaves; and split
+// into its 2 x 2 children otherwise.  Every block row thus carries up to
+// three factorized blocks per level and three dense leaves.
+//
+// Arithmetic, all in device kernels; the host walks the block tree and
+// launches them:
+//   S_m = A_mm - diag(a) T_{m-1} diag(a), a = diagonal of A_{m,m-1};
+//   T_m = S_m^{-1} by 2 x 2 block inversion through the Schur complement of
+//         the first diagonal block, recursively, with dense leaves inverted
+//         by Gauss-Jordan elimination with partial pivoting;
+//   every sum landing on a factorized block is recompressed: QR of both
+//         stacked factors, SVD of the small core, singular values above
+//         tol * sigma_1 kept (all nonzero ones for tol = 0), at most rmax;
+//   a product of two non-factorized blocks landing on a factorized block
+//         (F = H . H) is built by the randomized range finder of Halko,
+//         Martinsson and Tropp (2011): rmax + 8 complex Gaussian test
+//         vectors, QR of the sampled range, SVD of the projected block.
+// The QR, SVD and inverse kernels take one small matrix per thread: blocks
+// are at most a few hundred entries on a side and the factorization is
+// bound by the dependent chain of the block recursion, not by arithmetic.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hsweep.h"
+#include "internal.hpp"
+
+namespace {
+
+// ---------------------------------------------------------------- kernels
+
+// op(M)(r, c) of a column-major matrix with leading dimension ld:
+// 0 = M, 1 = M^t, 2 = conj(M), 3 = M^H.
+__device__ __forceinline__ c128 op_el(const c128* M, int op, int r, int c, int ld) {
+    c128 v = (op & 1) ? M[(size_t)r * ld + c] : M[(size_t)c * ld + r];
+    return (op & 2) ? conj(v) : v;
+}
+
+// C = alpha op(A) op(B) + beta C; C is m x n, the inner dimension k.
+__global__ void zgemm_kernel(int opa, int opb, int m, int n, int k, c128 alpha, const c128* A, int lda,
+                             const c128* B, int ldb, c128 beta, c128* C, int ldc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= m || j >= n) return;
+    c128 acc = czero<double>();
+    for (int p = 0; p < k; ++p) cfma(acc, op_el(A, opa, i, p, lda), op_el(B, opb, p, j, ldb));
+    c128 out = alpha * acc;
+    if (beta.re != 0.0 || beta.im != 0.0) out += beta * C[(size_t)j * ldc + i];
+    C[(size_t)j * ldc + i] = out;
+}
+
+// C = alpha op(A) + beta B (op 0 or 2), elementwise; C may be A or B.
+__global__ void zgeam_kernel(int m, int n, c128 alpha, int opa, const c128* A, int lda, c128 beta, const c128* B,
+                             int ldb, c128* C, int ldc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= m || j >= n) return;
+    c128 out = alpha * op_el(A, opa, i, j, lda);
+    if (B) out += beta * B[(size_t)j * ldb + i];
+    C[(size_t)j * ldc + i] = out;
+}
+
+// C = 0 (m x n).
+__global__ void zfill_kernel(int m, int n, c128* C, int ldc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= m || j >= n) return;
+    C[(size_t)j * ldc + i] = czero<double>();
+}
+
+// M(i, j) *= dl[i] (if dl) * dr[j] (if dr).
+__global__ void zscale_kernel(int m, int n, c128* M, int ld, const c128* dl, const c128* dr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= m || j >= n) return;
+    c128 v = M[(size_t)j * ld + i];
+    if (dl) v = v * dl[i];
+    if (dr) v = v * dr[j];
+    M[(size_t)j * ld + i] = v;
+}
+
+// The dense block (rows t0.., columns s0..) of the symmetric tridiagonal
+// layer operator with diagonal dg and off-diagonal eo (eo[i] = A(i, i+1)).
+__global__ void tridiag_block_kernel(int m, int q, int t0, int s0, const c128* dg, const c128* eo, c128* D) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= m || j >= q) return;
+    const int r = t0 + i, c = s0 + j;
+    c128 v = czero<double>();
+    if (r == c) v = dg[r];
+    else if (r == c + 1) v = eo[c];
+    else if (c == r + 1) v = eo[r];
+    D[(size_t)j * m + i] = v;
+}
+
+// Inverse X of one m x m matrix A (one thread): Gauss-Jordan elimination
+// with partial pivoting on a copy W, the same row operations applied to X = I.
+// A zero pivot sets *status.
+__global__ void zinv_kernel(int m, const c128* A, int lda, c128* W, c128* X, int* status) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) {
+            W[(size_t)j * m + i] = A[(size_t)j * lda + i];
+            X[(size_t)j * m + i] = mk(i == j ? 1.0 : 0.0, 0.0);
+        }
+    for (int c = 0; c < m; ++c) {
+        int p = c;
+        double best = abs2(W[(size_t)c * m + c]);
+        for (int r = c + 1; r < m; ++r) {
+            const double v = abs2(W[(size_t)c * m + r]);
+            if (v > best) { best = v; p = r; }
+        }
+        if (!(best > 0.0)) { *status = 1; return; }
+        if (p != c)
+            for (int j = 0; j < m; ++j) {
+                c128 t = W[(size_t)j * m + c]; W[(size_t)j * m + c] = W[(size_t)j * m + p]; W[(size_t)j * m + p] = t;
+                t = X[(size_t)j * m + c]; X[(size_t)j * m + c] = X[(size_t)j * m + p]; X[(size_t)j * m + p] = t;
+            }
+        const c128 piv = cinv(W[(size_t)c * m + c]);
+        for (int j = 0; j < m; ++j) {
+            W[(size_t)j * m + c] = piv * W[(size_t)j * m + c];
+            X[(size_t)j * m + c] = piv * X[(size_t)j * m + c];
+        }
+        for (int r = 0; r < m; ++r) {
+            if (r == c) continue;
+            const c128 f = W[(size_t)c * m + r];
+            if (f.re == 0.0 && f.im == 0.0) continue;
+            for (int j = 0; j < m; ++j) {
+                W[(size_t)j * m + r] -= f * W[(size_t)j * m + c];
+                X[(size_t)j * m + r] -= f * X[(size_t)j * m + c];
+            }
+        }
+    }
+}
+
+// Thin QR of one p x k matrix A (one thread), kk = min(p, k): Householder
+// reflections H_c = I - 2 v v^H / (v^H v) on a copy W (p x k), reflectors
+// kept in Vh (p x kk); R = the upper kk x k part of W, Q = H_0 ... H_{kk-1}
+// applied to the first kk columns of the identity (p x kk).
+__global__ void zqr_kernel(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int kk = p < k ? p : k;
+    for (int j = 0; j < k; ++j)
+        for (int i = 0; i < p; ++i) W[(size_t)j * p + i] = A[(size_t)j * lda + i];
+    for (int c = 0; c < kk; ++c) {
+        c128* v = Vh + (size_t)c * p;
+        double nx = 0.0;
+        for (int i = c; i < p; ++i) nx += abs2(W[(size_t)c * p + i]);
+        nx = sqrt(nx);
+        for (int i = 0; i < p; ++i) v[i] = czero<double>();
+        if (nx == 0.0) continue;                       // column already zero: H_c = I
+        const c128 x0 = W[(size_t)c * p + c];
+        const double a0 = sqrt(abs2(x0));
+        const c128 ph = a0 > 0.0 ? mk(x0.re / a0, x0.im / a0) : mk(1.0, 0.0);
+        // v = x + ph |x| e_c maps x to -ph |x| e_c without cancellation
+        for (int i = c; i < p; ++i) v[i] = W[(size_t)c * p + i];
+        v[c] = x0 + nx * ph;
+        double vv = 0.0;
+        for (int i = c; i < p; ++i) vv += abs2(v[i]);
+        for (int j = c; j < k; ++j) {
+            c128 s = czero<double>();
+            for (int i = c; i < p; ++i) cfma_conj(s, v[i], W[(size_t)j * p + i]);
+            const c128 f = (2.0 / vv) * s;
+            for (int i = c; i < p; ++i) W[(size_t)j * p + i] -= f * v[i];
+        }
+    }
+    for (int j = 0; j < k; ++j)
+        for (int i = 0; i < kk; ++i) R[(size_t)j * kk + i] = i <= j ? W[(size_t)j * p + i] : czero<double>();
+    for (int j = 0; j < kk; ++j)
+        for (int i = 0; i < p; ++i) Q[(size_t)j * p + i] = mk(i == j ? 1.0 : 0.0, 0.0);
+    for (int c = kk - 1; c >= 0; --c) {
+        const c128* v = Vh + (size_t)c * p;
+        double vv = 0.0;
+        for (int i = c; i < p; ++i) vv += abs2(v[i]);
+        if (vv == 0.0) continue;
+        for (int j = 0; j < kk; ++j) {
+            c128 s = czero<double>();
+            for (int i = c; i < p; ++i) cfma_conj(s, v[i], Q[(size_t)j * p + i]);
+            const c128 f = (2.0 / vv) * s;
+            for (int i = c; i < p; ++i) Q[(size_t)j * p + i] -= f * v[i];
+        }
+    }
+}
+
+// One-sided Jacobi SVD of one a x b matrix (one thread): rotations of column
+// pairs of A (in place, A becomes A V) until every pair is orthogonal to
+// 1e-15 relative or one column of the pair is below 1e-15 of the other (with
+// b > a the surplus columns shrink to rounding noise), V (b x b) the product
+// of the rotations.  Then sigma_j =
+// |column j|, perm lists the columns by decreasing sigma, and *rank is the
+// number kept: sigma > tol * sigma_max (sigma > 0 when tol = 0), at most rmax.
+__global__ void zsvd_kernel(int a, int b, c128* A, int lda, c128* V, double* sig, int* perm, int* rank, double tol,
+                            int rmax) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int j = 0; j < b; ++j)
+        for (int i = 0; i < b; ++i) V[(size_t)j * b + i] = mk(i == j ? 1.0 : 0.0, 0.0);
+    for (int sweep = 0; sweep < 80; ++sweep) {
+        bool rotated = false;
+        for (int p = 0; p < b - 1; ++p)
+            for (int q = p + 1; q < b; ++q) {
+                c128* x = A + (size_t)p * lda;
+                c128* y = A + (size_t)q * lda;
+                double al = 0.0, be = 0.0;
+                c128 ga = czero<double>();
+                for (int i = 0; i < a; ++i) {
+                    al += abs2(x[i]);
+                    be += abs2(y[i]);
+                    cfma_conj(ga, x[i], y[i]);
+                }
+                // |ga| without squaring (a square of a tiny inner product
+                // underflows, and the phase e below must have modulus 1 for
+                // the rotation to stay unitary); a column below 1e-15 of the
+                // other's norm is rounding noise next to it and is left alone
+                const double g = hypot(ga.re, ga.im);
+                if (!(g > 1e-15 * sqrt(al) * sqrt(be))) continue;
+                if (be < 1e-30 * al || al < 1e-30 * be) continue;
+                rotated = true;
+                // with w = e^{-i phi} y (phi = arg ga) the pair (x, w) has the
+                // real inner product g; the real rotation that diagonalizes
+                // [[al, g], [g, be]] is applied to (x, w)
+                const c128 e = mk(ga.re / g, -ga.im / g);
+                const double zeta = (be - al) / (2.0 * g);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                for (int i = 0; i < a; ++i) {
+                    const c128 xi = x[i], wi = e * y[i];
+                    x[i] = cs * xi - sn * wi;
+                    y[i] = sn * xi + cs * wi;
+                }
+                c128* vx = V + (size_t)p * b;
+                c128* vy = V + (size_t)q * b;
+                for (int i = 0; i < b; ++i) {
+                    const c128 xi = vx[i], wi = e * vy[i];
+                    vx[i] = cs * xi - sn * wi;
+                    vy[i] = sn * xi + cs * wi;
+                }
+            }
+        if (!rotated) break;
+    }
+    for (int j = 0; j < b; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < a; ++i) s += abs2(A[(size_t)j * lda + i]);
+        sig[j] = sqrt(s);
+        perm[j] = j;
+    }
+    for (int i = 0; i < b; ++i) {               // selection sort, decreasing
+        int best = i;
+        for (int j = i + 1; j < b; ++j)
+            if (sig[perm[j]] > sig[perm[best]]) best = j;
+        const int t = perm[i]; perm[i] = perm[best]; perm[best] = t;
+    }
+    int r = 0;
+    if (b > 0 && sig[perm[0]] > 0.0) {
+        const double cut = tol > 0.0 ? tol * sig[perm[0]] : 0.0;
+        for (int j = 0; j < b; ++j) r += sig[perm[j]] > cut ? 1 : 0;
+        if (r > rmax) r = rmax;
+    }
+    *rank = r;
+}
+
+// dst(:, j) = op(src(:, perm[j])) for j < k (op 0 or 2).
+__global__ void zgather_cols_kernel(int m, int k, const c128* src, int lds, const int* perm, int op, c128* dst,
+                                    int ldd) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= m || j >= k) return;
+    c128 v = src[(size_t)perm[j] * lds + i];
+    dst[(size_t)j * ldd + i] = op == 2 ? conj(v) : v;
+}
+
+// Complex Gaussian entries (re + i im) / sqrt(2), re and im standard normal
+// by the Box-Muller transform of two uniforms from the splitmix64 hash
+// (Steele, Lea and Flood 2014) of the entry's counter.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__global__ void zrandn_kernel(size_t count, uint64_t seed, c128* out) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint64_t h1 = splitmix64(seed ^ splitmix64(2 * (uint64_t)i));
+    const uint64_t h2 = splitmix64(seed ^ splitmix64(2 * (uint64_t)i + 1));
+    const double u1 = ((double)(h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = ((double)(h2 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double r = sqrt(-2.0 * log(u1)) * 0.70710678118654752;
+    const double th = 6.283185307179586477 * u2;
+    out[i] = mk(r * cos(th), r * sin(th));
+}
+
+// Grid index of position i of frame layer m (sweep direction dir): rows
+// upward or downward, columns rightward.
+__device__ __forceinline__ size_t frame_index(int n, int dir, int i, int m) {
+    if (dir == 0) return (size_t)m * n + i;
+    if (dir == 1) return (size_t)(n - 1 - m) * n + i;
+    return (size_t)i * n + m;
+}
+
+// L(i, r) = f_r(frame point (i, m)) - (a ? a[i] * Wp(i, r) : 0) for nrhs fields.
+__global__ void gather_layer_kernel(int n, int nrhs, int dir, int m, const c128* f, const c128* a, const c128* Wp,
+                                    c128* L) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= n || r >= nrhs) return;
+    c128 v = f[(size_t)r * n * n + frame_index(n, dir, i, m)];
+    if (a) v -= a[i] * Wp[(size_t)r * n + i];
+    L[(size_t)r * n + i] = v;
+}
+
+// u_r(frame point (i, m)) = L(i, r), or 0 for an inactive field.
+__global__ void scatter_layer_kernel(int n, int nrhs, int dir, int m, const c128* L, const int* active, c128* u) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= n || r >= nrhs) return;
+    u[(size_t)r * n * n + frame_index(n, dir, i, m)] =
+        (active && !active[r]) ? czero<double>() : L[(size_t)r * n + i];
+}
+
+// ---------------------------------------------------------------- host side
+
+constexpr int kOversample = 8;
+constexpr int kThreads = 64;
+
+inline dim3 grid2(int m, int n) { return dim3((m + kThreads - 1) / kThreads, n); }
+
+// Bump allocator over device chunks; reset() keeps the chunks for reuse.
+struct Arena {
+    std::vector<std::pair<char*, size_t>> chunks;
+    size_t ci = 0, used = 0;
+    size_t chunk = (size_t)16 << 20;
+    hipError_t err = hipSuccess;
+    c128* alloc(size_t count) {
+        const size_t bytes = ((count ? count : 1) * sizeof(c128) + 255) & ~(size_t)255;
+        while (ci < chunks.size() && used + bytes > chunks[ci].second) { ++ci; used = 0; }
+        if (ci == chunks.size()) {
+            size_t b = bytes > chunk ? bytes : chunk;
+            void* p = nullptr;
+            hipError_t e = hipMalloc(&p, b);
+            if (e != hipSuccess) { err = e; return nullptr; }
+            chunks.emplace_back((char*)p, b);
+            used = 0;
+        }
+        char* p = chunks[ci].first + used;
+        used += bytes;
+        return (c128*)p;
+    }
+    void reset() { ci = 0; used = 0; }
+    size_t reserved() const {
+        size_t s = 0;
+        for (auto& c : chunks) s += c.second;
+        return s;
+    }
+    void release() {
+        for (auto& c : chunks) (void)hipFree(c.first);
+        chunks.clear();
+        reset();
+    }
+};
+
+// One block of an H-matrix.  Index ranges are absolute positions of the
+// layer; d is m x q, u is m x rank, v is q x rank (column-major, leading
+// dimension = row count).
+struct Node {
+    int t0, t1, s0, s1, level;
+    char kind;          // 'D' dense, 'F' factorized, 'H' split
+    int ch[4];          // children (row-major 2 x 2) of an 'H' block
+    c128* d;
+    c128* u;
+    c128* v;
+    int rank;
+    int m() const { return t1 - t0; }
+    int q() const { return s1 - s0; }
+};
+
+// An H-matrix (or a block of one): nodes[0] is its root.
+struct HMat {
+    std::vector<Node> nd;
+};
+
+int depth_for(int n, int leaf) {
+    int L = 0;
+    while ((n + (1 << L) - 1) / (1 << L) > leaf) ++L;
+    return L;
+}
+
+bool well_separated(int t0, int t1, int s0, int s1) {
+    int dist = 0;
+    if (t1 <= s0) dist = s0 - (t1 - 1);
+    else if (s1 <= t0) dist = t0 - (s1 - 1);
+    const int w = std::max(t1 - t0, s1 - s0);
+    return dist >= w;
+}
+
+int build_structure(HMat& M, int t0, int t1, int s0, int s1, int level, int L) {
+    const int idx = (int)M.nd.size();
+    Node b{};
+    b.t0 = t0; b.t1 = t1; b.s0 = s0; b.s1 = s1; b.level = level;
+    b.d = b.u = b.v = nullptr;
+    b.rank = 0;
+    b.ch[0] = b.ch[1] = b.ch[2] = b.ch[3] = -1;
+    if (well_separated(t0, t1, s0, s1)) b.kind = 'F';
+    else if (level == L) b.kind = 'D';
+    else b.kind = 'H';
+    M.nd.push_back(b);
+    if (b.kind == 'H') {
+        const int tm = t0 + (t1 - t0) / 2, sm = s0 + (s1 - s0) / 2;
+        const int tr[2][2] = {{t0, tm}, {tm, t1}}, sr[2][2] = {{s0, sm}, {sm, s1}};
+        for (int a = 0; a < 2; ++a)
+            for (int c = 0; c < 2; ++c) {
+                const int k = build_structure(M, tr[a][0], tr[a][1], sr[c][0], sr[c][1], level + 1, L);
+                M.nd[idx].ch[2 * a + c] = k;
+            }
+    }
+    return idx;
+}
+
+}  // namespace
+
+struct StrongFactors {
+    int n = 0, leaf = 0, L = 0, rmax = 0;
+    double tol = 0.0;
+    uint64_t seed = 0, draws = 0;
+    HMat shape;                   // the block structure of a layer
+    std::vector<HMat> T;          // T_m of every layer (device data in `keep`)
+    Arena keep, tmp;
+    int* dint = nullptr;          // device ints: [0] rank of the last SVD, [1] zero-pivot status
+    c128* cpk = nullptr;          // couplings a_m = diagonal of A_{m+1,m}, (n-1) x n (in `keep`)
+    hipStream_t s = nullptr;
+    std::string err;
+    int rc = HSWEEP_OK;
+    // sweep work: W (n layers x n x nrhs), two layer vectors, product scratch
+    c128* sw = nullptr;
+    size_t sw_count = 0;
+    int max_rank_seen = 0;
+
+    // ---- launch helpers
+    bool ok() const { return rc == HSWEEP_OK; }
+    void fail_with(int code, const std::string& m) {
+        if (rc == HSWEEP_OK) { rc = code; err = m; }
+    }
+    c128* talloc(size_t count) {
+        c128* p = tmp.alloc(count);
+        if (!p) fail_with(HSWEEP_ENOMEM, "device memory for the strongly admissible factorization");
+        return p;
+    }
+    void gemm(int opa, int opb, int m, int n, int k, c128 alpha, const c128* A, int lda, const c128* B, int ldb,
+              c128 beta, c128* C, int ldc) {
+        if (!ok() || m <= 0 || n <= 0) return;
+        hipLaunchKernelGGL(zgemm_kernel, grid2(m, n), dim3(kThreads), 0, s, opa, opb, m, n, k, alpha, A, lda, B, ldb,
+                           beta, C, ldc);
+    }
+    void geam(int m, int n, c128 alpha, int opa, const c128* A, int lda, c128 beta, const c128* B, int ldb, c128* C,
+              int ldc) {
+        if (!ok() || m <= 0 || n <= 0) return;
+        hipLaunchKernelGGL(zgeam_kernel, grid2(m, n), dim3(kThreads), 0, s, m, n, alpha, opa, A, lda, beta, B, ldb,
+                           C, ldc);
+    }
+    void zero(c128* C, int m, int n, int ldc) {
+        if (!ok() || m <= 0 || n <= 0) return;
+        hipLaunchKernelGGL(zfill_kernel, grid2(m, n), dim3(kThreads), 0, s, m, n, C, ldc);
+    }
+    int read_rank() {
+        if (!ok()) return 0;
+        int r = 0;
+        hipError_t e = hipMemcpyAsync(&r, dint, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { fail_with(HSWEEP_EDEVICE, std::string("strong factorization: ") + hipGetErrorString(e)); return 0; }
+        return r;
+    }
+
+    // ---- structure
+    HMat zeros_like(const HMat& M, int idx) {
+        HMat R;
+        copy_shape(R, M, idx, true);
+        return R;
+    }
+    int copy_shape(HMat& R, const HMat& M, int idx, bool fresh) {
+        const int k = (int)R.nd.size();
+        Node b = M.nd[idx];
+        if (fresh) {
+            b.u = b.v = nullptr;
+            b.rank = 0;
+            b.d = nullptr;
+            if (b.kind == 'D') {
+                b.d = talloc((size_t)b.m() * b.q());
+                if (b.d) zero(b.d, b.m(), b.q(), b.m());
+            }
+        }
+        R.nd.push_back(b);
+        if (b.kind == 'H')
+            for (int c = 0; c < 4; ++c) {
+                const int kc = copy_shape(R, M, M.nd[idx].ch[c], fresh);
+                R.nd[k].ch[c] = kc;
+            }
+        return k;
+    }
+    // The block with root `top` (an 'H' node of `like`) assembled from four
+    // finished H-matrices (shallow: their device data is shared).
+    HMat assemble(const Node& top, const HMat* parts[4]) {
+        HMat R;
+        R.nd.push_back(top);
+        for (int c = 0; c < 4; ++c) {
+            const int k = copy_shape(R, *parts[c], 0, false);
+            R.nd[0].ch[c] = k;
+        }
+        return R;
+    }
+
+    // ---- products with blocks of vectors (accumulating)
+    // Y (B.m x ncol) += alpha B X
+    void matvec(const HMat& B, int bi, const c128* X, int ldx, int ncol, c128* Y, int ldy, c128 alpha) {
+        const Node& b = B.nd[bi];
+        if (!ok()) return;
+        if (b.kind == 'D') {
+            gemm(0, 0, b.m(), ncol, b.q(), alpha, b.d, b.m(), X, ldx, mk(1.0, 0.0), Y, ldy);
+        } else if (b.kind == 'F') {
+            if (b.rank == 0) return;
+            c128* t = talloc((size_t)b.rank * ncol);
+            if (!t) return;
+            gemm(1, 0, b.rank, ncol, b.q(), mk(1.0, 0.0), b.v, b.q(), X, ldx, czero<double>(), t, b.rank);
+            gemm(0, 0, b.m(), ncol, b.rank, alpha, b.u, b.m(), t, b.rank, mk(1.0, 0.0), Y, ldy);
+        } else {
+            for (int c = 0; c < 4; ++c) {
+                const Node& h = B.nd[b.ch[c]];
+                matvec(B, b.ch[c], X + (h.s0 - b.s0), ldx, ncol, Y + (h.t0 - b.t0), ldy, alpha);
+            }
+        }
+    }
+    // Y (B.q x ncol) += alpha B^t X
+    void matvec_t(const HMat& B, int bi, const c128* X, int ldx, int ncol, c128* Y, int ldy, c128 alpha) {
+        const Node& b = B.nd[bi];
+        if (!ok()) return;
+        if (b.kind == 'D') {
+            gemm(1, 0, b.q(), ncol, b.m(), alpha, b.d, b.m(), X, ldx, mk(1.0, 0.0), Y, ldy);
+        } else if (b.kind == 'F') {
+            if (b.rank == 0) return;
+            c128* t = talloc((size_t)b.rank * ncol);
+            if (!t) return;
+            gemm(1, 0, b.rank, ncol, b.m(), mk(1.0, 0.0), b.u, b.m(), X, ldx, czero<double>(), t, b.rank);
+            gemm(0, 0, b.q(), ncol, b.rank, alpha, b.v, b.q(), t, b.rank, mk(1.0, 0.0), Y, ldy);
+        } else {
+            for (int c = 0; c < 4; ++c) {
+                const Node& h = B.nd[b.ch[c]];
+                matvec_t(B, b.ch[c], X + (h.t0 - b.t0), ldx, ncol, Y + (h.s0 - b.s0), ldy, alpha);
+            }
+        }
+    }
+
+    // ---- small factorizations
+    // Thin QR of A (p x k): Q (p x kk), R (kk x k), kk = min(p, k).
+    void qr(int p, int k, const c128* A, int lda, c128*& Q, c128*& R) {
+        const int kk = std::min(p, k);
+        c128* W = talloc((size_t)p * k);
+        c128* Vh = talloc((size_t)p * kk);
+        Q = talloc((size_t)p * kk);
+        R = talloc((size_t)kk * k);
+        if (!ok()) return;
+        hipLaunchKernelGGL(zqr_kernel, dim3(1), dim3(1), 0, s, p, k, A, lda, W, Vh, Q, R);
+    }
+    // SVD of A (a x b, in place -> A V); returns the kept rank.
+    int svd(int a, int b, c128* A, int lda, c128*& V, int*& perm) {
+        V = talloc((size_t)b * b);
+        c128* sg = talloc(((size_t)b + 1) / 2 + 1);      // b doubles
+        c128* pm = talloc(((size_t)b + 3) / 4 + 1);      // b ints
+        if (!ok()) return 0;
+        perm = (int*)pm;
+        hipLaunchKernelGGL(zsvd_kernel, dim3(1), dim3(1), 0, s, a, b, A, lda, V, (double*)sg, perm, dint, tol, rmax);
+        return read_rank();
+    }
+
+    // Truncated U V^t of the m x k and q x k factors (QR of both, SVD of the
+    // core R_u R_v^t): new factors in `out`.
+    void compress(Node& out, const c128* U, int ldu, const c128* V, int ldv, int k) {
+        const int m = out.m(), q = out.q();
+        out.u = out.v = nullptr;
+        out.rank = 0;
+        if (k == 0 || !ok()) return;
+        c128 *Q1, *R1, *Q2, *R2;
+        qr(m, k, U, ldu, Q1, R1);
+        qr(q, k, V, ldv, Q2, R2);
+        const int k1 = std::min(m, k), k2 = std::min(q, k);
+        c128* C = talloc((size_t)k1 * k2);
+        if (!ok()) return;
+        gemm(0, 1, k1, k2, k, mk(1.0, 0.0), R1, k1, R2, k2, czero<double>(), C, k1);
+        c128* Vs;
+        int* perm;
+        const int r = svd(k1, k2, C, k1, Vs, perm);
+        if (!ok() || r == 0) return;
+        c128* Cg = talloc((size_t)k1 * r);
+        c128* Vg = talloc((size_t)k2 * r);
+        out.u = talloc((size_t)m * r);
+        out.v = talloc((size_t)q * r);
+        if (!ok()) return;
+        hipLaunchKernelGGL(zgather_cols_kernel, grid2(k1, r), dim3(kThreads), 0, s, k1, r, C, k1, perm, 0, Cg, k1);
+        hipLaunchKernelGGL(zgather_cols_kernel, grid2(k2, r), dim3(kThreads), 0, s, k2, r, Vs, k2, perm, 2, Vg, k2);
+        gemm(0, 0, m, r, k1, mk(1.0, 0.0), Q1, m, Cg, k1, czero<double>(), out.u, m);
+        gemm(0, 0, q, r, k2, mk(1.0, 0.0), Q2, q, Vg, k2, czero<double>(), out.v, q);
+        out.rank = r;
+        if (r > max_rank_seen) max_rank_seen = r;
+    }
+    // out = trunc([A.u, alpha U] [A.v, V]^t)
+    void compress_sum(Node& out, const Node& a, c128 alpha, const c128* U, int ldu, const c128* V, int ldv, int k2) {
+        const int m = out.m(), q = out.q(), k1 = a.rank, k = k1 + k2;
+        if (k == 0) { out.u = out.v = nullptr; out.rank = 0; return; }
+        c128* Uc = talloc((size_t)m * k);
+        c128* Vc = talloc((size_t)q * k);
+        if (!ok()) return;
+        if (k1) {
+            geam(m, k1, mk(1.0, 0.0), 0, a.u, m, czero<double>(), nullptr, 0, Uc, m);
+            geam(q, k1, mk(1.0, 0.0), 0, a.v, q, czero<double>(), nullptr, 0, Vc, q);
+        }
+        if (k2) {
+            geam(m, k2, alpha, 0, U, ldu, czero<double>(), nullptr, 0, Uc + (size_t)k1 * m, m);
+            geam(q, k2, mk(1.0, 0.0), 0, V, ldv, czero<double>(), nullptr, 0, Vc + (size_t)k1 * q, q);
+        }
+        compress(out, Uc, m, Vc, q, k);
+    }
+
+    // Randomized SVD of the m x q product G H (G on (t, u), H on (u, s)):
+    // Y = G (H Omega), Q = qr(Y), M = H^t (G^t conj(Q)) = (Q^H G H)^t, M V =
+    // U S from the SVD of M, and G H ~ (Q conj(V_r)) ((M V)_r)^t.
+    int rsvd(const HMat& G, int gi, const HMat& H, int hi, c128*& Uo, c128*& Vo) {
+        const Node& g = G.nd[gi];
+        const Node& h = H.nd[hi];
+        const int m = g.m(), q = h.q(), mid = g.q();
+        const int ell = std::min(std::min(rmax + kOversample, m), q);
+        Uo = Vo = nullptr;
+        if (ell <= 0 || !ok()) return 0;
+        c128* Om = talloc((size_t)q * ell);
+        c128* Y1 = talloc((size_t)mid * ell);
+        c128* Y = talloc((size_t)m * ell);
+        if (!ok()) return 0;
+        const size_t cnt = (size_t)q * ell;
+        hipLaunchKernelGGL(zrandn_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, seed + draws, Om);
+        draws += 0x9E3779B97F4A7C15ull;
+        zero(Y1, mid, ell, mid);
+        matvec(H, hi, Om, q, ell, Y1, mid, mk(1.0, 0.0));
+        zero(Y, m, ell, m);
+        matvec(G, gi, Y1, mid, ell, Y, m, mk(1.0, 0.0));
+        c128 *Q, *R;
+        qr(m, ell, Y, m, Q, R);                       // ell <= m: Q is m x ell
+        c128* Qc = talloc((size_t)m * ell);
+        c128* M1 = talloc((size_t)mid * ell);
+        c128* M = talloc((size_t)q * ell);
+        if (!ok()) return 0;
+        geam(m, ell, mk(1.0, 0.0), 2, Q, m, czero<double>(), nullptr, 0, Qc, m);
+        zero(M1, mid, ell, mid);
+        matvec_t(G, gi, Qc, m, ell, M1, mid, mk(1.0, 0.0));
+        zero(M, q, ell, q);
+        matvec_t(H, hi, M1, mid, ell, M, q, mk(1.0, 0.0));
+        c128* Vs;
+        int* perm;
+        const int r = svd(q, ell, M, q, Vs, perm);
+        if (!ok() || r == 0) return 0;
+        c128* Vg = talloc((size_t)ell * r);
+        Uo = talloc((size_t)m * r);
+        Vo = talloc((size_t)q * r);
+        if (!ok()) return 0;
+        hipLaunchKernelGGL(zgather_cols_kernel, grid2(ell, r), dim3(kThreads), 0, s, ell, r, Vs, ell, perm, 2, Vg, ell);
+        hipLaunchKernelGGL(zgather_cols_kernel, grid2(q, r), dim3(kThreads), 0, s, q, r, M, q, perm, 0, Vo, q);
+        gemm(0, 0, m, r, ell, mk(1.0, 0.0), Q, m, Vg, ell, czero<double>(), Uo, m);
+        return r;
+    }
+
+    // ---- H-arithmetic
+    // T += U V^t along T's tree (U: T.m x k, V: T.q x k)
+    void add_lowrank(HMat& T, int ti, const c128* U, int ldu, const c128* V, int ldv, int k, c128 alpha) {
+        if (k == 0 || !ok()) return;
+        Node& b = T.nd[ti];
+        if (b.kind == 'D') {
+            gemm(0, 1, b.m(), b.q(), k, alpha, U, ldu, V, ldv, mk(1.0, 0.0), b.d, b.m());
+        } else if (b.kind == 'F') {
+            Node old = b;
+            Node out = b;
+            compress_sum(out, old, alpha, U, ldu, V, ldv, k);
+            T.nd[ti] = out;
+        } else {
+            for (int c = 0; c < 4; ++c) {
+                const int ci = T.nd[ti].ch[c];
+                const Node& h = T.nd[ci];
+                add_lowrank(T, ci, U + (h.t0 - T.nd[ti].t0), ldu, V + (h.s0 - T.nd[ti].s0), ldv, k, alpha);
+            }
+        }
+    }
+    // T += alpha G H (three blocks of one level)
+    void mul_add(HMat& T, int ti, const HMat& G, int gi, const HMat& H, int hi, c128 alpha) {
+        if (!ok()) return;
+        const Node& g = G.nd[gi];
+        const Node& h = H.nd[hi];
+        const Node tb = T.nd[ti];
+        if (g.kind == 'F') {                            // U_g (H^t V_g)^t
+            if (g.rank == 0) return;
+            c128* Vn = talloc((size_t)h.q() * g.rank);
+            if (!ok()) return;
+            zero(Vn, h.q(), g.rank, h.q());
+            matvec_t(H, hi, g.v, g.q(), g.rank, Vn, h.q(), mk(1.0, 0.0));
+            add_lowrank(T, ti, g.u, g.m(), Vn, h.q(), g.rank, alpha);
+        } else if (h.kind == 'F') {                     // (G U_h) V_h^t
+            if (h.rank == 0) return;
+            c128* Un = talloc((size_t)g.m() * h.rank);
+            if (!ok()) return;
+            zero(Un, g.m(), h.rank, g.m());
+            matvec(G, gi, h.u, h.m(), h.rank, Un, g.m(), mk(1.0, 0.0));
+            add_lowrank(T, ti, Un, g.m(), h.v, h.q(), h.rank, alpha);
+        } else if (tb.kind == 'D') {
+            gemm(0, 0, tb.m(), tb.q(), g.q(), alpha, g.d, g.m(), h.d, h.m(), mk(1.0, 0.0), T.nd[ti].d, tb.m());
+        } else if (tb.kind == 'F') {                    // F = H . H
+            c128 *U, *V;
+            const int r = rsvd(G, gi, H, hi, U, V);
+            add_lowrank(T, ti, U, tb.m(), V, tb.q(), r, alpha);
+        } else {
+            for (int a = 0; a < 2; ++a)
+                for (int c = 0; c < 2; ++c)
+                    for (int b = 0; b < 2; ++b)
+                        mul_add(T, T.nd[ti].ch[2 * a + c], G, g.ch[2 * a + b], H, h.ch[2 * b + c], alpha);
+        }
+    }
+    HMat mul(const HMat& G, int gi, const HMat& H, int hi, const HMat& like, int li, c128 alpha) {
+        HMat T = zeros_like(like, li);
+        if (ok()) mul_add(T, 0, G, gi, H, hi, alpha);
+        return T;
+    }
+    // A + alpha B, two blocks of one structure
+    int add_into(HMat& R, const HMat& A, int ai, const HMat& B, int bi, c128 alpha) {
+        const int k = (int)R.nd.size();
+        Node out = A.nd[ai];
+        const Node& b = B.nd[bi];
+        out.ch[0] = out.ch[1] = out.ch[2] = out.ch[3] = -1;
+        if (out.kind == 'D') {
+            out.d = talloc((size_t)out.m() * out.q());
+            geam(out.m(), out.q(), mk(1.0, 0.0), 0, A.nd[ai].d, out.m(), alpha, b.d, out.m(), out.d, out.m());
+        } else if (out.kind == 'F') {
+            compress_sum(out, A.nd[ai], alpha, b.u, b.m(), b.v, b.q(), b.rank);
+        }
+        R.nd.push_back(out);
+        if (out.kind == 'H')
+            for (int c = 0; c < 4; ++c) {
+                const int kc = add_into(R, A, A.nd[ai].ch[c], B, b.ch[c], alpha);
+                R.nd[k].ch[c] = kc;
+            }
+        return k;
+    }
+    HMat add(const HMat& A, int ai, const HMat& B, int bi, c128 alpha) {
+        HMat R;
+        add_into(R, A, ai, B, bi, alpha);
+        return R;
+    }
+    // G^{-1} by 2 x 2 block inversion: Y = G11^{-1}, Z = Y G12, X = G21 Y,
+    // S = G22 - G21 Z, W = S^{-1}, T12 = -Z W, T21 = -W X, T11 = Y - Z T21.
+    HMat inv(const HMat& G, int gi) {
+        const Node& g = G.nd[gi];
+        HMat R;
+        if (!ok()) return R;
+        if (g.kind == 'D') {
+            Node out = g;
+            const int m = g.m();
+            c128* Wk = talloc((size_t)m * m);
+            out.d = talloc((size_t)m * m);
+            if (ok())
+                hipLaunchKernelGGL(zinv_kernel, dim3(1), dim3(1), 0, s, m, g.d, m, Wk, out.d, dint + 1);
+            R.nd.push_back(out);
+            return R;
+        }
+        const int g11 = g.ch[0], g12 = g.ch[1], g21 = g.ch[2], g22 = g.ch[3];
+        const c128 one = mk(1.0, 0.0), mone = mk(-1.0, 0.0);
+        HMat Y = inv(G, g11);
+        HMat Z = mul(Y, 0, G, g12, G, g12, one);
+        HMat X = mul(G, g21, Y, 0, G, g21, one);
+        HMat P = mul(G, g21, Z, 0, G, g22, one);
+        HMat S = add(G, g22, P, 0, mone);
+        HMat W = inv(S, 0);
+        HMat T12 = mul(Z, 0, W, 0, G, g12, mone);
+        HMat T21 = mul(W, 0, X, 0, G, g21, mone);
+        HMat Q = mul(Z, 0, T21, 0, G, g11, one);
+        HMat T11 = add(Y, 0, Q, 0, mone);
+        const HMat* parts[4] = {&T11, &T12, &T21, &W};
+        Node top = g;
+        return assemble(top, parts);
+    }
+
+    // A copy of M in the persistent arena.
+    HMat persist(const HMat& M) {
+        HMat R = M;
+        for (auto& b : R.nd) {
+            if (!ok()) break;
+            if (b.kind == 'D') {
+                c128* p = keep.alloc((size_t)b.m() * b.q());
+                if (!p) { fail_with(HSWEEP_ENOMEM, "device memory for the strong factors"); break; }
+                hipError_t e = hipMemcpyAsync(p, b.d, (size_t)b.m() * b.q() * sizeof(c128), hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) fail_with(HSWEEP_EDEVICE, hipGetErrorString(e));
+                b.d = p;
+            } else if (b.kind == 'F' && b.rank > 0) {
+                c128* pu = keep.alloc((size_t)b.m() * b.rank);
+                c128* pv = keep.alloc((size_t)b.q() * b.rank);
+                if (!pu || !pv) { fail_with(HSWEEP_ENOMEM, "device memory for the strong factors"); break; }
+                hipError_t e = hipMemcpyAsync(pu, b.u, (size_t)b.m() * b.rank * sizeof(c128), hipMemcpyDeviceToDevice, s);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(pv, b.v, (size_t)b.q() * b.rank * sizeof(c128), hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) fail_with(HSWEEP_EDEVICE, hipGetErrorString(e));
+                b.u = pu;
+                b.v = pv;
+            } else if (b.kind == 'F') {
+                b.u = b.v = nullptr;
+            }
+        }
+        return R;
+    }
+
+    ~StrongFactors() {
+        keep.release();
+        tmp.release();
+        if (dint) (void)hipFree(dint);
+        if (sw) (void)hipFree(sw);
+    }
+};
+
+// ---------------------------------------------------------------- interface
+
+size_t strong_layer_depth(int n, int leaf) { return (size_t)depth_for(n, leaf); }
+
+void strong_free(StrongFactors* sf) { delete sf; }
+
+size_t strong_bytes(const StrongFactors* sf) {
+    if (!sf) return 0;
+    size_t e = 0;
+    for (const HMat& M : sf->T)
+        for (const Node& b : M.nd) {
+            if (b.kind == 'D') e += (size_t)b.m() * b.q();
+            else if (b.kind == 'F') e += (size_t)(b.m() + b.q()) * b.rank;
+        }
+    return e * sizeof(c128);
+}
+
+int strong_levels(const StrongFactors* sf) { return sf ? sf->L : 0; }
+int strong_max_rank(const StrongFactors* sf) { return sf ? sf->max_rank_seen : 0; }
+
+// Factor the n layers (frame coefficients dg, eo: n x n; cp: (n-1) x n, see
+// layer_coeffs) into strongly admissible T_m.  On success *out owns the
+// factors; on failure returns an HSWEEP_* code and sets *msg.
+int strong_factor(StrongFactors** out, int n, int leaf, int rmax, double tol, uint64_t seed, const c128* dg,
+                  const c128* eo, const c128* cp, hipStream_t s, std::string* msg) {
+    *out = nullptr;
+    StrongFactors* sf = new StrongFactors();
+    sf->n = n; sf->leaf = leaf; sf->rmax = rmax; sf->tol = tol; sf->seed = seed; sf->s = s;
+    sf->L = depth_for(n, leaf);
+    build_structure(sf->shape, 0, n, 0, n, 0, sf->L);
+    hipError_t e = hipMalloc((void**)&sf->dint, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMemsetAsync(sf->dint, 0, 2 * sizeof(int), s);
+    if (e != hipSuccess) {
+        *msg = std::string("strong factorization: ") + hipGetErrorString(e);
+        delete sf;
+        return e == hipErrorOutOfMemory ? HSWEEP_ENOMEM : HSWEEP_EDEVICE;
+    }
+    if (n > 1) {
+        sf->cpk = sf->keep.alloc((size_t)(n - 1) * n);
+        if (!sf->cpk) {
+            *msg = "device memory for the strong factors";
+            delete sf;
+            return HSWEEP_ENOMEM;
+        }
+        e = hipMemcpyAsync(sf->cpk, cp, (size_t)(n - 1) * n * sizeof(c128), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) {
+            *msg = std::string("strong factorization: ") + hipGetErrorString(e);
+            delete sf;
+            return HSWEEP_EDEVICE;
+        }
+    }
+    const c128 one = mk(1.0, 0.0), mone = mk(-1.0, 0.0);
+    for (int m = 0; m < n && sf->ok(); ++m) {
+        // A_mm in the format: its tridiagonal entries all lie in dense blocks
+        HMat A = sf->zeros_like(sf->shape, 0);
+        for (Node& b : A.nd)
+            if (b.kind == 'D' && sf->ok())
+                hipLaunchKernelGGL(tridiag_block_kernel, grid2(b.m(), b.q()), dim3(kThreads), 0, s, b.m(), b.q(),
+                                   b.t0, b.s0, dg + (size_t)m * n, eo + (size_t)m * n, b.d);
+        HMat S;
+        if (m == 0) {
+            S = A;
+        } else {
+            // diag(a) T_{m-1} diag(a), a = diagonal of A_{m,m-1}
+            const c128* a = cp + (size_t)(m - 1) * n;
+            HMat D = sf->T[m - 1];
+            for (Node& b : D.nd) {
+                if (!sf->ok()) break;
+                if (b.kind == 'D') {
+                    c128* p = sf->talloc((size_t)b.m() * b.q());
+                    if (!p) break;
+                    sf->geam(b.m(), b.q(), one, 0, b.d, b.m(), czero<double>(), nullptr, 0, p, b.m());
+                    hipLaunchKernelGGL(zscale_kernel, grid2(b.m(), b.q()), dim3(kThreads), 0, s, b.m(), b.q(), p, b.m(),
+                                       a + b.t0, a + b.s0);
+                    b.d = p;
+                } else if (b.kind == 'F' && b.rank > 0) {
+                    c128* pu = sf->talloc((size_t)b.m() * b.rank);
+                    c128* pv = sf->talloc((size_t)b.q() * b.rank);
+                    if (!pu || !pv) break;
+                    sf->geam(b.m(), b.rank, one, 0, b.u, b.m(), czero<double>(), nullptr, 0, pu, b.m());
+                    sf->geam(b.q(), b.rank, one, 0, b.v, b.q(), czero<double>(), nullptr, 0, pv, b.q());
+                    hipLaunchKernelGGL(zscale_kernel, grid2(b.m(), b.rank), dim3(kThreads), 0, s, b.m(), b.rank, pu,
+                                       b.m(), a + b.t0, (const c128*)nullptr);
+                    hipLaunchKernelGGL(zscale_kernel, grid2(b.q(), b.rank), dim3(kThreads), 0, s, b.q(), b.rank, pv,
+                                       b.q(), a + b.s0, (const c128*)nullptr);
+                    b.u = pu;
+                    b.v = pv;
+                }
+            }
+            S = sf->add(A, 0, D, 0, mone);
+        }
+        HMat Tm = sf->inv(S, 0);
+        if (!sf->ok()) break;
+        sf->T.push_back(sf->persist(Tm));
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { sf->fail_with(HSWEEP_EDEVICE, std::string("strong factorization: ") + hipGetErrorString(e)); break; }
+        if (sf->tmp.err != hipSuccess || sf->keep.err != hipSuccess) {
+            sf->fail_with(HSWEEP_ENOMEM, "device memory for the strongly admissible factorization");
+            break;
+        }
+        int st = 0;
+        e = hipMemcpy(&st, sf->dint + 1, sizeof(int), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) { sf->fail_with(HSWEEP_EDEVICE, hipGetErrorString(e)); break; }
+        if (st) { sf->fail_with(HSWEEP_ESINGULAR, "zero pivot in a dense leaf inverse (strong format)"); break; }
+        sf->tmp.reset();
+    }
+    (void)one;
+    if (!sf->ok()) {
+        *msg = sf->err;
+        const int rc = sf->rc;
+        delete sf;
+        return rc;
+    }
+    sf->tmp.release();
+    *out = sf;
+    return HSWEEP_OK;
+}
+
+// Alg. 2.4 with T_m in the strong format, for nrhs complex128 fields f -> u
+// in natural grid order (frame of sweep direction dir):
+//   w_m = T_m (f_m - a_{m-1} w_{m-1}),  u_{n-1} = w_{n-1},
+//   u_m = w_m - T_m (a_m u_{m+1}).
+// Inactive fields (active[r] == 0) get u = 0.
+int strong_apply(StrongFactors* sf, int dir, const c128* f, c128* u, int nrhs, const int* active, hipStream_t s,
+                 std::string* msg) {
+    const int n = sf->n;
+    const size_t lay = (size_t)n * nrhs;
+    const size_t need = lay * ((size_t)n + 2);
+    if (need > sf->sw_count) {
+        if (sf->sw) (void)hipFree(sf->sw);
+        sf->sw = nullptr;
+        sf->sw_count = 0;
+        hipError_t e = hipMalloc((void**)&sf->sw, need * sizeof(c128));
+        if (e != hipSuccess) {
+            *msg = std::string("strong sweep work: ") + hipGetErrorString(e);
+            return e == hipErrorOutOfMemory ? HSWEEP_ENOMEM : HSWEEP_EDEVICE;
+        }
+        sf->sw_count = need;
+    }
+    c128* W = sf->sw;                          // w_m of the n layers, n x nrhs each
+    c128* L0 = W + lay * n;                    // the current layer's fields
+    c128* L1 = L0 + lay;                       // coupled fields a_m u_{m+1}
+    sf->s = s;
+    sf->rc = HSWEEP_OK;
+    sf->err.clear();
+    const dim3 g2 = grid2(n, nrhs);
+    for (int m = 0; m < n && sf->ok(); ++m) {
+        hipLaunchKernelGGL(gather_layer_kernel, g2, dim3(kThreads), 0, s, n, nrhs, dir, m, f,
+                           m > 0 ? sf->cpk + (size_t)(m - 1) * n : (const c128*)nullptr,
+                           m > 0 ? W + lay * (m - 1) : (const c128*)nullptr, L0);
+        sf->zero(W + lay * m, n, nrhs, n);
+        sf->matvec(sf->T[m], 0, L0, n, nrhs, W + lay * m, n, mk(1.0, 0.0));
+        sf->tmp.reset();          // F-block scratch is reused in stream order
+    }
+    for (int m = n - 1; m >= 0 && sf->ok(); --m) {
+        if (m == n - 1) {
+            hipLaunchKernelGGL(scatter_layer_kernel, g2, dim3(kThreads), 0, s, n, nrhs, dir, m, W + lay * m, active, u);
+            sf->geam(n, nrhs, mk(1.0, 0.0), 0, W + lay * m, n, czero<double>(), nullptr, 0, L0, n);
+            continue;
+        }
+        // L1 = a_m * u_{m+1} (u_{m+1} in L0), L0 = w_m - T_m L1
+        hipLaunchKernelGGL(zscale_kernel, g2, dim3(kThreads), 0, s, n, nrhs, L0, n, sf->cpk + (size_t)m * n,
+                           (const c128*)nullptr);
+        sf->geam(n, nrhs, mk(1.0, 0.0), 0, L0, n, czero<double>(), nullptr, 0, L1, n);
+        sf->geam(n, nrhs, mk(1.0, 0.0), 0, W + lay * m, n, czero<double>(), nullptr, 0, L0, n);
+        sf->matvec(sf->T[m], 0, L1, n, nrhs, L0, n, mk(-1.0, 0.0));
+        sf->tmp.reset();
+        hipLaunchKernelGGL(scatter_layer_kernel, g2, dim3(kThreads), 0, s, n, nrhs, dir, m, L0, active, u);
+    }
+    if (!sf->ok()) {
+        *msg = sf->err;
+        return sf->rc;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        *msg = std::string("strong sweep: ") + hipGetErrorString(e);
+        return HSWEEP_EDEVICE;
+    }
+    return HSWEEP_OK;
+}

@@ -41,11 +41,12 @@ class Solver:
     0 automatic, 1 or 4), direction ("+x2", "-x2", "+x1", "-x1"),
     pml_sides (layer widths on the sides x1=0, x1=1, x2=0, x2=1; 0 for a
     zero Dirichlet side, "abc" for the second-order absorbing boundary
-    condition; default: `pml` on every side).
+    condition; default: `pml` on every side), admissibility ("weak" or
+    "strong"; strong runs in complex128, one context at a time).
     """
 
     def __init__(self, c, omega, pml, leaf=16, rank=8, rank_tol=1e-6, precision="c128", dense=False,
-                 restart=40, pml_C=20.0, rhs_group=0, direction="+x2", pml_sides=None):
+                 restart=40, pml_C=20.0, rhs_group=0, direction="+x2", pml_sides=None, admissibility="weak"):
         lib = _lib.load()
         if isinstance(c, torch.Tensor):
             c_t = c.detach().to(torch.float64).contiguous()
@@ -72,6 +73,7 @@ class Solver:
             raise ValueError("pml_sides holds the widths of the sides x1=0, x1=1, x2=0, x2=1")
         for k in range(4):
             o.pml_sides[k] = sides[k]
+        o.admissibility = _lib.ADMISSIBILITY[admissibility]
         _lib.check(lib.hsweep_set_opts(self._ctx, ctypes.byref(o)))
         self.precision = precision
         self.factored = False

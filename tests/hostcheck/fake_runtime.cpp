@@ -21,7 +21,15 @@ bool fake_in_alloc(const void* p, size_t bytes) {
     --it;
     return a >= it->first && a + bytes <= it->first + it->second;
 }
-hipError_t hipMalloc(void** p, size_t b) { *p = calloc(1, b ? b : 1); g_alloc[(uintptr_t)*p] = b; return 0; }
+// Device allocations start as NaN bytes when set (a GPU leaves them
+// uninitialized), zeros otherwise.
+bool fake_poison = false;
+hipError_t hipMalloc(void** p, size_t b) {
+    *p = calloc(1, b ? b : 1);
+    if (fake_poison) memset(*p, 0xff, b);
+    g_alloc[(uintptr_t)*p] = b;
+    return 0;
+}
 hipError_t hipFree(void* p) { g_alloc.erase((uintptr_t)p); free(p); return 0; }
 hipError_t hipHostMalloc(void** p, size_t b, unsigned) { *p = calloc(1, b ? b : 1); return 0; }
 hipError_t hipHostFree(void* p) { free(p); return 0; }

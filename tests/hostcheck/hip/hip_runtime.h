@@ -51,3 +51,4 @@ hipError_t hipGraphExecDestroy(hipGraphExec_t e);
 hipError_t hipGraphDestroy(hipGraph_t g);
 // registry query used by the launch checks
 bool fake_in_alloc(const void* p, size_t bytes);
+extern bool fake_poison;

@@ -126,6 +126,33 @@ int main() {
         std::vector<hsweep_ctx*> two = {ctx[0], ctx[16]};      // leaf 16 and leaf 32 in one factor batch
         bad += expect(hsweep_factor_batch(two.data(), 2, nullptr), 0, "factor_batch of two leaf sizes");
     }
+    // the strongly admissible format: complex128 and one context at a time
+    {
+        hsweep_opts o;
+        hsweep_default_opts(&o);
+        o.admissibility = HSWEEP_ADM_STRONG;
+        o.precision = HSWEEP_C64;
+        bad += expect(hsweep_set_opts(ctx[2], &o), HSWEEP_EINVAL, "strong in complex64");
+        o.admissibility = 2;
+        o.precision = HSWEEP_C128;
+        bad += expect(hsweep_set_opts(ctx[2], &o), HSWEEP_EINVAL, "admissibility out of range");
+        o.admissibility = HSWEEP_ADM_STRONG;
+        bad += expect(hsweep_set_opts(ctx[2], &o), 0, "strong options");
+        int np = 0, lv = 0;
+        bad += expect(hsweep_plan_info(ctx[2], &np, &lv, nullptr), 0, "strong plan_info");
+        if (np != 127 || lv != 3) { printf("strong plan: n_p %d levels %d\n", np, lv); ++bad; }
+        std::vector<hsweep_ctx*> two = {ctx[2], ctx[3]};
+        bad += expect(hsweep_factor_batch(two.data(), 2, nullptr), HSWEEP_EINVAL, "strong in a factor batch");
+        double prof[4];
+        bad += expect(hsweep_factor_profile(ctx[2], nullptr, prof, 4), HSWEEP_EINVAL, "strong factor_profile");
+        bad += expect(hsweep_apply(ctx[2], F, U, 1, nullptr), HSWEEP_ESTATE, "strong apply before factor");
+        bad += expect(hsweep_apply_noalloc(ctx[2], F, U, 1, nullptr), HSWEEP_EINVAL, "strong allocation-free apply");
+        hsweep_ctx* one[1] = {ctx[2]};
+        const void* fs[1] = {F};
+        void* us[1] = {U};
+        bad += expect(hsweep_solve_batch(one, 1, fs, us, 1e-6, 10, it64.data(), r64.data(), nullptr), HSWEEP_EINVAL,
+                      "strong batched solve");
+    }
     // a complex128 batch of two grid sizes with one leaf size (one sweep launch per step)
     std::vector<hsweep_ctx*> c2(2);
     std::vector<void*> f2(2), u2(2);

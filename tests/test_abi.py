@@ -3,6 +3,8 @@ header declares, and validates arguments on the host before any device work."""
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -34,6 +36,24 @@ def test_default_options():
     assert (o.leaf, o.rank, o.precision, o.dense) == (16, 8, _lib.C128, 0)
     assert o.rank_tol == pytest.approx(1e-6)
     assert o.pml_C == pytest.approx(20.0)
+    assert o.admissibility == _lib.ADMISSIBILITY["weak"]
+    assert tuple(o.pml_sides) == (-1, -1, -1, -1)
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_binding_options_struct_matches_the_header(tmp_path):
+    # the ctypes mirror of hsweep_opts has the C layout: size and every offset
+    src = tmp_path / "opts.c"
+    fields = [f[0] for f in _lib.Opts._fields_]
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hsweep.h"\nint main(void) {\n'
+                   '  printf("%zu\\n", sizeof(hsweep_opts));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(hsweep_opts, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "opts"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(_lib.Opts)
+    assert vals[1:] == [getattr(_lib.Opts, f).offset for f in fields]
 
 
 def _setup(c, omega, pml, n):

@@ -1,0 +1,116 @@
+"""Strongly admissible layer factors on the GPU (Sec. 2.3, strongly
+admissible case; the paper's rank-2 setting) against the FP64 oracle.
+
+* Untruncated strong factors (tolerance 0, rank cap above every block's
+  size) make the sweep the exact inverse: the oracle's sparse LU solution to
+  1e-10, in three sweep directions, with a different layer width per side
+  and with absorbing-condition sides.
+* Rank-2 factors at tolerance 1e-6 precondition FP64 GMRES (tolerance
+  1e-10) to the oracle's solution within 1e-8, in a handful of iterations:
+  n = 63 (leaf 8) in three directions, and two sources at n = 127 (leaf 16).
+* The strong format is complex128 and one context at a time: the other
+  forms are refused with EINVAL.
+The same cases run on the CPU through the kernel emulation of
+tests/test_strong_emulated.py.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import assemble, direct  # noqa: E402
+import workloads as W  # noqa: E402
+from parity import assert_close  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), device=DEV)
+
+
+def _Solver():
+    from paper_1007_4290_amd.solver import Solver
+    return Solver
+
+
+@pytest.mark.parametrize("direction, sides", [
+    ("+x2", None), ("-x2", None), ("+x1", None),
+    ("+x2", (2, 5, 3, 4)),
+    ("+x2", ("abc", 4, 0, "abc")),
+])
+def test_untruncated_strong_factors_are_the_exact_inverse(direction, sides):
+    _need_gpu()
+    n = 31
+    c = W.random_field_medium(n, 41)
+    om = 2 * np.pi * 4
+    widths = (4, 4, 4, 4) if sides is None else tuple(0 if v == "abc" else v for v in sides)
+    abc = () if sides is None else tuple(e for e, v in zip(assemble.EDGES, sides) if v == "abc")
+    st = assemble.stencil(c, om, widths, abc=abc)
+    rng = np.random.default_rng(7)
+    F = rng.standard_normal((2, n * n)) + 1j * rng.standard_normal((2, n * n))
+    s = _Solver()(c, om, 4, leaf=4, rank=16, rank_tol=0.0, precision="c128", direction=direction,
+                  pml_sides=sides, admissibility="strong").factor()
+    info = s.plan_info()
+    assert info["n_p"] == n and info["levels"] == 3 and info["factor_bytes"] > 0
+    U = s.apply(_t(F)).cpu().numpy()
+    Ue = direct.solve_sparse(st, F)
+    for k in range(2):
+        assert_close(U[k], Ue[k], 1e-10, f"{direction} {sides} rhs {k}")
+
+
+@pytest.mark.parametrize("direction", ["+x2", "-x2", "+x1"])
+def test_rank_two_strong_factors_precondition_gmres_to_the_solution(direction):
+    _need_gpu()
+    n = 63
+    c = W.random_field_medium(n, 1)
+    om = 2 * np.pi * 8
+    f = W.gaussian_source(n, (0.5, 0.5)).reshape(1, -1)
+    s = _Solver()(c, om, 12, leaf=8, rank=2, rank_tol=1e-6, precision="c128", direction=direction,
+                  admissibility="strong").factor()
+    u, its, res = s.solve(_t(f), tol=1e-10, maxit=50)
+    assert res[0] <= 1e-10 and its[0] <= 5
+    assert_close(u.cpu().numpy()[0], direct.solve_sparse(assemble.stencil(c, om, 12), f[0]), 1e-8, direction)
+    print(f"strong rank 2, n = 63, {direction}: {its[0]} GMRES iterations")
+
+
+def test_rank_two_strong_factors_two_sources_n127():
+    _need_gpu()
+    n = 127
+    c = W.random_field_medium(n, 43)
+    om = 2 * np.pi * 16
+    F = np.stack([W.gaussian_source(n, (0.4, 0.6)).ravel(), W.gaussian_source(n, (0.7, 0.3)).ravel()])
+    s = _Solver()(c, om, 12, leaf=16, rank=2, rank_tol=1e-6, precision="c128", admissibility="strong").factor()
+    U, its, res = s.solve(_t(F.astype(complex)), tol=1e-10, maxit=50)
+    assert max(res) <= 1e-10 and max(its) <= 6
+    Ue = direct.solve_sparse(assemble.stencil(c, om, 12), F.astype(complex))
+    for k in range(2):
+        assert_close(U.cpu().numpy()[k], Ue[k], 1e-8, f"source {k}")
+
+
+def test_strong_format_rejects_other_forms():
+    _need_gpu()
+    from paper_1007_4290_amd import _lib
+    n = 31
+    c = W.constant_medium(n)
+    with pytest.raises(_lib.HsweepError) as e:
+        _Solver()(c, 2 * np.pi * 4, 4, precision="c64", admissibility="strong")
+    assert e.value.code == _lib.EINVAL
+    s = _Solver()(c, 2 * np.pi * 4, 4, leaf=4, rank=2, admissibility="strong")     # refused before any factor
+    z = _t(np.zeros((1, n * n), complex))
+    u = torch.empty_like(z)
+    lib = _lib.load()
+    assert lib.hsweep_apply_noalloc(s._ctx, ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(u.data_ptr()), 1,
+                                    None) == _lib.EINVAL
+    from paper_1007_4290_amd.solver import solve_batch
+    with pytest.raises(_lib.HsweepError) as e:
+        solve_batch([s], [z[0]], tol=1e-6)
+    assert e.value.code == _lib.EINVAL

@@ -13,16 +13,18 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HC = os.path.join(ROOT, "tests", "hostcheck")
+EMU = os.path.join(ROOT, "tests", "emucheck")
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
 def test_launch_ranges_of_batched_and_single_solves(tmp_path):
     exe = str(tmp_path / "hostcheck")
-    cmd = ["g++", "-std=c++17", "-O0", "-g", "-fsanitize=address,undefined", "-I", HC,
-           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_1007_4290_amd", "csrc"),
-           "-x", "c++", os.path.join(ROOT, "paper_1007_4290_amd", "csrc", "api.hip"), "-x", "none",
-           os.path.join(HC, "fake_runtime.cpp"), os.path.join(HC, "stubs.cpp"), os.path.join(HC, "main.cpp"),
-           "-o", exe]
+    csrc = os.path.join(ROOT, "paper_1007_4290_amd", "csrc")
+    cmd = ["g++", "-std=c++17", "-O0", "-g", "-fsanitize=address,undefined", "-I", EMU, "-I", HC,
+           "-I", os.path.join(ROOT, "include"), "-I", csrc,
+           "-x", "c++", os.path.join(csrc, "api.hip"), os.path.join(csrc, "strong.hip"), "-x", "none",
+           os.path.join(HC, "fake_runtime.cpp"), os.path.join(HC, "stubs.cpp"), os.path.join(EMU, "emu_state.cpp"),
+           os.path.join(HC, "main.cpp"), "-o", exe]
     build = subprocess.run(cmd, capture_output=True, text=True)
     assert build.returncode == 0, build.stderr[-3000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
