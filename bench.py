@@ -334,7 +334,45 @@ def bench_workloads(tol):
                       "gradient_ms": gm, "gradients_per_s": 1e3 / gm,
                       "note": "setup, factorization, 32 forward and 32 adjoint solves, gradient kernel"}
     print(f"[bench] gradient: {gm:.1f} ms", file=sys.stderr, flush=True)
+    out["strong_rank2_127"] = strong_workload(tol)
     return out
+
+
+def strong_workload(tol, n=127):
+    """Strongly admissible rank-2 factors (the paper's setting) on the n = 127
+    random medium (omega = 2 pi 16, 8 points per wavelength, layers of 12
+    points, leaf 16, complex128), beside the weak rank-8 complex128 factors
+    of the same problem."""
+    import torch
+    import workloads as W
+    from paper_1007_4290_amd.solver import Solver
+    leaf, q = (16, n // 8 + 1) if n >= 127 else (8, 8)
+    c = W.random_field_medium(n, 1)
+    om = 2 * np.pi * q
+    pml = 12
+    f = torch.as_tensor(W.gaussian_source(n, (0.5, 0.5)).reshape(1, -1).astype(complex), device="cuda:0")
+    row = {"n": n, "omega": f"2pi*{q}", "leaf": leaf, "precision": "c128"}
+    for adm, rank in (("strong", 2), ("weak", 8)):
+        s = Solver(c, om, pml, leaf=leaf, rank=rank, rank_tol=1e-6, precision="c128", admissibility=adm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.factor()
+        torch.cuda.synchronize()
+        fm = 1e3 * (time.perf_counter() - t0)
+        s.solve(f, tol=tol)
+        ms, U, its, res, tm = _timed_solve(s, f, tol, 2, torch)
+        _, its10, _ = s.solve(f, tol=1e-10)
+        row[f"{adm}_rank{rank}"] = {"factor_ms": fm, "solve_ms": ms, "gmres_iters": its[0],
+                                    "gmres_iters_at_1e-10": its10[0], "relres": res[0],
+                                    "factor_bytes": s.plan_info()["factor_bytes"],
+                                    "end_to_end_solves_per_s": 1e3 / (fm + ms)}
+        print(f"[bench] {adm} rank {rank}, n = {n}: factor {fm:.0f} ms, solve {ms:.1f} ms, its {its[0]}",
+              file=sys.stderr, flush=True)
+        del s
+    row["note"] = ("strong factorization: one kernel launch per small H-arithmetic operation (QR, SVD, inverse "
+                   "on one thread per matrix, products one thread per entry), bound by launch and "
+                   "synchronization latency")
+    return row
 
 
 def cpu_baseline(wl, budget_s=10.0):
@@ -444,6 +482,9 @@ def main():
     ap.add_argument("--kernel-probe", choices=["helm255_grf", "helm511_grf_64src"], default=None,
                     help="only factor the workload and apply its sweep 3 times with one and with four "
                          "right-hand sides per workgroup (a short run for the hardware counters); no JSON line")
+    ap.add_argument("--strong-probe", action="store_true",
+                    help="only the strongly admissible rank-2 factorization and solve at n = 63 (a short run "
+                         "for the kernel trace); no JSON line")
     ap.add_argument("--iteration-tables", action="store_true",
                     help="only the GMRES iteration counts of three media at 8 points per wavelength, "
                          "n = 127..1023 (one JSON line)")
@@ -471,6 +512,9 @@ def main():
         return
     if args.iteration_tables:
         iteration_tables()
+        return
+    if args.strong_probe:
+        print(json.dumps(strong_workload(1e-6, n=63)), file=sys.stderr, flush=True)
         return
     tol = 1e-6
     wl = W.get("helm255_grf", precision="c64")

@@ -53,15 +53,47 @@ __device__ __forceinline__ c128 op_el(const c128* M, int op, int r, int c, int l
     return (op & 2) ? conj(v) : v;
 }
 
+// sum_{i in [lo, hi)} conj(x[i]) y[i] and sum |x[i]|^2, with four partial
+// sums so that a single thread keeps four independent chains in flight.
+__device__ __forceinline__ c128 dot_conj(const c128* x, const c128* y, int lo, int hi) {
+    c128 s0 = czero<double>(), s1 = s0, s2 = s0, s3 = s0;
+    int i = lo;
+    for (; i + 3 < hi; i += 4) {
+        cfma_conj(s0, x[i], y[i]);
+        cfma_conj(s1, x[i + 1], y[i + 1]);
+        cfma_conj(s2, x[i + 2], y[i + 2]);
+        cfma_conj(s3, x[i + 3], y[i + 3]);
+    }
+    for (; i < hi; ++i) cfma_conj(s0, x[i], y[i]);
+    return (s0 + s1) + (s2 + s3);
+}
+__device__ __forceinline__ double norm2(const c128* x, int lo, int hi) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = lo;
+    for (; i + 3 < hi; i += 4) {
+        s0 += abs2(x[i]);
+        s1 += abs2(x[i + 1]);
+        s2 += abs2(x[i + 2]);
+        s3 += abs2(x[i + 3]);
+    }
+    for (; i < hi; ++i) s0 += abs2(x[i]);
+    return (s0 + s1) + (s2 + s3);
+}
+
 // C = alpha op(A) op(B) + beta C; C is m x n, the inner dimension k.
 __global__ void zgemm_kernel(int opa, int opb, int m, int n, int k, c128 alpha, const c128* A, int lda,
                              const c128* B, int ldb, c128 beta, c128* C, int ldc) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= m || j >= n) return;
-    c128 acc = czero<double>();
-    for (int p = 0; p < k; ++p) cfma(acc, op_el(A, opa, i, p, lda), op_el(B, opb, p, j, ldb));
-    c128 out = alpha * acc;
+    c128 a0 = czero<double>(), a1 = a0;
+    int p = 0;
+    for (; p + 1 < k; p += 2) {
+        cfma(a0, op_el(A, opa, i, p, lda), op_el(B, opb, p, j, ldb));
+        cfma(a1, op_el(A, opa, i, p + 1, lda), op_el(B, opb, p + 1, j, ldb));
+    }
+    if (p < k) cfma(a0, op_el(A, opa, i, p, lda), op_el(B, opb, p, j, ldb));
+    c128 out = alpha * (a0 + a1);
     if (beta.re != 0.0 || beta.im != 0.0) out += beta * C[(size_t)j * ldc + i];
     C[(size_t)j * ldc + i] = out;
 }
@@ -161,23 +193,18 @@ __global__ void zqr_kernel(int p, int k, const c128* A, int lda, c128* W, c128* 
         for (int i = 0; i < p; ++i) W[(size_t)j * p + i] = A[(size_t)j * lda + i];
     for (int c = 0; c < kk; ++c) {
         c128* v = Vh + (size_t)c * p;
-        double nx = 0.0;
-        for (int i = c; i < p; ++i) nx += abs2(W[(size_t)c * p + i]);
-        nx = sqrt(nx);
+        const double nx = sqrt(norm2(W + (size_t)c * p, c, p));
         for (int i = 0; i < p; ++i) v[i] = czero<double>();
         if (nx == 0.0) continue;                       // column already zero: H_c = I
         const c128 x0 = W[(size_t)c * p + c];
-        const double a0 = sqrt(abs2(x0));
+        const double a0 = hypot(x0.re, x0.im);
         const c128 ph = a0 > 0.0 ? mk(x0.re / a0, x0.im / a0) : mk(1.0, 0.0);
         // v = x + ph |x| e_c maps x to -ph |x| e_c without cancellation
         for (int i = c; i < p; ++i) v[i] = W[(size_t)c * p + i];
         v[c] = x0 + nx * ph;
-        double vv = 0.0;
-        for (int i = c; i < p; ++i) vv += abs2(v[i]);
+        const double vv = norm2(v, c, p);
         for (int j = c; j < k; ++j) {
-            c128 s = czero<double>();
-            for (int i = c; i < p; ++i) cfma_conj(s, v[i], W[(size_t)j * p + i]);
-            const c128 f = (2.0 / vv) * s;
+            const c128 f = (2.0 / vv) * dot_conj(v, W + (size_t)j * p, c, p);
             for (int i = c; i < p; ++i) W[(size_t)j * p + i] -= f * v[i];
         }
     }
@@ -187,13 +214,10 @@ __global__ void zqr_kernel(int p, int k, const c128* A, int lda, c128* W, c128* 
         for (int i = 0; i < p; ++i) Q[(size_t)j * p + i] = mk(i == j ? 1.0 : 0.0, 0.0);
     for (int c = kk - 1; c >= 0; --c) {
         const c128* v = Vh + (size_t)c * p;
-        double vv = 0.0;
-        for (int i = c; i < p; ++i) vv += abs2(v[i]);
+        const double vv = norm2(v, c, p);
         if (vv == 0.0) continue;
         for (int j = 0; j < kk; ++j) {
-            c128 s = czero<double>();
-            for (int i = c; i < p; ++i) cfma_conj(s, v[i], Q[(size_t)j * p + i]);
-            const c128 f = (2.0 / vv) * s;
+            const c128 f = (2.0 / vv) * dot_conj(v, Q + (size_t)j * p, c, p);
             for (int i = c; i < p; ++i) Q[(size_t)j * p + i] -= f * v[i];
         }
     }
@@ -217,13 +241,8 @@ __global__ void zsvd_kernel(int a, int b, c128* A, int lda, c128* V, double* sig
             for (int q = p + 1; q < b; ++q) {
                 c128* x = A + (size_t)p * lda;
                 c128* y = A + (size_t)q * lda;
-                double al = 0.0, be = 0.0;
-                c128 ga = czero<double>();
-                for (int i = 0; i < a; ++i) {
-                    al += abs2(x[i]);
-                    be += abs2(y[i]);
-                    cfma_conj(ga, x[i], y[i]);
-                }
+                const double al = norm2(x, 0, a), be = norm2(y, 0, a);
+                const c128 ga = dot_conj(x, y, 0, a);
                 // |ga| without squaring (a square of a tiny inner product
                 // underflows, and the phase e below must have modulus 1 for
                 // the rotation to stay unitary); a column below 1e-15 of the
@@ -255,9 +274,7 @@ __global__ void zsvd_kernel(int a, int b, c128* A, int lda, c128* V, double* sig
         if (!rotated) break;
     }
     for (int j = 0; j < b; ++j) {
-        double s = 0.0;
-        for (int i = 0; i < a; ++i) s += abs2(A[(size_t)j * lda + i]);
-        sig[j] = sqrt(s);
+        sig[j] = sqrt(norm2(A + (size_t)j * lda, 0, a));
         perm[j] = j;
     }
     for (int i = 0; i < b; ++i) {               // selection sort, decreasing
