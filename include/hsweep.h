@@ -280,6 +280,43 @@ int hsweep_factor_profile(hsweep_ctx* ctx, void* stream, double* out, int count)
  * work, out[4] number of applies in the last solve. */
 int hsweep_timings(const hsweep_ctx* ctx, double* out, int count);
 
+/* ---- 3D (Sec. 4): the n x n x n unit-cube grid, h = 1/(n+1), unknowns
+ * u[(k-1) n^2 + (j-1) n + (i-1)] at (i h, j h, k h) (x1 fastest, then x2,
+ * then x3), absorbing layers of `pml` points on all six sides, the 7-point
+ * operator of the equation divided by s1 s2 s3 (each edge coefficient
+ * s_a(half node) / (product of the other two s at the node) / h^2, the
+ * centre omega^2/(s1 s2 s3 c^2) minus the six couplings), zero Dirichlet
+ * values outside.  Swept face by face (faces x3 = const) with strongly
+ * admissible H-matrix factors of the face Schur complements on quadtree
+ * face clusters (boxes bisected in x1, then x2; boxes of one quadtree
+ * level are well separated when they differ by more than one box in x1 or
+ * x2).  Complex128; fields are device complex128 arrays of nrhs * n^3.
+ * Errors as in 2D, message in hsweep_last_error. */
+typedef struct hsweep3_ctx hsweep3_ctx;
+
+/* Context for velocity c (n^3 doubles, host or device, finite and > 0),
+ * omega > 0, layer width pml (2 pml < n), 3 <= n <= 255.  Defaults: leaf 16
+ * face points, rank 2, rank_tol 1e-6 (the paper's 3D setting), restart 40. */
+int hsweep3_setup(const double* c, double omega, int pml, int n, hsweep3_ctx** out);
+/* Uses leaf (face points per leaf box, 1..1024), rank (1..64), rank_tol,
+ * pml_C and restart of `o`; precision must be HSWEEP_C128 and
+ * admissibility HSWEEP_ADM_STRONG (EINVAL otherwise).  Invalidates the
+ * factors. */
+int hsweep3_set_opts(hsweep3_ctx* ctx, const hsweep_opts* o);
+/* The face factors T_m = S_m^{-1} (Alg. 2.3 face by face); synchronizes. */
+int hsweep3_factor(hsweep3_ctx* ctx, void* stream);
+/* u = M f, the face-by-face sweep (Alg. 2.4), nrhs fields. */
+int hsweep3_apply(hsweep3_ctx* ctx, const void* f, void* u, int nrhs, void* stream);
+/* y = A x in FP64. */
+int hsweep3_stencil(hsweep3_ctx* ctx, const void* x, void* y, int nrhs, void* stream);
+/* A u = f by right-preconditioned flexible GMRES as hsweep_solve. */
+int hsweep3_solve(hsweep3_ctx* ctx, const void* f, void* u, int nrhs, double tol, int maxit, int* iters,
+                  double* relres, void* stream);
+/* Binary levels of the face cluster tree and bytes of the stored face
+ * factors (0 before hsweep3_factor). */
+int hsweep3_plan_info(const hsweep3_ctx* ctx, int* levels, size_t* factor_bytes);
+void hsweep3_destroy(hsweep3_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,4 +1,4 @@
-"""Sweeping preconditioner for the 2D Helmholtz equation on MI355X (gfx950).
+"""Sweeping preconditioner for the Helmholtz equation (2D, and 3D face by face) on MI355X (gfx950).
 
 The numerical work lives in libhsweep.so (HIP C++, C-ABI declared in
 include/hsweep.h); this package only marshals arguments.  Importing the
@@ -9,7 +9,7 @@ from ._lib import HsweepError, EXPORTED  # noqa: F401
 
 
 def __getattr__(name):
-    if name in ("Solver", "helmholtz_solve", "factor_batch", "solve_batch"):
+    if name in ("Solver", "Solver3", "helmholtz_solve", "factor_batch", "solve_batch"):
         from . import solver
         return getattr(solver, name)
     raise AttributeError(name)

@@ -35,6 +35,8 @@ EXPORTED = [
     "hsweep_factor_batch", "hsweep_solve_batch", "hsweep_destroy", "hsweep_last_error", "hsweep_timings",
     "hsweep_factor_profile", "hsweep_solve_adjoint", "hsweep_workspace_bytes", "hsweep_apply_noalloc",
     "hsweep_dirichlet_forcing",
+    "hsweep3_setup", "hsweep3_set_opts", "hsweep3_factor", "hsweep3_apply", "hsweep3_stencil", "hsweep3_solve",
+    "hsweep3_plan_info", "hsweep3_destroy",
 ]
 # Size of the static device scratch of hsweep_apply_noalloc (HSWEEP_NOALLOC_SCRATCH_BYTES).
 NOALLOC_SCRATCH_BYTES = 32 << 20
@@ -98,6 +100,14 @@ def load():
         "hsweep_workspace_bytes": (i, [vp, i, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "hsweep_apply_noalloc": (i, [vp, vp, vp, i, vp]),
         "hsweep_dirichlet_forcing": (i, [vp, i, vp, vp, i, vp]),
+        "hsweep3_setup": (i, [vp, d, i, i, pp]),
+        "hsweep3_set_opts": (i, [vp, ctypes.POINTER(Opts)]),
+        "hsweep3_factor": (i, [vp, vp]),
+        "hsweep3_apply": (i, [vp, vp, vp, i, vp]),
+        "hsweep3_stencil": (i, [vp, vp, vp, i, vp]),
+        "hsweep3_solve": (i, [vp, vp, vp, i, d, i, ip, dp, vp]),
+        "hsweep3_plan_info": (i, [vp, ip, ctypes.POINTER(ctypes.c_size_t)]),
+        "hsweep3_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

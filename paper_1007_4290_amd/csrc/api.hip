@@ -83,6 +83,9 @@ struct HostBuf {
 
 }  // namespace
 
+int hsweep_report(int code, const std::string& msg) { return fail(code, msg); }
+void hsweep_clear_error() { g_err.clear(); }
+
 struct hsweep_ctx {
     int n = 0, pml = 0;
     double omega = 0.0;

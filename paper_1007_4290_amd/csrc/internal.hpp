@@ -176,3 +176,31 @@ size_t strong_bytes(const StrongFactors* sf);     // stored factor bytes
 int strong_levels(const StrongFactors* sf);
 int strong_max_rank(const StrongFactors* sf);
 size_t strong_layer_depth(int n, int leaf);
+// 3D (Sec. 4): factors of the n faces of an n x n x n grid in the strong
+// format with quadtree face clusters, from the 7-point coefficient fields
+// (n^3 each, x1 fastest, then x2, then x3), and their face-by-face sweep.
+int strong_factor3(StrongFactors** out, int n, int leaf, int rmax, double tol, uint64_t seed, const c128* D,
+                   const c128* X0, const c128* X1, const c128* Y0, const c128* Y1, const c128* Z0, hipStream_t s,
+                   std::string* msg);
+int strong_apply3(StrongFactors* sf, const c128* f, c128* u, int nrhs, const int* active, hipStream_t s,
+                  std::string* msg);
+size_t strong_face_depth(int n, int leaf);
+
+// ---- 3D coefficients (k_coeff3.hip) ----
+// The 7-point operator of Sec. 4 divided by s1 s2 s3: centre D and the
+// couplings to (i-1), (i+1), (j-1), (j+1), (k-1), (k+1), each edge
+// coefficient evaluated once for both rows it couples.  isn/sh: the
+// stretching tables of the three axes (as in 2D).
+struct Coef3 {
+    c128 *D, *X0, *X1, *Y0, *Y1, *Z0, *Z1;
+};
+void launch_coeff3(int n, double omega, const double* c, const c128* const isn[3], const c128* const sh[3],
+                   const Coef3& out, hipStream_t s);
+// y = A x, or y = f - A x when f is given, for nrhs fields of n^3 points.
+void launch_stencil3(int n, int nrhs, const Coef3& cf, const c128* x, const c128* f, c128* y, const int* active,
+                     hipStream_t s);
+
+// Error reporting shared by the entry points of the 2D and 3D contexts
+// (sets the message hsweep_last_error returns and passes the code through).
+int hsweep_report(int code, const std::string& msg);
+void hsweep_clear_error();

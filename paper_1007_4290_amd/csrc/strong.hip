@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -426,35 +427,98 @@ bool well_separated(int t0, int t1, int s0, int s1) {
     return dist >= w;
 }
 
-int build_structure(HMat& M, int t0, int t1, int s0, int s1, int level, int L) {
+// A cluster: the position range [lo, hi) of a layer.  On a face (Sec. 4)
+// it is also a box [i0, i1) x [j0, j1) of face points at binary level `lev`
+// with quadtree coordinates (qi, qj): boxes are bisected in x1 on even
+// levels and in x2 on odd ones, and positions follow that bisection.
+struct Cluster {
+    int lo, hi, i0, i1, j0, j1, lev, qi, qj;
+};
+
+// Cluster geometry: the bisected line of a 2D layer, or the quadtree of a
+// face, where two boxes of one quadtree level (an even binary level) are
+// well separated when max(|qi - qi'|, |qj - qj'|) > 1; the half levels in
+// between are always refined.
+struct Geometry {
+    bool face = false;
+    int L = 0;
+    bool admissible(const Cluster& t, const Cluster& s) const {
+        if (!face) return well_separated(t.lo, t.hi, s.lo, s.hi);
+        if (t.lev % 2) return false;
+        return std::max(std::abs(t.qi - s.qi), std::abs(t.qj - s.qj)) > 1;
+    }
+    void split(const Cluster& c, Cluster& a, Cluster& b) const {
+        a = c;
+        b = c;
+        a.lev = b.lev = c.lev + 1;
+        if (!face) {
+            const int mid = c.lo + (c.hi - c.lo) / 2;
+            a.hi = mid;
+            b.lo = mid;
+            return;
+        }
+        if (c.lev % 2 == 0) {
+            const int mid = c.i0 + (c.i1 - c.i0) / 2;
+            a.i1 = mid; b.i0 = mid;
+            a.qi = 2 * c.qi; b.qi = 2 * c.qi + 1;
+        } else {
+            const int mid = c.j0 + (c.j1 - c.j0) / 2;
+            a.j1 = mid; b.j0 = mid;
+            a.qj = 2 * c.qj; b.qj = 2 * c.qj + 1;
+        }
+        a.hi = c.lo + (a.i1 - a.i0) * (a.j1 - a.j0);
+        b.lo = a.hi;
+    }
+};
+
+int build_structure(HMat& M, const Geometry& geo, const Cluster& t, const Cluster& s, int level) {
     const int idx = (int)M.nd.size();
     Node b{};
-    b.t0 = t0; b.t1 = t1; b.s0 = s0; b.s1 = s1; b.level = level;
+    b.t0 = t.lo; b.t1 = t.hi; b.s0 = s.lo; b.s1 = s.hi; b.level = level;
     b.d = b.u = b.v = nullptr;
     b.rank = 0;
     b.ch[0] = b.ch[1] = b.ch[2] = b.ch[3] = -1;
-    if (well_separated(t0, t1, s0, s1)) b.kind = 'F';
-    else if (level == L) b.kind = 'D';
+    if (geo.admissible(t, s)) b.kind = 'F';
+    else if (level == geo.L) b.kind = 'D';
     else b.kind = 'H';
     M.nd.push_back(b);
     if (b.kind == 'H') {
-        const int tm = t0 + (t1 - t0) / 2, sm = s0 + (s1 - s0) / 2;
-        const int tr[2][2] = {{t0, tm}, {tm, t1}}, sr[2][2] = {{s0, sm}, {sm, s1}};
+        Cluster tc[2], sc[2];
+        geo.split(t, tc[0], tc[1]);
+        geo.split(s, sc[0], sc[1]);
         for (int a = 0; a < 2; ++a)
             for (int c = 0; c < 2; ++c) {
-                const int k = build_structure(M, tr[a][0], tr[a][1], sr[c][0], sr[c][1], level + 1, L);
+                const int k = build_structure(M, geo, tc[a], sc[c], level + 1);
                 M.nd[idx].ch[2 * a + c] = k;
             }
     }
     return idx;
 }
 
+// Face points in bisection order: perm[position] = natural face index j n + i.
+void face_order(const Geometry& geo, const Cluster& c, int n, std::vector<int>& out) {
+    if (c.lev == geo.L) {
+        for (int j = c.j0; j < c.j1; ++j)
+            for (int i = c.i0; i < c.i1; ++i) out.push_back(j * n + i);
+        return;
+    }
+    Cluster a, b;
+    geo.split(c, a, b);
+    face_order(geo, a, n, out);
+    face_order(geo, b, n, out);
+}
+
 }  // namespace
 
 struct StrongFactors {
-    int n = 0, leaf = 0, L = 0, rmax = 0;
+    int nl = 0;                   // layers (faces)
+    int N = 0;                    // positions per layer (n on a line, n^2 on a face)
+    int side = 0;                 // grid points per side
+    int leaf = 0, L = 0, rmax = 0;
     double tol = 0.0;
     uint64_t seed = 0, draws = 0;
+    Geometry geo;
+    int* permd = nullptr;         // face: perm[position] = natural face index (device)
     HMat shape;                   // the block structure of a layer
     std::vector<HMat> T;          // T_m of every layer (device data in `keep`)
     Arena keep, tmp;
@@ -846,74 +910,100 @@ struct StrongFactors {
         tmp.release();
         if (dint) (void)hipFree(dint);
         if (sw) (void)hipFree(sw);
+        if (permd) (void)hipFree(permd);
     }
 };
 
 // ---------------------------------------------------------------- interface
 
-size_t strong_layer_depth(int n, int leaf) { return (size_t)depth_for(n, leaf); }
+namespace {
 
-void strong_free(StrongFactors* sf) { delete sf; }
-
-size_t strong_bytes(const StrongFactors* sf) {
-    if (!sf) return 0;
-    size_t e = 0;
-    for (const HMat& M : sf->T)
-        for (const Node& b : M.nd) {
-            if (b.kind == 'D') e += (size_t)b.m() * b.q();
-            else if (b.kind == 'F') e += (size_t)(b.m() + b.q()) * b.rank;
-        }
-    return e * sizeof(c128);
+// The dense block (rows t0.., columns s0.., positions in bisection order)
+// of the face operator A_mm of the 7-point stencil: centre D and the
+// couplings of point p = j n + i to (i-1, j), (i+1, j), (i, j-1), (i, j+1)
+// (X0, X1, Y0, Y1, natural face order).
+__global__ void face_block_kernel(int m, int q, int t0, int s0, int n, const int* perm, const c128* D, const c128* X0,
+                                  const c128* X1, const c128* Y0, const c128* Y1, c128* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= m || j >= q) return;
+    const int p = perm[t0 + i], c = perm[s0 + j];
+    const int ip = p % n, jp = p / n, ic = c % n, jc = c / n;
+    c128 v = czero<double>();
+    if (p == c) v = D[p];
+    else if (jc == jp && ic == ip - 1) v = X0[p];
+    else if (jc == jp && ic == ip + 1) v = X1[p];
+    else if (ic == ip && jc == jp - 1) v = Y0[p];
+    else if (ic == ip && jc == jp + 1) v = Y1[p];
+    out[(size_t)j * m + i] = v;
 }
 
-int strong_levels(const StrongFactors* sf) { return sf ? sf->L : 0; }
-int strong_max_rank(const StrongFactors* sf) { return sf ? sf->max_rank_seen : 0; }
+// dst(r, pos) = src(r, perm[pos]) for `rows` rows of N entries.
+__global__ void permute_rows_kernel(int rows, int N, const int* perm, const c128* src, c128* dst) {
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (pos >= N || r >= rows) return;
+    dst[(size_t)r * N + pos] = src[(size_t)r * N + perm[pos]];
+}
 
-// Factor the n layers (frame coefficients dg, eo: n x n; cp: (n-1) x n, see
-// layer_coeffs) into strongly admissible T_m.  On success *out owns the
-// factors; on failure returns an HSWEEP_* code and sets *msg.
-int strong_factor(StrongFactors** out, int n, int leaf, int rmax, double tol, uint64_t seed, const c128* dg,
-                  const c128* eo, const c128* cp, hipStream_t s, std::string* msg) {
-    *out = nullptr;
-    StrongFactors* sf = new StrongFactors();
-    sf->n = n; sf->leaf = leaf; sf->rmax = rmax; sf->tol = tol; sf->seed = seed; sf->s = s;
-    sf->L = depth_for(n, leaf);
-    build_structure(sf->shape, 0, n, 0, n, 0, sf->L);
+// L(pos, r) = f_r(face m, point perm[pos]) - (a ? a[pos] Wp(pos, r) : 0);
+// field r holds nl faces of N points.
+__global__ void gather_face_kernel(int N, int nl, int nrhs, int m, const int* perm, const c128* f, const c128* a,
+                                   const c128* Wp, c128* L) {
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (pos >= N || r >= nrhs) return;
+    c128 v = f[(size_t)r * nl * N + (size_t)m * N + perm[pos]];
+    if (a) v -= a[pos] * Wp[(size_t)r * N + pos];
+    L[(size_t)r * N + pos] = v;
+}
+
+__global__ void scatter_face_kernel(int N, int nl, int nrhs, int m, const int* perm, const c128* L, const int* active,
+                                    c128* u) {
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (pos >= N || r >= nrhs) return;
+    u[(size_t)r * nl * N + (size_t)m * N + perm[pos]] =
+        (active && !active[r]) ? czero<double>() : L[(size_t)r * N + pos];
+}
+
+int fail_new(StrongFactors* sf, int code, const std::string& m, std::string* msg) {
+    *msg = m;
+    delete sf;
+    return code;
+}
+
+// Alg. 2.3 in the strong format over sf->nl layers: fill(m, block) writes
+// the dense blocks of A_mm, cp (device, (nl - 1) x N, position order) holds
+// the diagonals of A_{m+1,m}.
+template <typename Fill>
+int factor_layers(StrongFactors* sf, Fill fill, const c128* cp, hipStream_t s, std::string* msg) {
+    const int nl = sf->nl, N = sf->N;
+    sf->s = s;
     hipError_t e = hipMalloc((void**)&sf->dint, 2 * sizeof(int));
     if (e == hipSuccess) e = hipMemsetAsync(sf->dint, 0, 2 * sizeof(int), s);
-    if (e != hipSuccess) {
-        *msg = std::string("strong factorization: ") + hipGetErrorString(e);
-        delete sf;
-        return e == hipErrorOutOfMemory ? HSWEEP_ENOMEM : HSWEEP_EDEVICE;
-    }
-    if (n > 1) {
-        sf->cpk = sf->keep.alloc((size_t)(n - 1) * n);
-        if (!sf->cpk) {
-            *msg = "device memory for the strong factors";
-            delete sf;
-            return HSWEEP_ENOMEM;
-        }
-        e = hipMemcpyAsync(sf->cpk, cp, (size_t)(n - 1) * n * sizeof(c128), hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) {
-            *msg = std::string("strong factorization: ") + hipGetErrorString(e);
-            delete sf;
-            return HSWEEP_EDEVICE;
-        }
+    if (e != hipSuccess)
+        return fail_new(sf, e == hipErrorOutOfMemory ? HSWEEP_ENOMEM : HSWEEP_EDEVICE,
+                        std::string("strong factorization: ") + hipGetErrorString(e), msg);
+    if (nl > 1) {
+        sf->cpk = sf->keep.alloc((size_t)(nl - 1) * N);
+        if (!sf->cpk) return fail_new(sf, HSWEEP_ENOMEM, "device memory for the strong factors", msg);
+        e = hipMemcpyAsync(sf->cpk, cp, (size_t)(nl - 1) * N * sizeof(c128), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess)
+            return fail_new(sf, HSWEEP_EDEVICE, std::string("strong factorization: ") + hipGetErrorString(e), msg);
     }
     const c128 one = mk(1.0, 0.0), mone = mk(-1.0, 0.0);
-    for (int m = 0; m < n && sf->ok(); ++m) {
-        // A_mm in the format: its tridiagonal entries all lie in dense blocks
+    for (int m = 0; m < nl && sf->ok(); ++m) {
+        // A_mm in the format: all its entries lie in dense blocks
         HMat A = sf->zeros_like(sf->shape, 0);
         for (Node& b : A.nd)
-            if (b.kind == 'D' && sf->ok())
-                hipLaunchKernelGGL(tridiag_block_kernel, grid2(b.m(), b.q()), dim3(kThreads), 0, s, b.m(), b.q(),
-                                   b.t0, b.s0, dg + (size_t)m * n, eo + (size_t)m * n, b.d);
+            if (b.kind == 'D' && sf->ok()) fill(m, b);
         HMat S;
         if (m == 0) {
             S = A;
         } else {
             // diag(a) T_{m-1} diag(a), a = diagonal of A_{m,m-1}
-            const c128* a = cp + (size_t)(m - 1) * n;
+            const c128* a = sf->cpk + (size_t)(m - 1) * N;
             HMat D = sf->T[m - 1];
             for (Node& b : D.nd) {
                 if (!sf->ok()) break;
@@ -955,28 +1045,24 @@ int strong_factor(StrongFactors** out, int n, int leaf, int rmax, double tol, ui
         if (st) { sf->fail_with(HSWEEP_ESINGULAR, "zero pivot in a dense leaf inverse (strong format)"); break; }
         sf->tmp.reset();
     }
-    (void)one;
     if (!sf->ok()) {
-        *msg = sf->err;
         const int rc = sf->rc;
-        delete sf;
-        return rc;
+        return fail_new(sf, rc, sf->err, msg);
     }
     sf->tmp.release();
-    *out = sf;
     return HSWEEP_OK;
 }
 
-// Alg. 2.4 with T_m in the strong format, for nrhs complex128 fields f -> u
-// in natural grid order (frame of sweep direction dir):
-//   w_m = T_m (f_m - a_{m-1} w_{m-1}),  u_{n-1} = w_{n-1},
+// Alg. 2.4 with T_m in the strong format for nrhs fields:
+//   w_m = T_m (f_m - a_{m-1} w_{m-1}),  u_{nl-1} = w_{nl-1},
 //   u_m = w_m - T_m (a_m u_{m+1}).
-// Inactive fields (active[r] == 0) get u = 0.
-int strong_apply(StrongFactors* sf, int dir, const c128* f, c128* u, int nrhs, const int* active, hipStream_t s,
-                 std::string* msg) {
-    const int n = sf->n;
-    const size_t lay = (size_t)n * nrhs;
-    const size_t need = lay * ((size_t)n + 2);
+// gather(m, a, Wp, L) loads layer m of f (minus a * Wp when a is given) in
+// position order, scatter(m, L) stores layer m of u.
+template <typename Gather, typename Scatter>
+int apply_layers(StrongFactors* sf, int nrhs, Gather gather, Scatter scatter, hipStream_t s, std::string* msg) {
+    const int nl = sf->nl, N = sf->N;
+    const size_t lay = (size_t)N * nrhs;
+    const size_t need = lay * ((size_t)nl + 2);
     if (need > sf->sw_count) {
         if (sf->sw) (void)hipFree(sf->sw);
         sf->sw = nullptr;
@@ -988,35 +1074,34 @@ int strong_apply(StrongFactors* sf, int dir, const c128* f, c128* u, int nrhs, c
         }
         sf->sw_count = need;
     }
-    c128* W = sf->sw;                          // w_m of the n layers, n x nrhs each
-    c128* L0 = W + lay * n;                    // the current layer's fields
+    c128* W = sf->sw;                          // w_m of every layer, N x nrhs each
+    c128* L0 = W + lay * nl;                   // the current layer's fields
     c128* L1 = L0 + lay;                       // coupled fields a_m u_{m+1}
     sf->s = s;
     sf->rc = HSWEEP_OK;
     sf->err.clear();
-    const dim3 g2 = grid2(n, nrhs);
-    for (int m = 0; m < n && sf->ok(); ++m) {
-        hipLaunchKernelGGL(gather_layer_kernel, g2, dim3(kThreads), 0, s, n, nrhs, dir, m, f,
-                           m > 0 ? sf->cpk + (size_t)(m - 1) * n : (const c128*)nullptr,
-                           m > 0 ? W + lay * (m - 1) : (const c128*)nullptr, L0);
-        sf->zero(W + lay * m, n, nrhs, n);
-        sf->matvec(sf->T[m], 0, L0, n, nrhs, W + lay * m, n, mk(1.0, 0.0));
+    const dim3 g2 = grid2(N, nrhs);
+    for (int m = 0; m < nl && sf->ok(); ++m) {
+        gather(m, m > 0 ? sf->cpk + (size_t)(m - 1) * N : (const c128*)nullptr,
+               m > 0 ? W + lay * (m - 1) : (const c128*)nullptr, L0);
+        sf->zero(W + lay * m, N, nrhs, N);
+        sf->matvec(sf->T[m], 0, L0, N, nrhs, W + lay * m, N, mk(1.0, 0.0));
         sf->tmp.reset();          // F-block scratch is reused in stream order
     }
-    for (int m = n - 1; m >= 0 && sf->ok(); --m) {
-        if (m == n - 1) {
-            hipLaunchKernelGGL(scatter_layer_kernel, g2, dim3(kThreads), 0, s, n, nrhs, dir, m, W + lay * m, active, u);
-            sf->geam(n, nrhs, mk(1.0, 0.0), 0, W + lay * m, n, czero<double>(), nullptr, 0, L0, n);
+    for (int m = nl - 1; m >= 0 && sf->ok(); --m) {
+        if (m == nl - 1) {
+            scatter(m, W + lay * m);
+            sf->geam(N, nrhs, mk(1.0, 0.0), 0, W + lay * m, N, czero<double>(), nullptr, 0, L0, N);
             continue;
         }
         // L1 = a_m * u_{m+1} (u_{m+1} in L0), L0 = w_m - T_m L1
-        hipLaunchKernelGGL(zscale_kernel, g2, dim3(kThreads), 0, s, n, nrhs, L0, n, sf->cpk + (size_t)m * n,
+        hipLaunchKernelGGL(zscale_kernel, g2, dim3(kThreads), 0, s, N, nrhs, L0, N, sf->cpk + (size_t)m * N,
                            (const c128*)nullptr);
-        sf->geam(n, nrhs, mk(1.0, 0.0), 0, L0, n, czero<double>(), nullptr, 0, L1, n);
-        sf->geam(n, nrhs, mk(1.0, 0.0), 0, W + lay * m, n, czero<double>(), nullptr, 0, L0, n);
-        sf->matvec(sf->T[m], 0, L1, n, nrhs, L0, n, mk(-1.0, 0.0));
+        sf->geam(N, nrhs, mk(1.0, 0.0), 0, L0, N, czero<double>(), nullptr, 0, L1, N);
+        sf->geam(N, nrhs, mk(1.0, 0.0), 0, W + lay * m, N, czero<double>(), nullptr, 0, L0, N);
+        sf->matvec(sf->T[m], 0, L1, N, nrhs, L0, N, mk(-1.0, 0.0));
         sf->tmp.reset();
-        hipLaunchKernelGGL(scatter_layer_kernel, g2, dim3(kThreads), 0, s, n, nrhs, dir, m, L0, active, u);
+        scatter(m, L0);
     }
     if (!sf->ok()) {
         *msg = sf->err;
@@ -1028,4 +1113,124 @@ int strong_apply(StrongFactors* sf, int dir, const c128* f, c128* u, int nrhs, c
         return HSWEEP_EDEVICE;
     }
     return HSWEEP_OK;
+}
+
+int face_depth(int n, int leaf) {
+    int Lq = 0;
+    while (((n + (1 << Lq) - 1) >> Lq) * ((n + (1 << Lq) - 1) >> Lq) > leaf) ++Lq;
+    return 2 * Lq;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- interface
+
+size_t strong_layer_depth(int n, int leaf) { return (size_t)depth_for(n, leaf); }
+size_t strong_face_depth(int n, int leaf) { return (size_t)face_depth(n, leaf); }
+
+void strong_free(StrongFactors* sf) { delete sf; }
+
+size_t strong_bytes(const StrongFactors* sf) {
+    if (!sf) return 0;
+    size_t e = 0;
+    for (const HMat& M : sf->T)
+        for (const Node& b : M.nd) {
+            if (b.kind == 'D') e += (size_t)b.m() * b.q();
+            else if (b.kind == 'F') e += (size_t)(b.m() + b.q()) * b.rank;
+        }
+    return e * sizeof(c128);
+}
+
+int strong_levels(const StrongFactors* sf) { return sf ? sf->L : 0; }
+int strong_max_rank(const StrongFactors* sf) { return sf ? sf->max_rank_seen : 0; }
+
+// 2D: the n layers of an n x n grid (frame coefficients dg, eo: n x n; cp:
+// (n-1) x n, see layer_coeffs).
+int strong_factor(StrongFactors** out, int n, int leaf, int rmax, double tol, uint64_t seed, const c128* dg,
+                  const c128* eo, const c128* cp, hipStream_t s, std::string* msg) {
+    *out = nullptr;
+    StrongFactors* sf = new StrongFactors();
+    sf->nl = n; sf->N = n; sf->side = n;
+    sf->leaf = leaf; sf->rmax = rmax; sf->tol = tol; sf->seed = seed;
+    sf->geo.face = false;
+    sf->geo.L = sf->L = depth_for(n, leaf);
+    const Cluster root{0, n, 0, n, 0, 1, 0, 0, 0};
+    build_structure(sf->shape, sf->geo, root, root, 0);
+    auto fill = [&](int m, Node& b) {
+        hipLaunchKernelGGL(tridiag_block_kernel, grid2(b.m(), b.q()), dim3(kThreads), 0, s, b.m(), b.q(), b.t0, b.s0,
+                           dg + (size_t)m * n, eo + (size_t)m * n, b.d);
+    };
+    const int rc = factor_layers(sf, fill, cp, s, msg);
+    if (rc == HSWEEP_OK) *out = sf;
+    return rc;
+}
+
+int strong_apply(StrongFactors* sf, int dir, const c128* f, c128* u, int nrhs, const int* active, hipStream_t s,
+                 std::string* msg) {
+    const int n = sf->side;
+    const dim3 g2 = grid2(n, nrhs);
+    auto gather = [&](int m, const c128* a, const c128* Wp, c128* L) {
+        hipLaunchKernelGGL(gather_layer_kernel, g2, dim3(kThreads), 0, s, n, nrhs, dir, m, f, a, Wp, L);
+    };
+    auto scatter = [&](int m, const c128* L) {
+        hipLaunchKernelGGL(scatter_layer_kernel, g2, dim3(kThreads), 0, s, n, nrhs, dir, m, L, active, u);
+    };
+    return apply_layers(sf, nrhs, gather, scatter, s, msg);
+}
+
+// 3D (Sec. 4): the n faces x3 = const of an n x n x n grid, face points in
+// quadtree bisection order.  D, X0, X1, Y0, Y1, Z0: coefficient fields of
+// the 7-point operator (n^3 each, x1 fastest, then x2, then x3; Z0 = the
+// coupling to the face below).
+int strong_factor3(StrongFactors** out, int n, int leaf, int rmax, double tol, uint64_t seed, const c128* D,
+                   const c128* X0, const c128* X1, const c128* Y0, const c128* Y1, const c128* Z0, hipStream_t s,
+                   std::string* msg) {
+    *out = nullptr;
+    StrongFactors* sf = new StrongFactors();
+    const int N = n * n;
+    sf->nl = n; sf->N = N; sf->side = n;
+    sf->leaf = leaf; sf->rmax = rmax; sf->tol = tol; sf->seed = seed;
+    sf->geo.face = true;
+    sf->geo.L = sf->L = face_depth(n, leaf);
+    const Cluster root{0, N, 0, n, 0, n, 0, 0, 0};
+    build_structure(sf->shape, sf->geo, root, root, 0);
+    std::vector<int> perm;
+    face_order(sf->geo, root, n, perm);
+    hipError_t e = hipMalloc((void**)&sf->permd, (size_t)N * sizeof(int));
+    if (e == hipSuccess) e = hipMemcpy(sf->permd, perm.data(), (size_t)N * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return fail_new(sf, e == hipErrorOutOfMemory ? HSWEEP_ENOMEM : HSWEEP_EDEVICE,
+                        std::string("strong factorization: ") + hipGetErrorString(e), msg);
+    // couplings a_m = Z0 of face m + 1, in position order
+    c128* cp = nullptr;
+    if (n > 1) {
+        e = hipMalloc((void**)&cp, (size_t)(n - 1) * N * sizeof(c128));
+        if (e != hipSuccess) return fail_new(sf, HSWEEP_ENOMEM, "device memory for the face couplings", msg);
+        hipLaunchKernelGGL(permute_rows_kernel, grid2(N, n - 1), dim3(kThreads), 0, s, n - 1, N,
+                           (const int*)sf->permd, Z0 + N, cp);
+    }
+    const int* perm_d = sf->permd;
+    auto fill = [&](int m, Node& b) {
+        const size_t o = (size_t)m * N;
+        hipLaunchKernelGGL(face_block_kernel, grid2(b.m(), b.q()), dim3(kThreads), 0, s, b.m(), b.q(), b.t0, b.s0, n,
+                           perm_d, D + o, X0 + o, X1 + o, Y0 + o, Y1 + o, b.d);
+    };
+    const int rc = factor_layers(sf, fill, cp, s, msg);
+    if (cp) (void)hipFree(cp);
+    if (rc == HSWEEP_OK) *out = sf;
+    return rc;
+}
+
+int strong_apply3(StrongFactors* sf, const c128* f, c128* u, int nrhs, const int* active, hipStream_t s,
+                  std::string* msg) {
+    const int N = sf->N, nl = sf->nl;
+    const dim3 g2 = grid2(N, nrhs);
+    const int* perm = sf->permd;
+    auto gather = [&](int m, const c128* a, const c128* Wp, c128* L) {
+        hipLaunchKernelGGL(gather_face_kernel, g2, dim3(kThreads), 0, s, N, nl, nrhs, m, perm, f, a, Wp, L);
+    };
+    auto scatter = [&](int m, const c128* L) {
+        hipLaunchKernelGGL(scatter_face_kernel, g2, dim3(kThreads), 0, s, N, nl, nrhs, m, perm, L, active, u);
+    };
+    return apply_layers(sf, nrhs, gather, scatter, s, msg);
 }

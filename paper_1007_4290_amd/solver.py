@@ -201,6 +201,99 @@ class Solver:
         return g
 
 
+class Solver3:
+    """Face-by-face sweeping-preconditioned GMRES for the 3D problem (Sec. 4).
+
+    c: velocity of shape (n, n, n), indexed [k-1, j-1, i-1] (x3, x2, x1);
+    omega: angular frequency; pml: absorbing-layer width in grid points on
+    all six sides.  Fields are complex128 CUDA tensors of shape (nrhs, n^3)
+    (or (n^3,)), x1 fastest.  Face factors are strongly admissible H-matrices
+    on quadtree face clusters: leaf (face points per leaf box), rank,
+    rank_tol; complex128.
+    """
+
+    def __init__(self, c, omega, pml, leaf=16, rank=2, rank_tol=1e-6, restart=40, pml_C=20.0):
+        lib = _lib.load()
+        if isinstance(c, torch.Tensor):
+            c_t = c.detach().to(torch.float64).contiguous()
+        else:
+            c_t = torch.as_tensor(np.ascontiguousarray(c, dtype=np.float64))
+        n = int(c_t.shape[0])
+        if c_t.dim() != 3 or tuple(c_t.shape) != (n, n, n):
+            raise ValueError("c must be a cubic (n, n, n) array")
+        self.n = n
+        self._c = c_t
+        self._ctx = ctypes.c_void_p()
+        _lib.check(lib.hsweep3_setup(ctypes.c_void_p(c_t.data_ptr()), float(omega), int(pml), n,
+                                     ctypes.byref(self._ctx)))
+        o = _lib.default_opts()
+        o.leaf, o.rank, o.rank_tol = int(leaf), int(rank), float(rank_tol)
+        o.restart, o.pml_C = int(restart), float(pml_C)
+        o.precision = _lib.C128
+        o.admissibility = _lib.ADMISSIBILITY["strong"]
+        _lib.check(lib.hsweep3_set_opts(self._ctx, ctypes.byref(o)))
+        self.factored = False
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            _lib.load().hsweep3_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _fields(self, x):
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.complex128:
+            raise TypeError("fields must be complex128 CUDA tensors")
+        single = x.dim() == 1
+        x2 = x.reshape(1, -1) if single else x.reshape(x.shape[0], -1)
+        if x2.shape[1] != self.n ** 3:
+            raise ValueError(f"each field must have n^3 = {self.n ** 3} entries")
+        return x2.contiguous(), single
+
+    def plan_info(self):
+        lev, fb = ctypes.c_int(), ctypes.c_size_t()
+        _lib.check(_lib.load().hsweep3_plan_info(self._ctx, ctypes.byref(lev), ctypes.byref(fb)))
+        return {"levels": lev.value, "factor_bytes": fb.value}
+
+    def factor(self, stream=None):
+        _lib.check(_lib.load().hsweep3_factor(self._ctx, _stream_ptr(stream)))
+        self.factored = True
+        return self
+
+    def apply(self, f, stream=None):
+        """u = M f (one face-by-face sweep)."""
+        f2, single = self._fields(f)
+        u = torch.empty_like(f2)
+        _lib.check(_lib.load().hsweep3_apply(self._ctx, ctypes.c_void_p(f2.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                             f2.shape[0], _stream_ptr(stream)))
+        return u[0] if single else u
+
+    def stencil(self, x, stream=None):
+        """y = A x with the FP64 7-point operator."""
+        x2, single = self._fields(x)
+        y = torch.empty_like(x2)
+        _lib.check(_lib.load().hsweep3_stencil(self._ctx, ctypes.c_void_p(x2.data_ptr()),
+                                               ctypes.c_void_p(y.data_ptr()), x2.shape[0], _stream_ptr(stream)))
+        return y[0] if single else y
+
+    def solve(self, f, tol=1e-6, maxit=200, stream=None):
+        """Flexible GMRES; returns (u, iterations, relative residuals)."""
+        f2, single = self._fields(f)
+        k = f2.shape[0]
+        u = torch.empty_like(f2)
+        its = (ctypes.c_int * k)()
+        res = (ctypes.c_double * k)()
+        _lib.check(_lib.load().hsweep3_solve(self._ctx, ctypes.c_void_p(f2.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                             k, float(tol), int(maxit), its, res, _stream_ptr(stream)))
+        if single:
+            return u[0], its[0], res[0]
+        return u, list(its), list(res)
+
+
 def factor_batch(solvers, stream=None):
     arr = (ctypes.c_void_p * len(solvers))(*[s._ctx.value for s in solvers])
     _lib.check(_lib.load().hsweep_factor_batch(arr, len(solvers), _stream_ptr(stream)))

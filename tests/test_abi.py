@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "hsweep.h")
 def _declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(hsweep_\w+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(hsweep3?_\w+)\s*\(", txt)))
 
 
 def test_header_declares_the_binding_symbols():
