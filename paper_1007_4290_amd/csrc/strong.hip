@@ -293,14 +293,19 @@ __global__ void zsvd_kernel(int a, int b, c128* A, int lda, c128* V, double* sig
     *rank = r;
 }
 
-// dst(:, j) = op(src(:, perm[j])) for j < k (op 0 or 2).
-__global__ void zgather_cols_kernel(int m, int k, const c128* src, int lds, const int* perm, int op, c128* dst,
-                                    int ldd) {
+// dst(:, j) = op(src(:, perm[j])) for j < *rank, 0 for *rank <= j < k
+// (op 0 or 2): the kept columns of an SVD, zero-padded to the capacity k.
+__global__ void zgather_cols_kernel(int m, int k, const c128* src, int lds, const int* perm, const int* rank, int op,
+                                    c128* dst, int ldd) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= m || j >= k) return;
-    c128 v = src[(size_t)perm[j] * lds + i];
-    dst[(size_t)j * ldd + i] = op == 2 ? conj(v) : v;
+    c128 v = czero<double>();
+    if (j < *rank) {
+        v = src[(size_t)perm[j] * lds + i];
+        if (op == 2) v = conj(v);
+    }
+    dst[(size_t)j * ldd + i] = v;
 }
 
 // Complex Gaussian entries (re + i im) / sqrt(2), re and im standard normal
@@ -558,14 +563,6 @@ struct StrongFactors {
         if (!ok() || m <= 0 || n <= 0) return;
         hipLaunchKernelGGL(zfill_kernel, grid2(m, n), dim3(kThreads), 0, s, m, n, C, ldc);
     }
-    int read_rank() {
-        if (!ok()) return 0;
-        int r = 0;
-        hipError_t e = hipMemcpyAsync(&r, dint, sizeof(int), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) { fail_with(HSWEEP_EDEVICE, std::string("strong factorization: ") + hipGetErrorString(e)); return 0; }
-        return r;
-    }
 
     // ---- structure
     HMat zeros_like(const HMat& M, int idx) {
@@ -656,15 +653,18 @@ struct StrongFactors {
         if (!ok()) return;
         hipLaunchKernelGGL(zqr_kernel, dim3(1), dim3(1), 0, s, p, k, A, lda, W, Vh, Q, R);
     }
-    // SVD of A (a x b, in place -> A V); returns the kept rank.
-    int svd(int a, int b, c128* A, int lda, c128*& V, int*& perm) {
+    // SVD of A (a x b, in place -> A V); the kept rank is written to the
+    // returned device int (never read back by the host).
+    int* svd(int a, int b, c128* A, int lda, c128*& V, int*& perm) {
         V = talloc((size_t)b * b);
         c128* sg = talloc(((size_t)b + 1) / 2 + 1);      // b doubles
         c128* pm = talloc(((size_t)b + 3) / 4 + 1);      // b ints
-        if (!ok()) return 0;
+        c128* rk = talloc(1);                            // one int
+        if (!ok()) return nullptr;
         perm = (int*)pm;
-        hipLaunchKernelGGL(zsvd_kernel, dim3(1), dim3(1), 0, s, a, b, A, lda, V, (double*)sg, perm, dint, tol, rmax);
-        return read_rank();
+        hipLaunchKernelGGL(zsvd_kernel, dim3(1), dim3(1), 0, s, a, b, A, lda, V, (double*)sg, perm, (int*)rk, tol,
+                           rmax);
+        return (int*)rk;
     }
 
     // Truncated U V^t of the m x k and q x k factors (QR of both, SVD of the
@@ -683,15 +683,19 @@ struct StrongFactors {
         gemm(0, 1, k1, k2, k, mk(1.0, 0.0), R1, k1, R2, k2, czero<double>(), C, k1);
         c128* Vs;
         int* perm;
-        const int r = svd(k1, k2, C, k1, Vs, perm);
+        const int* rk = svd(k1, k2, C, k1, Vs, perm);
+        // the kept rank stays on the device: the factors get its upper bound
+        // as their width, the columns past the rank being zero
+        const int r = std::min(std::min(k1, k2), rmax);
         if (!ok() || r == 0) return;
         c128* Cg = talloc((size_t)k1 * r);
         c128* Vg = talloc((size_t)k2 * r);
         out.u = talloc((size_t)m * r);
         out.v = talloc((size_t)q * r);
         if (!ok()) return;
-        hipLaunchKernelGGL(zgather_cols_kernel, grid2(k1, r), dim3(kThreads), 0, s, k1, r, C, k1, perm, 0, Cg, k1);
-        hipLaunchKernelGGL(zgather_cols_kernel, grid2(k2, r), dim3(kThreads), 0, s, k2, r, Vs, k2, perm, 2, Vg, k2);
+        hipLaunchKernelGGL(zgather_cols_kernel, grid2(k1, r), dim3(kThreads), 0, s, k1, r, C, k1, perm, rk, 0, Cg, k1);
+        hipLaunchKernelGGL(zgather_cols_kernel, grid2(k2, r), dim3(kThreads), 0, s, k2, r, Vs, k2, perm, rk, 2, Vg,
+                           k2);
         gemm(0, 0, m, r, k1, mk(1.0, 0.0), Q1, m, Cg, k1, czero<double>(), out.u, m);
         gemm(0, 0, q, r, k2, mk(1.0, 0.0), Q2, q, Vg, k2, czero<double>(), out.v, q);
         out.rank = r;
@@ -749,14 +753,16 @@ struct StrongFactors {
         matvec_t(H, hi, M1, mid, ell, M, q, mk(1.0, 0.0));
         c128* Vs;
         int* perm;
-        const int r = svd(q, ell, M, q, Vs, perm);
+        const int* rk = svd(q, ell, M, q, Vs, perm);
+        const int r = std::min(ell, rmax);               // width: the kept rank's bound
         if (!ok() || r == 0) return 0;
         c128* Vg = talloc((size_t)ell * r);
         Uo = talloc((size_t)m * r);
         Vo = talloc((size_t)q * r);
         if (!ok()) return 0;
-        hipLaunchKernelGGL(zgather_cols_kernel, grid2(ell, r), dim3(kThreads), 0, s, ell, r, Vs, ell, perm, 2, Vg, ell);
-        hipLaunchKernelGGL(zgather_cols_kernel, grid2(q, r), dim3(kThreads), 0, s, q, r, M, q, perm, 0, Vo, q);
+        hipLaunchKernelGGL(zgather_cols_kernel, grid2(ell, r), dim3(kThreads), 0, s, ell, r, Vs, ell, perm, rk, 2, Vg,
+                           ell);
+        hipLaunchKernelGGL(zgather_cols_kernel, grid2(q, r), dim3(kThreads), 0, s, q, r, M, q, perm, rk, 0, Vo, q);
         gemm(0, 0, m, r, ell, mk(1.0, 0.0), Q, m, Vg, ell, czero<double>(), Uo, m);
         return r;
     }
