@@ -19,7 +19,7 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhsweep.so")
 
 SOURCES = ["api.hip", "k_coeff.hip", "k_factor.hip", "k_factor_f64.hip", "k_sweep.hip", "k_sweep_a.hip",
-           "k_sweep_b.hip", "k_sweep_c.hip", "k_sweep_g4.hip", "k_krylov.hip", "strong.hip", "api3.hip", "k_coeff3.hip"]
+           "k_sweep_b.hip", "k_sweep_c.hip", "k_sweep_g4.hip", "k_krylov.hip", "strong.hip", "k_dense.hip", "api3.hip", "k_coeff3.hip"]
 
 ARCH = ["--offload-arch=gfx950"]
 FLAGS = ARCH + [

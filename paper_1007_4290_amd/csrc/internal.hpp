@@ -158,6 +158,21 @@ int krylov_dot_blocks(size_t N);
 // y = conj(x), n complex entries
 void launch_conj(const c128* x, c128* y, size_t n, hipStream_t s);
 
+// ---- small dense complex128 factorizations (k_dense.hip), one wavefront
+// per matrix, column-major, all buffers device memory ----
+// Thin QR of the p x k matrix A (leading dimension lda), kk = min(p, k):
+// Q (p x kk), R (kk x k, upper), with W (p x k) and Vh (p x kk) as work.
+void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, hipStream_t s);
+// One-sided Jacobi SVD of the a x b matrix A in place (A becomes A V), V
+// (b x b); sig (b) the column norms, perm (b) the columns by decreasing
+// norm, *rank the count above tol * sigma_max (above 0 for tol = 0), at
+// most rmax.
+void launch_small_svd(int a, int b, c128* A, int lda, c128* V, double* sig, int* perm, int* rank, double tol,
+                      int rmax, hipStream_t s);
+// X = A^{-1} (m x m) by Gauss-Jordan with partial pivoting; W holds
+// m (m + 1) entries of work; a zero pivot sets *status = 1.
+void launch_small_inv(int m, const c128* A, int lda, c128* W, c128* X, int* status, hipStream_t s);
+
 // ---- strongly admissible layer factors (complex128, strong.hip) ----
 // Factors of the n layers in the strong format from the frame coefficients
 // of layer_coeffs (dg, eo: n x n; cp: (n-1) x n, all with row stride n):

@@ -1,0 +1,330 @@
+// Small dense complex128 factorizations of the strongly admissible
+// H-arithmetic (Sec. 2.3, strongly admissible case): the thin QR and the
+// SVD of a recompression, and the inverse of a dense leaf.  One wavefront
+// of 64 lanes works on one matrix: the blocks are at most a few hundred
+// rows by a few dozen columns, and the factorization's critical path is a
+// long chain of such small operations, so what counts is the length of
+// each one's dependent chain, which the lanes shorten by splitting rows and
+// columns between them.
+//
+// Matrices are column-major with the stated leading dimensions; every
+// buffer is device memory owned by the caller.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.hpp"
+
+namespace {
+
+constexpr int kWave = 64;
+
+// Sum over all lanes; every lane gets lane 0's result (the butterfly leaves
+// results that can differ in the last bit from lane to lane, and control
+// flow that depends on them has to be uniform).
+__device__ __forceinline__ double wave_sum(double x) {
+    for (int m = kWave / 2; m > 0; m >>= 1) x += __shfl_xor(x, m);
+    return __shfl(x, 0);
+}
+__device__ __forceinline__ int wave_sum_int(int x) {
+    for (int m = kWave / 2; m > 0; m >>= 1) x += __shfl_xor(x, m);
+    return __shfl(x, 0);
+}
+
+// Sum over an aligned group of g lanes (g a power of two), the group's first
+// lane's result given to all of its lanes.
+__device__ __forceinline__ double group_sum(double x, int g) {
+    for (int m = g / 2; m > 0; m >>= 1) x += __shfl_xor(x, m);
+    return __shfl(x, (int)(threadIdx.x & ~(unsigned)(g - 1)));
+}
+
+// M(:, j) -= (2 / vv) v (v^H M(:, j)) for j in [j0, j1): the Householder
+// reflector I - 2 v v^H / vv, v zero above row c, applied to columns of the
+// p-row matrix M.  The lanes form kc column slots (kc the power of two at
+// or above the column count, at most 64) times 64 / kc row strides; a
+// column's inner product is the sum over its slot's lanes.
+__device__ void apply_reflector(int p, int c, const c128* __restrict__ v, double vv, c128* M, int j0, int j1) {
+    const int lane = threadIdx.x;
+    const double sc = 2.0 / vv;
+    for (int jb = j0; jb < j1; jb += kWave) {
+        const int nc = min(kWave, j1 - jb);
+        int kc = 1;
+        while (kc < nc) kc <<= 1;
+        const int G = kWave / kc, col = lane & (kc - 1), rg = lane / kc;
+        const bool act = col < nc;
+        c128* Mj = M + (size_t)(jb + (act ? col : 0)) * p;
+        c128 s = czero<double>();
+        if (act)
+            for (int i = c + rg; i < p; i += G) cfma_conj(s, v[i], Mj[i]);
+        for (int m = kc; m < kWave; m <<= 1) {
+            s.re += __shfl_xor(s.re, m);
+            s.im += __shfl_xor(s.im, m);
+        }
+        s.re = __shfl(s.re, col);
+        s.im = __shfl(s.im, col);
+        const c128 f = sc * s;
+        if (act)
+            for (int i = c + rg; i < p; i += G) Mj[i] -= f * v[i];
+    }
+}
+
+// Thin QR of the p x k matrix A, kk = min(p, k): Householder reflectors
+// H_c = I - 2 v v^H / (v^H v) reduce a copy W (p x k) to R, the upper
+// kk x k part of W; the reflectors are kept in Vh (p x kk) and Q = H_0 ...
+// H_{kk-1} applied to the first kk columns of the identity (p x kk).
+__global__ void __launch_bounds__(kWave) zqr_wave_kernel(int p, int k, const c128* __restrict__ A, int lda, c128* W,
+                                                         c128* Vh, c128* Q, c128* R) {
+    const int lane = threadIdx.x;
+    const int kk = min(p, k);
+    for (size_t e = lane; e < (size_t)p * k; e += kWave) {
+        const int i = (int)(e % p), j = (int)(e / p);
+        W[e] = A[(size_t)j * lda + i];
+    }
+    for (size_t e = lane; e < (size_t)p * kk; e += kWave) Vh[e] = czero<double>();
+    __syncthreads();
+    for (int c = 0; c < kk; ++c) {
+        c128* v = Vh + (size_t)c * p;
+        const c128* w = W + (size_t)c * p;
+        double part = 0.0;
+        for (int i = c + lane; i < p; i += kWave) part += abs2(w[i]);
+        const double nx = sqrt(wave_sum(part));
+        if (nx == 0.0) continue;                     // column already zero: H_c = I, v stays zero
+        const c128 x0 = w[c];
+        const double a0 = hypot(x0.re, x0.im);
+        const c128 ph = a0 > 0.0 ? mk(x0.re / a0, x0.im / a0) : mk(1.0, 0.0);
+        // v = x + ph |x| e_c maps x to -ph |x| e_c without cancellation, and
+        // v^H v = 2 |x| (|x| + |x_c|)
+        for (int i = c + lane; i < p; i += kWave) v[i] = i == c ? x0 + nx * ph : w[i];
+        const double vv = 2.0 * nx * (nx + a0);
+        __syncthreads();
+        apply_reflector(p, c, v, vv, W, c, k);
+        __syncthreads();
+    }
+    for (size_t e = lane; e < (size_t)kk * k; e += kWave) {
+        const int i = (int)(e % kk), j = (int)(e / kk);
+        R[e] = i <= j ? W[(size_t)j * p + i] : czero<double>();
+    }
+    for (size_t e = lane; e < (size_t)p * kk; e += kWave) {
+        const int i = (int)(e % p), j = (int)(e / p);
+        Q[e] = mk(i == j ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    // backward accumulation: when H_c is applied, columns j < c of Q are
+    // still e_j, zero on rows >= c, so only columns c.. change
+    for (int c = kk - 1; c >= 0; --c) {
+        const c128* v = Vh + (size_t)c * p;
+        double part = 0.0;
+        for (int i = c + lane; i < p; i += kWave) part += abs2(v[i]);
+        const double vv = wave_sum(part);
+        if (vv == 0.0) continue;
+        apply_reflector(p, c, v, vv, Q, c, kk);
+        __syncthreads();
+    }
+}
+
+// Pair kp of round r of the circle-method round robin over B (even)
+// players: player B - 1 stays, the others turn; over B - 1 rounds every
+// pair meets once and each round's pairs are disjoint.  p < q.
+__device__ __forceinline__ void round_robin_pair(int B, int r, int kp, int& p, int& q) {
+    const int n1 = B - 1;
+    if (kp == 0) {
+        p = r;
+        q = n1;
+    } else {
+        p = (r + kp) % n1;
+        q = (r - kp + n1) % n1;
+    }
+    if (p > q) { const int t = p; p = q; q = t; }
+}
+
+// One-sided Jacobi SVD of the a x b matrix A (in place, A becomes A V): each
+// round rotates a set of disjoint column pairs at once (round-robin order),
+// a group of lanes per pair; a pair is rotated unless it is orthogonal to
+// 1e-15 relative or one of its columns is below 1e-15 of the other's norm
+// (with b > a the surplus columns shrink to rounding noise).  Sweeps of all
+// pairs repeat until one rotates nothing (at most 80); a pair whose columns
+// are both below 1e-15 of the matrix's Frobenius norm is left alone.  V (b x b) is the
+// product of the rotations.  Then sigma_j = |column j|, perm lists the
+// columns by decreasing sigma (ties by index; NaN last), and *rank is the
+// number kept: sigma > tol * sigma_max (sigma > 0 when tol = 0), at most
+// rmax.
+__global__ void __launch_bounds__(kWave) zsvd_wave_kernel(int a, int b, c128* A, int lda, c128* V, double* sig,
+                                                          int* perm, int* rank, double tol, int rmax) {
+    const int lane = threadIdx.x;
+    for (size_t e = lane; e < (size_t)b * b; e += kWave) {
+        const int i = (int)(e % b), j = (int)(e / b);
+        V[e] = mk(i == j ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    // the squared Frobenius norm, which the rotations keep: pairs of columns
+    // that are both below 1e-15 of it are rounding noise and stay as they are
+    // (rotating them never converges once b > a, and their inner products
+    // reach the subnormal range, where the phase below loses its modulus 1)
+    double fro = 0.0;
+    for (size_t e = lane; e < (size_t)a * b; e += kWave) fro += abs2(A[(e / a) * lda + e % a]);
+    const double noise = 1e-30 * wave_sum(fro);
+    const int B = b + (b & 1);                       // a dummy player when b is odd
+    const int npair = B / 2;
+    int g = 1;                                       // lanes per pair
+    while (2 * g * npair <= kWave) g <<= 1;
+    const int per = kWave / g;                       // pairs per pass
+    const int gl = lane & (g - 1);
+    for (int sweep = 0; sweep < 80 && B >= 2; ++sweep) {
+        int rot = 0;
+        for (int r = 0; r < B - 1; ++r) {
+            for (int k0 = 0; k0 < npair; k0 += per) {
+                const int kp = k0 + lane / g;
+                int p = 0, q = 0;
+                if (kp < npair) round_robin_pair(B, r, kp, p, q);
+                const bool valid = kp < npair && q < b;
+                c128* x = A + (size_t)(valid ? p : 0) * lda;
+                c128* y = A + (size_t)(valid ? q : 0) * lda;
+                double al = 0.0, be = 0.0;
+                c128 ga = czero<double>();
+                if (valid)
+                    for (int i = gl; i < a; i += g) {
+                        const c128 xi = x[i], yi = y[i];
+                        al += abs2(xi);
+                        be += abs2(yi);
+                        cfma_conj(ga, xi, yi);
+                    }
+                al = group_sum(al, g);
+                be = group_sum(be, g);
+                ga.re = group_sum(ga.re, g);
+                ga.im = group_sum(ga.im, g);
+                // |ga| without squaring: a squared tiny inner product
+                // underflows, and the phase below must have modulus 1
+                const double gabs = hypot(ga.re, ga.im);
+                bool turn = valid && gabs > 1e-15 * sqrt(al) * sqrt(be);
+                if (be < 1e-30 * al || al < 1e-30 * be || (al <= noise && be <= noise)) turn = false;
+                if (turn) {
+                    if (gl == 0) ++rot;
+                    // with w = e^{-i phi} y (phi = arg ga) the pair (x, w)
+                    // has the real inner product |ga|; the real rotation that
+                    // diagonalizes [[al, |ga|], [|ga|, be]] is applied to (x, w)
+                    const c128 e = mk(ga.re / gabs, -ga.im / gabs);
+                    const double zeta = (be - al) / (2.0 * gabs);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                    for (int i = gl; i < a; i += g) {
+                        const c128 xi = x[i], wi = e * y[i];
+                        x[i] = cs * xi - sn * wi;
+                        y[i] = sn * xi + cs * wi;
+                    }
+                    c128* vx = V + (size_t)p * b;
+                    c128* vy = V + (size_t)q * b;
+                    for (int i = gl; i < b; i += g) {
+                        const c128 xi = vx[i], wi = e * vy[i];
+                        vx[i] = cs * xi - sn * wi;
+                        vy[i] = sn * xi + cs * wi;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (wave_sum_int(rot) == 0) break;
+    }
+    for (int j = lane; j < b; j += kWave) {
+        const c128* x = A + (size_t)j * lda;
+        double s0 = 0.0, s1 = 0.0;
+        int i = 0;
+        for (; i + 1 < a; i += 2) {
+            s0 += abs2(x[i]);
+            s1 += abs2(x[i + 1]);
+        }
+        if (i < a) s0 += abs2(x[i]);
+        sig[j] = sqrt(s0 + s1);
+    }
+    __syncthreads();
+    // position of column j in decreasing order: the number of columns ahead
+    // of it (larger sigma, or equal and a smaller index; NaN counts as -1,
+    // so the order is total and perm a permutation)
+    for (int j = lane; j < b; j += kWave) {
+        const double sj = isnan(sig[j]) ? -1.0 : sig[j];
+        int pos = 0;
+        for (int i = 0; i < b; ++i) {
+            const double si = isnan(sig[i]) ? -1.0 : sig[i];
+            pos += (si > sj || (si == sj && i < j)) ? 1 : 0;
+        }
+        perm[pos] = j;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        int r = 0;
+        if (b > 0 && sig[perm[0]] > 0.0) {
+            const double cut = tol > 0.0 ? tol * sig[perm[0]] : 0.0;
+            for (int j = 0; j < b; ++j) r += sig[perm[j]] > cut ? 1 : 0;
+            if (r > rmax) r = rmax;
+        }
+        *rank = r;
+    }
+}
+
+// Inverse X (m x m) of the m x m matrix A by Gauss-Jordan elimination with
+// partial pivoting (the largest modulus, the first on ties), on a copy in W
+// (m x m, followed by one column of m multipliers), the same row operations
+// applied to X = I.  A lane owns columns of [W X].  A zero pivot sets
+// *status to 1.
+__global__ void __launch_bounds__(kWave) zinv_wave_kernel(int m, const c128* __restrict__ A, int lda, c128* W,
+                                                          c128* X, int* status) {
+    const int lane = threadIdx.x;
+    c128* F = W + (size_t)m * m;
+    for (size_t e = lane; e < (size_t)m * m; e += kWave) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        W[e] = A[(size_t)j * lda + i];
+        X[e] = mk(i == j ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    for (int c = 0; c < m; ++c) {
+        double best = -1.0;
+        int p = m;
+        for (int r = c + lane; r < m; r += kWave) {
+            const double v = abs2(W[(size_t)c * m + r]);
+            if (v > best) { best = v; p = r; }
+        }
+        for (int s = kWave / 2; s > 0; s >>= 1) {
+            const double ob = __shfl_xor(best, s);
+            const int op = __shfl_xor(p, s);
+            if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
+        }
+        best = __shfl(best, 0);
+        p = __shfl(p, 0);
+        if (!(best > 0.0)) {
+            if (lane == 0) *status = 1;
+            return;
+        }
+        if (p != c)
+            for (int j = lane; j < 2 * m; j += kWave) {
+                c128* M = j < m ? W + (size_t)j * m : X + (size_t)(j - m) * m;
+                const c128 t = M[c];
+                M[c] = M[p];
+                M[p] = t;
+            }
+        __syncthreads();
+        const c128 piv = cinv(W[(size_t)c * m + c]);
+        for (int r = lane; r < m; r += kWave) F[r] = W[(size_t)c * m + r];
+        __syncthreads();
+        for (int j = lane; j < 2 * m; j += kWave) {
+            c128* M = j < m ? W + (size_t)j * m : X + (size_t)(j - m) * m;
+            const c128 t = piv * M[c];
+            M[c] = t;
+            for (int r = 0; r < m; ++r)
+                if (r != c) M[r] -= F[r] * t;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, hipStream_t s) {
+    hipLaunchKernelGGL(zqr_wave_kernel, dim3(1), dim3(kWave), 0, s, p, k, A, lda, W, Vh, Q, R);
+}
+
+void launch_small_svd(int a, int b, c128* A, int lda, c128* V, double* sig, int* perm, int* rank, double tol,
+                      int rmax, hipStream_t s) {
+    hipLaunchKernelGGL(zsvd_wave_kernel, dim3(1), dim3(kWave), 0, s, a, b, A, lda, V, sig, perm, rank, tol, rmax);
+}
+
+void launch_small_inv(int m, const c128* A, int lda, c128* W, c128* X, int* status, hipStream_t s) {
+    hipLaunchKernelGGL(zinv_wave_kernel, dim3(1), dim3(kWave), 0, s, m, A, lda, W, X, status);
+}

@@ -26,9 +26,10 @@
 //         (F = H . H) is built by the randomized range finder of Halko,
 //         Martinsson and Tropp (2011): rmax + 8 complex Gaussian test
 //         vectors, QR of the sampled range, SVD of the projected block.
-// The QR, SVD and inverse kernels take one small matrix per thread: blocks
-// are at most a few hundred entries on a side and the factorization is
-// bound by the dependent chain of the block recursion, not by arithmetic.
+// The QR, SVD and inverse kernels (k_dense.hip) take one small matrix per
+// wavefront: blocks are at most a few hundred entries on a side and the
+// factorization is bound by the dependent chain of the block recursion, not
+// by arithmetic.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -52,33 +53,6 @@ namespace {
 __device__ __forceinline__ c128 op_el(const c128* M, int op, int r, int c, int ld) {
     c128 v = (op & 1) ? M[(size_t)r * ld + c] : M[(size_t)c * ld + r];
     return (op & 2) ? conj(v) : v;
-}
-
-// sum_{i in [lo, hi)} conj(x[i]) y[i] and sum |x[i]|^2, with four partial
-// sums so that a single thread keeps four independent chains in flight.
-__device__ __forceinline__ c128 dot_conj(const c128* x, const c128* y, int lo, int hi) {
-    c128 s0 = czero<double>(), s1 = s0, s2 = s0, s3 = s0;
-    int i = lo;
-    for (; i + 3 < hi; i += 4) {
-        cfma_conj(s0, x[i], y[i]);
-        cfma_conj(s1, x[i + 1], y[i + 1]);
-        cfma_conj(s2, x[i + 2], y[i + 2]);
-        cfma_conj(s3, x[i + 3], y[i + 3]);
-    }
-    for (; i < hi; ++i) cfma_conj(s0, x[i], y[i]);
-    return (s0 + s1) + (s2 + s3);
-}
-__device__ __forceinline__ double norm2(const c128* x, int lo, int hi) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int i = lo;
-    for (; i + 3 < hi; i += 4) {
-        s0 += abs2(x[i]);
-        s1 += abs2(x[i + 1]);
-        s2 += abs2(x[i + 2]);
-        s3 += abs2(x[i + 3]);
-    }
-    for (; i < hi; ++i) s0 += abs2(x[i]);
-    return (s0 + s1) + (s2 + s3);
 }
 
 // C = alpha op(A) op(B) + beta C; C is m x n, the inner dimension k.
@@ -141,156 +115,6 @@ __global__ void tridiag_block_kernel(int m, int q, int t0, int s0, const c128* d
     else if (r == c + 1) v = eo[c];
     else if (c == r + 1) v = eo[r];
     D[(size_t)j * m + i] = v;
-}
-
-// Inverse X of one m x m matrix A (one thread): Gauss-Jordan elimination
-// with partial pivoting on a copy W, the same row operations applied to X = I.
-// A zero pivot sets *status.
-__global__ void zinv_kernel(int m, const c128* A, int lda, c128* W, c128* X, int* status) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    for (int j = 0; j < m; ++j)
-        for (int i = 0; i < m; ++i) {
-            W[(size_t)j * m + i] = A[(size_t)j * lda + i];
-            X[(size_t)j * m + i] = mk(i == j ? 1.0 : 0.0, 0.0);
-        }
-    for (int c = 0; c < m; ++c) {
-        int p = c;
-        double best = abs2(W[(size_t)c * m + c]);
-        for (int r = c + 1; r < m; ++r) {
-            const double v = abs2(W[(size_t)c * m + r]);
-            if (v > best) { best = v; p = r; }
-        }
-        if (!(best > 0.0)) { *status = 1; return; }
-        if (p != c)
-            for (int j = 0; j < m; ++j) {
-                c128 t = W[(size_t)j * m + c]; W[(size_t)j * m + c] = W[(size_t)j * m + p]; W[(size_t)j * m + p] = t;
-                t = X[(size_t)j * m + c]; X[(size_t)j * m + c] = X[(size_t)j * m + p]; X[(size_t)j * m + p] = t;
-            }
-        const c128 piv = cinv(W[(size_t)c * m + c]);
-        for (int j = 0; j < m; ++j) {
-            W[(size_t)j * m + c] = piv * W[(size_t)j * m + c];
-            X[(size_t)j * m + c] = piv * X[(size_t)j * m + c];
-        }
-        for (int r = 0; r < m; ++r) {
-            if (r == c) continue;
-            const c128 f = W[(size_t)c * m + r];
-            if (f.re == 0.0 && f.im == 0.0) continue;
-            for (int j = 0; j < m; ++j) {
-                W[(size_t)j * m + r] -= f * W[(size_t)j * m + c];
-                X[(size_t)j * m + r] -= f * X[(size_t)j * m + c];
-            }
-        }
-    }
-}
-
-// Thin QR of one p x k matrix A (one thread), kk = min(p, k): Householder
-// reflections H_c = I - 2 v v^H / (v^H v) on a copy W (p x k), reflectors
-// kept in Vh (p x kk); R = the upper kk x k part of W, Q = H_0 ... H_{kk-1}
-// applied to the first kk columns of the identity (p x kk).
-__global__ void zqr_kernel(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    const int kk = p < k ? p : k;
-    for (int j = 0; j < k; ++j)
-        for (int i = 0; i < p; ++i) W[(size_t)j * p + i] = A[(size_t)j * lda + i];
-    for (int c = 0; c < kk; ++c) {
-        c128* v = Vh + (size_t)c * p;
-        const double nx = sqrt(norm2(W + (size_t)c * p, c, p));
-        for (int i = 0; i < p; ++i) v[i] = czero<double>();
-        if (nx == 0.0) continue;                       // column already zero: H_c = I
-        const c128 x0 = W[(size_t)c * p + c];
-        const double a0 = hypot(x0.re, x0.im);
-        const c128 ph = a0 > 0.0 ? mk(x0.re / a0, x0.im / a0) : mk(1.0, 0.0);
-        // v = x + ph |x| e_c maps x to -ph |x| e_c without cancellation
-        for (int i = c; i < p; ++i) v[i] = W[(size_t)c * p + i];
-        v[c] = x0 + nx * ph;
-        const double vv = norm2(v, c, p);
-        for (int j = c; j < k; ++j) {
-            const c128 f = (2.0 / vv) * dot_conj(v, W + (size_t)j * p, c, p);
-            for (int i = c; i < p; ++i) W[(size_t)j * p + i] -= f * v[i];
-        }
-    }
-    for (int j = 0; j < k; ++j)
-        for (int i = 0; i < kk; ++i) R[(size_t)j * kk + i] = i <= j ? W[(size_t)j * p + i] : czero<double>();
-    for (int j = 0; j < kk; ++j)
-        for (int i = 0; i < p; ++i) Q[(size_t)j * p + i] = mk(i == j ? 1.0 : 0.0, 0.0);
-    for (int c = kk - 1; c >= 0; --c) {
-        const c128* v = Vh + (size_t)c * p;
-        const double vv = norm2(v, c, p);
-        if (vv == 0.0) continue;
-        for (int j = 0; j < kk; ++j) {
-            const c128 f = (2.0 / vv) * dot_conj(v, Q + (size_t)j * p, c, p);
-            for (int i = c; i < p; ++i) Q[(size_t)j * p + i] -= f * v[i];
-        }
-    }
-}
-
-// One-sided Jacobi SVD of one a x b matrix (one thread): rotations of column
-// pairs of A (in place, A becomes A V) until every pair is orthogonal to
-// 1e-15 relative or one column of the pair is below 1e-15 of the other (with
-// b > a the surplus columns shrink to rounding noise), V (b x b) the product
-// of the rotations.  Then sigma_j =
-// |column j|, perm lists the columns by decreasing sigma, and *rank is the
-// number kept: sigma > tol * sigma_max (sigma > 0 when tol = 0), at most rmax.
-__global__ void zsvd_kernel(int a, int b, c128* A, int lda, c128* V, double* sig, int* perm, int* rank, double tol,
-                            int rmax) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    for (int j = 0; j < b; ++j)
-        for (int i = 0; i < b; ++i) V[(size_t)j * b + i] = mk(i == j ? 1.0 : 0.0, 0.0);
-    for (int sweep = 0; sweep < 80; ++sweep) {
-        bool rotated = false;
-        for (int p = 0; p < b - 1; ++p)
-            for (int q = p + 1; q < b; ++q) {
-                c128* x = A + (size_t)p * lda;
-                c128* y = A + (size_t)q * lda;
-                const double al = norm2(x, 0, a), be = norm2(y, 0, a);
-                const c128 ga = dot_conj(x, y, 0, a);
-                // |ga| without squaring (a square of a tiny inner product
-                // underflows, and the phase e below must have modulus 1 for
-                // the rotation to stay unitary); a column below 1e-15 of the
-                // other's norm is rounding noise next to it and is left alone
-                const double g = hypot(ga.re, ga.im);
-                if (!(g > 1e-15 * sqrt(al) * sqrt(be))) continue;
-                if (be < 1e-30 * al || al < 1e-30 * be) continue;
-                rotated = true;
-                // with w = e^{-i phi} y (phi = arg ga) the pair (x, w) has the
-                // real inner product g; the real rotation that diagonalizes
-                // [[al, g], [g, be]] is applied to (x, w)
-                const c128 e = mk(ga.re / g, -ga.im / g);
-                const double zeta = (be - al) / (2.0 * g);
-                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-                for (int i = 0; i < a; ++i) {
-                    const c128 xi = x[i], wi = e * y[i];
-                    x[i] = cs * xi - sn * wi;
-                    y[i] = sn * xi + cs * wi;
-                }
-                c128* vx = V + (size_t)p * b;
-                c128* vy = V + (size_t)q * b;
-                for (int i = 0; i < b; ++i) {
-                    const c128 xi = vx[i], wi = e * vy[i];
-                    vx[i] = cs * xi - sn * wi;
-                    vy[i] = sn * xi + cs * wi;
-                }
-            }
-        if (!rotated) break;
-    }
-    for (int j = 0; j < b; ++j) {
-        sig[j] = sqrt(norm2(A + (size_t)j * lda, 0, a));
-        perm[j] = j;
-    }
-    for (int i = 0; i < b; ++i) {               // selection sort, decreasing
-        int best = i;
-        for (int j = i + 1; j < b; ++j)
-            if (sig[perm[j]] > sig[perm[best]]) best = j;
-        const int t = perm[i]; perm[i] = perm[best]; perm[best] = t;
-    }
-    int r = 0;
-    if (b > 0 && sig[perm[0]] > 0.0) {
-        const double cut = tol > 0.0 ? tol * sig[perm[0]] : 0.0;
-        for (int j = 0; j < b; ++j) r += sig[perm[j]] > cut ? 1 : 0;
-        if (r > rmax) r = rmax;
-    }
-    *rank = r;
 }
 
 // dst(:, j) = op(src(:, perm[j])) for j < *rank, 0 for *rank <= j < k
@@ -651,7 +475,7 @@ struct StrongFactors {
         Q = talloc((size_t)p * kk);
         R = talloc((size_t)kk * k);
         if (!ok()) return;
-        hipLaunchKernelGGL(zqr_kernel, dim3(1), dim3(1), 0, s, p, k, A, lda, W, Vh, Q, R);
+        launch_small_qr(p, k, A, lda, W, Vh, Q, R, s);
     }
     // SVD of A (a x b, in place -> A V); the kept rank is written to the
     // returned device int (never read back by the host).
@@ -662,8 +486,7 @@ struct StrongFactors {
         c128* rk = talloc(1);                            // one int
         if (!ok()) return nullptr;
         perm = (int*)pm;
-        hipLaunchKernelGGL(zsvd_kernel, dim3(1), dim3(1), 0, s, a, b, A, lda, V, (double*)sg, perm, (int*)rk, tol,
-                           rmax);
+        launch_small_svd(a, b, A, lda, V, (double*)sg, perm, (int*)rk, tol, rmax, s);
         return (int*)rk;
     }
 
@@ -859,10 +682,9 @@ struct StrongFactors {
         if (g.kind == 'D') {
             Node out = g;
             const int m = g.m();
-            c128* Wk = talloc((size_t)m * m);
+            c128* Wk = talloc((size_t)m * (m + 1));
             out.d = talloc((size_t)m * m);
-            if (ok())
-                hipLaunchKernelGGL(zinv_kernel, dim3(1), dim3(1), 0, s, m, g.d, m, Wk, out.d, dint + 1);
+            if (ok()) launch_small_inv(m, g.d, m, Wk, out.d, dint + 1, s);
             R.nd.push_back(out);
             return R;
         }

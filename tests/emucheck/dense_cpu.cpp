@@ -1,0 +1,149 @@
+// CPU stand-ins of the small dense launchers (k_dense.hip) for the
+// sequential kernel emulation, which runs each kernel once per thread index
+// and cannot run the wavefront kernels' cross-lane exchanges and barriers
+// (those are checked on their own by tests/wavecheck).  Same contracts,
+// plain loops: Householder QR, cyclic one-sided Jacobi SVD, Gauss-Jordan.
+#include <math.h>
+#include "internal.hpp"
+
+void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, hipStream_t) {
+    const int kk = p < k ? p : k;
+    for (int j = 0; j < k; ++j)
+        for (int i = 0; i < p; ++i) W[(size_t)j * p + i] = A[(size_t)j * lda + i];
+    for (size_t e = 0; e < (size_t)p * kk; ++e) Vh[e] = czero<double>();
+    for (int c = 0; c < kk; ++c) {
+        c128* v = Vh + (size_t)c * p;
+        double nx2 = 0.0;
+        for (int i = c; i < p; ++i) nx2 += abs2(W[(size_t)c * p + i]);
+        const double nx = sqrt(nx2);
+        if (nx == 0.0) continue;
+        const c128 x0 = W[(size_t)c * p + c];
+        const double a0 = hypot(x0.re, x0.im);
+        const c128 ph = a0 > 0.0 ? mk(x0.re / a0, x0.im / a0) : mk(1.0, 0.0);
+        for (int i = c; i < p; ++i) v[i] = W[(size_t)c * p + i];
+        v[c] = x0 + nx * ph;
+        double vv = 0.0;
+        for (int i = c; i < p; ++i) vv += abs2(v[i]);
+        for (int j = c; j < k; ++j) {
+            c128 d = czero<double>();
+            for (int i = c; i < p; ++i) cfma_conj(d, v[i], W[(size_t)j * p + i]);
+            const c128 f = (2.0 / vv) * d;
+            for (int i = c; i < p; ++i) W[(size_t)j * p + i] -= f * v[i];
+        }
+    }
+    for (int j = 0; j < k; ++j)
+        for (int i = 0; i < kk; ++i) R[(size_t)j * kk + i] = i <= j ? W[(size_t)j * p + i] : czero<double>();
+    for (int j = 0; j < kk; ++j)
+        for (int i = 0; i < p; ++i) Q[(size_t)j * p + i] = mk(i == j ? 1.0 : 0.0, 0.0);
+    for (int c = kk - 1; c >= 0; --c) {
+        const c128* v = Vh + (size_t)c * p;
+        double vv = 0.0;
+        for (int i = c; i < p; ++i) vv += abs2(v[i]);
+        if (vv == 0.0) continue;
+        for (int j = c; j < kk; ++j) {
+            c128 d = czero<double>();
+            for (int i = c; i < p; ++i) cfma_conj(d, v[i], Q[(size_t)j * p + i]);
+            const c128 f = (2.0 / vv) * d;
+            for (int i = c; i < p; ++i) Q[(size_t)j * p + i] -= f * v[i];
+        }
+    }
+}
+
+void launch_small_svd(int a, int b, c128* A, int lda, c128* V, double* sig, int* perm, int* rank, double tol,
+                      int rmax, hipStream_t) {
+    for (int j = 0; j < b; ++j)
+        for (int i = 0; i < b; ++i) V[(size_t)j * b + i] = mk(i == j ? 1.0 : 0.0, 0.0);
+    double fro = 0.0;
+    for (int j = 0; j < b; ++j)
+        for (int i = 0; i < a; ++i) fro += abs2(A[(size_t)j * lda + i]);
+    const double noise = 1e-30 * fro;
+    for (int sweep = 0; sweep < 80; ++sweep) {
+        bool rotated = false;
+        for (int p = 0; p < b - 1; ++p)
+            for (int q = p + 1; q < b; ++q) {
+                c128* x = A + (size_t)p * lda;
+                c128* y = A + (size_t)q * lda;
+                double al = 0.0, be = 0.0;
+                c128 ga = czero<double>();
+                for (int i = 0; i < a; ++i) {
+                    al += abs2(x[i]);
+                    be += abs2(y[i]);
+                    cfma_conj(ga, x[i], y[i]);
+                }
+                const double g = hypot(ga.re, ga.im);
+                if (!(g > 1e-15 * sqrt(al) * sqrt(be))) continue;
+                if (be < 1e-30 * al || al < 1e-30 * be || (al <= noise && be <= noise)) continue;
+                rotated = true;
+                const c128 e = mk(ga.re / g, -ga.im / g);
+                const double zeta = (be - al) / (2.0 * g);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                for (int i = 0; i < a; ++i) {
+                    const c128 xi = x[i], wi = e * y[i];
+                    x[i] = cs * xi - sn * wi;
+                    y[i] = sn * xi + cs * wi;
+                }
+                c128* vx = V + (size_t)p * b;
+                c128* vy = V + (size_t)q * b;
+                for (int i = 0; i < b; ++i) {
+                    const c128 xi = vx[i], wi = e * vy[i];
+                    vx[i] = cs * xi - sn * wi;
+                    vy[i] = sn * xi + cs * wi;
+                }
+            }
+        if (!rotated) break;
+    }
+    for (int j = 0; j < b; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < a; ++i) s += abs2(A[(size_t)j * lda + i]);
+        sig[j] = sqrt(s);
+    }
+    for (int j = 0; j < b; ++j) {
+        const double sj = isnan(sig[j]) ? -1.0 : sig[j];
+        int pos = 0;
+        for (int i = 0; i < b; ++i) {
+            const double si = isnan(sig[i]) ? -1.0 : sig[i];
+            pos += (si > sj || (si == sj && i < j)) ? 1 : 0;
+        }
+        perm[pos] = j;
+    }
+    int r = 0;
+    if (b > 0 && sig[perm[0]] > 0.0) {
+        const double cut = tol > 0.0 ? tol * sig[perm[0]] : 0.0;
+        for (int j = 0; j < b; ++j) r += sig[perm[j]] > cut ? 1 : 0;
+        if (r > rmax) r = rmax;
+    }
+    *rank = r;
+}
+
+void launch_small_inv(int m, const c128* A, int lda, c128* W, c128* X, int* status, hipStream_t) {
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) {
+            W[(size_t)j * m + i] = A[(size_t)j * lda + i];
+            X[(size_t)j * m + i] = mk(i == j ? 1.0 : 0.0, 0.0);
+        }
+    for (int c = 0; c < m; ++c) {
+        int p = c;
+        double best = abs2(W[(size_t)c * m + c]);
+        for (int r = c + 1; r < m; ++r)
+            if (abs2(W[(size_t)c * m + r]) > best) { best = abs2(W[(size_t)c * m + r]); p = r; }
+        if (!(best > 0.0)) { *status = 1; return; }
+        for (int j = 0; j < m && p != c; ++j) {
+            c128 t = W[(size_t)j * m + c]; W[(size_t)j * m + c] = W[(size_t)j * m + p]; W[(size_t)j * m + p] = t;
+            t = X[(size_t)j * m + c]; X[(size_t)j * m + c] = X[(size_t)j * m + p]; X[(size_t)j * m + p] = t;
+        }
+        const c128 piv = cinv(W[(size_t)c * m + c]);
+        for (int j = 0; j < m; ++j) {
+            W[(size_t)j * m + c] = piv * W[(size_t)j * m + c];
+            X[(size_t)j * m + c] = piv * X[(size_t)j * m + c];
+        }
+        for (int r = 0; r < m; ++r) {
+            if (r == c) continue;
+            const c128 f = W[(size_t)c * m + r];
+            for (int j = 0; j < m; ++j) {
+                W[(size_t)j * m + r] -= f * W[(size_t)j * m + c];
+                X[(size_t)j * m + r] -= f * X[(size_t)j * m + c];
+            }
+        }
+    }
+}

@@ -147,3 +147,19 @@ void launch_combine(const c128* Z, int nz, size_t ld, const c128* y, c128* x, co
     need(y, nz * S * 16, "combine y"); need(x, off[S] * 16, "combine x");
 }
 int multi_launches() { return g_multi; }
+void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, hipStream_t) {
+    const int kk = p < k ? p : k;
+    if (k > 0) need(A, ((size_t)(k - 1) * lda + p) * 16, "qr A");
+    need(W, (size_t)p * k * 16, "qr W"); need(Vh, (size_t)p * kk * 16, "qr Vh");
+    need(Q, (size_t)p * kk * 16, "qr Q"); need(R, (size_t)kk * k * 16, "qr R");
+}
+void launch_small_svd(int a, int b, c128* A, int lda, c128* V, double* sig, int* perm, int* rank, double, int,
+                      hipStream_t) {
+    if (b > 0) need(A, ((size_t)(b - 1) * lda + a) * 16, "svd A");
+    need(V, (size_t)b * b * 16, "svd V"); need(sig, (size_t)b * 8, "svd sig"); need(perm, (size_t)b * 4, "svd perm");
+    need(rank, 4, "svd rank");
+}
+void launch_small_inv(int m, const c128* A, int lda, c128* W, c128* X, int* status, hipStream_t) {
+    if (m > 0) need(A, ((size_t)(m - 1) * lda + m) * 16, "inv A");
+    need(W, (size_t)m * (m + 1) * 16, "inv W"); need(X, (size_t)m * m * 16, "inv X"); need(status, 4, "inv status");
+}

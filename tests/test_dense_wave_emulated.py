@@ -1,0 +1,141 @@
+"""The small dense factorizations of the strongly admissible H-arithmetic
+(k_dense.hip: thin QR, one-sided Jacobi SVD, Gauss-Jordan inverse), one
+wavefront of 64 lanes per matrix, run on the CPU: the kernels are compiled
+with g++ against a stand-in of the HIP runtime that runs each lane as a
+thread with a real barrier and real shuffles (tests/wavecheck), under the
+address and undefined-behaviour sanitizers, with device allocations
+starting as NaN bytes.
+
+Each result is checked against what defines it, with numpy for reference
+values: Q R = A with Q orthonormal and R upper triangular; A V with V unitary
+and mutually orthogonal columns whose norms are A's singular values, the
+permutation sorting them, the kept count as specified; A X = I.  The shapes
+cover one and several passes of the column and pair loops, more columns than
+rows, zero columns (the zero-padded factor widths), odd and even column
+counts and a singular leaf.
+"""
+import os
+import shutil
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1007_4290_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def wave(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("wave") / "wave")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-pthread",
+           "-I", os.path.join(ROOT, "tests", "wavecheck"), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           "-x", "c++", os.path.join(CSRC, "k_dense.hip"), "-x", "none",
+           os.path.join(ROOT, "tests", "hostcheck", "fake_runtime.cpp"),
+           os.path.join(ROOT, "tests", "wavecheck", "main.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    return exe
+
+
+def _run(exe, tmp_path, op, A, rows, cols, rmax=0, tol=0.0):
+    lda = A.shape[0]
+    fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    with open(fin, "wb") as fp:
+        fp.write(struct.pack("5i", op, rows, cols, lda, rmax))
+        fp.write(struct.pack("d", tol))
+        fp.write(np.asfortranarray(A, dtype=np.complex128).tobytes(order="F"))
+    r = subprocess.run([exe, fin, fout], capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    return open(fout, "rb").read()
+
+
+def _mat(buf, off, rows, cols):
+    n = rows * cols
+    M = np.frombuffer(buf, dtype=np.complex128, count=n, offset=off).reshape(cols, rows).T
+    return M, off + 16 * n
+
+
+def _rand(rng, m, n):
+    return rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+
+
+QR_CASES = [(1, 1), (5, 3), (3, 5), (64, 10), (130, 7), (20, 70), (33, 33), (200, 2)]
+
+
+@pytest.mark.parametrize("p, k", QR_CASES)
+def test_qr(wave, tmp_path, p, k):
+    rng = np.random.default_rng(100 + p + 7 * k)
+    A = _rand(rng, p + 3, k)                      # leading dimension p + 3
+    if k >= 4:
+        A[:, 1] = 0.0                             # a zero column
+        A[:, 3] = 2.0 * A[:, 2]                   # a dependent one
+    out = _run(wave, tmp_path, 0, A, p, k)
+    kk = min(p, k)
+    Q, off = _mat(out, 0, p, kk)
+    R, _ = _mat(out, off, kk, k)
+    a = A[:p]
+    assert np.allclose(Q.conj().T @ Q, np.eye(kk), atol=1e-13)
+    assert np.allclose(np.tril(R, -1), 0.0)
+    assert np.linalg.norm(Q @ R - a) <= 1e-13 * max(np.linalg.norm(a), 1.0)
+
+
+SVD_CASES = [(1, 1), (4, 2), (6, 9), (20, 11), (12, 12), (3, 40), (10, 130), (70, 5)]
+
+
+@pytest.mark.parametrize("a, b", SVD_CASES)
+def test_svd(wave, tmp_path, a, b):
+    rng = np.random.default_rng(200 + a + 3 * b)
+    A = _rand(rng, a + 2, b)
+    if b >= 3:
+        A[:, b - 1] = 0.0                         # a zero column
+    tol, rmax = 1e-6, max(1, min(a, b) - 1)
+    out = _run(wave, tmp_path, 1, A, a, b, rmax=rmax, tol=tol)
+    AV, off = _mat(out, 0, a + 2, b)
+    V, off = _mat(out, off, b, b)
+    sig = np.frombuffer(out, dtype=np.float64, count=b, offset=off)
+    off += 8 * b
+    perm = np.frombuffer(out, dtype=np.int32, count=b, offset=off)
+    off += 4 * b
+    rank = struct.unpack_from("i", out, off)[0]
+    a0 = A[:a]
+    assert np.allclose(AV[a:], A[a:]), "rows past the matrix were written"
+    assert np.allclose(V.conj().T @ V, np.eye(b), atol=1e-12)
+    assert np.linalg.norm(a0 @ V - AV[:a]) <= 1e-12 * np.linalg.norm(a0)
+    G = AV[:a].conj().T @ AV[:a]
+    nrm = np.sqrt(np.abs(np.diag(G)))
+    off_diag = np.abs(G - np.diag(np.diag(G)))
+    assert np.all(off_diag <= 1e-12 * np.outer(nrm, nrm) + 1e-13 * nrm.max() ** 2)
+    assert np.allclose(sig, nrm, rtol=1e-13, atol=1e-14 * nrm.max())
+    assert sorted(perm.tolist()) == list(range(b))
+    assert np.all(np.diff(sig[perm]) <= 0.0)
+    ref = np.linalg.svd(a0, compute_uv=False)
+    assert np.allclose(sig[perm][:len(ref)], ref, rtol=1e-11, atol=1e-13 * ref[0])
+    assert np.all(sig[perm][len(ref):] <= 1e-13 * ref[0])
+    want = min(int(np.sum(sig > tol * sig.max())), rmax)
+    assert rank == want
+
+
+@pytest.mark.parametrize("m", [1, 2, 7, 16, 33, 40])
+def test_inverse(wave, tmp_path, m):
+    rng = np.random.default_rng(300 + m)
+    A = _rand(rng, m + 1, m)
+    if m >= 2:
+        A[0, 0] = 0.0                             # needs a row exchange
+    out = _run(wave, tmp_path, 2, A, m, m)
+    X, off = _mat(out, 0, m, m)
+    st = struct.unpack_from("i", out, off)[0]
+    assert st == 0
+    assert np.linalg.norm(A[:m] @ X - np.eye(m)) <= 1e-11 * np.linalg.cond(A[:m])
+
+
+def test_inverse_of_a_singular_leaf_sets_the_status(wave, tmp_path):
+    rng = np.random.default_rng(7)
+    A = _rand(rng, 6, 6)
+    A[:, 4] = 0.0
+    out = _run(wave, tmp_path, 2, A, 6, 6)
+    assert struct.unpack_from("i", out, 16 * 36)[0] == 1

@@ -36,7 +36,7 @@ def emu3(tmp_path_factory):
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
            "-I", EMU, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-x", "c++", *srcs, "-x", "none",
            os.path.join(HC, "fake_runtime.cpp"), os.path.join(EMU, "emu_state.cpp"),
-           os.path.join(EMU, "cpu_kernels.cpp"), os.path.join(EMU, "main3.cpp"), "-o", exe]
+           os.path.join(EMU, "cpu_kernels.cpp"), os.path.join(EMU, "dense_cpu.cpp"), os.path.join(EMU, "main3.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     return exe

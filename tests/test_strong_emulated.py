@@ -38,7 +38,7 @@ def emu(tmp_path_factory):
            "-x", "c++", os.path.join(CSRC, "api.hip"), os.path.join(CSRC, "k_coeff.hip"),
            os.path.join(CSRC, "strong.hip"), "-x", "none",
            os.path.join(HC, "fake_runtime.cpp"), os.path.join(EMU, "emu_state.cpp"),
-           os.path.join(EMU, "cpu_kernels.cpp"), os.path.join(EMU, "main.cpp"), "-o", exe]
+           os.path.join(EMU, "cpu_kernels.cpp"), os.path.join(EMU, "dense_cpu.cpp"), os.path.join(EMU, "main.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     return exe
