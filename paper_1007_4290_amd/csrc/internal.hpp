@@ -172,6 +172,49 @@ void launch_small_svd(int a, int b, c128* A, int lda, c128* V, double* sig, int*
 // X = A^{-1} (m x m) by Gauss-Jordan with partial pivoting; W holds
 // m (m + 1) entries of work; a zero pivot sets *status = 1.
 void launch_small_inv(int m, const c128* A, int lda, c128* W, c128* X, int* status, hipStream_t s);
+// Work layout of a recompression of m x k and q x k factors (offsets in
+// complex128 entries, each piece on a 256-byte boundary): the two QRs
+// (W, Vh, Q, R), the core C and its SVD (Vs, sigma, perm, rank), the kept
+// columns Cg and Vg.
+struct RecompressLayout {
+    size_t W1, Vh1, Q1, R1, W2, Vh2, Q2, R2, C, Vs, sig, perm, rank, Cg, Vg, total;
+};
+__host__ __device__ inline RecompressLayout recompress_layout(int m, int q, int k, int rmax) {
+    const int kk1 = m < k ? m : k, kk2 = q < k ? q : k;
+    const int r0 = kk1 < kk2 ? kk1 : kk2, r = r0 < rmax ? r0 : rmax;
+    RecompressLayout L;
+    size_t o = 0;
+    auto take = [&o](size_t n) {
+        const size_t at = o;
+        o += (n + 15) & ~(size_t)15;
+        return at;
+    };
+    L.W1 = take((size_t)m * k);
+    L.Vh1 = take((size_t)m * kk1);
+    L.Q1 = take((size_t)m * kk1);
+    L.R1 = take((size_t)kk1 * k);
+    L.W2 = take((size_t)q * k);
+    L.Vh2 = take((size_t)q * kk2);
+    L.Q2 = take((size_t)q * kk2);
+    L.R2 = take((size_t)kk2 * k);
+    L.C = take((size_t)kk1 * kk2);
+    L.Vs = take((size_t)kk2 * kk2);
+    L.sig = take(((size_t)kk2 + 1) / 2);
+    L.perm = take(((size_t)kk2 + 3) / 4);
+    L.rank = take(1);
+    L.Cg = take((size_t)kk1 * r);
+    L.Vg = take((size_t)kk2 * r);
+    L.total = o;
+    return L;
+}
+// The truncated product of [au, alpha U] (m x k1 + k2) and [av, V] (q x k1 +
+// k2) as ou (m x r) and ov (q x r), r = min(m, q, k1 + k2, rmax), the
+// columns past the kept rank (singular values above tol * sigma_1, at most
+// rmax) zero; work holds recompress_layout(m, q, k1 + k2, rmax).total
+// entries.  au, av have leading dimensions m and q.
+void launch_small_recompress(int m, int q, int k1, int k2, int rmax, double tol, c128 alpha, const c128* au,
+                             const c128* av, const c128* U, int ldu, const c128* V, int ldv, c128* work, c128* ou,
+                             c128* ov, hipStream_t s);
 
 // ---- strongly admissible layer factors (complex128, strong.hip) ----
 // Factors of the n layers in the strong format from the frame coefficients

@@ -17,6 +17,18 @@
 namespace {
 
 constexpr int kWave = 64;
+// A kernel whose working set fits in this much shared memory (LDS) works
+// there, the inputs copied in and the results out; a larger one works in
+// the caller's device buffers.
+constexpr size_t kLdsBytes = 64 * 1024;
+
+// Copy of an m x n column-major block between leading dimensions.
+__device__ __forceinline__ void wave_copy(int m, int n, const c128* src, int lds_, c128* dst, int ldd) {
+    for (size_t e = threadIdx.x; e < (size_t)m * n; e += kWave) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        dst[(size_t)j * ldd + i] = src[(size_t)j * lds_ + i];
+    }
+}
 
 // Sum over all lanes; every lane gets lane 0's result (the butterfly leaves
 // results that can differ in the last bit from lane to lane, and control
@@ -71,14 +83,10 @@ __device__ void apply_reflector(int p, int c, const c128* __restrict__ v, double
 // H_c = I - 2 v v^H / (v^H v) reduce a copy W (p x k) to R, the upper
 // kk x k part of W; the reflectors are kept in Vh (p x kk) and Q = H_0 ...
 // H_{kk-1} applied to the first kk columns of the identity (p x kk).
-__global__ void __launch_bounds__(kWave) zqr_wave_kernel(int p, int k, const c128* __restrict__ A, int lda, c128* W,
-                                                         c128* Vh, c128* Q, c128* R) {
+// The matrix is in W on entry (overwritten); ends after a barrier.
+__device__ void wave_qr(int p, int k, c128* W, c128* Vh, c128* Q, c128* R) {
     const int lane = threadIdx.x;
     const int kk = min(p, k);
-    for (size_t e = lane; e < (size_t)p * k; e += kWave) {
-        const int i = (int)(e % p), j = (int)(e / p);
-        W[e] = A[(size_t)j * lda + i];
-    }
     for (size_t e = lane; e < (size_t)p * kk; e += kWave) Vh[e] = czero<double>();
     __syncthreads();
     for (int c = 0; c < kk; ++c) {
@@ -119,6 +127,27 @@ __global__ void __launch_bounds__(kWave) zqr_wave_kernel(int p, int k, const c12
         apply_reflector(p, c, v, vv, Q, c, kk);
         __syncthreads();
     }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kWave) zqr_wave_kernel(int p, int k, const c128* __restrict__ A, int lda, c128* W,
+                                                         c128* Vh, c128* Q, c128* R, int staged) {
+    HIP_DYNAMIC_SHARED(c128, lds)
+    const int kk = min(p, k);
+    c128 *w = W, *vh = Vh, *q = Q, *r = R;
+    if (staged) {
+        w = lds;
+        vh = w + (size_t)p * k;
+        q = vh + (size_t)p * kk;
+        r = q + (size_t)p * kk;
+    }
+    wave_copy(p, k, A, lda, w, p);
+    __syncthreads();
+    wave_qr(p, k, w, vh, q, r);
+    if (staged) {
+        wave_copy(p, kk, q, p, Q, p);
+        wave_copy(kk, k, r, kk, R, kk);
+    }
 }
 
 // Pair kp of round r of the circle-method round robin over B (even)
@@ -147,8 +176,9 @@ __device__ __forceinline__ void round_robin_pair(int B, int r, int kp, int& p, i
 // columns by decreasing sigma (ties by index; NaN last), and *rank is the
 // number kept: sigma > tol * sigma_max (sigma > 0 when tol = 0), at most
 // rmax.
-__global__ void __launch_bounds__(kWave) zsvd_wave_kernel(int a, int b, c128* A, int lda, c128* V, double* sig,
-                                                          int* perm, int* rank, double tol, int rmax) {
+// Ends after a barrier, *rank written.
+__device__ void wave_svd(int a, int b, c128* A, int lda, c128* V, double* sig, int* perm, int* rank, double tol,
+                         int rmax) {
     const int lane = threadIdx.x;
     for (size_t e = lane; e < (size_t)b * b; e += kWave) {
         const int i = (int)(e % b), j = (int)(e / b);
@@ -257,6 +287,31 @@ __global__ void __launch_bounds__(kWave) zsvd_wave_kernel(int a, int b, c128* A,
         }
         *rank = r;
     }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kWave) zsvd_wave_kernel(int a, int b, c128* A, int lda, c128* V, double* sig,
+                                                          int* perm, int* rank, double tol, int rmax, int staged) {
+    HIP_DYNAMIC_SHARED(c128, lds)
+    if (!staged) {
+        wave_svd(a, b, A, lda, V, sig, perm, rank, tol, rmax);
+        return;
+    }
+    c128* As = lds;
+    c128* Vs = As + (size_t)a * b;
+    double* sg = (double*)(Vs + (size_t)b * b);
+    int* pm = (int*)(sg + b);
+    int* rk = pm + b;
+    wave_copy(a, b, A, lda, As, a);
+    __syncthreads();
+    wave_svd(a, b, As, a, Vs, sg, pm, rk, tol, rmax);
+    wave_copy(a, b, As, a, A, lda);
+    wave_copy(b, b, Vs, b, V, b);
+    for (int j = threadIdx.x; j < b; j += kWave) {
+        sig[j] = sg[j];
+        perm[j] = pm[j];
+    }
+    if (threadIdx.x == 0) *rank = *rk;
 }
 
 // Inverse X (m x m) of the m x m matrix A by Gauss-Jordan elimination with
@@ -264,9 +319,12 @@ __global__ void __launch_bounds__(kWave) zsvd_wave_kernel(int a, int b, c128* A,
 // (m x m, followed by one column of m multipliers), the same row operations
 // applied to X = I.  A lane owns columns of [W X].  A zero pivot sets
 // *status to 1.
-__global__ void __launch_bounds__(kWave) zinv_wave_kernel(int m, const c128* __restrict__ A, int lda, c128* W,
-                                                          c128* X, int* status) {
+__global__ void __launch_bounds__(kWave) zinv_wave_kernel(int m, const c128* __restrict__ A, int lda, c128* Wg,
+                                                          c128* Xg, int* status, int staged) {
+    HIP_DYNAMIC_SHARED(c128, lds)
     const int lane = threadIdx.x;
+    c128* W = staged ? lds : Wg;
+    c128* X = staged ? lds + (size_t)m * (m + 1) : Xg;
     c128* F = W + (size_t)m * m;
     for (size_t e = lane; e < (size_t)m * m; e += kWave) {
         const int i = (int)(e % m), j = (int)(e / m);
@@ -312,19 +370,102 @@ __global__ void __launch_bounds__(kWave) zinv_wave_kernel(int m, const c128* __r
         }
         __syncthreads();
     }
+    if (staged) wave_copy(m, m, X, m, Xg, m);
+}
+
+// The truncated product of [au, alpha U] (m x k) and [av, V] (q x k), k =
+// k1 + k2: QR of both stacked factors, SVD of the core C = R1 R2^t, and the
+// factors ou = Q1 (C V)_r (m x r) and ov = Q2 conj(V_r) (q x r), r = min(m,
+// q, k, rmax) columns of which those past the kept rank are zero.
+__global__ void __launch_bounds__(kWave) zrecompress_wave_kernel(int m, int q, int k1, int k2, int rmax, double tol,
+                                                                 c128 alpha, const c128* __restrict__ au,
+                                                                 const c128* __restrict__ av,
+                                                                 const c128* __restrict__ U, int ldu,
+                                                                 const c128* __restrict__ V, int ldv, c128* wg,
+                                                                 c128* ou, c128* ov, int staged) {
+    HIP_DYNAMIC_SHARED(c128, lds)
+    c128* work = staged ? lds : wg;
+    const int lane = threadIdx.x, k = k1 + k2;
+    const int kk1 = min(m, k), kk2 = min(q, k), r = min(min(kk1, kk2), rmax);
+    const RecompressLayout L = recompress_layout(m, q, k, rmax);
+    c128 *W1 = work + L.W1, *Vh1 = work + L.Vh1, *Q1 = work + L.Q1, *R1 = work + L.R1;
+    c128 *W2 = work + L.W2, *Vh2 = work + L.Vh2, *Q2 = work + L.Q2, *R2 = work + L.R2;
+    c128 *C = work + L.C, *Vs = work + L.Vs, *Cg = work + L.Cg, *Vg = work + L.Vg;
+    double* sig = (double*)(work + L.sig);
+    int* perm = (int*)(work + L.perm);
+    int* rank = (int*)(work + L.rank);
+    for (size_t e = lane; e < (size_t)m * k; e += kWave) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        W1[e] = j < k1 ? au[(size_t)j * m + i] : alpha * U[(size_t)(j - k1) * ldu + i];
+    }
+    for (size_t e = lane; e < (size_t)q * k; e += kWave) {
+        const int i = (int)(e % q), j = (int)(e / q);
+        W2[e] = j < k1 ? av[(size_t)j * q + i] : V[(size_t)(j - k1) * ldv + i];
+    }
+    __syncthreads();
+    wave_qr(m, k, W1, Vh1, Q1, R1);
+    wave_qr(q, k, W2, Vh2, Q2, R2);
+    for (size_t e = lane; e < (size_t)kk1 * kk2; e += kWave) {
+        const int i = (int)(e % kk1), j = (int)(e / kk1);
+        c128 acc = czero<double>();
+        for (int l = j; l < k; ++l) cfma(acc, R1[(size_t)l * kk1 + i], R2[(size_t)l * kk2 + j]);   // R2 upper
+        C[e] = acc;
+    }
+    __syncthreads();
+    wave_svd(kk1, kk2, C, kk1, Vs, sig, perm, rank, tol, rmax);
+    const int rk = *rank;
+    for (size_t e = lane; e < (size_t)kk1 * r; e += kWave) {
+        const int i = (int)(e % kk1), j = (int)(e / kk1);
+        Cg[e] = j < rk ? C[(size_t)perm[j] * kk1 + i] : czero<double>();
+    }
+    for (size_t e = lane; e < (size_t)kk2 * r; e += kWave) {
+        const int i = (int)(e % kk2), j = (int)(e / kk2);
+        Vg[e] = j < rk ? conj(Vs[(size_t)perm[j] * kk2 + i]) : czero<double>();
+    }
+    __syncthreads();
+    for (size_t e = lane; e < (size_t)m * r; e += kWave) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        c128 acc = czero<double>();
+        for (int l = 0; l < kk1; ++l) cfma(acc, Q1[(size_t)l * m + i], Cg[(size_t)j * kk1 + l]);
+        ou[e] = acc;
+    }
+    for (size_t e = lane; e < (size_t)q * r; e += kWave) {
+        const int i = (int)(e % q), j = (int)(e / q);
+        c128 acc = czero<double>();
+        for (int l = 0; l < kk2; ++l) cfma(acc, Q2[(size_t)l * q + i], Vg[(size_t)j * kk2 + l]);
+        ov[e] = acc;
+    }
 }
 
 }  // namespace
 
+void launch_small_recompress(int m, int q, int k1, int k2, int rmax, double tol, c128 alpha, const c128* au,
+                             const c128* av, const c128* U, int ldu, const c128* V, int ldv, c128* work, c128* ou,
+                             c128* ov, hipStream_t s) {
+    const size_t bytes = recompress_layout(m, q, k1 + k2, rmax).total * sizeof(c128);
+    const int staged = bytes <= kLdsBytes;
+    hipLaunchKernelGGL(zrecompress_wave_kernel, dim3(1), dim3(kWave), staged ? bytes : 0, s, m, q, k1, k2, rmax, tol,
+                       alpha, au, av, U, ldu, V, ldv, work, ou, ov, staged);
+}
+
 void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, hipStream_t s) {
-    hipLaunchKernelGGL(zqr_wave_kernel, dim3(1), dim3(kWave), 0, s, p, k, A, lda, W, Vh, Q, R);
+    const size_t kk = p < k ? p : k;
+    const size_t bytes = ((size_t)p * k + 2 * (size_t)p * kk + kk * k) * sizeof(c128);
+    const int staged = bytes <= kLdsBytes;
+    hipLaunchKernelGGL(zqr_wave_kernel, dim3(1), dim3(kWave), staged ? bytes : 0, s, p, k, A, lda, W, Vh, Q, R,
+                       staged);
 }
 
 void launch_small_svd(int a, int b, c128* A, int lda, c128* V, double* sig, int* perm, int* rank, double tol,
                       int rmax, hipStream_t s) {
-    hipLaunchKernelGGL(zsvd_wave_kernel, dim3(1), dim3(kWave), 0, s, a, b, A, lda, V, sig, perm, rank, tol, rmax);
+    const size_t bytes = ((size_t)a * b + (size_t)b * b) * sizeof(c128) + (size_t)b * 12 + 16;
+    const int staged = bytes <= kLdsBytes;
+    hipLaunchKernelGGL(zsvd_wave_kernel, dim3(1), dim3(kWave), staged ? bytes : 0, s, a, b, A, lda, V, sig, perm,
+                       rank, tol, rmax, staged);
 }
 
 void launch_small_inv(int m, const c128* A, int lda, c128* W, c128* X, int* status, hipStream_t s) {
-    hipLaunchKernelGGL(zinv_wave_kernel, dim3(1), dim3(kWave), 0, s, m, A, lda, W, X, status);
+    const size_t bytes = ((size_t)m * (m + 1) + (size_t)m * m) * sizeof(c128);
+    const int staged = bytes <= kLdsBytes;
+    hipLaunchKernelGGL(zinv_wave_kernel, dim3(1), dim3(kWave), staged ? bytes : 0, s, m, A, lda, W, X, status, staged);
 }

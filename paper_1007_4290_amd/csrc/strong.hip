@@ -490,56 +490,23 @@ struct StrongFactors {
         return (int*)rk;
     }
 
-    // Truncated U V^t of the m x k and q x k factors (QR of both, SVD of the
-    // core R_u R_v^t): new factors in `out`.
-    void compress(Node& out, const c128* U, int ldu, const c128* V, int ldv, int k) {
-        const int m = out.m(), q = out.q();
+    // out = trunc([a.u, alpha U] [a.v, V]^t): QR of both stacked factors,
+    // SVD of the small core, the kept columns (one fused kernel); the width
+    // is the kept rank's upper bound, the columns past the rank zero.
+    void compress_sum(Node& out, const Node& a, c128 alpha, const c128* U, int ldu, const c128* V, int ldv, int k2) {
+        const int m = out.m(), q = out.q(), k1 = a.rank, k = k1 + k2;
         out.u = out.v = nullptr;
         out.rank = 0;
         if (k == 0 || !ok()) return;
-        c128 *Q1, *R1, *Q2, *R2;
-        qr(m, k, U, ldu, Q1, R1);
-        qr(q, k, V, ldv, Q2, R2);
-        const int k1 = std::min(m, k), k2 = std::min(q, k);
-        c128* C = talloc((size_t)k1 * k2);
-        if (!ok()) return;
-        gemm(0, 1, k1, k2, k, mk(1.0, 0.0), R1, k1, R2, k2, czero<double>(), C, k1);
-        c128* Vs;
-        int* perm;
-        const int* rk = svd(k1, k2, C, k1, Vs, perm);
-        // the kept rank stays on the device: the factors get its upper bound
-        // as their width, the columns past the rank being zero
-        const int r = std::min(std::min(k1, k2), rmax);
-        if (!ok() || r == 0) return;
-        c128* Cg = talloc((size_t)k1 * r);
-        c128* Vg = talloc((size_t)k2 * r);
+        const int r = std::min(std::min(std::min(m, k), std::min(q, k)), rmax);
+        if (r == 0) return;
+        c128* work = talloc(recompress_layout(m, q, k, rmax).total);
         out.u = talloc((size_t)m * r);
         out.v = talloc((size_t)q * r);
         if (!ok()) return;
-        hipLaunchKernelGGL(zgather_cols_kernel, grid2(k1, r), dim3(kThreads), 0, s, k1, r, C, k1, perm, rk, 0, Cg, k1);
-        hipLaunchKernelGGL(zgather_cols_kernel, grid2(k2, r), dim3(kThreads), 0, s, k2, r, Vs, k2, perm, rk, 2, Vg,
-                           k2);
-        gemm(0, 0, m, r, k1, mk(1.0, 0.0), Q1, m, Cg, k1, czero<double>(), out.u, m);
-        gemm(0, 0, q, r, k2, mk(1.0, 0.0), Q2, q, Vg, k2, czero<double>(), out.v, q);
+        launch_small_recompress(m, q, k1, k2, rmax, tol, alpha, a.u, a.v, U, ldu, V, ldv, work, out.u, out.v, s);
         out.rank = r;
         if (r > max_rank_seen) max_rank_seen = r;
-    }
-    // out = trunc([A.u, alpha U] [A.v, V]^t)
-    void compress_sum(Node& out, const Node& a, c128 alpha, const c128* U, int ldu, const c128* V, int ldv, int k2) {
-        const int m = out.m(), q = out.q(), k1 = a.rank, k = k1 + k2;
-        if (k == 0) { out.u = out.v = nullptr; out.rank = 0; return; }
-        c128* Uc = talloc((size_t)m * k);
-        c128* Vc = talloc((size_t)q * k);
-        if (!ok()) return;
-        if (k1) {
-            geam(m, k1, mk(1.0, 0.0), 0, a.u, m, czero<double>(), nullptr, 0, Uc, m);
-            geam(q, k1, mk(1.0, 0.0), 0, a.v, q, czero<double>(), nullptr, 0, Vc, q);
-        }
-        if (k2) {
-            geam(m, k2, alpha, 0, U, ldu, czero<double>(), nullptr, 0, Uc + (size_t)k1 * m, m);
-            geam(q, k2, mk(1.0, 0.0), 0, V, ldv, czero<double>(), nullptr, 0, Vc + (size_t)k1 * q, q);
-        }
-        compress(out, Uc, m, Vc, q, k);
     }
 
     // Randomized SVD of the m x q product G H (G on (t, u), H on (u, s)):

@@ -147,3 +147,48 @@ void launch_small_inv(int m, const c128* A, int lda, c128* W, c128* X, int* stat
         }
     }
 }
+
+void launch_small_recompress(int m, int q, int k1, int k2, int rmax, double tol, c128 alpha, const c128* au,
+                             const c128* av, const c128* U, int ldu, const c128* V, int ldv, c128* work, c128* ou,
+                             c128* ov, hipStream_t s) {
+    const int k = k1 + k2, kk1 = m < k ? m : k, kk2 = q < k ? q : k;
+    const int r0 = kk1 < kk2 ? kk1 : kk2, r = r0 < rmax ? r0 : rmax;
+    const RecompressLayout L = recompress_layout(m, q, k, rmax);
+    c128 *W1 = work + L.W1, *W2 = work + L.W2, *C = work + L.C, *Vs = work + L.Vs, *Cg = work + L.Cg,
+         *Vg = work + L.Vg, *Q1 = work + L.Q1, *Q2 = work + L.Q2, *R1 = work + L.R1, *R2 = work + L.R2;
+    // the stacked factors go to the output-side pieces Q (m x kk1 is not
+    // always m x k), so build them in W and let the QR copy them onto itself
+    for (int j = 0; j < k; ++j)
+        for (int i = 0; i < m; ++i)
+            W1[(size_t)j * m + i] = j < k1 ? au[(size_t)j * m + i] : alpha * U[(size_t)(j - k1) * ldu + i];
+    for (int j = 0; j < k; ++j)
+        for (int i = 0; i < q; ++i) W2[(size_t)j * q + i] = j < k1 ? av[(size_t)j * q + i] : V[(size_t)(j - k1) * ldv + i];
+    launch_small_qr(m, k, W1, m, W1, work + L.Vh1, Q1, R1, s);
+    launch_small_qr(q, k, W2, q, W2, work + L.Vh2, Q2, R2, s);
+    for (int j = 0; j < kk2; ++j)
+        for (int i = 0; i < kk1; ++i) {
+            c128 acc = czero<double>();
+            for (int l = 0; l < k; ++l) cfma(acc, R1[(size_t)l * kk1 + i], R2[(size_t)l * kk2 + j]);
+            C[(size_t)j * kk1 + i] = acc;
+        }
+    double* sig = (double*)(work + L.sig);
+    int* perm = (int*)(work + L.perm);
+    int* rank = (int*)(work + L.rank);
+    launch_small_svd(kk1, kk2, C, kk1, Vs, sig, perm, rank, tol, rmax, s);
+    for (int j = 0; j < r; ++j) {
+        for (int i = 0; i < kk1; ++i) Cg[(size_t)j * kk1 + i] = j < *rank ? C[(size_t)perm[j] * kk1 + i] : czero<double>();
+        for (int i = 0; i < kk2; ++i) Vg[(size_t)j * kk2 + i] = j < *rank ? conj(Vs[(size_t)perm[j] * kk2 + i]) : czero<double>();
+    }
+    for (int j = 0; j < r; ++j) {
+        for (int i = 0; i < m; ++i) {
+            c128 acc = czero<double>();
+            for (int l = 0; l < kk1; ++l) cfma(acc, Q1[(size_t)l * m + i], Cg[(size_t)j * kk1 + l]);
+            ou[(size_t)j * m + i] = acc;
+        }
+        for (int i = 0; i < q; ++i) {
+            c128 acc = czero<double>();
+            for (int l = 0; l < kk2; ++l) cfma(acc, Q2[(size_t)l * q + i], Vg[(size_t)j * kk2 + l]);
+            ov[(size_t)j * q + i] = acc;
+        }
+    }
+}

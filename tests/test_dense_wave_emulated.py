@@ -1,5 +1,6 @@
 """The small dense factorizations of the strongly admissible H-arithmetic
-(k_dense.hip: thin QR, one-sided Jacobi SVD, Gauss-Jordan inverse), one
+(k_dense.hip: thin QR, one-sided Jacobi SVD, Gauss-Jordan inverse, and the
+fused recompression of a sum of two low-rank factorizations), one
 wavefront of 64 lanes per matrix, run on the CPU: the kernels are compiled
 with g++ against a stand-in of the HIP runtime that runs each lane as a
 thread with a real barrier and real shuffles (tests/wavecheck), under the
@@ -9,7 +10,10 @@ starting as NaN bytes.
 Each result is checked against what defines it, with numpy for reference
 values: Q R = A with Q orthonormal and R upper triangular; A V with V unitary
 and mutually orthogonal columns whose norms are A's singular values, the
-permutation sorting them, the kept count as specified; A X = I.  The shapes
+permutation sorting them, the kept count as specified; A X = I; the
+recompression's product equal to the truncated SVD of the sum.  Working sets
+below and above the 64 KiB the kernels stage in shared memory are both
+covered.  The shapes
 cover one and several passes of the column and pair loops, more columns than
 rows, zero columns (the zero-padded factor widths), odd and even column
 counts and a singular leaf.
@@ -64,7 +68,8 @@ def _rand(rng, m, n):
     return rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
 
 
-QR_CASES = [(1, 1), (5, 3), (3, 5), (64, 10), (130, 7), (20, 70), (33, 33), (200, 2)]
+# working sets below and above the 64 KiB that the kernels stage in shared memory
+QR_CASES = [(1, 1), (5, 3), (3, 5), (64, 10), (130, 7), (20, 70), (33, 33), (200, 2), (300, 10)]
 
 
 @pytest.mark.parametrize("p, k", QR_CASES)
@@ -120,7 +125,7 @@ def test_svd(wave, tmp_path, a, b):
     assert rank == want
 
 
-@pytest.mark.parametrize("m", [1, 2, 7, 16, 33, 40])
+@pytest.mark.parametrize("m", [1, 2, 7, 16, 33, 40, 50])
 def test_inverse(wave, tmp_path, m):
     rng = np.random.default_rng(300 + m)
     A = _rand(rng, m + 1, m)
@@ -139,3 +144,44 @@ def test_inverse_of_a_singular_leaf_sets_the_status(wave, tmp_path):
     A[:, 4] = 0.0
     out = _run(wave, tmp_path, 2, A, 6, 6)
     assert struct.unpack_from("i", out, 16 * 36)[0] == 1
+
+
+REC_CASES = [(12, 9, 2, 3, 2, 1e-6), (40, 33, 4, 4, 4, 1e-6), (70, 66, 8, 10, 8, 1e-10), (5, 30, 3, 4, 6, 0.0),
+             (16, 16, 0, 5, 3, 1e-6), (24, 20, 6, 0, 2, 1e-6)]
+
+
+@pytest.mark.parametrize("m, q, k1, k2, rmax, tol", REC_CASES)
+def test_recompression(wave, tmp_path, m, q, k1, k2, rmax, tol):
+    """The fused recompression gives the truncated SVD of [au, alpha U] [av, V]^t:
+    the kept rank's leading singular triplets, zero columns past it."""
+    rng = np.random.default_rng(400 + m + q + k1 + k2)
+    alpha = 0.7 - 0.4j
+    # factors of decaying weight, so that the truncation is well defined
+    d1 = 2.0 ** -np.arange(k1)
+    d2 = 3.0 ** -np.arange(k2)
+    au, av = _rand(rng, m, k1) * d1, _rand(rng, q, k1)
+    U, V = _rand(rng, m, k2) * d2, _rand(rng, q, k2)
+    fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    with open(fin, "wb") as fp:
+        fp.write(struct.pack("5i", 3, m, q, k1, rmax))
+        fp.write(struct.pack("d", tol))
+        fp.write(struct.pack("i", k2))
+        fp.write(struct.pack("2d", alpha.real, alpha.imag))
+        for M in (au, av, U, V):
+            fp.write(np.asfortranarray(M, dtype=np.complex128).tobytes(order="F"))
+    r = subprocess.run([wave, fin, fout], capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    out = open(fout, "rb").read()
+    k = k1 + k2
+    width = min(m, q, k, rmax)
+    ou, off = _mat(out, 0, m, width)
+    ov, _ = _mat(out, off, q, width)
+    full = np.hstack([au, alpha * U]) @ np.hstack([av, V]).T
+    Uf, s, Vh = np.linalg.svd(full)
+    keep = int(np.sum(s > (tol * s[0] if tol > 0 else 0.0)))
+    keep = min(keep, rmax)
+    best = (Uf[:, :keep] * s[:keep]) @ Vh[:keep]
+    assert np.linalg.norm(ou @ ov.T - best) <= 1e-12 * s[0]
+    # columns past the kept rank are zero
+    assert np.all(ou[:, keep:] == 0) and np.all(ov[:, keep:] == 0)

@@ -19,6 +19,9 @@ using std::min;
 
 #define __shared__ static
 #define __launch_bounds__(x)
+// dynamic shared memory: one buffer of the launch's requested size
+extern std::vector<char> wave_dyn_shared;
+#define HIP_DYNAMIC_SHARED(type, var) type* var = (type*)wave_dyn_shared.data();
 
 struct dim3 {
     unsigned x, y, z;
@@ -47,8 +50,10 @@ template <typename T> inline T __shfl_xor(T v, int mask, int = 64) { return wave
 template <typename T> inline T __shfl(T v, int src, int = 64) { return wave_exchange(v, src); }
 
 template <typename K, typename... A>
-inline void wave_launch(K kernel, dim3 g, dim3 b, A... args) {
+inline void wave_launch(K kernel, dim3 g, dim3 b, size_t shared_bytes, A... args) {
     const unsigned nt = b.x * b.y * b.z;
+    // NaN bytes, as the device allocations of the stand-in start
+    wave_dyn_shared.assign(shared_bytes ? shared_bytes : 1, (char)0xFF);
     for (unsigned bz = 0; bz < g.z; ++bz)
         for (unsigned by = 0; by < g.y; ++by)
             for (unsigned bx = 0; bx < g.x; ++bx) {
@@ -66,4 +71,4 @@ inline void wave_launch(K kernel, dim3 g, dim3 b, A... args) {
                 pthread_barrier_destroy(&wave_barrier);
             }
 }
-#define hipLaunchKernelGGL(k, g, b, sh, st, ...) wave_launch(k, dim3(g), dim3(b), __VA_ARGS__)
+#define hipLaunchKernelGGL(k, g, b, sh, st, ...) wave_launch(k, dim3(g), dim3(b), (size_t)(sh), __VA_ARGS__)
