@@ -207,14 +207,20 @@ __host__ __device__ inline RecompressLayout recompress_layout(int m, int q, int 
     L.total = o;
     return L;
 }
-// The truncated product of [au, alpha U] (m x k1 + k2) and [av, V] (q x k1 +
-// k2) as ou (m x r) and ov (q x r), r = min(m, q, k1 + k2, rmax), the
-// columns past the kept rank (singular values above tol * sigma_1, at most
-// rmax) zero; work holds recompress_layout(m, q, k1 + k2, rmax).total
-// entries.  au, av have leading dimensions m and q.
-void launch_small_recompress(int m, int q, int k1, int k2, int rmax, double tol, c128 alpha, const c128* au,
-                             const c128* av, const c128* U, int ldu, const c128* V, int ldv, c128* work, c128* ou,
-                             c128* ov, hipStream_t s);
+// One recompression: the truncated product of [au, alpha U] (m x k1 + k2)
+// and [av, V] (q x k1 + k2) as ou (m x r) and ov (q x r), r = min(m, q,
+// k1 + k2, rmax), the columns past the kept rank (singular values above
+// tol * sigma_1, at most rmax) zero; work holds recompress_layout(m, q,
+// k1 + k2, rmax).total entries.  au, av have leading dimensions m and q.
+struct RecompressJob {
+    const c128 *au, *av, *U, *V;
+    c128 *work, *ou, *ov;
+    c128 alpha;
+    int m, q, k1, k2, ldu, ldv;
+};
+// count independent recompressions (host array), one workgroup each, in
+// launches of up to 32; no job may read what another writes.
+void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rmax, double tol, hipStream_t s);
 
 // ---- strongly admissible layer factors (complex128, strong.hip) ----
 // Factors of the n layers in the strong format from the frame coefficients

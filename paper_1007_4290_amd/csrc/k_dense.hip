@@ -373,34 +373,42 @@ __global__ void __launch_bounds__(kWave) zinv_wave_kernel(int m, const c128* __r
     if (staged) wave_copy(m, m, X, m, Xg, m);
 }
 
-// The truncated product of [au, alpha U] (m x k) and [av, V] (q x k), k =
-// k1 + k2: QR of both stacked factors, SVD of the core C = R1 R2^t, and the
-// factors ou = Q1 (C V)_r (m x r) and ov = Q2 conj(V_r) (q x r), r = min(m,
-// q, k, rmax) columns of which those past the kept rank are zero.
-__global__ void __launch_bounds__(kWave) zrecompress_wave_kernel(int m, int q, int k1, int k2, int rmax, double tol,
-                                                                 c128 alpha, const c128* __restrict__ au,
-                                                                 const c128* __restrict__ av,
-                                                                 const c128* __restrict__ U, int ldu,
-                                                                 const c128* __restrict__ V, int ldv, c128* wg,
-                                                                 c128* ou, c128* ov, int staged) {
+// Recompressions of one launch, one workgroup each, passed by value.
+constexpr int kRecBatch = 32;
+struct RecompressBatch {
+    RecompressJob job[kRecBatch];
+    double tol;
+    int rmax;
+    unsigned lds;          // shared-memory bytes of the launch
+};
+
+// Job blockIdx.x: the truncated product of [au, alpha U] (m x k) and [av, V]
+// (q x k), k = k1 + k2: QR of both stacked factors, SVD of the core C =
+// R1 R2^t, and the factors ou = Q1 (C V)_r (m x r) and ov = Q2 conj(V_r)
+// (q x r), r = min(m, q, k, rmax) columns of which those past the kept rank
+// are zero.
+__global__ void __launch_bounds__(kWave) zrecompress_batch_kernel(RecompressBatch B) {
     HIP_DYNAMIC_SHARED(c128, lds)
-    c128* work = staged ? lds : wg;
+    const RecompressJob& J = B.job[blockIdx.x];
+    const int m = J.m, q = J.q, k1 = J.k1, k2 = J.k2, rmax = B.rmax;
     const int lane = threadIdx.x, k = k1 + k2;
     const int kk1 = min(m, k), kk2 = min(q, k), r = min(min(kk1, kk2), rmax);
     const RecompressLayout L = recompress_layout(m, q, k, rmax);
+    c128* work = L.total * sizeof(c128) <= B.lds ? lds : J.work;
     c128 *W1 = work + L.W1, *Vh1 = work + L.Vh1, *Q1 = work + L.Q1, *R1 = work + L.R1;
     c128 *W2 = work + L.W2, *Vh2 = work + L.Vh2, *Q2 = work + L.Q2, *R2 = work + L.R2;
     c128 *C = work + L.C, *Vs = work + L.Vs, *Cg = work + L.Cg, *Vg = work + L.Vg;
     double* sig = (double*)(work + L.sig);
     int* perm = (int*)(work + L.perm);
     int* rank = (int*)(work + L.rank);
+    const c128 alpha = J.alpha;
     for (size_t e = lane; e < (size_t)m * k; e += kWave) {
         const int i = (int)(e % m), j = (int)(e / m);
-        W1[e] = j < k1 ? au[(size_t)j * m + i] : alpha * U[(size_t)(j - k1) * ldu + i];
+        W1[e] = j < k1 ? J.au[(size_t)j * m + i] : alpha * J.U[(size_t)(j - k1) * J.ldu + i];
     }
     for (size_t e = lane; e < (size_t)q * k; e += kWave) {
         const int i = (int)(e % q), j = (int)(e / q);
-        W2[e] = j < k1 ? av[(size_t)j * q + i] : V[(size_t)(j - k1) * ldv + i];
+        W2[e] = j < k1 ? J.av[(size_t)j * q + i] : J.V[(size_t)(j - k1) * J.ldv + i];
     }
     __syncthreads();
     wave_qr(m, k, W1, Vh1, Q1, R1);
@@ -412,7 +420,7 @@ __global__ void __launch_bounds__(kWave) zrecompress_wave_kernel(int m, int q, i
         C[e] = acc;
     }
     __syncthreads();
-    wave_svd(kk1, kk2, C, kk1, Vs, sig, perm, rank, tol, rmax);
+    wave_svd(kk1, kk2, C, kk1, Vs, sig, perm, rank, B.tol, rmax);
     const int rk = *rank;
     for (size_t e = lane; e < (size_t)kk1 * r; e += kWave) {
         const int i = (int)(e % kk1), j = (int)(e / kk1);
@@ -427,25 +435,34 @@ __global__ void __launch_bounds__(kWave) zrecompress_wave_kernel(int m, int q, i
         const int i = (int)(e % m), j = (int)(e / m);
         c128 acc = czero<double>();
         for (int l = 0; l < kk1; ++l) cfma(acc, Q1[(size_t)l * m + i], Cg[(size_t)j * kk1 + l]);
-        ou[e] = acc;
+        J.ou[e] = acc;
     }
     for (size_t e = lane; e < (size_t)q * r; e += kWave) {
         const int i = (int)(e % q), j = (int)(e / q);
         c128 acc = czero<double>();
         for (int l = 0; l < kk2; ++l) cfma(acc, Q2[(size_t)l * q + i], Vg[(size_t)j * kk2 + l]);
-        ov[e] = acc;
+        J.ov[e] = acc;
     }
 }
 
 }  // namespace
 
-void launch_small_recompress(int m, int q, int k1, int k2, int rmax, double tol, c128 alpha, const c128* au,
-                             const c128* av, const c128* U, int ldu, const c128* V, int ldv, c128* work, c128* ou,
-                             c128* ov, hipStream_t s) {
-    const size_t bytes = recompress_layout(m, q, k1 + k2, rmax).total * sizeof(c128);
-    const int staged = bytes <= kLdsBytes;
-    hipLaunchKernelGGL(zrecompress_wave_kernel, dim3(1), dim3(kWave), staged ? bytes : 0, s, m, q, k1, k2, rmax, tol,
-                       alpha, au, av, U, ldu, V, ldv, work, ou, ov, staged);
+void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rmax, double tol, hipStream_t s) {
+    for (int j0 = 0; j0 < count; j0 += kRecBatch) {
+        RecompressBatch B;
+        const int nb = count - j0 < kRecBatch ? count - j0 : kRecBatch;
+        size_t lds = 0;
+        for (int j = 0; j < nb; ++j) {
+            const RecompressJob& J = jobs[j0 + j];
+            B.job[j] = J;
+            const size_t bytes = recompress_layout(J.m, J.q, J.k1 + J.k2, rmax).total * sizeof(c128);
+            if (bytes <= kLdsBytes && bytes > lds) lds = bytes;
+        }
+        B.tol = tol;
+        B.rmax = rmax;
+        B.lds = (unsigned)lds;
+        hipLaunchKernelGGL(zrecompress_batch_kernel, dim3(nb), dim3(kWave), lds, s, B);
+    }
 }
 
 void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, hipStream_t s) {

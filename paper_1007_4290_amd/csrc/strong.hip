@@ -360,6 +360,8 @@ struct StrongFactors {
     c128* sw = nullptr;
     size_t sw_count = 0;
     int max_rank_seen = 0;
+    std::vector<RecompressJob> pend;   // recompressions not yet launched
+    int defer = 0;                     // depth of walks whose recompressions wait in pend
 
     // ---- launch helpers
     bool ok() const { return rc == HSWEEP_OK; }
@@ -492,7 +494,10 @@ struct StrongFactors {
 
     // out = trunc([a.u, alpha U] [a.v, V]^t): QR of both stacked factors,
     // SVD of the small core, the kept columns (one fused kernel); the width
-    // is the kept rank's upper bound, the columns past the rank zero.
+    // is the kept rank's upper bound, the columns past the rank zero.  Inside
+    // a walk over disjoint blocks (defer > 0) the job waits in `pend` and the
+    // walk launches all of its jobs at once when it ends: the walk's other
+    // launches neither read what the jobs write nor write what they read.
     void compress_sum(Node& out, const Node& a, c128 alpha, const c128* U, int ldu, const c128* V, int ldv, int k2) {
         const int m = out.m(), q = out.q(), k1 = a.rank, k = k1 + k2;
         out.u = out.v = nullptr;
@@ -504,9 +509,30 @@ struct StrongFactors {
         out.u = talloc((size_t)m * r);
         out.v = talloc((size_t)q * r);
         if (!ok()) return;
-        launch_small_recompress(m, q, k1, k2, rmax, tol, alpha, a.u, a.v, U, ldu, V, ldv, work, out.u, out.v, s);
+        RecompressJob J;
+        J.au = a.u;
+        J.av = a.v;
+        J.U = U;
+        J.V = V;
+        J.work = work;
+        J.ou = out.u;
+        J.ov = out.v;
+        J.alpha = alpha;
+        J.m = m;
+        J.q = q;
+        J.k1 = k1;
+        J.k2 = k2;
+        J.ldu = ldu;
+        J.ldv = ldv;
+        pend.push_back(J);
+        if (defer == 0) flush();
         out.rank = r;
         if (r > max_rank_seen) max_rank_seen = r;
+    }
+    // Launch the queued recompressions (one workgroup each).
+    void flush() {
+        if (!pend.empty() && ok()) launch_small_recompress_batch(pend.data(), (int)pend.size(), rmax, tol, s);
+        pend.clear();
     }
 
     // Randomized SVD of the m x q product G H (G on (t, u), H on (u, s)):
@@ -558,8 +584,14 @@ struct StrongFactors {
     }
 
     // ---- H-arithmetic
-    // T += U V^t along T's tree (U: T.m x k, V: T.q x k)
+    // T += U V^t along T's tree (U: T.m x k, V: T.q x k); the recompressions
+    // of its factorized blocks go out as one batch
     void add_lowrank(HMat& T, int ti, const c128* U, int ldu, const c128* V, int ldv, int k, c128 alpha) {
+        ++defer;
+        add_lowrank_walk(T, ti, U, ldu, V, ldv, k, alpha);
+        if (--defer == 0) flush();
+    }
+    void add_lowrank_walk(HMat& T, int ti, const c128* U, int ldu, const c128* V, int ldv, int k, c128 alpha) {
         if (k == 0 || !ok()) return;
         Node& b = T.nd[ti];
         if (b.kind == 'D') {
@@ -573,7 +605,7 @@ struct StrongFactors {
             for (int c = 0; c < 4; ++c) {
                 const int ci = T.nd[ti].ch[c];
                 const Node& h = T.nd[ci];
-                add_lowrank(T, ci, U + (h.t0 - T.nd[ti].t0), ldu, V + (h.s0 - T.nd[ti].s0), ldv, k, alpha);
+                add_lowrank_walk(T, ci, U + (h.t0 - T.nd[ti].t0), ldu, V + (h.s0 - T.nd[ti].s0), ldv, k, alpha);
             }
         }
     }
@@ -637,7 +669,9 @@ struct StrongFactors {
     }
     HMat add(const HMat& A, int ai, const HMat& B, int bi, c128 alpha) {
         HMat R;
+        ++defer;
         add_into(R, A, ai, B, bi, alpha);
+        if (--defer == 0) flush();
         return R;
     }
     // G^{-1} by 2 x 2 block inversion: Y = G11^{-1}, Z = Y G12, X = G21 Y,

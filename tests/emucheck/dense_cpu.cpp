@@ -148,9 +148,9 @@ void launch_small_inv(int m, const c128* A, int lda, c128* W, c128* X, int* stat
     }
 }
 
-void launch_small_recompress(int m, int q, int k1, int k2, int rmax, double tol, c128 alpha, const c128* au,
-                             const c128* av, const c128* U, int ldu, const c128* V, int ldv, c128* work, c128* ou,
-                             c128* ov, hipStream_t s) {
+static void recompress_one(int m, int q, int k1, int k2, int rmax, double tol, c128 alpha, const c128* au,
+                           const c128* av, const c128* U, int ldu, const c128* V, int ldv, c128* work, c128* ou,
+                           c128* ov, hipStream_t s) {
     const int k = k1 + k2, kk1 = m < k ? m : k, kk2 = q < k ? q : k;
     const int r0 = kk1 < kk2 ? kk1 : kk2, r = r0 < rmax ? r0 : rmax;
     const RecompressLayout L = recompress_layout(m, q, k, rmax);
@@ -190,5 +190,13 @@ void launch_small_recompress(int m, int q, int k1, int k2, int rmax, double tol,
             for (int l = 0; l < kk2; ++l) cfma(acc, Q2[(size_t)l * q + i], Vg[(size_t)j * kk2 + l]);
             ov[(size_t)j * q + i] = acc;
         }
+    }
+}
+
+void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rmax, double tol, hipStream_t s) {
+    for (int j = 0; j < count; ++j) {
+        const RecompressJob& J = jobs[j];
+        recompress_one(J.m, J.q, J.k1, J.k2, rmax, tol, J.alpha, J.au, J.av, J.U, J.ldu, J.V, J.ldv, J.work, J.ou,
+                       J.ov, s);
     }
 }

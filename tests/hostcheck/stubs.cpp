@@ -163,13 +163,18 @@ void launch_small_inv(int m, const c128* A, int lda, c128* W, c128* X, int* stat
     if (m > 0) need(A, ((size_t)(m - 1) * lda + m) * 16, "inv A");
     need(W, (size_t)m * (m + 1) * 16, "inv W"); need(X, (size_t)m * m * 16, "inv X"); need(status, 4, "inv status");
 }
-void launch_small_recompress(int m, int q, int k1, int k2, int rmax, double, c128, const c128* au, const c128* av,
-                             const c128* U, int ldu, const c128* V, int ldv, c128* work, c128* ou, c128* ov,
-                             hipStream_t) {
+static void recompress_ranges(int m, int q, int k1, int k2, int rmax, const c128* au, const c128* av,
+                              const c128* U, int ldu, const c128* V, int ldv, c128* work, c128* ou, c128* ov) {
     const int k = k1 + k2, kk1 = m < k ? m : k, kk2 = q < k ? q : k;
     const int r0 = kk1 < kk2 ? kk1 : kk2, r = r0 < rmax ? r0 : rmax;
     need(au, (size_t)m * k1 * 16, "recompress au"); need(av, (size_t)q * k1 * 16, "recompress av");
     if (k2 > 0) { need(U, ((size_t)(k2 - 1) * ldu + m) * 16, "recompress U"); need(V, ((size_t)(k2 - 1) * ldv + q) * 16, "recompress V"); }
     need(work, recompress_layout(m, q, k, rmax).total * 16, "recompress work");
     need(ou, (size_t)m * r * 16, "recompress ou"); need(ov, (size_t)q * r * 16, "recompress ov");
+}
+void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rmax, double, hipStream_t) {
+    for (int j = 0; j < count; ++j) {
+        const RecompressJob& J = jobs[j];
+        recompress_ranges(J.m, J.q, J.k1, J.k2, rmax, J.au, J.av, J.U, J.ldu, J.V, J.ldv, J.work, J.ou, J.ov);
+    }
 }

@@ -146,42 +146,66 @@ def test_inverse_of_a_singular_leaf_sets_the_status(wave, tmp_path):
     assert struct.unpack_from("i", out, 16 * 36)[0] == 1
 
 
-REC_CASES = [(12, 9, 2, 3, 2, 1e-6), (40, 33, 4, 4, 4, 1e-6), (70, 66, 8, 10, 8, 1e-10), (5, 30, 3, 4, 6, 0.0),
-             (16, 16, 0, 5, 3, 1e-6), (24, 20, 6, 0, 2, 1e-6)]
+REC_CASES = [(12, 9, 2, 3, 1e-6), (40, 33, 4, 4, 1e-6), (70, 66, 8, 10, 1e-10), (5, 30, 3, 4, 0.0),
+             (16, 16, 0, 5, 1e-6), (24, 20, 6, 0, 1e-6)]
 
 
-@pytest.mark.parametrize("m, q, k1, k2, rmax, tol", REC_CASES)
-def test_recompression(wave, tmp_path, m, q, k1, k2, rmax, tol):
-    """The fused recompression gives the truncated SVD of [au, alpha U] [av, V]^t:
-    the kept rank's leading singular triplets, zero columns past it."""
-    rng = np.random.default_rng(400 + m + q + k1 + k2)
-    alpha = 0.7 - 0.4j
-    # factors of decaying weight, so that the truncation is well defined
-    d1 = 2.0 ** -np.arange(k1)
-    d2 = 3.0 ** -np.arange(k2)
-    au, av = _rand(rng, m, k1) * d1, _rand(rng, q, k1)
-    U, V = _rand(rng, m, k2) * d2, _rand(rng, q, k2)
+def _recompress(exe, tmp_path, cases, rmax):
+    """Run the cases (m, q, k1, k2, tol: one tol for all) as one batched launch;
+    returns [(inputs, ou, ov)]."""
+    tol = cases[0][4]
     fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    jobs = []
     with open(fin, "wb") as fp:
-        fp.write(struct.pack("5i", 3, m, q, k1, rmax))
+        fp.write(struct.pack("5i", 3, len(cases), rmax, 0, rmax))
         fp.write(struct.pack("d", tol))
-        fp.write(struct.pack("i", k2))
-        fp.write(struct.pack("2d", alpha.real, alpha.imag))
-        for M in (au, av, U, V):
-            fp.write(np.asfortranarray(M, dtype=np.complex128).tobytes(order="F"))
-    r = subprocess.run([wave, fin, fout], capture_output=True, text=True, timeout=600,
+        for t, (m, q, k1, k2, _) in enumerate(cases):
+            rng = np.random.default_rng(400 + m + q + k1 + k2 + t)
+            alpha = 0.7 - 0.4j
+            # factors of decaying weight, so that the truncation is well defined
+            au, av = _rand(rng, m, k1) * 2.0 ** -np.arange(k1), _rand(rng, q, k1)
+            U, V = _rand(rng, m, k2) * 3.0 ** -np.arange(k2), _rand(rng, q, k2)
+            fp.write(struct.pack("4i", m, q, k1, k2))
+            fp.write(struct.pack("2d", alpha.real, alpha.imag))
+            for M in (au, av, U, V):
+                fp.write(np.asfortranarray(M, dtype=np.complex128).tobytes(order="F"))
+            jobs.append((m, q, k1, k2, alpha, au, av, U, V))
+    r = subprocess.run([exe, fin, fout], capture_output=True, text=True, timeout=600,
                        env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     out = open(fout, "rb").read()
-    k = k1 + k2
-    width = min(m, q, k, rmax)
-    ou, off = _mat(out, 0, m, width)
-    ov, _ = _mat(out, off, q, width)
+    res, off = [], 0
+    for (m, q, k1, k2, alpha, au, av, U, V) in jobs:
+        width = min(m, q, k1 + k2, rmax)
+        ou, off = _mat(out, off, m, width)
+        ov, off = _mat(out, off, q, width)
+        res.append(((alpha, au, av, U, V), ou, ov))
+    return res
+
+
+def _check_truncation(inputs, ou, ov, tol, rmax):
+    alpha, au, av, U, V = inputs
     full = np.hstack([au, alpha * U]) @ np.hstack([av, V]).T
     Uf, s, Vh = np.linalg.svd(full)
-    keep = int(np.sum(s > (tol * s[0] if tol > 0 else 0.0)))
-    keep = min(keep, rmax)
+    keep = min(int(np.sum(s > (tol * s[0] if tol > 0 else 0.0))), rmax)
     best = (Uf[:, :keep] * s[:keep]) @ Vh[:keep]
     assert np.linalg.norm(ou @ ov.T - best) <= 1e-12 * s[0]
     # columns past the kept rank are zero
     assert np.all(ou[:, keep:] == 0) and np.all(ov[:, keep:] == 0)
+
+
+@pytest.mark.parametrize("case", REC_CASES)
+def test_recompression(wave, tmp_path, case):
+    """One recompression gives the truncated SVD of [au, alpha U] [av, V]^t:
+    the kept rank's leading singular triplets, zero columns past it."""
+    rmax = 8 if case[2] + case[3] >= 16 else max(2, case[2])
+    (inputs, ou, ov), = _recompress(wave, tmp_path, [case], rmax)
+    _check_truncation(inputs, ou, ov, case[4], rmax)
+
+
+def test_recompression_batch(wave, tmp_path):
+    """Forty jobs in one call (two launches of up to 32 workgroups), with
+    working sets in and beyond the 64 KiB of shared memory side by side."""
+    cases = [REC_CASES[t % 4][:4] + (1e-6,) for t in range(40)]
+    for (inputs, ou, ov), c in zip(_recompress(wave, tmp_path, cases, 6), cases):
+        _check_truncation(inputs, ou, ov, 1e-6, 6)

@@ -35,29 +35,43 @@ int main(int argc, char** argv) {
     if (!rd(fp, hd, sizeof hd) || !rd(fp, &tol, 8)) return 2;
     const int op = hd[0], p = hd[1], k = hd[2], lda = hd[3], rmax = hd[4];
     if (op == 3) {
-        // recompression: p = m, k = q, lda = k1; then int32 k2, float64
-        // alpha (re, im), au (m x k1), av (q x k1), U (m x k2), V (q x k2)
-        const int m = p, q = k, k1 = lda;
-        int32_t k2;
-        double al[2];
-        if (!rd(fp, &k2, 4) || !rd(fp, al, 16)) return 2;
-        const size_t n1 = (size_t)m * k1, n2 = (size_t)q * k1, n3 = (size_t)m * k2, n4 = (size_t)q * k2;
-        std::vector<c128> h(n1 + n2 + n3 + n4);
-        if (!rd(fp, h.data(), h.size() * 16)) return 2;
+        // a batch of recompressions: p = number of jobs, k = rmax, lda unused;
+        // per job int32 m, q, k1, k2, float64 alpha (re, im), then au (m x k1),
+        // av (q x k1), U (m x k2), V (q x k2); output each job's ou, ov
+        const int count = p;
+        std::vector<RecompressJob> jobs(count);
+        std::vector<int> rw(count);
+        for (int t = 0; t < count; ++t) {
+            int32_t d[4];
+            double al[2];
+            if (!rd(fp, d, 16) || !rd(fp, al, 16)) return 2;
+            const int m = d[0], q = d[1], k1 = d[2], k2 = d[3];
+            const size_t n1 = (size_t)m * k1, n2 = (size_t)q * k1, n3 = (size_t)m * k2, n4 = (size_t)q * k2;
+            std::vector<c128> h(n1 + n2 + n3 + n4);
+            if (!rd(fp, h.data(), h.size() * 16)) return 2;
+            c128 *au = dev<c128>(n1), *av = dev<c128>(n2), *U = dev<c128>(n3), *V = dev<c128>(n4);
+            hipMemcpy(au, h.data(), n1 * 16, hipMemcpyHostToDevice);
+            hipMemcpy(av, h.data() + n1, n2 * 16, hipMemcpyHostToDevice);
+            hipMemcpy(U, h.data() + n1 + n2, n3 * 16, hipMemcpyHostToDevice);
+            hipMemcpy(V, h.data() + n1 + n2 + n3, n4 * 16, hipMemcpyHostToDevice);
+            const int kt = k1 + k2, kk1 = m < kt ? m : kt, kk2 = q < kt ? q : kt;
+            const int r0 = kk1 < kk2 ? kk1 : kk2, r = r0 < rmax ? r0 : rmax;
+            RecompressJob& J = jobs[t];
+            J.au = au; J.av = av; J.U = U; J.V = V;
+            J.work = dev<c128>(recompress_layout(m, q, kt, rmax).total);
+            J.ou = dev<c128>((size_t)m * r);
+            J.ov = dev<c128>((size_t)q * r);
+            J.alpha = mk(al[0], al[1]);
+            J.m = m; J.q = q; J.k1 = k1; J.k2 = k2; J.ldu = m; J.ldv = q;
+            rw[t] = r;
+        }
         fclose(fp);
-        c128 *au = dev<c128>(n1), *av = dev<c128>(n2), *U = dev<c128>(n3), *V = dev<c128>(n4);
-        hipMemcpy(au, h.data(), n1 * 16, hipMemcpyHostToDevice);
-        hipMemcpy(av, h.data() + n1, n2 * 16, hipMemcpyHostToDevice);
-        hipMemcpy(U, h.data() + n1 + n2, n3 * 16, hipMemcpyHostToDevice);
-        hipMemcpy(V, h.data() + n1 + n2 + n3, n4 * 16, hipMemcpyHostToDevice);
-        const int kt = k1 + k2, kk1 = m < kt ? m : kt, kk2 = q < kt ? q : kt;
-        const int r0 = kk1 < kk2 ? kk1 : kk2, r = r0 < rmax ? r0 : rmax;
-        c128* work = dev<c128>(recompress_layout(m, q, kt, rmax).total);
-        c128 *ou = dev<c128>((size_t)m * r), *ov = dev<c128>((size_t)q * r);
-        launch_small_recompress(m, q, k1, k2, rmax, tol, mk(al[0], al[1]), au, av, U, m, V, q, work, ou, ov, nullptr);
+        launch_small_recompress_batch(jobs.data(), count, rmax, tol, nullptr);
         FILE* out = fopen(argv[2], "wb");
-        fwrite(ou, 16, (size_t)m * r, out);
-        fwrite(ov, 16, (size_t)q * r, out);
+        for (int t = 0; t < count; ++t) {
+            fwrite(jobs[t].ou, 16, (size_t)jobs[t].m * rw[t], out);
+            fwrite(jobs[t].ov, 16, (size_t)jobs[t].q * rw[t], out);
+        }
         fclose(out);
         return 0;
     }
