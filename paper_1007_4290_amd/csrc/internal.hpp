@@ -222,6 +222,30 @@ struct RecompressJob {
 // launches of up to 32; no job may read what another writes.
 void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rmax, double tol, hipStream_t s);
 
+// One leaf block of an H-matrix product Y += alpha op(B) X: dense (kind 0,
+// a = the m x q block) or factorized (kind 1, a = U (m x r), b = V (q x r),
+// the block U V^t); op is the block (trans 0: X rows xo.., Y rows yo..) or
+// its transpose (trans 1: q output rows).  Leading dimensions m and q.
+struct MatvecOp {
+    const c128* a;
+    const c128* b;
+    int kind, m, q, r, yo, xo;
+};
+// The largest r * ncol of the factorized ops whose temporary fits in shared
+// memory (4096 complex128 entries); past it each op takes max_r * ncol
+// entries of device scratch.
+inline size_t hmatvec_scratch(const MatvecOp* ops, int count, int ncol) {
+    size_t mr = 0;
+    for (int j = 0; j < count; ++j)
+        if (ops[j].kind == 1 && (size_t)ops[j].r > mr) mr = ops[j].r;
+    return mr * ncol <= 4096 ? 0 : mr * ncol * (size_t)count;
+}
+// Y += alpha op(block) X for count ops whose output rows are disjoint, one
+// workgroup each (launches of up to 64); tscratch holds
+// hmatvec_scratch(ops, count, ncol) entries (may be null when that is 0).
+void launch_hmatvec(const MatvecOp* ops, int count, int trans, const c128* X, int ldx, c128* Y, int ldy, int ncol,
+                    c128 alpha, c128* tscratch, hipStream_t s);
+
 // ---- strongly admissible layer factors (complex128, strong.hip) ----
 // Factors of the n layers in the strong format from the frame coefficients
 // of layer_coeffs (dg, eo: n x n; cp: (n-1) x n, all with row stride n):

@@ -445,6 +445,83 @@ __global__ void __launch_bounds__(kWave) zrecompress_batch_kernel(RecompressBatc
     }
 }
 
+// Products of leaf blocks with blocks of vectors, one workgroup each.
+constexpr int kMvBatch = 64;
+constexpr int kMvThreads = 128;
+struct MatvecBatch {
+    MatvecOp op[kMvBatch];
+    const c128* X;
+    c128* Y;
+    c128* T;              // device temporaries of the factorized ops (or null: shared memory)
+    c128 alpha;
+    int ldx, ldy, ncol, trans;
+    size_t tstride;       // entries of T per op
+};
+
+// Y(yo + i, j) += alpha sum_l op(block)(i, l) X(xo + l, j) for op blockIdx.x.
+// op(block) of a dense block is its entries (trans 0) or their transpose;
+// of a factorized block U V^t it is U (V^t X) or V (U^t X), the r x ncol
+// middle product in shared memory.
+__global__ void __launch_bounds__(kMvThreads) hmatvec_kernel(MatvecBatch B) {
+    HIP_DYNAMIC_SHARED(c128, lds)
+    const MatvecOp& o = B.op[blockIdx.x];
+    const int tid = threadIdx.x, ncol = B.ncol, tr = B.trans;
+    const int out = tr ? o.q : o.m, in = tr ? o.m : o.q;
+    const c128* X = B.X + o.xo;
+    c128* Y = B.Y + o.yo;
+    const c128 alpha = B.alpha;
+    if (o.kind == 0) {
+        const c128* D = o.a;
+        for (int e = tid; e < out * ncol; e += kMvThreads) {
+            const int i = e % out, j = e / out;
+            const c128* x = X + (size_t)j * B.ldx;
+            c128 a0 = czero<double>(), a1 = a0;
+            int l = 0;
+            if (tr) {
+                const c128* d = D + (size_t)i * o.m;            // column i of the block = row i of its transpose
+                for (; l + 1 < in; l += 2) {
+                    cfma(a0, d[l], x[l]);
+                    cfma(a1, d[l + 1], x[l + 1]);
+                }
+                if (l < in) cfma(a0, d[l], x[l]);
+            } else {
+                for (; l + 1 < in; l += 2) {
+                    cfma(a0, D[(size_t)l * o.m + i], x[l]);
+                    cfma(a1, D[(size_t)(l + 1) * o.m + i], x[l + 1]);
+                }
+                if (l < in) cfma(a0, D[(size_t)l * o.m + i], x[l]);
+            }
+            Y[(size_t)j * B.ldy + i] += alpha * (a0 + a1);
+        }
+        return;
+    }
+    // factorized: P (in x r) applied first, then Q (out x r)
+    const c128* P = tr ? o.a : o.b;
+    const c128* Q = tr ? o.b : o.a;
+    const int r = o.r;
+    c128* T = B.T ? B.T + (size_t)blockIdx.x * B.tstride : lds;
+    for (int e = tid; e < r * ncol; e += kMvThreads) {
+        const int k = e % r, j = e / r;
+        const c128* p = P + (size_t)k * in;
+        const c128* x = X + (size_t)j * B.ldx;
+        c128 a0 = czero<double>(), a1 = a0;
+        int l = 0;
+        for (; l + 1 < in; l += 2) {
+            cfma(a0, p[l], x[l]);
+            cfma(a1, p[l + 1], x[l + 1]);
+        }
+        if (l < in) cfma(a0, p[l], x[l]);
+        T[e] = a0 + a1;
+    }
+    __syncthreads();
+    for (int e = tid; e < out * ncol; e += kMvThreads) {
+        const int i = e % out, j = e / out;
+        c128 acc = czero<double>();
+        for (int k = 0; k < r; ++k) cfma(acc, Q[(size_t)k * out + i], T[(size_t)j * r + k]);
+        Y[(size_t)j * B.ldy + i] += alpha * acc;
+    }
+}
+
 }  // namespace
 
 void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rmax, double tol, hipStream_t s) {
@@ -485,4 +562,28 @@ void launch_small_inv(int m, const c128* A, int lda, c128* W, c128* X, int* stat
     const size_t bytes = ((size_t)m * (m + 1) + (size_t)m * m) * sizeof(c128);
     const int staged = bytes <= kLdsBytes;
     hipLaunchKernelGGL(zinv_wave_kernel, dim3(1), dim3(kWave), staged ? bytes : 0, s, m, A, lda, W, X, status, staged);
+}
+
+void launch_hmatvec(const MatvecOp* ops, int count, int trans, const c128* X, int ldx, c128* Y, int ldy, int ncol,
+                    c128 alpha, c128* tscratch, hipStream_t s) {
+    const size_t need = hmatvec_scratch(ops, count, ncol);
+    size_t mr = 0;
+    for (int j = 0; j < count; ++j)
+        if (ops[j].kind == 1 && (size_t)ops[j].r > mr) mr = ops[j].r;
+    for (int j0 = 0; j0 < count; j0 += kMvBatch) {
+        MatvecBatch B;
+        const int nb = count - j0 < kMvBatch ? count - j0 : kMvBatch;
+        for (int j = 0; j < nb; ++j) B.op[j] = ops[j0 + j];
+        B.X = X;
+        B.Y = Y;
+        B.alpha = alpha;
+        B.ldx = ldx;
+        B.ldy = ldy;
+        B.ncol = ncol;
+        B.trans = trans;
+        B.tstride = need ? mr * ncol : 0;
+        B.T = need ? tscratch + (size_t)j0 * B.tstride : nullptr;
+        const size_t lds = need ? 0 : mr * ncol * sizeof(c128);
+        hipLaunchKernelGGL(hmatvec_kernel, dim3(nb), dim3(kMvThreads), lds, s, B);
+    }
 }

@@ -429,43 +429,67 @@ struct StrongFactors {
     }
 
     // ---- products with blocks of vectors (accumulating)
+    // The leaves of B's subtree bi as product ops, offsets relative to the
+    // subtree's corner (output rows along t for op = B, along s for B^t).
+    void collect(const HMat& B, int bi, int trans, int rt, int rs, std::vector<MatvecOp>& ops) {
+        const Node& b = B.nd[bi];
+        if (b.kind == 'H') {
+            for (int c = 0; c < 4; ++c) collect(B, b.ch[c], trans, rt, rs, ops);
+            return;
+        }
+        if (b.kind == 'F' && b.rank == 0) return;
+        MatvecOp o;
+        o.kind = b.kind == 'D' ? 0 : 1;
+        o.a = b.kind == 'D' ? b.d : b.u;
+        o.b = b.kind == 'D' ? nullptr : b.v;
+        o.m = b.m();
+        o.q = b.q();
+        o.r = b.kind == 'D' ? 0 : b.rank;
+        const int to = b.t0 - rt, so = b.s0 - rs;
+        o.yo = trans ? so : to;
+        o.xo = trans ? to : so;
+        ops.push_back(o);
+    }
+    // Y += alpha op(B) X over the subtree bi (op = B or B^t): its leaves in
+    // classes of disjoint output rows (intervals coloured greedily in order
+    // of their first row, which uses the fewest classes), one launch per
+    // class, so each row sums its leaves in a fixed order.
+    void hprod(const HMat& B, int bi, int trans, const c128* X, int ldx, int ncol, c128* Y, int ldy, c128 alpha) {
+        if (!ok() || ncol <= 0) return;
+        const Node& b = B.nd[bi];
+        std::vector<MatvecOp> ops;
+        collect(B, bi, trans, b.t0, b.s0, ops);
+        std::vector<int> idx(ops.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return ops[x].yo < ops[y].yo; });
+        std::vector<int> last_end;
+        std::vector<std::vector<MatvecOp>> cls;
+        for (int i : idx) {
+            const int y0 = ops[i].yo, y1 = y0 + (trans ? ops[i].q : ops[i].m);
+            size_t c = 0;
+            while (c < last_end.size() && last_end[c] > y0) ++c;
+            if (c == last_end.size()) {
+                last_end.push_back(y1);
+                cls.emplace_back();
+            } else {
+                last_end[c] = y1;
+            }
+            cls[c].push_back(ops[i]);
+        }
+        for (auto& cl : cls) {
+            const size_t need = hmatvec_scratch(cl.data(), (int)cl.size(), ncol);
+            c128* T = need ? talloc(need) : nullptr;
+            if (!ok()) return;
+            launch_hmatvec(cl.data(), (int)cl.size(), trans, X, ldx, Y, ldy, ncol, alpha, T, s);
+        }
+    }
     // Y (B.m x ncol) += alpha B X
     void matvec(const HMat& B, int bi, const c128* X, int ldx, int ncol, c128* Y, int ldy, c128 alpha) {
-        const Node& b = B.nd[bi];
-        if (!ok()) return;
-        if (b.kind == 'D') {
-            gemm(0, 0, b.m(), ncol, b.q(), alpha, b.d, b.m(), X, ldx, mk(1.0, 0.0), Y, ldy);
-        } else if (b.kind == 'F') {
-            if (b.rank == 0) return;
-            c128* t = talloc((size_t)b.rank * ncol);
-            if (!t) return;
-            gemm(1, 0, b.rank, ncol, b.q(), mk(1.0, 0.0), b.v, b.q(), X, ldx, czero<double>(), t, b.rank);
-            gemm(0, 0, b.m(), ncol, b.rank, alpha, b.u, b.m(), t, b.rank, mk(1.0, 0.0), Y, ldy);
-        } else {
-            for (int c = 0; c < 4; ++c) {
-                const Node& h = B.nd[b.ch[c]];
-                matvec(B, b.ch[c], X + (h.s0 - b.s0), ldx, ncol, Y + (h.t0 - b.t0), ldy, alpha);
-            }
-        }
+        hprod(B, bi, 0, X, ldx, ncol, Y, ldy, alpha);
     }
     // Y (B.q x ncol) += alpha B^t X
     void matvec_t(const HMat& B, int bi, const c128* X, int ldx, int ncol, c128* Y, int ldy, c128 alpha) {
-        const Node& b = B.nd[bi];
-        if (!ok()) return;
-        if (b.kind == 'D') {
-            gemm(1, 0, b.q(), ncol, b.m(), alpha, b.d, b.m(), X, ldx, mk(1.0, 0.0), Y, ldy);
-        } else if (b.kind == 'F') {
-            if (b.rank == 0) return;
-            c128* t = talloc((size_t)b.rank * ncol);
-            if (!t) return;
-            gemm(1, 0, b.rank, ncol, b.m(), mk(1.0, 0.0), b.u, b.m(), X, ldx, czero<double>(), t, b.rank);
-            gemm(0, 0, b.q(), ncol, b.rank, alpha, b.v, b.q(), t, b.rank, mk(1.0, 0.0), Y, ldy);
-        } else {
-            for (int c = 0; c < 4; ++c) {
-                const Node& h = B.nd[b.ch[c]];
-                matvec_t(B, b.ch[c], X + (h.t0 - b.t0), ldx, ncol, Y + (h.s0 - b.s0), ldy, alpha);
-            }
-        }
+        hprod(B, bi, 1, X, ldx, ncol, Y, ldy, alpha);
     }
 
     // ---- small factorizations

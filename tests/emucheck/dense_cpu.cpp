@@ -200,3 +200,35 @@ void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rma
                        J.ov, s);
     }
 }
+
+void launch_hmatvec(const MatvecOp* ops, int count, int trans, const c128* X, int ldx, c128* Y, int ldy, int ncol,
+                    c128 alpha, c128*, hipStream_t) {
+    for (int t = 0; t < count; ++t) {
+        const MatvecOp& o = ops[t];
+        const int out = trans ? o.q : o.m, in = trans ? o.m : o.q;
+        for (int j = 0; j < ncol; ++j) {
+            const c128* x = X + (size_t)j * ldx + o.xo;
+            c128* y = Y + (size_t)j * ldy + o.yo;
+            if (o.kind == 0) {
+                for (int i = 0; i < out; ++i) {
+                    c128 acc = czero<double>();
+                    for (int l = 0; l < in; ++l)
+                        cfma(acc, trans ? o.a[(size_t)i * o.m + l] : o.a[(size_t)l * o.m + i], x[l]);
+                    y[i] += alpha * acc;
+                }
+            } else {
+                const c128* P = trans ? o.a : o.b;
+                const c128* Q = trans ? o.b : o.a;
+                for (int i = 0; i < out; ++i) {
+                    c128 acc = czero<double>();
+                    for (int k = 0; k < o.r; ++k) {
+                        c128 tk = czero<double>();
+                        for (int l = 0; l < in; ++l) cfma(tk, P[(size_t)k * in + l], x[l]);
+                        cfma(acc, Q[(size_t)k * out + i], tk);
+                    }
+                    y[i] += alpha * acc;
+                }
+            }
+        }
+    }
+}

@@ -11,7 +11,8 @@ Each result is checked against what defines it, with numpy for reference
 values: Q R = A with Q orthonormal and R upper triangular; A V with V unitary
 and mutually orthogonal columns whose norms are A's singular values, the
 permutation sorting them, the kept count as specified; A X = I; the
-recompression's product equal to the truncated SVD of the sum.  Working sets
+recompression's product equal to the truncated SVD of the sum; the
+leaf-block products of an H-matrix product equal to the dense products.  Working sets
 below and above the 64 KiB the kernels stage in shared memory are both
 covered.  The shapes
 cover one and several passes of the column and pair loops, more columns than
@@ -209,3 +210,49 @@ def test_recompression_batch(wave, tmp_path):
     cases = [REC_CASES[t % 4][:4] + (1e-6,) for t in range(40)]
     for (inputs, ou, ov), c in zip(_recompress(wave, tmp_path, cases, 6), cases):
         _check_truncation(inputs, ou, ov, 1e-6, 6)
+
+
+@pytest.mark.parametrize("trans", [0, 1])
+@pytest.mark.parametrize("ncol, rank", [(1, 2), (3, 6), (40, 120)])
+def test_leaf_block_products(wave, tmp_path, trans, ncol, rank):
+    """Y += alpha op(block) X over dense and factorized leaf blocks whose
+    output rows are disjoint (one class of a product over an H-matrix), for
+    the blocks and their transposes; the largest case keeps its r x ncol
+    temporaries in device memory instead of shared memory."""
+    rng = np.random.default_rng(500 + 7 * trans + ncol)
+    # output row ranges [0,8), [8,24), [24,30), [40,56), [60,61); input rows anywhere
+    spec = [(0, 8, 12, 0, 0), (1, 16, 10, 8, 20), (0, 6, 6, 24, 3), (1, 16, 16, 40, 0), (0, 1, 30, 60, 1)]
+    rows_x, rows_y = 70, 64
+    X = _rand(rng, rows_x, ncol)
+    Y = _rand(rng, rows_y, ncol)
+    alpha = -0.3 + 1.1j
+    ref = Y.copy()
+    fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    with open(fin, "wb") as fp:
+        fp.write(struct.pack("5i", 4, len(spec), trans, ncol, 0))
+        fp.write(struct.pack("d", 0.0))
+        fp.write(struct.pack("2i", rows_x, rows_y))
+        fp.write(struct.pack("2d", alpha.real, alpha.imag))
+        for M in (X, Y):
+            fp.write(np.asfortranarray(M).tobytes(order="F"))
+        for kind, out, inn, yo, xo in spec:
+            # the block is m x q; op(block) maps `inn` input rows to `out` output rows
+            m, q = (inn, out) if trans else (out, inn)
+            r = rank if kind else 0
+            fp.write(struct.pack("6i", kind, m, q, r, yo, xo))
+            if kind == 0:
+                D = _rand(rng, m, q)
+                blk = D
+                fp.write(np.asfortranarray(D).tobytes(order="F"))
+            else:
+                U, V = _rand(rng, m, r), _rand(rng, q, r)
+                blk = U @ V.T
+                fp.write(np.asfortranarray(U).tobytes(order="F"))
+                fp.write(np.asfortranarray(V).tobytes(order="F"))
+            op = blk.T if trans else blk
+            ref[yo:yo + out] += alpha * (op @ X[xo:xo + inn])
+    r = subprocess.run([wave, fin, fout], capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    out = np.frombuffer(open(fout, "rb").read(), dtype=np.complex128).reshape(ncol, rows_y).T
+    assert np.linalg.norm(out - ref) <= 1e-13 * np.linalg.norm(ref)

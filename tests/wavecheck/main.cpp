@@ -75,6 +75,48 @@ int main(int argc, char** argv) {
         fclose(out);
         return 0;
     }
+    if (op == 4) {
+        // leaf-block products: p = ops, k = trans, lda = ncol; then int32
+        // rows of X and Y, float64 alpha (re, im), X, Y; per op int32 kind,
+        // m, q, r, yo, xo and its data (D: m x q; F: m x r, then q x r)
+        const int count = p, trans = k, ncol = lda;
+        int32_t rw[2];
+        double al[2];
+        if (!rd(fp, rw, 8) || !rd(fp, al, 16)) return 2;
+        const size_t nx = (size_t)rw[0] * ncol, ny = (size_t)rw[1] * ncol;
+        std::vector<c128> hx(nx), hy(ny);
+        if (!rd(fp, hx.data(), nx * 16) || !rd(fp, hy.data(), ny * 16)) return 2;
+        c128 *X = dev<c128>(nx), *Y = dev<c128>(ny);
+        hipMemcpy(X, hx.data(), nx * 16, hipMemcpyHostToDevice);
+        hipMemcpy(Y, hy.data(), ny * 16, hipMemcpyHostToDevice);
+        std::vector<MatvecOp> ops(count);
+        for (int t = 0; t < count; ++t) {
+            int32_t d[6];
+            if (!rd(fp, d, 24)) return 2;
+            MatvecOp& o = ops[t];
+            o.kind = d[0]; o.m = d[1]; o.q = d[2]; o.r = d[3]; o.yo = d[4]; o.xo = d[5];
+            const size_t na = o.kind == 0 ? (size_t)o.m * o.q : (size_t)o.m * o.r, nb = o.kind == 0 ? 0 : (size_t)o.q * o.r;
+            std::vector<c128> h(na + nb);
+            if (!rd(fp, h.data(), h.size() * 16)) return 2;
+            c128* A = dev<c128>(na);
+            hipMemcpy(A, h.data(), na * 16, hipMemcpyHostToDevice);
+            o.a = A;
+            o.b = nullptr;
+            if (nb) {
+                c128* Bv = dev<c128>(nb);
+                hipMemcpy(Bv, h.data() + na, nb * 16, hipMemcpyHostToDevice);
+                o.b = Bv;
+            }
+        }
+        fclose(fp);
+        const size_t need = hmatvec_scratch(ops.data(), count, ncol);
+        c128* T = need ? dev<c128>(need) : nullptr;
+        launch_hmatvec(ops.data(), count, trans, X, rw[0], Y, rw[1], ncol, mk(al[0], al[1]), T, nullptr);
+        FILE* out = fopen(argv[2], "wb");
+        fwrite(Y, 16, ny, out);
+        fclose(out);
+        return 0;
+    }
     std::vector<c128> a((size_t)lda * k);
     if (!rd(fp, a.data(), a.size() * 16)) return 2;
     fclose(fp);
