@@ -369,7 +369,8 @@ def threed_workload(tol, n=15):
     print(f"[bench] 3D n = {n}: factor {fm:.0f} ms, solve {sm:.1f} ms, its {its}", file=sys.stderr, flush=True)
     return {"n": n, "omega": "2pi*2", "pml": 3, "leaf": 16, "rank": 2, "precision": "c128", "factor_ms": fm,
             "solve_ms": sm, "gmres_iters": its, "relres": res, "factor_bytes": s.plan_info()["factor_bytes"],
-            "note": "face factorization walks the block recursion from the host (launch bound)"}
+            "note": "face factorization walks the block recursion from the host (the strong-format kernels of "
+                    "the 2D layers on quadtree face clusters; latency bound)"}
 
 
 def strong_workload(tol, n=127):
@@ -403,9 +404,10 @@ def strong_workload(tol, n=127):
         print(f"[bench] {adm} rank {rank}, n = {n}: factor {fm:.0f} ms, solve {ms:.1f} ms, its {its[0]}",
               file=sys.stderr, flush=True)
         del s
-    row["note"] = ("strong factorization: one kernel launch per small H-arithmetic operation (QR, SVD, inverse "
-                   "on one thread per matrix, products one thread per entry), bound by launch and "
-                   "synchronization latency")
+    row["note"] = ("strong factorization: the host walks the block recursion; each recompression is one "
+                   "wavefront (two QRs, core SVD, kept columns; a walk's recompressions in one launch), "
+                   "H-matrix products one launch per class of leaf blocks with disjoint rows; bound by the "
+                   "latency of that dependent chain")
     return row
 
 
