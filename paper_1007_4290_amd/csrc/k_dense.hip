@@ -130,6 +130,98 @@ __device__ void wave_qr(int p, int k, c128* W, c128* Vh, c128* Q, c128* R) {
     __syncthreads();
 }
 
+// The two QRs of a recompression at once, one per half-wavefront (team t =
+// lane / 32 factors the p_t x k matrix in W_t): both halves run the same
+// instructions on their own matrix, every loop bound, shuffle and barrier
+// taken by the whole wave (a half with nothing left to do idles), so the
+// pair costs about one QR.  Same results as wave_qr on each matrix; ends
+// after a barrier.
+__device__ void wave_qr_pair(int k, int p0, c128* W0, c128* Vh0, c128* Q0, c128* R0, int p1, c128* W1, c128* Vh1,
+                             c128* Q1, c128* R1) {
+    constexpr int kHalf = kWave / 2;
+    const int lane = threadIdx.x, team = lane / kHalf, tl = lane % kHalf, lead = team * kHalf;
+    const int p = team ? p1 : p0;
+    c128* W = team ? W1 : W0;
+    c128* Vh = team ? Vh1 : Vh0;
+    c128* Q = team ? Q1 : Q0;
+    c128* R = team ? R1 : R0;
+    const int kk = min(p, k);
+    const int kk0 = min(p0, k), kk1 = min(p1, k), kmax = max(kk0, kk1);
+    for (size_t e = tl; e < (size_t)p * kk; e += kHalf) Vh[e] = czero<double>();
+    __syncthreads();
+    // one reflector on columns [j0, j_t) of each half's matrix (j_t per half)
+    auto reflect = [&](bool go, int c, const c128* v, double vv, c128* M, int j0, int j1, int j1max) {
+        const double sc = go ? 2.0 / vv : 0.0;
+        for (int jb = j0; jb < j1max; jb += kHalf) {
+            const int nc = go ? max(0, min(kHalf, j1 - jb)) : 0;
+            const int ncmax = min(kHalf, j1max - jb);
+            int kc = 1;
+            while (kc < ncmax) kc <<= 1;                // the same slot count in both halves
+            const int G = kHalf / kc, col = tl & (kc - 1), rg = tl / kc;
+            const bool act = col < nc;
+            c128* Mj = M + (size_t)(jb + (act ? col : 0)) * p;
+            c128 s = czero<double>();
+            if (act)
+                for (int i = c + rg; i < p; i += G) cfma_conj(s, v[i], Mj[i]);
+            for (int m = kc; m < kHalf; m <<= 1) {
+                s.re += __shfl_xor(s.re, m);
+                s.im += __shfl_xor(s.im, m);
+            }
+            s.re = __shfl(s.re, lead + col);
+            s.im = __shfl(s.im, lead + col);
+            const c128 f = sc * s;
+            if (act)
+                for (int i = c + rg; i < p; i += G) Mj[i] -= f * v[i];
+        }
+    };
+    auto half_sum = [&](double x) {
+        for (int m = kHalf / 2; m > 0; m >>= 1) x += __shfl_xor(x, m);
+        return __shfl(x, lead);
+    };
+    for (int c = 0; c < kmax; ++c) {
+        const bool on = c < kk;
+        c128* v = Vh + (size_t)(on ? c : 0) * p;
+        const c128* w = W + (size_t)(on ? c : 0) * p;
+        double part = 0.0;
+        if (on)
+            for (int i = c + tl; i < p; i += kHalf) part += abs2(w[i]);
+        const double nx = sqrt(half_sum(part));
+        const bool go = on && nx != 0.0;
+        double vv = 1.0;
+        if (go) {
+            const c128 x0 = w[c];
+            const double a0 = hypot(x0.re, x0.im);
+            const c128 ph = a0 > 0.0 ? mk(x0.re / a0, x0.im / a0) : mk(1.0, 0.0);
+            for (int i = c + tl; i < p; i += kHalf) v[i] = i == c ? x0 + nx * ph : w[i];
+            vv = 2.0 * nx * (nx + a0);
+        }
+        __syncthreads();
+        reflect(go, c, v, vv, W, c, k, k);
+        __syncthreads();
+    }
+    for (size_t e = tl; e < (size_t)kk * k; e += kHalf) {
+        const int i = (int)(e % kk), j = (int)(e / kk);
+        R[e] = i <= j ? W[(size_t)j * p + i] : czero<double>();
+    }
+    for (size_t e = tl; e < (size_t)p * kk; e += kHalf) {
+        const int i = (int)(e % p), j = (int)(e / p);
+        Q[e] = mk(i == j ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    for (int c = kmax - 1; c >= 0; --c) {
+        const bool on = c < kk;
+        const c128* v = Vh + (size_t)(on ? c : 0) * p;
+        double part = 0.0;
+        if (on)
+            for (int i = c + tl; i < p; i += kHalf) part += abs2(v[i]);
+        const double vv = half_sum(part);
+        const bool go = on && vv != 0.0;
+        reflect(go, c, v, vv, Q, c, kk, kmax);
+        __syncthreads();
+    }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(kWave) zqr_wave_kernel(int p, int k, const c128* __restrict__ A, int lda, c128* W,
                                                          c128* Vh, c128* Q, c128* R, int staged) {
     HIP_DYNAMIC_SHARED(c128, lds)
@@ -411,8 +503,7 @@ __global__ void __launch_bounds__(kWave) zrecompress_batch_kernel(RecompressBatc
         W2[e] = j < k1 ? J.av[(size_t)j * q + i] : J.V[(size_t)(j - k1) * J.ldv + i];
     }
     __syncthreads();
-    wave_qr(m, k, W1, Vh1, Q1, R1);
-    wave_qr(q, k, W2, Vh2, Q2, R2);
+    wave_qr_pair(k, m, W1, Vh1, Q1, R1, q, W2, Vh2, Q2, R2);
     for (size_t e = lane; e < (size_t)kk1 * kk2; e += kWave) {
         const int i = (int)(e % kk1), j = (int)(e / kk1);
         c128 acc = czero<double>();
