@@ -391,22 +391,33 @@ struct StrongFactors {
     }
 
     // ---- structure
+    // A zero H-matrix with the block structure of M's subtree idx: its dense
+    // blocks share one allocation, cleared by one launch.
     HMat zeros_like(const HMat& M, int idx) {
         HMat R;
         copy_shape(R, M, idx, true);
+        size_t tot = 0;
+        for (const Node& b : R.nd)
+            if (b.kind == 'D') tot += ((size_t)b.m() * b.q() + 15) & ~(size_t)15;
+        if (tot == 0 || !ok()) return R;
+        c128* base = talloc(tot);
+        if (!base) return R;
+        zero(base, (int)tot, 1, (int)tot);
+        size_t at = 0;
+        for (Node& b : R.nd)
+            if (b.kind == 'D') {
+                b.d = base + at;
+                at += ((size_t)b.m() * b.q() + 15) & ~(size_t)15;
+            }
         return R;
     }
     int copy_shape(HMat& R, const HMat& M, int idx, bool fresh) {
         const int k = (int)R.nd.size();
         Node b = M.nd[idx];
-        if (fresh) {
+        if (fresh) {            // data pointers set by the caller
             b.u = b.v = nullptr;
             b.rank = 0;
             b.d = nullptr;
-            if (b.kind == 'D') {
-                b.d = talloc((size_t)b.m() * b.q());
-                if (b.d) zero(b.d, b.m(), b.q(), b.m());
-            }
         }
         R.nd.push_back(b);
         if (b.kind == 'H')

@@ -205,9 +205,9 @@ def test_recompression(wave, tmp_path, case):
 
 
 def test_recompression_batch(wave, tmp_path):
-    """Forty jobs in one call (two launches of up to 32 workgroups), with
+    """Thirty-four jobs in one call (two launches of up to 32 workgroups), with
     working sets in and beyond the 64 KiB of shared memory side by side."""
-    cases = [REC_CASES[t % 4][:4] + (1e-6,) for t in range(40)]
+    cases = [REC_CASES[t % 2][:4] + (1e-6,) for t in range(33)] + [REC_CASES[2][:4] + (1e-6,)]
     for (inputs, ou, ov), c in zip(_recompress(wave, tmp_path, cases, 6), cases):
         _check_truncation(inputs, ou, ov, 1e-6, 6)
 
