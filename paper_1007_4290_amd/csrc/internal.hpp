@@ -226,6 +226,7 @@ void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rma
 // a = the m x q block) or factorized (kind 1, a = U (m x r), b = V (q x r),
 // the block U V^t); op is the block (trans 0: X rows xo.., Y rows yo..) or
 // its transpose (trans 1: q output rows).  Leading dimensions m and q.
+// Kind 2 clears output rows yo.. (m = q = their count).
 struct MatvecOp {
     const c128* a;
     const c128* b;
@@ -240,11 +241,12 @@ inline size_t hmatvec_scratch(const MatvecOp* ops, int count, int ncol) {
         if (ops[j].kind == 1 && (size_t)ops[j].r > mr) mr = ops[j].r;
     return mr * ncol <= 4096 ? 0 : mr * ncol * (size_t)count;
 }
-// Y += alpha op(block) X for count ops whose output rows are disjoint, one
-// workgroup each (launches of up to 64); tscratch holds
-// hmatvec_scratch(ops, count, ncol) entries (may be null when that is 0).
-void launch_hmatvec(const MatvecOp* ops, int count, int trans, const c128* X, int ldx, c128* Y, int ldy, int ncol,
-                    c128 alpha, c128* tscratch, hipStream_t s);
+// Y += alpha op(block) X (Y = alpha op(block) X when assign) for count ops
+// whose output rows are disjoint, one workgroup each (launches of up to 64);
+// tscratch holds hmatvec_scratch(ops, count, ncol) entries (may be null
+// when that is 0).
+void launch_hmatvec(const MatvecOp* ops, int count, int trans, int assign, const c128* X, int ldx, c128* Y, int ldy,
+                    int ncol, c128 alpha, c128* tscratch, hipStream_t s);
 
 // ---- strongly admissible layer factors (complex128, strong.hip) ----
 // Factors of the n layers in the strong format from the frame coefficients

@@ -545,11 +545,12 @@ struct MatvecBatch {
     c128* Y;
     c128* T;              // device temporaries of the factorized ops (or null: shared memory)
     c128 alpha;
-    int ldx, ldy, ncol, trans;
+    int ldx, ldy, ncol, trans, assign;
     size_t tstride;       // entries of T per op
 };
 
-// Y(yo + i, j) += alpha sum_l op(block)(i, l) X(xo + l, j) for op blockIdx.x.
+// Y(yo + i, j) += alpha sum_l op(block)(i, l) X(xo + l, j) for op blockIdx.x
+// (= instead of += when B.assign; kind 2 clears its rows).
 // op(block) of a dense block is its entries (trans 0) or their transpose;
 // of a factorized block U V^t it is U (V^t X) or V (U^t X), the r x ncol
 // middle product in shared memory.
@@ -561,6 +562,11 @@ __global__ void __launch_bounds__(kMvThreads) hmatvec_kernel(MatvecBatch B) {
     const c128* X = B.X + o.xo;
     c128* Y = B.Y + o.yo;
     const c128 alpha = B.alpha;
+    if (o.kind == 2) {
+        for (int e = tid; e < o.m * ncol; e += kMvThreads) Y[(size_t)(e / o.m) * B.ldy + e % o.m] = czero<double>();
+        return;
+    }
+    const bool add = !B.assign;
     if (o.kind == 0) {
         const c128* D = o.a;
         for (int e = tid; e < out * ncol; e += kMvThreads) {
@@ -582,7 +588,8 @@ __global__ void __launch_bounds__(kMvThreads) hmatvec_kernel(MatvecBatch B) {
                 }
                 if (l < in) cfma(a0, D[(size_t)l * o.m + i], x[l]);
             }
-            Y[(size_t)j * B.ldy + i] += alpha * (a0 + a1);
+            const c128 v = alpha * (a0 + a1);
+            Y[(size_t)j * B.ldy + i] = add ? Y[(size_t)j * B.ldy + i] + v : v;
         }
         return;
     }
@@ -609,7 +616,8 @@ __global__ void __launch_bounds__(kMvThreads) hmatvec_kernel(MatvecBatch B) {
         const int i = e % out, j = e / out;
         c128 acc = czero<double>();
         for (int k = 0; k < r; ++k) cfma(acc, Q[(size_t)k * out + i], T[(size_t)j * r + k]);
-        Y[(size_t)j * B.ldy + i] += alpha * acc;
+        const c128 v = alpha * acc;
+        Y[(size_t)j * B.ldy + i] = add ? Y[(size_t)j * B.ldy + i] + v : v;
     }
 }
 
@@ -655,8 +663,8 @@ void launch_small_inv(int m, const c128* A, int lda, c128* W, c128* X, int* stat
     hipLaunchKernelGGL(zinv_wave_kernel, dim3(1), dim3(kWave), staged ? bytes : 0, s, m, A, lda, W, X, status, staged);
 }
 
-void launch_hmatvec(const MatvecOp* ops, int count, int trans, const c128* X, int ldx, c128* Y, int ldy, int ncol,
-                    c128 alpha, c128* tscratch, hipStream_t s) {
+void launch_hmatvec(const MatvecOp* ops, int count, int trans, int assign, const c128* X, int ldx, c128* Y, int ldy,
+                    int ncol, c128 alpha, c128* tscratch, hipStream_t s) {
     const size_t need = hmatvec_scratch(ops, count, ncol);
     size_t mr = 0;
     for (int j = 0; j < count; ++j)
@@ -672,6 +680,7 @@ void launch_hmatvec(const MatvecOp* ops, int count, int trans, const c128* X, in
         B.ldy = ldy;
         B.ncol = ncol;
         B.trans = trans;
+        B.assign = assign;
         B.tstride = need ? mr * ncol : 0;
         B.T = need ? tscratch + (size_t)j0 * B.tstride : nullptr;
         const size_t lds = need ? 0 : mr * ncol * sizeof(c128);

@@ -461,11 +461,14 @@ struct StrongFactors {
         o.xo = trans ? to : so;
         ops.push_back(o);
     }
-    // Y += alpha op(B) X over the subtree bi (op = B or B^t): its leaves in
-    // classes of disjoint output rows (intervals coloured greedily in order
-    // of their first row, which uses the fewest classes), one launch per
-    // class, so each row sums its leaves in a fixed order.
-    void hprod(const HMat& B, int bi, int trans, const c128* X, int ldx, int ncol, c128* Y, int ldy, c128 alpha) {
+    // Y += alpha op(B) X over the subtree bi (op = B or B^t), or Y = alpha
+    // op(B) X when assign: its leaves in classes of disjoint output rows
+    // (intervals coloured greedily in order of their first row, which uses
+    // the fewest classes), one launch per class, so each row sums its leaves
+    // in a fixed order.  With assign the first class writes instead of adding
+    // and clears the rows none of its leaves cover.
+    void hprod(const HMat& B, int bi, int trans, const c128* X, int ldx, int ncol, c128* Y, int ldy, c128 alpha,
+               bool assign = false) {
         if (!ok() || ncol <= 0) return;
         const Node& b = B.nd[bi];
         std::vector<MatvecOp> ops;
@@ -487,12 +490,43 @@ struct StrongFactors {
             }
             cls[c].push_back(ops[i]);
         }
-        for (auto& cl : cls) {
+        const int rows = trans ? b.q() : b.m();
+        if (assign) {
+            if (cls.empty()) cls.emplace_back();
+            // the rows class 0 leaves uncovered (its intervals are sorted and disjoint)
+            std::vector<MatvecOp> gaps;
+            int at = 0;
+            for (const MatvecOp& o : cls[0]) {
+                if (o.yo > at) gaps.push_back(clear_op(at, o.yo - at));
+                at = o.yo + (trans ? o.q : o.m);
+            }
+            if (at < rows) gaps.push_back(clear_op(at, rows - at));
+            cls[0].insert(cls[0].end(), gaps.begin(), gaps.end());
+        }
+        for (size_t c = 0; c < cls.size(); ++c) {
+            auto& cl = cls[c];
             const size_t need = hmatvec_scratch(cl.data(), (int)cl.size(), ncol);
             c128* T = need ? talloc(need) : nullptr;
             if (!ok()) return;
-            launch_hmatvec(cl.data(), (int)cl.size(), trans, X, ldx, Y, ldy, ncol, alpha, T, s);
+            launch_hmatvec(cl.data(), (int)cl.size(), trans, assign && c == 0, X, ldx, Y, ldy, ncol, alpha, T, s);
         }
+    }
+    static MatvecOp clear_op(int y0, int count) {
+        MatvecOp o;
+        o.a = o.b = nullptr;
+        o.kind = 2;
+        o.m = o.q = count;
+        o.r = 0;
+        o.yo = y0;
+        o.xo = 0;
+        return o;
+    }
+    // Y (B.m x ncol) = alpha B X and Y (B.q x ncol) = alpha B^t X
+    void matvec_set(const HMat& B, int bi, const c128* X, int ldx, int ncol, c128* Y, int ldy, c128 alpha) {
+        hprod(B, bi, 0, X, ldx, ncol, Y, ldy, alpha, true);
+    }
+    void matvec_t_set(const HMat& B, int bi, const c128* X, int ldx, int ncol, c128* Y, int ldy, c128 alpha) {
+        hprod(B, bi, 1, X, ldx, ncol, Y, ldy, alpha, true);
     }
     // Y (B.m x ncol) += alpha B X
     void matvec(const HMat& B, int bi, const c128* X, int ldx, int ncol, c128* Y, int ldy, c128 alpha) {
@@ -587,10 +621,8 @@ struct StrongFactors {
         const size_t cnt = (size_t)q * ell;
         hipLaunchKernelGGL(zrandn_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, seed + draws, Om);
         draws += 0x9E3779B97F4A7C15ull;
-        zero(Y1, mid, ell, mid);
-        matvec(H, hi, Om, q, ell, Y1, mid, mk(1.0, 0.0));
-        zero(Y, m, ell, m);
-        matvec(G, gi, Y1, mid, ell, Y, m, mk(1.0, 0.0));
+        matvec_set(H, hi, Om, q, ell, Y1, mid, mk(1.0, 0.0));
+        matvec_set(G, gi, Y1, mid, ell, Y, m, mk(1.0, 0.0));
         c128 *Q, *R;
         qr(m, ell, Y, m, Q, R);                       // ell <= m: Q is m x ell
         c128* Qc = talloc((size_t)m * ell);
@@ -598,10 +630,8 @@ struct StrongFactors {
         c128* M = talloc((size_t)q * ell);
         if (!ok()) return 0;
         geam(m, ell, mk(1.0, 0.0), 2, Q, m, czero<double>(), nullptr, 0, Qc, m);
-        zero(M1, mid, ell, mid);
-        matvec_t(G, gi, Qc, m, ell, M1, mid, mk(1.0, 0.0));
-        zero(M, q, ell, q);
-        matvec_t(H, hi, M1, mid, ell, M, q, mk(1.0, 0.0));
+        matvec_t_set(G, gi, Qc, m, ell, M1, mid, mk(1.0, 0.0));
+        matvec_t_set(H, hi, M1, mid, ell, M, q, mk(1.0, 0.0));
         c128* Vs;
         int* perm;
         const int* rk = svd(q, ell, M, q, Vs, perm);
@@ -654,15 +684,13 @@ struct StrongFactors {
             if (g.rank == 0) return;
             c128* Vn = talloc((size_t)h.q() * g.rank);
             if (!ok()) return;
-            zero(Vn, h.q(), g.rank, h.q());
-            matvec_t(H, hi, g.v, g.q(), g.rank, Vn, h.q(), mk(1.0, 0.0));
+            matvec_t_set(H, hi, g.v, g.q(), g.rank, Vn, h.q(), mk(1.0, 0.0));
             add_lowrank(T, ti, g.u, g.m(), Vn, h.q(), g.rank, alpha);
         } else if (h.kind == 'F') {                     // (G U_h) V_h^t
             if (h.rank == 0) return;
             c128* Un = talloc((size_t)g.m() * h.rank);
             if (!ok()) return;
-            zero(Un, g.m(), h.rank, g.m());
-            matvec(G, gi, h.u, h.m(), h.rank, Un, g.m(), mk(1.0, 0.0));
+            matvec_set(G, gi, h.u, h.m(), h.rank, Un, g.m(), mk(1.0, 0.0));
             add_lowrank(T, ti, Un, g.m(), h.v, h.q(), h.rank, alpha);
         } else if (tb.kind == 'D') {
             gemm(0, 0, tb.m(), tb.q(), g.q(), alpha, g.d, g.m(), h.d, h.m(), mk(1.0, 0.0), T.nd[ti].d, tb.m());
@@ -948,8 +976,7 @@ int apply_layers(StrongFactors* sf, int nrhs, Gather gather, Scatter scatter, hi
     for (int m = 0; m < nl && sf->ok(); ++m) {
         gather(m, m > 0 ? sf->cpk + (size_t)(m - 1) * N : (const c128*)nullptr,
                m > 0 ? W + lay * (m - 1) : (const c128*)nullptr, L0);
-        sf->zero(W + lay * m, N, nrhs, N);
-        sf->matvec(sf->T[m], 0, L0, N, nrhs, W + lay * m, N, mk(1.0, 0.0));
+        sf->matvec_set(sf->T[m], 0, L0, N, nrhs, W + lay * m, N, mk(1.0, 0.0));
         sf->tmp.reset();          // F-block scratch is reused in stream order
     }
     for (int m = nl - 1; m >= 0 && sf->ok(); --m) {

@@ -201,11 +201,16 @@ void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rma
     }
 }
 
-void launch_hmatvec(const MatvecOp* ops, int count, int trans, const c128* X, int ldx, c128* Y, int ldy, int ncol,
-                    c128 alpha, c128*, hipStream_t) {
+void launch_hmatvec(const MatvecOp* ops, int count, int trans, int assign, const c128* X, int ldx, c128* Y, int ldy,
+                    int ncol, c128 alpha, c128*, hipStream_t) {
     for (int t = 0; t < count; ++t) {
         const MatvecOp& o = ops[t];
         const int out = trans ? o.q : o.m, in = trans ? o.m : o.q;
+        const int cleared = o.kind == 2 ? o.m : out;
+        if (o.kind == 2 || assign)
+            for (int j = 0; j < ncol; ++j)
+                for (int i = 0; i < cleared; ++i) Y[(size_t)j * ldy + o.yo + i] = czero<double>();
+        if (o.kind == 2) continue;
         for (int j = 0; j < ncol; ++j) {
             const c128* x = X + (size_t)j * ldx + o.xo;
             c128* y = Y + (size_t)j * ldy + o.yo;

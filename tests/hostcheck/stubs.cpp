@@ -178,12 +178,16 @@ void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rma
         recompress_ranges(J.m, J.q, J.k1, J.k2, rmax, J.au, J.av, J.U, J.ldu, J.V, J.ldv, J.work, J.ou, J.ov);
     }
 }
-void launch_hmatvec(const MatvecOp* ops, int count, int trans, const c128* X, int ldx, c128* Y, int ldy, int ncol,
-                    c128, c128* tscratch, hipStream_t) {
+void launch_hmatvec(const MatvecOp* ops, int count, int trans, int, const c128* X, int ldx, c128* Y, int ldy,
+                    int ncol, c128, c128* tscratch, hipStream_t) {
     need(tscratch, hmatvec_scratch(ops, count, ncol) * 16, "hmatvec T");
     for (int t = 0; t < count; ++t) {
         const MatvecOp& o = ops[t];
         const int out = trans ? o.q : o.m, in = trans ? o.m : o.q;
+        if (o.kind == 2) {
+            if (ncol > 0) need(Y + o.yo, ((size_t)(ncol - 1) * ldy + o.m) * 16, "hmatvec cleared rows");
+            continue;
+        }
         if (o.kind == 0) need(o.a, (size_t)o.m * o.q * 16, "hmatvec D");
         else { need(o.a, (size_t)o.m * o.r * 16, "hmatvec U"); need(o.b, (size_t)o.q * o.r * 16, "hmatvec V"); }
         if (ncol > 0) {

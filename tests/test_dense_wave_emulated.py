@@ -212,16 +212,19 @@ def test_recompression_batch(wave, tmp_path):
         _check_truncation(inputs, ou, ov, 1e-6, 6)
 
 
+@pytest.mark.parametrize("assign", [0, 1])
 @pytest.mark.parametrize("trans", [0, 1])
 @pytest.mark.parametrize("ncol, rank", [(1, 2), (3, 6), (40, 120)])
-def test_leaf_block_products(wave, tmp_path, trans, ncol, rank):
-    """Y += alpha op(block) X over dense and factorized leaf blocks whose
-    output rows are disjoint (one class of a product over an H-matrix), for
-    the blocks and their transposes; the largest case keeps its r x ncol
-    temporaries in device memory instead of shared memory."""
-    rng = np.random.default_rng(500 + 7 * trans + ncol)
-    # output row ranges [0,8), [8,24), [24,30), [40,56), [60,61); input rows anywhere
-    spec = [(0, 8, 12, 0, 0), (1, 16, 10, 8, 20), (0, 6, 6, 24, 3), (1, 16, 16, 40, 0), (0, 1, 30, 60, 1)]
+def test_leaf_block_products(wave, tmp_path, assign, trans, ncol, rank):
+    """Y += alpha op(block) X (Y = ... when assigning) over dense and
+    factorized leaf blocks whose output rows are disjoint (one class of a
+    product over an H-matrix), for the blocks and their transposes, with a
+    block of cleared rows; the largest case keeps its r x ncol temporaries in
+    device memory instead of shared memory."""
+    rng = np.random.default_rng(500 + 7 * trans + ncol + 3 * assign)
+    # output row ranges [0,8), [8,24), [24,30), [40,56), [60,61), cleared [30,40); input rows anywhere
+    spec = [(0, 8, 12, 0, 0), (1, 16, 10, 8, 20), (0, 6, 6, 24, 3), (1, 16, 16, 40, 0), (0, 1, 30, 60, 1),
+            (2, 10, 0, 30, 0)]
     rows_x, rows_y = 70, 64
     X = _rand(rng, rows_x, ncol)
     Y = _rand(rng, rows_y, ncol)
@@ -229,13 +232,17 @@ def test_leaf_block_products(wave, tmp_path, trans, ncol, rank):
     ref = Y.copy()
     fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
     with open(fin, "wb") as fp:
-        fp.write(struct.pack("5i", 4, len(spec), trans, ncol, 0))
+        fp.write(struct.pack("5i", 4, len(spec), trans + 2 * assign, ncol, 0))
         fp.write(struct.pack("d", 0.0))
         fp.write(struct.pack("2i", rows_x, rows_y))
         fp.write(struct.pack("2d", alpha.real, alpha.imag))
         for M in (X, Y):
             fp.write(np.asfortranarray(M).tobytes(order="F"))
         for kind, out, inn, yo, xo in spec:
+            if kind == 2:
+                fp.write(struct.pack("6i", 2, out, out, 0, yo, 0))
+                ref[yo:yo + out] = 0.0
+                continue
             # the block is m x q; op(block) maps `inn` input rows to `out` output rows
             m, q = (inn, out) if trans else (out, inn)
             r = rank if kind else 0
@@ -250,7 +257,7 @@ def test_leaf_block_products(wave, tmp_path, trans, ncol, rank):
                 fp.write(np.asfortranarray(U).tobytes(order="F"))
                 fp.write(np.asfortranarray(V).tobytes(order="F"))
             op = blk.T if trans else blk
-            ref[yo:yo + out] += alpha * (op @ X[xo:xo + inn])
+            ref[yo:yo + out] = (0.0 if assign else ref[yo:yo + out]) + alpha * (op @ X[xo:xo + inn])
     r = subprocess.run([wave, fin, fout], capture_output=True, text=True, timeout=600,
                        env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]

@@ -79,7 +79,7 @@ int main(int argc, char** argv) {
         // leaf-block products: p = ops, k = trans, lda = ncol; then int32
         // rows of X and Y, float64 alpha (re, im), X, Y; per op int32 kind,
         // m, q, r, yo, xo and its data (D: m x q; F: m x r, then q x r)
-        const int count = p, trans = k, ncol = lda;
+        const int count = p, trans = k & 1, assign = k >> 1, ncol = lda;
         int32_t rw[2];
         double al[2];
         if (!rd(fp, rw, 8) || !rd(fp, al, 16)) return 2;
@@ -95,7 +95,8 @@ int main(int argc, char** argv) {
             if (!rd(fp, d, 24)) return 2;
             MatvecOp& o = ops[t];
             o.kind = d[0]; o.m = d[1]; o.q = d[2]; o.r = d[3]; o.yo = d[4]; o.xo = d[5];
-            const size_t na = o.kind == 0 ? (size_t)o.m * o.q : (size_t)o.m * o.r, nb = o.kind == 0 ? 0 : (size_t)o.q * o.r;
+            const size_t na = o.kind == 0 ? (size_t)o.m * o.q : o.kind == 1 ? (size_t)o.m * o.r : 0;
+            const size_t nb = o.kind == 1 ? (size_t)o.q * o.r : 0;
             std::vector<c128> h(na + nb);
             if (!rd(fp, h.data(), h.size() * 16)) return 2;
             c128* A = dev<c128>(na);
@@ -111,7 +112,7 @@ int main(int argc, char** argv) {
         fclose(fp);
         const size_t need = hmatvec_scratch(ops.data(), count, ncol);
         c128* T = need ? dev<c128>(need) : nullptr;
-        launch_hmatvec(ops.data(), count, trans, X, rw[0], Y, rw[1], ncol, mk(al[0], al[1]), T, nullptr);
+        launch_hmatvec(ops.data(), count, trans, assign, X, rw[0], Y, rw[1], ncol, mk(al[0], al[1]), T, nullptr);
         FILE* out = fopen(argv[2], "wb");
         fwrite(Y, 16, ny, out);
         fclose(out);
