@@ -263,3 +263,36 @@ def test_leaf_block_products(wave, tmp_path, assign, trans, ncol, rank):
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     out = np.frombuffer(open(fout, "rb").read(), dtype=np.complex128).reshape(ncol, rows_y).T
     assert np.linalg.norm(out - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("a, b", [(16, 10), (30, 12)])
+def test_svd_with_a_cut_keeps_the_leading_triplets(wave, tmp_path, a, b):
+    """Singular values graded from 1 down to 1e-13 and a cut at 1e-6: the
+    kept triplets match numpy, the kept count is the number above the cut,
+    and the columns past it stay below the cut."""
+    rng = np.random.default_rng(600 + a + b)
+    Uq, _ = np.linalg.qr(_rand(rng, a, b))
+    Vq, _ = np.linalg.qr(_rand(rng, b, b))
+    sv = 10.0 ** -np.linspace(0, 13, b)
+    A = (Uq * sv) @ Vq.conj().T
+    tol, rmax = 1e-6, b
+    out = _run(wave, tmp_path, 1, A, a, b, rmax=rmax, tol=tol)
+    AV, off = _mat(out, 0, a, b)
+    V, off = _mat(out, off, b, b)
+    sig = np.frombuffer(out, dtype=np.float64, count=b, offset=off)
+    off += 8 * b
+    perm = np.frombuffer(out, dtype=np.int32, count=b, offset=off)
+    off += 4 * b
+    rank = struct.unpack_from("i", out, off)[0]
+    keep = int(np.sum(sv > tol * sv[0]))
+    assert rank == keep
+    assert np.allclose(V.conj().T @ V, np.eye(b), atol=1e-12)
+    assert np.linalg.norm(A @ V - AV) <= 1e-12 * np.linalg.norm(A)
+    assert np.allclose(sig[perm][:keep], sv[:keep], rtol=1e-10)
+    assert np.all(sig[perm][keep:] < tol * sv[0])
+    # the kept left directions are orthonormal and match the truncated SVD
+    Ur = AV[:, perm[:keep]] / sig[perm[:keep]]
+    assert np.allclose(Ur.conj().T @ Ur, np.eye(keep), atol=1e-10)
+    best = (Uq[:, :keep] * sv[:keep]) @ Vq[:, :keep].conj().T
+    approx = AV[:, perm[:keep]] @ V[:, perm[:keep]].conj().T
+    assert np.linalg.norm(approx - best) <= 1e-10
