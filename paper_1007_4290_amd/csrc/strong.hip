@@ -27,9 +27,14 @@
 //         Martinsson and Tropp (2011): rmax + 8 complex Gaussian test
 //         vectors, QR of the sampled range, SVD of the projected block.
 // The QR, SVD and inverse kernels (k_dense.hip) take one small matrix per
-// wavefront: blocks are at most a few hundred entries on a side and the
-// factorization is bound by the dependent chain of the block recursion, not
-// by arithmetic.
+// wavefront, and so does the fused recompression (both QRs, the core SVD and
+// the kept columns in one kernel); the recompressions of one tree walk share
+// a launch, and a product of an H-matrix with a block of vectors goes out as
+// one launch per class of leaf blocks with disjoint output rows (hprod).
+// Blocks are at most a few hundred entries on a side and the factorization
+// is bound by the dependent chain of the block recursion, not by arithmetic.
+// No rank is read back: a factor's width is its kept rank's upper bound, so
+// the launch sequence of a layer does not depend on the data.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
