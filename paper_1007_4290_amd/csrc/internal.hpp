@@ -207,20 +207,29 @@ __host__ __device__ inline RecompressLayout recompress_layout(int m, int q, int 
     L.total = o;
     return L;
 }
-// One recompression: the truncated product of [au, alpha U] (m x k1 + k2)
-// and [av, V] (q x k1 + k2) as ou (m x r) and ov (q x r), r = min(m, q,
-// k1 + k2, rmax), the columns past the kept rank (singular values above
-// tol * sigma_1, at most rmax) zero; work holds recompress_layout(m, q,
-// k1 + k2, rmax).total entries.  au, av have leading dimensions m and q.
-struct RecompressJob {
+// One block operation of a batch (kind):
+//   JOB_RECOMPRESS  the truncated product of [au, alpha U] (m x k1 + k2) and
+//                   [av, V] (q x k1 + k2) as ou (m x r) and ov (q x r), r =
+//                   min(m, q, k1 + k2, rmax), the columns past the kept rank
+//                   (singular values above tol * sigma_1, at most rmax) zero;
+//                   work holds recompress_layout(m, q, k1 + k2, rmax).total
+//                   entries; au, av have leading dimensions m and q;
+//   JOB_SUM         ou = au + alpha av (m x q, leading dimension m);
+//   JOB_LOWRANK     ou += alpha U V^t (ou m x q with leading dimension m; U
+//                   m x k2, V q x k2 with ldu, ldv);
+//   JOB_SCALE       ou(i, j) = U[i] au(i, j) (V ? V[j] : 1) (m x q, leading
+//                   dimension m);
+//   JOB_COPY        ou[e] = au[e], e < m q.
+enum { JOB_RECOMPRESS = 0, JOB_SUM = 1, JOB_LOWRANK = 2, JOB_SCALE = 3, JOB_COPY = 4 };
+struct BlockJob {
     const c128 *au, *av, *U, *V;
     c128 *work, *ou, *ov;
     c128 alpha;
-    int m, q, k1, k2, ldu, ldv;
+    int kind, m, q, k1, k2, ldu, ldv;
 };
-// count independent recompressions (host array), one workgroup each, in
+// count independent block operations (host array), one workgroup each, in
 // launches of up to 32; no job may read what another writes.
-void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rmax, double tol, hipStream_t s);
+void launch_block_jobs(const BlockJob* jobs, int count, int rmax, double tol, hipStream_t s);
 
 // One leaf block of an H-matrix product Y += alpha op(B) X: dense (kind 0,
 // a = the m x q block) or factorized (kind 1, a = U (m x r), b = V (q x r),

@@ -465,23 +465,56 @@ __global__ void __launch_bounds__(kWave) zinv_wave_kernel(int m, const c128* __r
     if (staged) wave_copy(m, m, X, m, Xg, m);
 }
 
-// Recompressions of one launch, one workgroup each, passed by value.
-constexpr int kRecBatch = 32;
-struct RecompressBatch {
-    RecompressJob job[kRecBatch];
+// Block operations of one launch, one workgroup each, passed by value.
+constexpr int kJobBatch = 32;
+struct BlockJobBatch {
+    BlockJob job[kJobBatch];
     double tol;
     int rmax;
     unsigned lds;          // shared-memory bytes of the launch
 };
 
-// Job blockIdx.x: the truncated product of [au, alpha U] (m x k) and [av, V]
-// (q x k), k = k1 + k2: QR of both stacked factors, SVD of the core C =
-// R1 R2^t, and the factors ou = Q1 (C V)_r (m x r) and ov = Q2 conj(V_r)
-// (q x r), r = min(m, q, k, rmax) columns of which those past the kept rank
-// are zero.
-__global__ void __launch_bounds__(kWave) zrecompress_batch_kernel(RecompressBatch B) {
+// The dense block operations of a batch (one workgroup, lanes over entries).
+__device__ void dense_job(const BlockJob& J) {
+    const int m = J.m, q = J.q;
+    const size_t n = (size_t)m * q;
+    const c128 alpha = J.alpha;
+    for (size_t e = threadIdx.x; e < n; e += kWave) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        c128 v;
+        if (J.kind == JOB_SUM) {
+            v = J.au[e] + alpha * J.av[e];
+        } else if (J.kind == JOB_LOWRANK) {
+            c128 a0 = czero<double>(), a1 = a0;
+            int l = 0;
+            for (; l + 1 < J.k2; l += 2) {
+                cfma(a0, J.U[(size_t)l * J.ldu + i], J.V[(size_t)l * J.ldv + j]);
+                cfma(a1, J.U[(size_t)(l + 1) * J.ldu + i], J.V[(size_t)(l + 1) * J.ldv + j]);
+            }
+            if (l < J.k2) cfma(a0, J.U[(size_t)l * J.ldu + i], J.V[(size_t)l * J.ldv + j]);
+            v = J.ou[e] + alpha * (a0 + a1);
+        } else if (J.kind == JOB_SCALE) {
+            v = J.U[i] * J.au[e];
+            if (J.V) v = v * J.V[j];
+        } else {
+            v = J.au[e];
+        }
+        J.ou[e] = v;
+    }
+}
+
+// Job blockIdx.x: a dense block operation (dense_job), or the truncated
+// product of [au, alpha U] (m x k) and [av, V] (q x k), k = k1 + k2: QR of
+// both stacked factors, SVD of the core C = R1 R2^t, and the factors ou =
+// Q1 (C V)_r (m x r) and ov = Q2 conj(V_r) (q x r), r = min(m, q, k, rmax)
+// columns of which those past the kept rank are zero.
+__global__ void __launch_bounds__(kWave) block_jobs_kernel(BlockJobBatch B) {
     HIP_DYNAMIC_SHARED(c128, lds)
-    const RecompressJob& J = B.job[blockIdx.x];
+    const BlockJob& J = B.job[blockIdx.x];
+    if (J.kind != JOB_RECOMPRESS) {
+        dense_job(J);
+        return;
+    }
     const int m = J.m, q = J.q, k1 = J.k1, k2 = J.k2, rmax = B.rmax;
     const int lane = threadIdx.x, k = k1 + k2;
     const int kk1 = min(m, k), kk2 = min(q, k), r = min(min(kk1, kk2), rmax);
@@ -623,21 +656,22 @@ __global__ void __launch_bounds__(kMvThreads) hmatvec_kernel(MatvecBatch B) {
 
 }  // namespace
 
-void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rmax, double tol, hipStream_t s) {
-    for (int j0 = 0; j0 < count; j0 += kRecBatch) {
-        RecompressBatch B;
-        const int nb = count - j0 < kRecBatch ? count - j0 : kRecBatch;
+void launch_block_jobs(const BlockJob* jobs, int count, int rmax, double tol, hipStream_t s) {
+    for (int j0 = 0; j0 < count; j0 += kJobBatch) {
+        BlockJobBatch B;
+        const int nb = count - j0 < kJobBatch ? count - j0 : kJobBatch;
         size_t lds = 0;
         for (int j = 0; j < nb; ++j) {
-            const RecompressJob& J = jobs[j0 + j];
+            const BlockJob& J = jobs[j0 + j];
             B.job[j] = J;
+            if (J.kind != JOB_RECOMPRESS) continue;
             const size_t bytes = recompress_layout(J.m, J.q, J.k1 + J.k2, rmax).total * sizeof(c128);
             if (bytes <= kLdsBytes && bytes > lds) lds = bytes;
         }
         B.tol = tol;
         B.rmax = rmax;
         B.lds = (unsigned)lds;
-        hipLaunchKernelGGL(zrecompress_batch_kernel, dim3(nb), dim3(kWave), lds, s, B);
+        hipLaunchKernelGGL(block_jobs_kernel, dim3(nb), dim3(kWave), lds, s, B);
     }
 }
 

@@ -365,7 +365,7 @@ struct StrongFactors {
     c128* sw = nullptr;
     size_t sw_count = 0;
     int max_rank_seen = 0;
-    std::vector<RecompressJob> pend;   // recompressions not yet launched
+    std::vector<BlockJob> pend;   // recompressions not yet launched
     int defer = 0;                     // depth of walks whose recompressions wait in pend
 
     // ---- launch helpers
@@ -583,7 +583,8 @@ struct StrongFactors {
         out.u = talloc((size_t)m * r);
         out.v = talloc((size_t)q * r);
         if (!ok()) return;
-        RecompressJob J;
+        BlockJob J;
+        J.kind = JOB_RECOMPRESS;
         J.au = a.u;
         J.av = a.v;
         J.U = U;
@@ -598,14 +599,32 @@ struct StrongFactors {
         J.k2 = k2;
         J.ldu = ldu;
         J.ldv = ldv;
-        pend.push_back(J);
-        if (defer == 0) flush();
+        job(J);
         out.rank = r;
         if (r > max_rank_seen) max_rank_seen = r;
     }
-    // Launch the queued recompressions (one workgroup each).
+    // Queue a block operation; outside a walk it goes out at once.
+    void job(const BlockJob& J) {
+        pend.push_back(J);
+        if (defer == 0) flush();
+    }
+    static BlockJob dense_job(int kind, int m, int q, const c128* src, c128* dst) {
+        BlockJob J;
+        J.kind = kind;
+        J.au = src;
+        J.av = J.U = J.V = nullptr;
+        J.work = J.ov = nullptr;
+        J.ou = dst;
+        J.alpha = mk(1.0, 0.0);
+        J.m = m;
+        J.q = q;
+        J.k1 = J.k2 = 0;
+        J.ldu = J.ldv = m;
+        return J;
+    }
+    // Launch the queued block operations (one workgroup each).
     void flush() {
-        if (!pend.empty() && ok()) launch_small_recompress_batch(pend.data(), (int)pend.size(), rmax, tol, s);
+        if (!pend.empty() && ok()) launch_block_jobs(pend.data(), (int)pend.size(), rmax, tol, s);
         pend.clear();
     }
 
@@ -664,8 +683,15 @@ struct StrongFactors {
     void add_lowrank_walk(HMat& T, int ti, const c128* U, int ldu, const c128* V, int ldv, int k, c128 alpha) {
         if (k == 0 || !ok()) return;
         Node& b = T.nd[ti];
-        if (b.kind == 'D') {
-            gemm(0, 1, b.m(), b.q(), k, alpha, U, ldu, V, ldv, mk(1.0, 0.0), b.d, b.m());
+        if (b.kind == 'D') {                          // b.d += alpha U V^t
+            BlockJob J = dense_job(JOB_LOWRANK, b.m(), b.q(), nullptr, b.d);
+            J.U = U;
+            J.V = V;
+            J.ldu = ldu;
+            J.ldv = ldv;
+            J.k2 = k;
+            J.alpha = alpha;
+            job(J);
         } else if (b.kind == 'F') {
             Node old = b;
             Node out = b;
@@ -721,9 +747,14 @@ struct StrongFactors {
         Node out = A.nd[ai];
         const Node& b = B.nd[bi];
         out.ch[0] = out.ch[1] = out.ch[2] = out.ch[3] = -1;
-        if (out.kind == 'D') {
+        if (out.kind == 'D') {                        // out.d = A.d + alpha b.d
             out.d = talloc((size_t)out.m() * out.q());
-            geam(out.m(), out.q(), mk(1.0, 0.0), 0, A.nd[ai].d, out.m(), alpha, b.d, out.m(), out.d, out.m());
+            if (ok()) {
+                BlockJob J = dense_job(JOB_SUM, out.m(), out.q(), A.nd[ai].d, out.d);
+                J.av = b.d;
+                J.alpha = alpha;
+                job(J);
+            }
         } else if (out.kind == 'F') {
             compress_sum(out, A.nd[ai], alpha, b.u, b.m(), b.v, b.q(), b.rank);
         }
@@ -775,30 +806,30 @@ struct StrongFactors {
     }
 
     // A copy of M in the persistent arena.
+    // (the block copies go out as one batch)
     HMat persist(const HMat& M) {
         HMat R = M;
+        ++defer;
         for (auto& b : R.nd) {
             if (!ok()) break;
             if (b.kind == 'D') {
                 c128* p = keep.alloc((size_t)b.m() * b.q());
                 if (!p) { fail_with(HSWEEP_ENOMEM, "device memory for the strong factors"); break; }
-                hipError_t e = hipMemcpyAsync(p, b.d, (size_t)b.m() * b.q() * sizeof(c128), hipMemcpyDeviceToDevice, s);
-                if (e != hipSuccess) fail_with(HSWEEP_EDEVICE, hipGetErrorString(e));
+                job(dense_job(JOB_COPY, b.m(), b.q(), b.d, p));
                 b.d = p;
             } else if (b.kind == 'F' && b.rank > 0) {
                 c128* pu = keep.alloc((size_t)b.m() * b.rank);
                 c128* pv = keep.alloc((size_t)b.q() * b.rank);
                 if (!pu || !pv) { fail_with(HSWEEP_ENOMEM, "device memory for the strong factors"); break; }
-                hipError_t e = hipMemcpyAsync(pu, b.u, (size_t)b.m() * b.rank * sizeof(c128), hipMemcpyDeviceToDevice, s);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(pv, b.v, (size_t)b.q() * b.rank * sizeof(c128), hipMemcpyDeviceToDevice, s);
-                if (e != hipSuccess) fail_with(HSWEEP_EDEVICE, hipGetErrorString(e));
+                job(dense_job(JOB_COPY, b.m(), b.rank, b.u, pu));
+                job(dense_job(JOB_COPY, b.q(), b.rank, b.v, pv));
                 b.u = pu;
                 b.v = pv;
             } else if (b.kind == 'F') {
                 b.u = b.v = nullptr;
             }
         }
+        if (--defer == 0) flush();
         return R;
     }
 
@@ -889,7 +920,7 @@ int factor_layers(StrongFactors* sf, Fill fill, const c128* cp, hipStream_t s, s
         if (e != hipSuccess)
             return fail_new(sf, HSWEEP_EDEVICE, std::string("strong factorization: ") + hipGetErrorString(e), msg);
     }
-    const c128 one = mk(1.0, 0.0), mone = mk(-1.0, 0.0);
+    const c128 mone = mk(-1.0, 0.0);
     for (int m = 0; m < nl && sf->ok(); ++m) {
         // A_mm in the format: all its entries lie in dense blocks
         HMat A = sf->zeros_like(sf->shape, 0);
@@ -900,31 +931,35 @@ int factor_layers(StrongFactors* sf, Fill fill, const c128* cp, hipStream_t s, s
             S = A;
         } else {
             // diag(a) T_{m-1} diag(a), a = diagonal of A_{m,m-1}
+            // (scaled copies of the blocks of T_{m-1}, one batch)
             const c128* a = sf->cpk + (size_t)(m - 1) * N;
             HMat D = sf->T[m - 1];
+            ++sf->defer;
             for (Node& b : D.nd) {
                 if (!sf->ok()) break;
                 if (b.kind == 'D') {
                     c128* p = sf->talloc((size_t)b.m() * b.q());
                     if (!p) break;
-                    sf->geam(b.m(), b.q(), one, 0, b.d, b.m(), czero<double>(), nullptr, 0, p, b.m());
-                    hipLaunchKernelGGL(zscale_kernel, grid2(b.m(), b.q()), dim3(kThreads), 0, s, b.m(), b.q(), p, b.m(),
-                                       a + b.t0, a + b.s0);
+                    BlockJob J = StrongFactors::dense_job(JOB_SCALE, b.m(), b.q(), b.d, p);
+                    J.U = a + b.t0;
+                    J.V = a + b.s0;
+                    sf->job(J);
                     b.d = p;
                 } else if (b.kind == 'F' && b.rank > 0) {
                     c128* pu = sf->talloc((size_t)b.m() * b.rank);
                     c128* pv = sf->talloc((size_t)b.q() * b.rank);
                     if (!pu || !pv) break;
-                    sf->geam(b.m(), b.rank, one, 0, b.u, b.m(), czero<double>(), nullptr, 0, pu, b.m());
-                    sf->geam(b.q(), b.rank, one, 0, b.v, b.q(), czero<double>(), nullptr, 0, pv, b.q());
-                    hipLaunchKernelGGL(zscale_kernel, grid2(b.m(), b.rank), dim3(kThreads), 0, s, b.m(), b.rank, pu,
-                                       b.m(), a + b.t0, (const c128*)nullptr);
-                    hipLaunchKernelGGL(zscale_kernel, grid2(b.q(), b.rank), dim3(kThreads), 0, s, b.q(), b.rank, pv,
-                                       b.q(), a + b.s0, (const c128*)nullptr);
+                    BlockJob J = StrongFactors::dense_job(JOB_SCALE, b.m(), b.rank, b.u, pu);
+                    J.U = a + b.t0;
+                    sf->job(J);
+                    J = StrongFactors::dense_job(JOB_SCALE, b.q(), b.rank, b.v, pv);
+                    J.U = a + b.s0;
+                    sf->job(J);
                     b.u = pu;
                     b.v = pv;
                 }
             }
+            if (--sf->defer == 0) sf->flush();
             S = sf->add(A, 0, D, 0, mone);
         }
         HMat Tm = sf->inv(S, 0);

@@ -193,9 +193,33 @@ static void recompress_one(int m, int q, int k1, int k2, int rmax, double tol, c
     }
 }
 
-void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rmax, double tol, hipStream_t s) {
+static void dense_one(const BlockJob& J) {
+    for (int j = 0; j < J.q; ++j)
+        for (int i = 0; i < J.m; ++i) {
+            const size_t e = (size_t)j * J.m + i;
+            if (J.kind == JOB_SUM) {
+                J.ou[e] = J.au[e] + J.alpha * J.av[e];
+            } else if (J.kind == JOB_LOWRANK) {
+                c128 acc = czero<double>();
+                for (int l = 0; l < J.k2; ++l) cfma(acc, J.U[(size_t)l * J.ldu + i], J.V[(size_t)l * J.ldv + j]);
+                J.ou[e] += J.alpha * acc;
+            } else if (J.kind == JOB_SCALE) {
+                c128 v = J.U[i] * J.au[e];
+                if (J.V) v = v * J.V[j];
+                J.ou[e] = v;
+            } else {
+                J.ou[e] = J.au[e];
+            }
+        }
+}
+
+void launch_block_jobs(const BlockJob* jobs, int count, int rmax, double tol, hipStream_t s) {
     for (int j = 0; j < count; ++j) {
-        const RecompressJob& J = jobs[j];
+        const BlockJob& J = jobs[j];
+        if (J.kind != JOB_RECOMPRESS) {
+            dense_one(J);
+            continue;
+        }
         recompress_one(J.m, J.q, J.k1, J.k2, rmax, tol, J.alpha, J.au, J.av, J.U, J.ldu, J.V, J.ldv, J.work, J.ou,
                        J.ov, s);
     }

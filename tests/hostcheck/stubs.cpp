@@ -172,9 +172,21 @@ static void recompress_ranges(int m, int q, int k1, int k2, int rmax, const c128
     need(work, recompress_layout(m, q, k, rmax).total * 16, "recompress work");
     need(ou, (size_t)m * r * 16, "recompress ou"); need(ov, (size_t)q * r * 16, "recompress ov");
 }
-void launch_small_recompress_batch(const RecompressJob* jobs, int count, int rmax, double, hipStream_t) {
+void launch_block_jobs(const BlockJob* jobs, int count, int rmax, double, hipStream_t) {
     for (int j = 0; j < count; ++j) {
-        const RecompressJob& J = jobs[j];
+        const BlockJob& J = jobs[j];
+        if (J.kind != JOB_RECOMPRESS) {
+            const size_t n = (size_t)J.m * J.q * 16;
+            need(J.ou, n, "block job out");
+            if (J.kind == JOB_SUM) { need(J.au, n, "sum a"); need(J.av, n, "sum b"); }
+            if (J.kind == JOB_SCALE || J.kind == JOB_COPY) need(J.au, n, "scaled/copied block");
+            if (J.kind == JOB_SCALE) { need(J.U, (size_t)J.m * 16, "row scale"); if (J.V) need(J.V, (size_t)J.q * 16, "column scale"); }
+            if (J.kind == JOB_LOWRANK && J.k2 > 0) {
+                need(J.U, ((size_t)(J.k2 - 1) * J.ldu + J.m) * 16, "low-rank U");
+                need(J.V, ((size_t)(J.k2 - 1) * J.ldv + J.q) * 16, "low-rank V");
+            }
+            continue;
+        }
         recompress_ranges(J.m, J.q, J.k1, J.k2, rmax, J.au, J.av, J.U, J.ldu, J.V, J.ldv, J.work, J.ou, J.ov);
     }
 }

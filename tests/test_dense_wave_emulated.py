@@ -166,7 +166,7 @@ def _recompress(exe, tmp_path, cases, rmax):
             # factors of decaying weight, so that the truncation is well defined
             au, av = _rand(rng, m, k1) * 2.0 ** -np.arange(k1), _rand(rng, q, k1)
             U, V = _rand(rng, m, k2) * 3.0 ** -np.arange(k2), _rand(rng, q, k2)
-            fp.write(struct.pack("4i", m, q, k1, k2))
+            fp.write(struct.pack("5i", 0, m, q, k1, k2))
             fp.write(struct.pack("2d", alpha.real, alpha.imag))
             for M in (au, av, U, V):
                 fp.write(np.asfortranarray(M, dtype=np.complex128).tobytes(order="F"))
@@ -296,3 +296,50 @@ def test_svd_with_a_cut_keeps_the_leading_triplets(wave, tmp_path, a, b):
     best = (Uq[:, :keep] * sv[:keep]) @ Vq[:, :keep].conj().T
     approx = AV[:, perm[:keep]] @ V[:, perm[:keep]].conj().T
     assert np.linalg.norm(approx - best) <= 1e-10
+
+
+def test_dense_block_jobs(wave, tmp_path):
+    """The dense kinds of a block-job batch, side by side with a
+    recompression in one launch: a sum, a low-rank update, a row-and-column
+    scaling and a copy."""
+    rng = np.random.default_rng(700)
+    alpha = 0.4 + 0.9j
+    m, q, k2 = 13, 9, 3
+    A, Bm, O = _rand(rng, m, q), _rand(rng, m, q), _rand(rng, m, q)
+    U, V = _rand(rng, m, k2), _rand(rng, q, k2)
+    dl, dr = _rand(rng, m, 1)[:, 0], _rand(rng, q, 1)[:, 0]
+    # (kind, data arrays in file order, expected)
+    jobs = [(1, [A, Bm, O], A + alpha * Bm),
+            (2, [A, U, V, O], O + alpha * U @ V.T),
+            (3, [A, dl, dr, O], dl[:, None] * A * dr[None, :]),
+            (4, [A, O], A)]
+    rec = REC_CASES[0]
+    fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    rec_rng = np.random.default_rng(9)
+    with open(fin, "wb") as fp:
+        fp.write(struct.pack("5i", 3, len(jobs) + 1, 2, 0, 2))
+        fp.write(struct.pack("d", 1e-6))
+        for kind, arrs, _ in jobs:
+            fp.write(struct.pack("5i", kind, m, q, 0, k2 if kind == 2 else 0))
+            fp.write(struct.pack("2d", alpha.real, alpha.imag))
+            for M in arrs:
+                fp.write(np.asfortranarray(np.asarray(M, dtype=np.complex128)).tobytes(order="F"))
+        mm, qq, k1r, k2r = rec[:4]
+        au, av = _rand(rec_rng, mm, k1r), _rand(rec_rng, qq, k1r)
+        Ur, Vr = _rand(rec_rng, mm, k2r), _rand(rec_rng, qq, k2r)
+        fp.write(struct.pack("5i", 0, mm, qq, k1r, k2r))
+        fp.write(struct.pack("2d", alpha.real, alpha.imag))
+        for M in (au, av, Ur, Vr):
+            fp.write(np.asfortranarray(M).tobytes(order="F"))
+    r = subprocess.run([wave, fin, fout], capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    out = open(fout, "rb").read()
+    off = 0
+    for kind, _, want in jobs:
+        got, off = _mat(out, off, m, q)
+        assert np.linalg.norm(got - want) <= 1e-13 * np.linalg.norm(want), kind
+    width = min(mm, qq, k1r + k2r, 2)
+    ou, off = _mat(out, off, mm, width)
+    ov, off = _mat(out, off, qq, width)
+    _check_truncation((alpha, au, av, Ur, Vr), ou, ov, 1e-6, 2)

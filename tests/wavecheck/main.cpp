@@ -39,13 +39,39 @@ int main(int argc, char** argv) {
         // per job int32 m, q, k1, k2, float64 alpha (re, im), then au (m x k1),
         // av (q x k1), U (m x k2), V (q x k2); output each job's ou, ov
         const int count = p;
-        std::vector<RecompressJob> jobs(count);
+        std::vector<BlockJob> jobs(count);
         std::vector<int> rw(count);
         for (int t = 0; t < count; ++t) {
+            int32_t kind;
             int32_t d[4];
             double al[2];
-            if (!rd(fp, d, 16) || !rd(fp, al, 16)) return 2;
+            if (!rd(fp, &kind, 4) || !rd(fp, d, 16) || !rd(fp, al, 16)) return 2;
             const int m = d[0], q = d[1], k1 = d[2], k2 = d[3];
+            if (kind != JOB_RECOMPRESS) {
+                // dense kinds: a (m x q), b (m x q; SUM), U (m x k2), V (q x k2) (LOWRANK),
+                // row and column scales (m, q; SCALE), the output's initial m x q
+                const size_t nq = (size_t)m * q;
+                const size_t na = nq, nb = kind == JOB_SUM ? nq : 0;
+                const size_t nu = kind == JOB_LOWRANK ? (size_t)m * k2 : kind == JOB_SCALE ? m : 0;
+                const size_t nv = kind == JOB_LOWRANK ? (size_t)q * k2 : kind == JOB_SCALE ? q : 0;
+                std::vector<c128> h(na + nb + nu + nv + nq);
+                if (!rd(fp, h.data(), h.size() * 16)) return 2;
+                c128 *A = dev<c128>(na), *Bm = dev<c128>(nb), *Uu = dev<c128>(nu), *Vv = dev<c128>(nv), *O = dev<c128>(nq);
+                hipMemcpy(A, h.data(), na * 16, hipMemcpyHostToDevice);
+                hipMemcpy(Bm, h.data() + na, nb * 16, hipMemcpyHostToDevice);
+                hipMemcpy(Uu, h.data() + na + nb, nu * 16, hipMemcpyHostToDevice);
+                hipMemcpy(Vv, h.data() + na + nb + nu, nv * 16, hipMemcpyHostToDevice);
+                hipMemcpy(O, h.data() + na + nb + nu + nv, nq * 16, hipMemcpyHostToDevice);
+                BlockJob& J = jobs[t];
+            J.kind = JOB_RECOMPRESS;
+                J.kind = kind;
+                J.au = A; J.av = Bm; J.U = nu ? Uu : nullptr; J.V = nv ? Vv : nullptr;
+                J.work = nullptr; J.ou = O; J.ov = nullptr;
+                J.alpha = mk(al[0], al[1]);
+                J.m = m; J.q = q; J.k1 = 0; J.k2 = k2; J.ldu = m; J.ldv = q;
+                rw[t] = -1;
+                continue;
+            }
             const size_t n1 = (size_t)m * k1, n2 = (size_t)q * k1, n3 = (size_t)m * k2, n4 = (size_t)q * k2;
             std::vector<c128> h(n1 + n2 + n3 + n4);
             if (!rd(fp, h.data(), h.size() * 16)) return 2;
@@ -56,7 +82,8 @@ int main(int argc, char** argv) {
             hipMemcpy(V, h.data() + n1 + n2 + n3, n4 * 16, hipMemcpyHostToDevice);
             const int kt = k1 + k2, kk1 = m < kt ? m : kt, kk2 = q < kt ? q : kt;
             const int r0 = kk1 < kk2 ? kk1 : kk2, r = r0 < rmax ? r0 : rmax;
-            RecompressJob& J = jobs[t];
+            BlockJob& J = jobs[t];
+            J.kind = JOB_RECOMPRESS;
             J.au = au; J.av = av; J.U = U; J.V = V;
             J.work = dev<c128>(recompress_layout(m, q, kt, rmax).total);
             J.ou = dev<c128>((size_t)m * r);
@@ -66,9 +93,13 @@ int main(int argc, char** argv) {
             rw[t] = r;
         }
         fclose(fp);
-        launch_small_recompress_batch(jobs.data(), count, rmax, tol, nullptr);
+        launch_block_jobs(jobs.data(), count, rmax, tol, nullptr);
         FILE* out = fopen(argv[2], "wb");
         for (int t = 0; t < count; ++t) {
+            if (rw[t] < 0) {
+                fwrite(jobs[t].ou, 16, (size_t)jobs[t].m * jobs[t].q, out);
+                continue;
+            }
             fwrite(jobs[t].ou, 16, (size_t)jobs[t].m * rw[t], out);
             fwrite(jobs[t].ov, 16, (size_t)jobs[t].q * rw[t], out);
         }
