@@ -730,10 +730,19 @@ struct StrongFactors {
             const int r = rsvd(G, gi, H, hi, U, V);
             add_lowrank(T, ti, U, tb.m(), V, tb.q(), r, alpha);
         } else {
-            for (int a = 0; a < 2; ++a)
-                for (int c = 0; c < 2; ++c)
-                    for (int b = 0; b < 2; ++b)
+            // the four target blocks are independent, so the four products of
+            // one b go out side by side (their block jobs share launches);
+            // the b = 1 products add to what b = 0 left, so a flush separates
+            // them.  Launching queued jobs early is always safe.
+            for (int b = 0; b < 2; ++b) {
+                flush();
+                ++defer;
+                for (int a = 0; a < 2; ++a)
+                    for (int c = 0; c < 2; ++c)
                         mul_add(T, T.nd[ti].ch[2 * a + c], G, g.ch[2 * a + b], H, h.ch[2 * b + c], alpha);
+                --defer;
+                flush();
+            }
         }
     }
     HMat mul(const HMat& G, int gi, const HMat& H, int hi, const HMat& like, int li, c128 alpha) {

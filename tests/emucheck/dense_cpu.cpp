@@ -4,6 +4,9 @@
 // (those are checked on their own by tests/wavecheck).  Same contracts,
 // plain loops: Householder QR, cyclic one-sided Jacobi SVD, Gauss-Jordan.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <vector>
 #include "internal.hpp"
 
 void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, hipStream_t) {
@@ -213,7 +216,59 @@ static void dense_one(const BlockJob& J) {
         }
 }
 
+// The byte ranges a job reads and writes (its work buffer counts as written).
+struct Span {
+    const char* p;
+    size_t n;
+};
+static Span span(const void* p, size_t entries) { return Span{(const char*)p, entries * sizeof(c128)}; }
+static Span cols(const c128* p, int ld, int rows, int ncol) {
+    return ncol > 0 && p ? span(p, (size_t)(ncol - 1) * ld + rows) : Span{nullptr, 0};
+}
+static void job_spans(const BlockJob& J, int rmax, std::vector<Span>& rd, std::vector<Span>& wr) {
+    const size_t mq = (size_t)J.m * J.q;
+    if (J.kind == JOB_RECOMPRESS) {
+        const int k = J.k1 + J.k2, kk1 = J.m < k ? J.m : k, kk2 = J.q < k ? J.q : k;
+        const int r0 = kk1 < kk2 ? kk1 : kk2, r = r0 < rmax ? r0 : rmax;
+        rd = {cols(J.au, J.m, J.m, J.k1), cols(J.av, J.q, J.q, J.k1), cols(J.U, J.ldu, J.m, J.k2),
+              cols(J.V, J.ldv, J.q, J.k2)};
+        wr = {span(J.work, recompress_layout(J.m, J.q, k, rmax).total), span(J.ou, (size_t)J.m * r),
+              span(J.ov, (size_t)J.q * r)};
+    } else if (J.kind == JOB_SUM) {
+        rd = {span(J.au, mq), span(J.av, mq)};
+        wr = {span(J.ou, mq)};
+    } else if (J.kind == JOB_LOWRANK) {
+        rd = {cols(J.U, J.ldu, J.m, J.k2), cols(J.V, J.ldv, J.q, J.k2), span(J.ou, mq)};
+        wr = {span(J.ou, mq)};
+    } else if (J.kind == JOB_SCALE) {
+        rd = {span(J.au, mq), span(J.U, J.m), J.V ? span(J.V, J.q) : Span{nullptr, 0}};
+        wr = {span(J.ou, mq)};
+    } else {
+        rd = {span(J.au, mq)};
+        wr = {span(J.ou, mq)};
+    }
+}
+static bool meet(const Span& a, const Span& b) {
+    return a.p && b.p && a.n && b.n && a.p < b.p + b.n && b.p < a.p + a.n;
+}
+
 void launch_block_jobs(const BlockJob* jobs, int count, int rmax, double tol, hipStream_t s) {
+    // the jobs of a batch run side by side on the device: none may write what
+    // another reads or writes
+    for (int a = 0; a < count; ++a) {
+        std::vector<Span> ra, wa, rb, wb;
+        job_spans(jobs[a], rmax, ra, wa);
+        for (int b = 0; b < count; ++b) {
+            if (a == b) continue;
+            job_spans(jobs[b], rmax, rb, wb);
+            for (const Span& w : wa) {
+                for (const Span& x : rb)
+                    if (meet(w, x)) { fprintf(stderr, "BATCH DEPENDENCE: job %d writes what job %d reads\n", a, b); abort(); }
+                for (const Span& x : wb)
+                    if (meet(w, x)) { fprintf(stderr, "BATCH DEPENDENCE: jobs %d and %d write the same bytes\n", a, b); abort(); }
+            }
+        }
+    }
     for (int j = 0; j < count; ++j) {
         const BlockJob& J = jobs[j];
         if (J.kind != JOB_RECOMPRESS) {
