@@ -231,6 +231,21 @@ struct BlockJob {
 // launches of up to 32; no job may read what another writes.
 void launch_block_jobs(const BlockJob* jobs, int count, int rmax, double tol, hipStream_t s);
 
+// The tail of a randomized SVD: the SVD of the projected block M (q x ell,
+// overwritten with M V; right singular vectors in V, norms in sig, order in
+// perm, kept count in *rank as launch_small_svd), then Vg = conj(V_r) (ell x
+// r), Vo = (M V)_r (q x r) and Uo = Q Vg (m x r), r = min(ell, rmax), the
+// columns past the kept rank zero.  Q is m x ell.
+struct RsvdTail {
+    const c128* Q;
+    c128 *M, *V, *Vg, *Uo, *Vo;
+    double* sig;
+    int *perm, *rank;
+    int m, q, ell;
+};
+// count independent tails (host array), one workgroup each, in launches of up to 32.
+void launch_rsvd_tails(const RsvdTail* jobs, int count, int rmax, double tol, hipStream_t s);
+
 // One leaf block of an H-matrix product Y += alpha op(B) X: dense (kind 0,
 // a = the m x q block) or factorized (kind 1, a = U (m x r), b = V (q x r),
 // the block U V^t); op is the block (trans 0: X rows xo.., Y rows yo..) or

@@ -654,6 +654,45 @@ __global__ void __launch_bounds__(kMvThreads) hmatvec_kernel(MatvecBatch B) {
     }
 }
 
+// Randomized-SVD tails of one launch, one workgroup each, passed by value.
+constexpr int kTailBatch = 32;
+struct RsvdTailBatch {
+    RsvdTail job[kTailBatch];
+    double tol;
+    int rmax;
+    unsigned lds;          // shared-memory bytes of the launch
+};
+
+// Tail blockIdx.x: SVD of M (staged in shared memory with V when they fit),
+// the kept columns, Uo = Q Vg.
+__global__ void __launch_bounds__(kWave) rsvd_tail_kernel(RsvdTailBatch B) {
+    HIP_DYNAMIC_SHARED(c128, lds)
+    const RsvdTail& J = B.job[blockIdx.x];
+    const int m = J.m, q = J.q, ell = J.ell, r = min(ell, B.rmax);
+    const bool staged = ((size_t)q * ell + (size_t)ell * ell) * sizeof(c128) <= B.lds;
+    c128* A = staged ? lds : J.M;
+    c128* V = staged ? lds + (size_t)q * ell : J.V;
+    if (staged) wave_copy(q, ell, J.M, q, A, q);
+    __syncthreads();
+    wave_svd(q, ell, A, q, V, J.sig, J.perm, J.rank, B.tol, B.rmax);
+    const int kept = *J.rank;
+    for (size_t e = threadIdx.x; e < (size_t)ell * r; e += kWave) {
+        const int i = (int)(e % ell), j = (int)(e / ell);
+        J.Vg[e] = j < kept ? conj(V[(size_t)J.perm[j] * ell + i]) : czero<double>();
+    }
+    for (size_t e = threadIdx.x; e < (size_t)q * r; e += kWave) {
+        const int i = (int)(e % q), j = (int)(e / q);
+        J.Vo[e] = j < kept ? A[(size_t)J.perm[j] * q + i] : czero<double>();
+    }
+    __syncthreads();
+    for (size_t e = threadIdx.x; e < (size_t)m * r; e += kWave) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        c128 acc = czero<double>();
+        for (int l = 0; l < ell; ++l) cfma(acc, J.Q[(size_t)l * m + i], J.Vg[(size_t)j * ell + l]);
+        J.Uo[e] = acc;
+    }
+}
+
 }  // namespace
 
 void launch_block_jobs(const BlockJob* jobs, int count, int rmax, double tol, hipStream_t s) {
@@ -719,5 +758,23 @@ void launch_hmatvec(const MatvecOp* ops, int count, int trans, int assign, const
         B.T = need ? tscratch + (size_t)j0 * B.tstride : nullptr;
         const size_t lds = need ? 0 : mr * ncol * sizeof(c128);
         hipLaunchKernelGGL(hmatvec_kernel, dim3(nb), dim3(kMvThreads), lds, s, B);
+    }
+}
+
+void launch_rsvd_tails(const RsvdTail* jobs, int count, int rmax, double tol, hipStream_t s) {
+    for (int j0 = 0; j0 < count; j0 += kTailBatch) {
+        RsvdTailBatch B;
+        const int nb = count - j0 < kTailBatch ? count - j0 : kTailBatch;
+        size_t lds = 0;
+        for (int j = 0; j < nb; ++j) {
+            const RsvdTail& J = jobs[j0 + j];
+            B.job[j] = J;
+            const size_t bytes = ((size_t)J.q * J.ell + (size_t)J.ell * J.ell) * sizeof(c128);
+            if (bytes <= kLdsBytes && bytes > lds) lds = bytes;
+        }
+        B.tol = tol;
+        B.rmax = rmax;
+        B.lds = (unsigned)lds;
+        hipLaunchKernelGGL(rsvd_tail_kernel, dim3(nb), dim3(kWave), lds, s, B);
     }
 }

@@ -122,20 +122,6 @@ __global__ void tridiag_block_kernel(int m, int q, int t0, int s0, const c128* d
     D[(size_t)j * m + i] = v;
 }
 
-// dst(:, j) = op(src(:, perm[j])) for j < *rank, 0 for *rank <= j < k
-// (op 0 or 2): the kept columns of an SVD, zero-padded to the capacity k.
-__global__ void zgather_cols_kernel(int m, int k, const c128* src, int lds, const int* perm, const int* rank, int op,
-                                    c128* dst, int ldd) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= m || j >= k) return;
-    c128 v = czero<double>();
-    if (j < *rank) {
-        v = src[(size_t)perm[j] * lds + i];
-        if (op == 2) v = conj(v);
-    }
-    dst[(size_t)j * ldd + i] = v;
-}
 
 // Complex Gaussian entries (re + i im) / sqrt(2), re and im standard normal
 // by the Box-Muller transform of two uniforms from the splitmix64 hash
@@ -553,18 +539,6 @@ struct StrongFactors {
         if (!ok()) return;
         launch_small_qr(p, k, A, lda, W, Vh, Q, R, s);
     }
-    // SVD of A (a x b, in place -> A V); the kept rank is written to the
-    // returned device int (never read back by the host).
-    int* svd(int a, int b, c128* A, int lda, c128*& V, int*& perm) {
-        V = talloc((size_t)b * b);
-        c128* sg = talloc(((size_t)b + 1) / 2 + 1);      // b doubles
-        c128* pm = talloc(((size_t)b + 3) / 4 + 1);      // b ints
-        c128* rk = talloc(1);                            // one int
-        if (!ok()) return nullptr;
-        perm = (int*)pm;
-        launch_small_svd(a, b, A, lda, V, (double*)sg, perm, (int*)rk, tol, rmax, s);
-        return (int*)rk;
-    }
 
     // out = trunc([a.u, alpha U] [a.v, V]^t): QR of both stacked factors,
     // SVD of the small core, the kept columns (one fused kernel); the width
@@ -631,12 +605,15 @@ struct StrongFactors {
     // Randomized SVD of the m x q product G H (G on (t, u), H on (u, s)):
     // Y = G (H Omega), Q = qr(Y), M = H^t (G^t conj(Q)) = (Q^H G H)^t, M V =
     // U S from the SVD of M, and G H ~ (Q conj(V_r)) ((M V)_r)^t.
-    int rsvd(const HMat& G, int gi, const HMat& H, int hi, c128*& Uo, c128*& Vo) {
+    // The head of the randomized SVD of G H, up to the projected block M
+    // (launched at once); the tail goes into `out` (its SVD, the kept
+    // columns, Uo = Q Vg, launched with other tails by finish_rsvds).
+    // Returns the factors' width r (0: nothing to add).
+    int rsvd_begin(const HMat& G, int gi, const HMat& H, int hi, RsvdTail& out) {
         const Node& g = G.nd[gi];
         const Node& h = H.nd[hi];
         const int m = g.m(), q = h.q(), mid = g.q();
         const int ell = std::min(std::min(rmax + kOversample, m), q);
-        Uo = Vo = nullptr;
         if (ell <= 0 || !ok()) return 0;
         c128* Om = talloc((size_t)q * ell);
         c128* Y1 = talloc((size_t)mid * ell);
@@ -656,20 +633,43 @@ struct StrongFactors {
         geam(m, ell, mk(1.0, 0.0), 2, Q, m, czero<double>(), nullptr, 0, Qc, m);
         matvec_t_set(G, gi, Qc, m, ell, M1, mid, mk(1.0, 0.0));
         matvec_t_set(H, hi, M1, mid, ell, M, q, mk(1.0, 0.0));
-        c128* Vs;
-        int* perm;
-        const int* rk = svd(q, ell, M, q, Vs, perm);
         const int r = std::min(ell, rmax);               // width: the kept rank's bound
-        if (!ok() || r == 0) return 0;
-        c128* Vg = talloc((size_t)ell * r);
-        Uo = talloc((size_t)m * r);
-        Vo = talloc((size_t)q * r);
-        if (!ok()) return 0;
-        hipLaunchKernelGGL(zgather_cols_kernel, grid2(ell, r), dim3(kThreads), 0, s, ell, r, Vs, ell, perm, rk, 2, Vg,
-                           ell);
-        hipLaunchKernelGGL(zgather_cols_kernel, grid2(q, r), dim3(kThreads), 0, s, q, r, M, q, perm, rk, 0, Vo, q);
-        gemm(0, 0, m, r, ell, mk(1.0, 0.0), Q, m, Vg, ell, czero<double>(), Uo, m);
-        return r;
+        if (r == 0) return 0;
+        out.Q = Q;
+        out.M = M;
+        out.V = talloc((size_t)ell * ell);
+        out.sig = (double*)talloc(((size_t)ell + 1) / 2 + 1);
+        out.perm = (int*)talloc(((size_t)ell + 3) / 4 + 1);
+        out.rank = (int*)talloc(1);
+        out.Vg = talloc((size_t)ell * r);
+        out.Uo = talloc((size_t)m * r);
+        out.Vo = talloc((size_t)q * r);
+        out.m = m;
+        out.q = q;
+        out.ell = ell;
+        return ok() ? r : 0;
+    }
+    // A randomized SVD waiting for its tail and its low-rank update of T's block ti.
+    struct RsvdPending {
+        RsvdTail tail;
+        HMat* T;
+        int ti, r;
+        c128 alpha;
+    };
+    std::vector<RsvdPending> rpend;
+    int phase = 0;                     // depth of product phases whose tails wait in rpend
+    // The tails queued since `from` in one batch, then their updates.
+    void finish_rsvds(size_t from) {
+        if (rpend.size() > from && ok()) {
+            std::vector<RsvdTail> tails;
+            for (size_t i = from; i < rpend.size(); ++i) tails.push_back(rpend[i].tail);
+            launch_rsvd_tails(tails.data(), (int)tails.size(), rmax, tol, s);
+            for (size_t i = from; i < rpend.size() && ok(); ++i) {
+                const RsvdPending& e = rpend[i];
+                add_lowrank(*e.T, e.ti, e.tail.Uo, e.tail.m, e.tail.Vo, e.tail.q, e.r, e.alpha);
+            }
+        }
+        rpend.resize(from);
     }
 
     // ---- H-arithmetic
@@ -726,20 +726,31 @@ struct StrongFactors {
         } else if (tb.kind == 'D') {
             gemm(0, 0, tb.m(), tb.q(), g.q(), alpha, g.d, g.m(), h.d, h.m(), mk(1.0, 0.0), T.nd[ti].d, tb.m());
         } else if (tb.kind == 'F') {                    // F = H . H
-            c128 *U, *V;
-            const int r = rsvd(G, gi, H, hi, U, V);
-            add_lowrank(T, ti, U, tb.m(), V, tb.q(), r, alpha);
+            RsvdPending e;
+            e.r = rsvd_begin(G, gi, H, hi, e.tail);
+            if (e.r == 0) return;
+            e.T = &T;
+            e.ti = ti;
+            e.alpha = alpha;
+            const size_t from = rpend.size();
+            rpend.push_back(e);
+            if (phase == 0) finish_rsvds(from);      // inside a phase: at the phase's end
         } else {
             // the four target blocks are independent, so the four products of
-            // one b go out side by side (their block jobs share launches);
+            // one b go out side by side (their block jobs share launches, and
+            // so do the tails of their randomized SVDs);
             // the b = 1 products add to what b = 0 left, so a flush separates
             // them.  Launching queued jobs early is always safe.
             for (int b = 0; b < 2; ++b) {
                 flush();
+                const size_t from = rpend.size();
                 ++defer;
+                ++phase;
                 for (int a = 0; a < 2; ++a)
                     for (int c = 0; c < 2; ++c)
                         mul_add(T, T.nd[ti].ch[2 * a + c], G, g.ch[2 * a + b], H, h.ch[2 * b + c], alpha);
+                finish_rsvds(from);                    // the phase's randomized-SVD tails, side by side
+                --phase;
                 --defer;
                 flush();
             }

@@ -316,3 +316,22 @@ void launch_hmatvec(const MatvecOp* ops, int count, int trans, int assign, const
         }
     }
 }
+
+void launch_rsvd_tails(const RsvdTail* jobs, int count, int rmax, double tol, hipStream_t s) {
+    for (int t = 0; t < count; ++t) {
+        const RsvdTail& J = jobs[t];
+        launch_small_svd(J.q, J.ell, J.M, J.q, J.V, J.sig, J.perm, J.rank, tol, rmax, s);
+        const int r = J.ell < rmax ? J.ell : rmax, kept = *J.rank;
+        for (int j = 0; j < r; ++j) {
+            for (int i = 0; i < J.ell; ++i)
+                J.Vg[(size_t)j * J.ell + i] = j < kept ? conj(J.V[(size_t)J.perm[j] * J.ell + i]) : czero<double>();
+            for (int i = 0; i < J.q; ++i)
+                J.Vo[(size_t)j * J.q + i] = j < kept ? J.M[(size_t)J.perm[j] * J.q + i] : czero<double>();
+            for (int i = 0; i < J.m; ++i) {
+                c128 acc = czero<double>();
+                for (int l = 0; l < J.ell; ++l) cfma(acc, J.Q[(size_t)l * J.m + i], J.Vg[(size_t)j * J.ell + l]);
+                J.Uo[(size_t)j * J.m + i] = acc;
+            }
+        }
+    }
+}

@@ -208,3 +208,14 @@ void launch_hmatvec(const MatvecOp* ops, int count, int trans, int, const c128* 
         }
     }
 }
+void launch_rsvd_tails(const RsvdTail* jobs, int count, int rmax, double, hipStream_t) {
+    for (int t = 0; t < count; ++t) {
+        const RsvdTail& J = jobs[t];
+        const int r = J.ell < rmax ? J.ell : rmax;
+        need(J.Q, (size_t)J.m * J.ell * 16, "tail Q"); need(J.M, (size_t)J.q * J.ell * 16, "tail M");
+        need(J.V, (size_t)J.ell * J.ell * 16, "tail V"); need(J.sig, (size_t)J.ell * 8, "tail sig");
+        need(J.perm, (size_t)J.ell * 4, "tail perm"); need(J.rank, 4, "tail rank");
+        need(J.Vg, (size_t)J.ell * r * 16, "tail Vg"); need(J.Uo, (size_t)J.m * r * 16, "tail Uo");
+        need(J.Vo, (size_t)J.q * r * 16, "tail Vo");
+    }
+}

@@ -343,3 +343,39 @@ def test_dense_block_jobs(wave, tmp_path):
     ou, off = _mat(out, off, mm, width)
     ov, off = _mat(out, off, qq, width)
     _check_truncation((alpha, au, av, Ur, Vr), ou, ov, 1e-6, 2)
+
+
+def test_randomized_svd_tails(wave, tmp_path):
+    """Two randomized-SVD tails in one launch (one staged in shared memory,
+    one too large for it): Uo Vo^t is the truncated SVD of Q M^t, with Q an
+    orthonormal sample basis, rank capped at rmax and cut at tol."""
+    rng = np.random.default_rng(800)
+    rmax, tol = 3, 1e-6
+    cases = [(24, 20, 10), (200, 420, 10)]
+    data = []
+    fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    with open(fin, "wb") as fp:
+        fp.write(struct.pack("5i", 5, len(cases), 0, 0, rmax))
+        fp.write(struct.pack("d", tol))
+        for m, q, ell in cases:
+            Q, _ = np.linalg.qr(_rand(rng, m, ell))
+            # a projected block with a decaying spectrum
+            M = (_rand(rng, q, ell) * 4.0 ** -np.arange(ell)) @ np.linalg.qr(_rand(rng, ell, ell))[0]
+            fp.write(struct.pack("3i", m, q, ell))
+            fp.write(np.asfortranarray(Q).tobytes(order="F"))
+            fp.write(np.asfortranarray(M).tobytes(order="F"))
+            data.append((Q, M))
+    r = subprocess.run([wave, fin, fout], capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    out = open(fout, "rb").read()
+    off = 0
+    for (m, q, ell), (Q, M) in zip(cases, data):
+        w = min(ell, rmax)
+        Uo, off = _mat(out, off, m, w)
+        Vo, off = _mat(out, off, q, w)
+        full = Q @ M.T
+        Uf, sv, Vh = np.linalg.svd(full, full_matrices=False)
+        keep = min(int(np.sum(sv > tol * sv[0])), rmax)
+        best = (Uf[:, :keep] * sv[:keep]) @ Vh[:keep]
+        assert np.linalg.norm(Uo @ Vo.T - best) <= 1e-12 * sv[0]

@@ -149,6 +149,43 @@ int main(int argc, char** argv) {
         fclose(out);
         return 0;
     }
+    if (op == 5) {
+        // randomized-SVD tails: p = jobs, rmax; per job int32 m, q, ell, then
+        // Q (m x ell), M (q x ell); output each job's Uo (m x r), Vo (q x r)
+        const int count = p;
+        std::vector<RsvdTail> jobs(count);
+        for (int t = 0; t < count; ++t) {
+            int32_t d[3];
+            if (!rd(fp, d, 12)) return 2;
+            RsvdTail& J = jobs[t];
+            J.m = d[0]; J.q = d[1]; J.ell = d[2];
+            const int r = J.ell < rmax ? J.ell : rmax;
+            std::vector<c128> h((size_t)J.m * J.ell + (size_t)J.q * J.ell);
+            if (!rd(fp, h.data(), h.size() * 16)) return 2;
+            c128* Qd = dev<c128>((size_t)J.m * J.ell);
+            J.M = dev<c128>((size_t)J.q * J.ell);
+            hipMemcpy(Qd, h.data(), (size_t)J.m * J.ell * 16, hipMemcpyHostToDevice);
+            hipMemcpy(J.M, h.data() + (size_t)J.m * J.ell, (size_t)J.q * J.ell * 16, hipMemcpyHostToDevice);
+            J.Q = Qd;
+            J.V = dev<c128>((size_t)J.ell * J.ell);
+            J.sig = dev<double>(J.ell);
+            J.perm = dev<int>(J.ell);
+            J.rank = dev<int>(1);
+            J.Vg = dev<c128>((size_t)J.ell * r);
+            J.Uo = dev<c128>((size_t)J.m * r);
+            J.Vo = dev<c128>((size_t)J.q * r);
+        }
+        fclose(fp);
+        launch_rsvd_tails(jobs.data(), count, rmax, tol, nullptr);
+        FILE* out = fopen(argv[2], "wb");
+        for (const RsvdTail& J : jobs) {
+            const int r = J.ell < rmax ? J.ell : rmax;
+            fwrite(J.Uo, 16, (size_t)J.m * r, out);
+            fwrite(J.Vo, 16, (size_t)J.q * r, out);
+        }
+        fclose(out);
+        return 0;
+    }
     std::vector<c128> a((size_t)lda * k);
     if (!rd(fp, a.data(), a.size() * 16)) return 2;
     fclose(fp);
