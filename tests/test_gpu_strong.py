@@ -96,6 +96,23 @@ def test_rank_two_strong_factors_two_sources_n127():
         assert_close(U.cpu().numpy()[k], Ue[k], 1e-8, f"source {k}")
 
 
+def test_rank_two_strong_factors_n255():
+    """A layer tree of 255 positions (leaf 16, 16 leaves): batches of more
+    than 32 block jobs and products over deeper trees; GMRES to 1e-10 gives
+    the sparse-LU solution element by element."""
+    _need_gpu()
+    n = 255
+    c = W.random_field_medium(n, 47)
+    om = 2 * np.pi * 32
+    F = W.gaussian_source(n, (0.45, 0.55)).reshape(1, -1).astype(complex)
+    s = _Solver()(c, om, 16, leaf=16, rank=2, rank_tol=1e-6, precision="c128", admissibility="strong").factor()
+    U, its, res = s.solve(_t(F), tol=1e-10, maxit=50)
+    print(f"strong rank 2, n = 255: {its[0]} GMRES iterations")
+    assert res[0] <= 1e-10 and its[0] <= 8
+    Ue = direct.solve_sparse(assemble.stencil(c, om, 16), F)
+    assert_close(U.cpu().numpy()[0], Ue[0], 1e-7, "source")
+
+
 def test_strong_format_rejects_other_forms():
     _need_gpu()
     from paper_1007_4290_amd import _lib
