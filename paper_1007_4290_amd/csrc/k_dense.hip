@@ -1,11 +1,22 @@
-// Small dense complex128 factorizations of the strongly admissible
-// H-arithmetic (Sec. 2.3, strongly admissible case): the thin QR and the
-// SVD of a recompression, and the inverse of a dense leaf.  One wavefront
-// of 64 lanes works on one matrix: the blocks are at most a few hundred
-// rows by a few dozen columns, and the factorization's critical path is a
-// long chain of such small operations, so what counts is the length of
-// each one's dependent chain, which the lanes shorten by splitting rows and
-// columns between them.
+// Small dense complex128 kernels of the strongly admissible H-arithmetic
+// (Sec. 2.3, strongly admissible case):
+//   block_jobs_kernel   a batch of block operations, one workgroup each: the
+//                       recompression of a sum of two low-rank blocks (QRs
+//                       of both stacked factors, SVD of the core, the kept
+//                       columns), dense sums, low-rank updates, scalings and
+//                       copies;
+//   rsvd_tail_kernel    a batch of randomized-SVD tails (SVD of the projected
+//                       block, the kept columns, U = Q conj(V_r));
+//   hmatvec_kernel      one class of leaf blocks of an H-matrix product;
+//   zqr_wave_kernel     the randomized SVD's sample QR;
+//   zinv_wave_kernel    the inverse of a dense leaf;
+//   zsvd_wave_kernel    the one-sided Jacobi SVD on its own (the recompression
+//                       and the tail run the same code inside their kernels).
+// One wavefront of 64 lanes works on one matrix: the blocks are at most a
+// few hundred rows by a few dozen columns, and the factorization's critical
+// path is a long chain of such small operations, so what counts is the
+// length of each one's dependent chain, which the lanes shorten by
+// splitting rows and columns between them.
 //
 // Matrices are column-major with the stated leading dimensions; every
 // buffer is device memory owned by the caller.
