@@ -346,12 +346,12 @@ def test_dense_block_jobs(wave, tmp_path):
 
 
 def test_randomized_svd_tails(wave, tmp_path):
-    """Two randomized-SVD tails in one launch (one staged in shared memory,
-    one too large for it): Uo Vo^t is the truncated SVD of Q M^t, with Q an
-    orthonormal sample basis, rank capped at rmax and cut at tol."""
+    """Three randomized-SVD tails in one launch (one staged in shared memory,
+    one too large for it, one square): Uo Vo^t is the truncated SVD of Q M^t,
+    with Q an orthonormal sample basis, rank capped at rmax and cut at tol."""
     rng = np.random.default_rng(800)
     rmax, tol = 3, 1e-6
-    cases = [(24, 20, 10), (200, 420, 10)]
+    cases = [(24, 20, 10), (200, 420, 10), (12, 10, 10)]
     data = []
     fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
     with open(fin, "wb") as fp:
