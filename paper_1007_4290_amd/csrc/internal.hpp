@@ -235,14 +235,21 @@ void launch_block_jobs(const BlockJob* jobs, int count, int rmax, double tol, hi
 // overwritten with M V; right singular vectors in V, norms in sig, order in
 // perm, kept count in *rank as launch_small_svd), then Vg = conj(V_r) (ell x
 // r), Vo = (M V)_r (q x r) and Uo = Q Vg (m x r), r = min(ell, rmax), the
-// columns past the kept rank zero.  Q is m x ell.
+// columns past the kept rank zero.  Q is m x ell; work holds
+// rsvd_tail_work(q, ell) entries.
 struct RsvdTail {
     const c128* Q;
-    c128 *M, *V, *Vg, *Uo, *Vo;
+    c128 *M, *V, *Vg, *Uo, *Vo, *work;
     double* sig;
     int *perm, *rank;
     int m, q, ell;
 };
+// Device work of a tail (A V and the Gram matrix) and its whole working set,
+// which is staged in shared memory when small enough.
+inline size_t rsvd_tail_work(int q, int ell) { return (size_t)q * ell + (size_t)ell * ell; }
+__host__ __device__ inline size_t rsvd_tail_entries(int q, int ell) {
+    return 2 * ((size_t)q * ell + (size_t)ell * ell);
+}
 // count independent tails (host array), one workgroup each, in launches of up to 32.
 void launch_rsvd_tails(const RsvdTail* jobs, int count, int rmax, double tol, hipStream_t s);
 

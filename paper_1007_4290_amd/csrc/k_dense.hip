@@ -279,6 +279,9 @@ __device__ __forceinline__ void round_robin_pair(int B, int r, int kp, int& p, i
 // columns by decreasing sigma (ties by index; NaN last), and *rank is the
 // number kept: sigma > tol * sigma_max (sigma > 0 when tol = 0), at most
 // rmax.
+__device__ void order_columns(int a, int b, const c128* A, int lda, double* sig, int* perm, int* rank, double tol,
+                              int rmax);
+
 // Ends after a barrier, *rank written.
 __device__ void wave_svd(int a, int b, c128* A, int lda, c128* V, double* sig, int* perm, int* rank, double tol,
                          int rmax) {
@@ -356,6 +359,15 @@ __device__ void wave_svd(int a, int b, c128* A, int lda, c128* V, double* sig, i
         }
         if (wave_sum_int(rot) == 0) break;
     }
+    order_columns(a, b, A, lda, sig, perm, rank, tol, rmax);
+}
+
+// sigma_j = |column j| of the a x b matrix A, perm the columns by decreasing
+// sigma (ties by index; NaN last), *rank the number kept: sigma > tol *
+// sigma_max (sigma > 0 when tol = 0), at most rmax.  Ends after a barrier.
+__device__ void order_columns(int a, int b, const c128* A, int lda, double* sig, int* perm, int* rank, double tol,
+                              int rmax) {
+    const int lane = threadIdx.x;
     for (int j = lane; j < b; j += kWave) {
         const c128* x = A + (size_t)j * lda;
         double s0 = 0.0, s1 = 0.0;
@@ -665,6 +677,115 @@ __global__ void __launch_bounds__(kMvThreads) hmatvec_kernel(MatvecBatch B) {
     }
 }
 
+// The SVD of a tall a x b matrix A (b <= 64 columns) through its Gram
+// matrix: G = A^H A in FP64, diagonalized by a parallel two-sided Jacobi
+// (each round rotates a round-robin set of disjoint index pairs: the
+// rotation's parameters are entries of G, so a round needs no cross-lane
+// sums; the columns of G and V are rotated, then the rows of G), then W = A V
+// and its columns ordered as wave_svd orders A V.  Squaring costs accuracy
+// only for singular values far below the largest (relative error about
+// 1e-16 (sigma_1 / sigma_j)^2), where the truncation cuts.  A pair is
+// rotated unless its off-diagonal entry is below 1e-15 of the geometric
+// mean of its diagonal, or one diagonal is below 1e-30 of the other, or both
+// are below 1e-30 of the trace.  Ends after a barrier.
+__device__ void wave_gram_svd(int a, int b, const c128* A, int lda, c128* G, c128* V, c128* W, double* sig, int* perm,
+                              int* rank, double tol, int rmax) {
+    __shared__ double pcs[32], psn[32];
+    __shared__ c128 pe[32];
+    __shared__ int pturn[32];
+    const int lane = threadIdx.x;
+    for (int e = lane; e < b * b; e += kWave) V[e] = mk(e % b == e / b ? 1.0 : 0.0, 0.0);
+    // G (column-major, both triangles), entry (i, j) with i <= j by one lane
+    for (int e = lane; e < b * (b + 1) / 2; e += kWave) {
+        int j = 0;
+        while ((j + 1) * (j + 2) / 2 <= e) ++j;
+        const int i = e - j * (j + 1) / 2;
+        const c128* x = A + (size_t)i * lda;
+        const c128* y = A + (size_t)j * lda;
+        c128 g0 = czero<double>(), g1 = g0;
+        int l = 0;
+        for (; l + 1 < a; l += 2) {
+            cfma_conj(g0, x[l], y[l]);
+            cfma_conj(g1, x[l + 1], y[l + 1]);
+        }
+        if (l < a) cfma_conj(g0, x[l], y[l]);
+        const c128 g = g0 + g1;
+        G[(size_t)j * b + i] = g;
+        G[(size_t)i * b + j] = conj(g);
+    }
+    __syncthreads();
+    double tr = 0.0;
+    for (int j = lane; j < b; j += kWave) tr += G[(size_t)j * b + j].re;
+    const double noise = 1e-30 * wave_sum(tr);
+    const int B = b + (b & 1), npair = B / 2;
+    for (int sweep = 0; sweep < 80 && B >= 2; ++sweep) {
+        int rot = 0;
+        for (int r = 0; r < B - 1; ++r) {
+            for (int kp = lane; kp < npair; kp += kWave) {
+                int p = 0, q = 0;
+                round_robin_pair(B, r, kp, p, q);
+                bool turn = q < b;
+                double cs = 1.0, sn = 0.0;
+                c128 e = mk(1.0, 0.0);
+                if (turn) {
+                    const double al = G[(size_t)p * b + p].re, be = G[(size_t)q * b + q].re;
+                    const c128 ga = G[(size_t)q * b + p];
+                    const double gabs = hypot(ga.re, ga.im);
+                    turn = gabs > 1e-15 * sqrt(fabs(al)) * sqrt(fabs(be));
+                    if (be < 1e-30 * al || al < 1e-30 * be || (al <= noise && be <= noise)) turn = false;
+                    if (turn) {
+                        ++rot;
+                        e = mk(ga.re / gabs, -ga.im / gabs);
+                        const double zeta = (be - al) / (2.0 * gabs);
+                        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        cs = 1.0 / sqrt(1.0 + t * t);
+                        sn = cs * t;
+                    }
+                }
+                pturn[kp] = turn;
+                pcs[kp] = cs;
+                psn[kp] = sn;
+                pe[kp] = e;
+            }
+            __syncthreads();
+            // columns p, q of G and V: x' = cs x - sn e y, y' = sn x + cs e y
+            for (int e2 = lane; e2 < npair * 2 * b; e2 += kWave) {
+                const int kp = e2 / (2 * b), i = e2 % b;
+                const bool onv = (e2 / b) % 2 == 1;
+                if (!pturn[kp]) continue;
+                int p = 0, q = 0;
+                round_robin_pair(B, r, kp, p, q);
+                c128* M = onv ? V : G;
+                const c128 x = M[(size_t)p * b + i], w = pe[kp] * M[(size_t)q * b + i];
+                M[(size_t)p * b + i] = pcs[kp] * x - psn[kp] * w;
+                M[(size_t)q * b + i] = psn[kp] * x + pcs[kp] * w;
+            }
+            __syncthreads();
+            // rows p, q of G: row_p' = cs row_p - sn conj(e) row_q, row_q' = sn row_p + cs conj(e) row_q
+            for (int e2 = lane; e2 < npair * b; e2 += kWave) {
+                const int kp = e2 / b, j = e2 % b;
+                if (!pturn[kp]) continue;
+                int p = 0, q = 0;
+                round_robin_pair(B, r, kp, p, q);
+                const c128 x = G[(size_t)j * b + p], w = conj(pe[kp]) * G[(size_t)j * b + q];
+                G[(size_t)j * b + p] = pcs[kp] * x - psn[kp] * w;
+                G[(size_t)j * b + q] = psn[kp] * x + pcs[kp] * w;
+            }
+            __syncthreads();
+        }
+        if (wave_sum_int(rot) == 0) break;
+    }
+    // W = A V (a x b)
+    for (size_t e2 = lane; e2 < (size_t)a * b; e2 += kWave) {
+        const int i = (int)(e2 % a), j = (int)(e2 / a);
+        c128 acc = czero<double>();
+        for (int l = 0; l < b; ++l) cfma(acc, A[(size_t)l * lda + i], V[(size_t)j * b + l]);
+        W[e2] = acc;
+    }
+    __syncthreads();
+    order_columns(a, b, W, a, sig, perm, rank, tol, rmax);
+}
+
 // Randomized-SVD tails of one launch, one workgroup each, passed by value.
 constexpr int kTailBatch = 32;
 struct RsvdTailBatch {
@@ -680,12 +801,21 @@ __global__ void __launch_bounds__(kWave) rsvd_tail_kernel(RsvdTailBatch B) {
     HIP_DYNAMIC_SHARED(c128, lds)
     const RsvdTail& J = B.job[blockIdx.x];
     const int m = J.m, q = J.q, ell = J.ell, r = min(ell, B.rmax);
-    const bool staged = ((size_t)q * ell + (size_t)ell * ell) * sizeof(c128) <= B.lds;
+    const size_t qe = (size_t)q * ell, ee = (size_t)ell * ell;
+    const bool staged = rsvd_tail_entries(q, ell) * sizeof(c128) <= B.lds;
     c128* A = staged ? lds : J.M;
-    c128* V = staged ? lds + (size_t)q * ell : J.V;
+    c128* V = staged ? lds + qe : J.V;
     if (staged) wave_copy(q, ell, J.M, q, A, q);
     __syncthreads();
-    wave_svd(q, ell, A, q, V, J.sig, J.perm, J.rank, B.tol, B.rmax);
+    if (ell <= 64) {
+        // through the ell x ell Gram matrix; A V lands in W
+        c128* W = staged ? V + ee : J.work;
+        c128* G = W + qe;
+        wave_gram_svd(q, ell, A, q, G, V, W, J.sig, J.perm, J.rank, B.tol, B.rmax);
+        A = W;
+    } else {
+        wave_svd(q, ell, A, q, V, J.sig, J.perm, J.rank, B.tol, B.rmax);
+    }
     const int kept = *J.rank;
     for (size_t e = threadIdx.x; e < (size_t)ell * r; e += kWave) {
         const int i = (int)(e % ell), j = (int)(e / ell);
@@ -780,7 +910,7 @@ void launch_rsvd_tails(const RsvdTail* jobs, int count, int rmax, double tol, hi
         for (int j = 0; j < nb; ++j) {
             const RsvdTail& J = jobs[j0 + j];
             B.job[j] = J;
-            const size_t bytes = ((size_t)J.q * J.ell + (size_t)J.ell * J.ell) * sizeof(c128);
+            const size_t bytes = rsvd_tail_entries(J.q, J.ell) * sizeof(c128);
             if (bytes <= kLdsBytes && bytes > lds) lds = bytes;
         }
         B.tol = tol;

@@ -638,6 +638,7 @@ struct StrongFactors {
         out.Q = Q;
         out.M = M;
         out.V = talloc((size_t)ell * ell);
+        out.work = talloc(rsvd_tail_work(q, ell));
         out.sig = (double*)talloc(((size_t)ell + 1) / 2 + 1);
         out.perm = (int*)talloc(((size_t)ell + 3) / 4 + 1);
         out.rank = (int*)talloc(1);

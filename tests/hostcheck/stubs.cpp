@@ -217,5 +217,6 @@ void launch_rsvd_tails(const RsvdTail* jobs, int count, int rmax, double, hipStr
         need(J.perm, (size_t)J.ell * 4, "tail perm"); need(J.rank, 4, "tail rank");
         need(J.Vg, (size_t)J.ell * r * 16, "tail Vg"); need(J.Uo, (size_t)J.m * r * 16, "tail Uo");
         need(J.Vo, (size_t)J.q * r * 16, "tail Vo");
+        need(J.work, rsvd_tail_work(J.q, J.ell) * 16, "tail work");
     }
 }

@@ -168,6 +168,7 @@ int main(int argc, char** argv) {
             hipMemcpy(J.M, h.data() + (size_t)J.m * J.ell, (size_t)J.q * J.ell * 16, hipMemcpyHostToDevice);
             J.Q = Qd;
             J.V = dev<c128>((size_t)J.ell * J.ell);
+            J.work = dev<c128>(rsvd_tail_work(J.q, J.ell));
             J.sig = dev<double>(J.ell);
             J.perm = dev<int>(J.ell);
             J.rank = dev<int>(1);
