@@ -30,8 +30,9 @@ namespace {
 constexpr int kWave = 64;
 // A kernel whose working set fits in this much shared memory (LDS) works
 // there, the inputs copied in and the results out; a larger one works in
-// the caller's device buffers.
-constexpr size_t kLdsBytes = 64 * 1024;
+// the caller's device buffers.  (64 KiB per workgroup in all, a few KiB
+// left for the kernels' own shared arrays.)
+constexpr size_t kLdsBytes = 60 * 1024;
 
 // Copy of an m x n column-major block between leading dimensions.
 __device__ __forceinline__ void wave_copy(int m, int n, const c128* src, int lds_, c128* dst, int ldd) {
