@@ -13,7 +13,7 @@ and mutually orthogonal columns whose norms are A's singular values, the
 permutation sorting them, the kept count as specified; A X = I; the
 recompression's product equal to the truncated SVD of the sum; the
 leaf-block products of an H-matrix product equal to the dense products.  Working sets
-below and above the 64 KiB the kernels stage in shared memory are both
+below and above the 60 KiB the kernels stage in shared memory are both
 covered.  The shapes
 cover one and several passes of the column and pair loops, more columns than
 rows, zero columns (the zero-padded factor widths), odd and even column
@@ -69,7 +69,7 @@ def _rand(rng, m, n):
     return rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
 
 
-# working sets below and above the 64 KiB that the kernels stage in shared memory
+# working sets below and above the 60 KiB that the kernels stage in shared memory
 QR_CASES = [(1, 1), (5, 3), (3, 5), (64, 10), (130, 7), (20, 70), (33, 33), (200, 2), (300, 10)]
 
 
@@ -206,7 +206,7 @@ def test_recompression(wave, tmp_path, case):
 
 def test_recompression_batch(wave, tmp_path):
     """Thirty-four jobs in one call (two launches of up to 32 workgroups), with
-    working sets in and beyond the 64 KiB of shared memory side by side."""
+    working sets in and beyond the 60 KiB of shared memory side by side."""
     cases = [REC_CASES[t % 2][:4] + (1e-6,) for t in range(33)] + [REC_CASES[2][:4] + (1e-6,)]
     for (inputs, ou, ov), c in zip(_recompress(wave, tmp_path, cases, 6), cases):
         _check_truncation(inputs, ou, ov, 1e-6, 6)
