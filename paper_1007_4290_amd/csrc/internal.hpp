@@ -161,8 +161,10 @@ void launch_conj(const c128* x, c128* y, size_t n, hipStream_t s);
 // ---- small dense complex128 factorizations (k_dense.hip), one wavefront
 // per matrix, column-major, all buffers device memory ----
 // Thin QR of the p x k matrix A (leading dimension lda), kk = min(p, k):
-// Q (p x kk), R (kk x k, upper), with W (p x k) and Vh (p x kk) as work.
-void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, hipStream_t s);
+// Q (p x kk), R (kk x k, upper), with W (p x k) and Vh (p x kk) as work;
+// conj(Q) also into Qc (p x kk) when it is not null.
+void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, c128* Qc,
+                     hipStream_t s);
 // One-sided Jacobi SVD of the a x b matrix A in place (A becomes A V), V
 // (b x b); sig (b) the column norms, perm (b) the columns by decreasing
 // norm, *rank the count above tol * sigma_max (above 0 for tol = 0), at

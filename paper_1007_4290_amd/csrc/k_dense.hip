@@ -235,7 +235,7 @@ __device__ void wave_qr_pair(int k, int p0, c128* W0, c128* Vh0, c128* Q0, c128*
 }
 
 __global__ void __launch_bounds__(kWave) zqr_wave_kernel(int p, int k, const c128* __restrict__ A, int lda, c128* W,
-                                                         c128* Vh, c128* Q, c128* R, int staged) {
+                                                         c128* Vh, c128* Q, c128* R, c128* Qc, int staged) {
     HIP_DYNAMIC_SHARED(c128, lds)
     const int kk = min(p, k);
     c128 *w = W, *vh = Vh, *q = Q, *r = R;
@@ -252,6 +252,8 @@ __global__ void __launch_bounds__(kWave) zqr_wave_kernel(int p, int k, const c12
         wave_copy(p, kk, q, p, Q, p);
         wave_copy(kk, k, r, kk, R, kk);
     }
+    if (Qc)
+        for (size_t e = threadIdx.x; e < (size_t)p * kk; e += kWave) Qc[e] = conj(q[e]);
 }
 
 // Pair kp of round r of the circle-method round robin over B (even)
@@ -856,11 +858,12 @@ void launch_block_jobs(const BlockJob* jobs, int count, int rmax, double tol, hi
     }
 }
 
-void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, hipStream_t s) {
+void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, c128* Qc,
+                     hipStream_t s) {
     const size_t kk = p < k ? p : k;
     const size_t bytes = ((size_t)p * k + 2 * (size_t)p * kk + kk * k) * sizeof(c128);
     const int staged = bytes <= kLdsBytes;
-    hipLaunchKernelGGL(zqr_wave_kernel, dim3(1), dim3(kWave), staged ? bytes : 0, s, p, k, A, lda, W, Vh, Q, R,
+    hipLaunchKernelGGL(zqr_wave_kernel, dim3(1), dim3(kWave), staged ? bytes : 0, s, p, k, A, lda, W, Vh, Q, R, Qc,
                        staged);
 }
 

@@ -530,14 +530,14 @@ struct StrongFactors {
 
     // ---- small factorizations
     // Thin QR of A (p x k): Q (p x kk), R (kk x k), kk = min(p, k).
-    void qr(int p, int k, const c128* A, int lda, c128*& Q, c128*& R) {
+    void qr(int p, int k, const c128* A, int lda, c128*& Q, c128*& R, c128* Qc = nullptr) {
         const int kk = std::min(p, k);
         c128* W = talloc((size_t)p * k);
         c128* Vh = talloc((size_t)p * kk);
         Q = talloc((size_t)p * kk);
         R = talloc((size_t)kk * k);
         if (!ok()) return;
-        launch_small_qr(p, k, A, lda, W, Vh, Q, R, s);
+        launch_small_qr(p, k, A, lda, W, Vh, Q, R, Qc, s);
     }
 
     // out = trunc([a.u, alpha U] [a.v, V]^t): QR of both stacked factors,
@@ -625,12 +625,11 @@ struct StrongFactors {
         matvec_set(H, hi, Om, q, ell, Y1, mid, mk(1.0, 0.0));
         matvec_set(G, gi, Y1, mid, ell, Y, m, mk(1.0, 0.0));
         c128 *Q, *R;
-        qr(m, ell, Y, m, Q, R);                       // ell <= m: Q is m x ell
         c128* Qc = talloc((size_t)m * ell);
+        qr(m, ell, Y, m, Q, R, Qc);                   // ell <= m: Q and conj(Q) are m x ell
         c128* M1 = talloc((size_t)mid * ell);
         c128* M = talloc((size_t)q * ell);
         if (!ok()) return 0;
-        geam(m, ell, mk(1.0, 0.0), 2, Q, m, czero<double>(), nullptr, 0, Qc, m);
         matvec_t_set(G, gi, Qc, m, ell, M1, mid, mk(1.0, 0.0));
         matvec_t_set(H, hi, M1, mid, ell, M, q, mk(1.0, 0.0));
         const int r = std::min(ell, rmax);               // width: the kept rank's bound

@@ -9,7 +9,8 @@
 #include <vector>
 #include "internal.hpp"
 
-void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, hipStream_t) {
+void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, c128* Qc,
+                     hipStream_t) {
     const int kk = p < k ? p : k;
     for (int j = 0; j < k; ++j)
         for (int i = 0; i < p; ++i) W[(size_t)j * p + i] = A[(size_t)j * lda + i];
@@ -50,6 +51,8 @@ void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c1
             for (int i = c; i < p; ++i) Q[(size_t)j * p + i] -= f * v[i];
         }
     }
+    if (Qc)
+        for (size_t e = 0; e < (size_t)p * kk; ++e) Qc[e] = conj(Q[e]);
 }
 
 void launch_small_svd(int a, int b, c128* A, int lda, c128* V, double* sig, int* perm, int* rank, double tol,
@@ -166,8 +169,8 @@ static void recompress_one(int m, int q, int k1, int k2, int rmax, double tol, c
             W1[(size_t)j * m + i] = j < k1 ? au[(size_t)j * m + i] : alpha * U[(size_t)(j - k1) * ldu + i];
     for (int j = 0; j < k; ++j)
         for (int i = 0; i < q; ++i) W2[(size_t)j * q + i] = j < k1 ? av[(size_t)j * q + i] : V[(size_t)(j - k1) * ldv + i];
-    launch_small_qr(m, k, W1, m, W1, work + L.Vh1, Q1, R1, s);
-    launch_small_qr(q, k, W2, q, W2, work + L.Vh2, Q2, R2, s);
+    launch_small_qr(m, k, W1, m, W1, work + L.Vh1, Q1, R1, nullptr, s);
+    launch_small_qr(q, k, W2, q, W2, work + L.Vh2, Q2, R2, nullptr, s);
     for (int j = 0; j < kk2; ++j)
         for (int i = 0; i < kk1; ++i) {
             c128 acc = czero<double>();

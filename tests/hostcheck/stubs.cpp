@@ -147,8 +147,10 @@ void launch_combine(const c128* Z, int nz, size_t ld, const c128* y, c128* x, co
     need(y, nz * S * 16, "combine y"); need(x, off[S] * 16, "combine x");
 }
 int multi_launches() { return g_multi; }
-void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, hipStream_t) {
+void launch_small_qr(int p, int k, const c128* A, int lda, c128* W, c128* Vh, c128* Q, c128* R, c128* Qc,
+                     hipStream_t) {
     const int kk = p < k ? p : k;
+    if (Qc) need(Qc, (size_t)p * kk * 16, "qr conj(Q)");
     if (k > 0) need(A, ((size_t)(k - 1) * lda + p) * 16, "qr A");
     need(W, (size_t)p * k * 16, "qr W"); need(Vh, (size_t)p * kk * 16, "qr Vh");
     need(Q, (size_t)p * kk * 16, "qr Q"); need(R, (size_t)kk * k * 16, "qr R");

@@ -83,7 +83,9 @@ def test_qr(wave, tmp_path, p, k):
     out = _run(wave, tmp_path, 0, A, p, k)
     kk = min(p, k)
     Q, off = _mat(out, 0, p, kk)
-    R, _ = _mat(out, off, kk, k)
+    R, off = _mat(out, off, kk, k)
+    Qc, _ = _mat(out, off, p, kk)
+    assert np.array_equal(Qc, Q.conj())
     a = A[:p]
     assert np.allclose(Q.conj().T @ Q, np.eye(kk), atol=1e-13)
     assert np.allclose(np.tril(R, -1), 0.0)

@@ -196,10 +196,11 @@ int main(int argc, char** argv) {
     if (op == 0) {
         const int kk = p < k ? p : k;
         c128 *W = dev<c128>((size_t)p * k), *Vh = dev<c128>((size_t)p * kk), *Q = dev<c128>((size_t)p * kk),
-             *R = dev<c128>((size_t)kk * k);
-        launch_small_qr(p, k, A, lda, W, Vh, Q, R, nullptr);
+             *R = dev<c128>((size_t)kk * k), *Qc = dev<c128>((size_t)p * kk);
+        launch_small_qr(p, k, A, lda, W, Vh, Q, R, Qc, nullptr);
         fwrite(Q, 16, (size_t)p * kk, out);
         fwrite(R, 16, (size_t)kk * k, out);
+        fwrite(Qc, 16, (size_t)p * kk, out);
     } else if (op == 1) {
         c128* V = dev<c128>((size_t)k * k);
         double* sig = dev<double>(k);
