@@ -418,6 +418,22 @@ def strong_workload(tol, n=127):
 PAPER_LENS_STRONG = {255: (5.05, 2, 0.25), 511: (34.4, 3, 1.45)}
 
 
+def strong_lens_factor(n):
+    """One strongly admissible rank-2 factorization of the lens workload of
+    strong_lens_workload at size n, timed."""
+    import torch
+    import workloads as W
+    from paper_1007_4290_amd.solver import Solver
+    s = Solver(W.lens_medium(n), 2 * np.pi * ((n + 1) // 8), 16, leaf=16, rank=2, rank_tol=1e-6, precision="c128",
+               admissibility="strong")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.factor()
+    torch.cuda.synchronize()
+    print(f"[bench] strong rank 2 lens, n = {n}: factor {1e3 * (time.perf_counter() - t0):.0f} ms", file=sys.stderr,
+          flush=True)
+
+
 def strong_lens_workload(sizes=(255, 511)):
     """Strongly admissible rank-2 factors at the paper's lens sizes: the lens
     medium, 8 points per wavelength (omega = 2 pi (n + 1) / 8), layers of 16
@@ -564,6 +580,9 @@ def main():
     ap.add_argument("--strong-probe", action="store_true",
                     help="only the strongly admissible rank-2 factorization and solve at n = 63 (a short run "
                          "for the kernel trace); no JSON line")
+    ap.add_argument("--strong-lens-probe", action="store_true",
+                    help="only one strongly admissible rank-2 factorization of the n = 255 lens (the first row of "
+                         "the strong_rank2_lens workload; a run for the kernel trace); no JSON line")
     ap.add_argument("--iteration-tables", action="store_true",
                     help="only the GMRES iteration counts of three media at 8 points per wavelength, "
                          "n = 127..1023 (one JSON line)")
@@ -594,6 +613,9 @@ def main():
         return
     if args.strong_probe:
         print(json.dumps(strong_workload(1e-6, n=63)), file=sys.stderr, flush=True)
+        return
+    if args.strong_lens_probe:
+        strong_lens_factor(255)
         return
     tol = 1e-6
     wl = W.get("helm255_grf", precision="c64")
